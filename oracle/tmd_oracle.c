@@ -1,0 +1,588 @@
+/*
+ * Plain CPU oracle for TPC track-model decoding -- TEST INFRASTRUCTURE ONLY.
+ *
+ * This file is the slow, obviously-correct reference that the GPU library is
+ * checked against.  Only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark may load it; the product path never does.  It shares no
+ * source with the HIP library.
+ *
+ * What it computes (arXiv:2411.02206, section 4, "TPC track-model decoding on
+ * GPU"): attached clusters are stored as residuals to a track, so decoding
+ * propagates each track through the TPC and adds the stored residuals (the
+ * paper's first kernel: one track at a time); unattached clusters were sorted
+ * by position and stored as differences to their predecessor, so decoding sums
+ * the differences onto the last decoded cluster within one TPC region (the
+ * paper's second kernel).  The paper leaves the track model itself undefined;
+ * the model below is this project's own, documented one:
+ *   - local sector frame (x radial through the sector centre, y along
+ *     increasing azimuth), state y, z, sin(phi), tan(lambda), q/pT;
+ *   - helix propagation in a uniform Bz field, exact for y, chord for z;
+ *   - rotation into the neighbouring sector frame at a sector crossing;
+ *   - residual-driven fixed-gain update after every cluster.
+ * Every float32 operation is written out in a fixed order; the library is
+ * compiled with -ffp-contract=off so no multiply-add is ever fused.
+ *
+ * Compile: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define O_NSEC 36
+#define O_NROW 152
+#define O_NBIN (O_NSEC * O_NROW)
+
+/* status bits */
+#define O_F_HDR 1u
+#define O_F_SEC 2u
+#define O_F_ROW 4u
+#define O_F_ROT 8u
+#define O_F_SNP 16u
+#define O_F_PAD 32u
+#define O_F_TIME 64u
+#define O_F_COUNT 128u
+
+/* return codes (mirrors the documented ones of the library, written anew) */
+#define O_OK 0
+#define O_E_ARG (-1)
+#define O_E_CAPACITY (-2)
+
+#define O_TIME_LIM 16777216 /* 2^24: times are kept below this */
+
+/* ------------------------------------------------------------------------ */
+/* Geometry and constants.  Every float value is the float nearest to the    */
+/* double expression that defines it (one rounding).                          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    float x[O_NROW];      /* pad-row local x (cm) */
+    float pw[O_NROW];     /* pad width (cm) */
+    float inv_pw[O_NROW]; /* 1 / pad width */
+    float padoff[O_NROW]; /* half the number of pads: pad 0 sits at the -y edge */
+    float pwq[O_NROW];    /* pad quantum = pad width / 32 (exact) */
+    float ks[O_NROW];     /* sin(phi) gain of the update */
+    float kt[O_NROW];     /* tan(lambda) gain of the update */
+    int npads[O_NROW];
+    float cosb[18], sinb[18]; /* rotation by d * 20 degrees */
+    float kb;                 /* curvature per unit q/pT (1/cm per c/GeV) */
+    float vdq;                /* time quantum in cm = drift velocity / 32 */
+    float inv_vd32;           /* 32 / drift velocity */
+    float snp_max;
+} otab;
+
+static const int o_region_start[5] = {0, 63, 97, 127, 152};
+static const double o_region_x0[4] = {84.85, 134.0, 168.0, 204.0};
+static const double o_pitch[4] = {0.75, 1.00, 1.20, 1.50};
+static const double o_padw[4] = {0.416, 0.608, 0.608, 0.608};
+static const double o_vdrift = 0.516; /* cm per time bin */
+
+static int o_region(int row)
+{
+    int g = 0;
+    while (row >= o_region_start[g + 1]) g++;
+    return g;
+}
+
+static void o_tables(float bz, otab *t)
+{
+    const double pi = 3.14159265358979323846;
+    for (int r = 0; r < O_NROW; r++) {
+        int g = o_region(r);
+        double xd = o_region_x0[g] + ((double)(r - o_region_start[g]) + 0.5) * o_pitch[g];
+        t->x[r] = (float)xd;
+        t->pw[r] = (float)o_padw[g];
+        t->inv_pw[r] = (float)(1.0 / o_padw[g]);
+        t->npads[r] = 2 * (int)floor(xd * tan(pi / 18.0) / o_padw[g]);
+        t->padoff[r] = (float)(t->npads[r] / 2);
+        t->pwq[r] = t->pw[r] * 0.03125f; /* exact: scaling by 2^-5 */
+        t->ks[r] = (float)(0.0625 / o_pitch[g]);
+        t->kt[r] = t->ks[r];
+    }
+    /* rotation by d * 20 degrees; d >= 9 is written as 180 + (d - 9) * 20
+     * degrees so that the half turn gives exactly (-1, 0) */
+    for (int d = 0; d < 18; d++) {
+        int e = d < 9 ? d : d - 9;
+        double sg = d < 9 ? 1.0 : -1.0;
+        t->cosb[d] = (float)(sg * cos((double)e * pi / 9.0));
+        t->sinb[d] = (float)(sg * sin((double)e * pi / 9.0));
+    }
+    t->kb = (float)((double)bz * 0.00299792458);
+    t->vdq = (float)o_vdrift * 0.03125f; /* exact: scaling by 2^-5 */
+    t->inv_vd32 = (float)(32.0 / o_vdrift);
+    t->snp_max = (float)0.999;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Small helpers with fully specified edge behaviour                          */
+/* ------------------------------------------------------------------------ */
+
+/* sin(phi) limiter: NaN -> 0, beyond +-SNP_MAX -> +-SNP_MAX; flags F_SNP. */
+static float o_clamp_snp(const otab *t, float v, uint32_t *flags)
+{
+    if (v != v) { *flags |= O_F_SNP; return 0.0f; }
+    if (v > t->snp_max) { *flags |= O_F_SNP; return t->snp_max; }
+    if (v < -t->snp_max) { *flags |= O_F_SNP; return -t->snp_max; }
+    return v;
+}
+
+/* float (already integral after rintf) -> int32: NaN -> 0, clamp to +-2^30. */
+static int32_t o_sat(float v)
+{
+    if (v != v) return 0;
+    if (v > 1073741824.0f) return 1073741824;
+    if (v < -1073741824.0f) return -1073741824;
+    return (int32_t)v;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Track state and the three model steps                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    float x, y, z, s, tgl, k;
+    int sec, row;
+    int32_t t0;
+} ostate;
+
+/* Track header -> initial state (the first cluster sits on the header). */
+static void o_init(const otab *t, ostate *st, int sec0, int row0, uint16_t pad0, uint32_t time0,
+                   int16_t qptq, int16_t snpq, int16_t tglq, uint32_t *flags)
+{
+    if (sec0 >= O_NSEC) { *flags |= O_F_HDR; sec0 = sec0 % O_NSEC; }
+    if (row0 >= O_NROW) { *flags |= O_F_HDR; row0 = O_NROW - 1; }
+    uint32_t t0 = time0;
+    if (t0 >= O_TIME_LIM) { *flags |= O_F_TIME; t0 = O_TIME_LIM - 1; }
+    st->sec = sec0;
+    st->row = row0;
+    st->t0 = (int32_t)t0;
+    st->x = t->x[row0];
+    st->y = ((float)pad0 * 0x1p-5f - t->padoff[row0]) * t->pw[row0];
+    st->z = 0.0f;
+    st->s = o_clamp_snp(t, (float)snpq * 0x1p-15f, flags);
+    st->tgl = (float)tglq * 0x1p-12f;
+    st->k = ((float)qptq * 0x1p-10f) * t->kb;
+}
+
+/* Move to the next cluster: optional rotation by secdiff sectors, row step,
+ * helix propagation to the new pad row, and the predicted (pad, time) codes
+ * P and T in units of 1/32 pad and 1/32 time bin. */
+static void o_predict(const otab *t, ostate *st, uint8_t secdiff, int8_t rowdiff, int32_t *P,
+                      int32_t *T, uint32_t *flags)
+{
+    int d = secdiff;
+    if (d >= 18) { *flags |= O_F_SEC; d = d % 18; }
+    if (d != 0) {
+        float ca = t->cosb[d];
+        float sa = t->sinb[d];
+        float cs = sqrtf((1.0f - st->s) * (1.0f + st->s));
+        float xn = (st->x * ca) + (st->y * sa);
+        float yn = (st->y * ca) - (st->x * sa);
+        float sn = (st->s * ca) - (cs * sa);
+        float cn = (cs * ca) + (st->s * sa);
+        if (!(cn > 0.0f)) *flags |= O_F_ROT;
+        st->x = xn;
+        st->y = yn;
+        st->s = o_clamp_snp(t, sn, flags);
+        st->sec = (st->sec / 18) * 18 + (st->sec % 18 + d) % 18;
+    }
+    int row = st->row + rowdiff;
+    if (row < 0) { *flags |= O_F_ROW; row = 0; }
+    if (row >= O_NROW) { *flags |= O_F_ROW; row = O_NROW - 1; }
+    st->row = row;
+
+    float xr = t->x[row];
+    float dx = xr - st->x;
+    float s1 = o_clamp_snp(t, st->s + (st->k * dx), flags);
+    float a0 = sqrtf((1.0f - st->s) * (1.0f + st->s));
+    float a1 = sqrtf((1.0f - s1) * (1.0f + s1));
+    float dydx = (st->s + s1) / (a0 + a1);
+    st->y = st->y + (dx * dydx);
+    st->z = st->z + (st->tgl * (dx * sqrtf(1.0f + (dydx * dydx))));
+    st->s = s1;
+    st->x = xr;
+
+    *P = o_sat(rintf(((st->y * t->inv_pw[row]) + t->padoff[row]) * 32.0f));
+    *T = o_sat(rintf(st->z * t->inv_vd32));
+}
+
+/* Residual-driven update: the stored residual, in cm, moves the state onto the
+ * decoded cluster and tilts the direction by a fixed gain. */
+static void o_update(const otab *t, ostate *st, int16_t padres, int16_t timeres, uint32_t *flags)
+{
+    float nuy = (float)padres * t->pwq[st->row];
+    float nuz = (float)timeres * t->vdq;
+    st->y = st->y + nuy;
+    st->z = st->z + nuz;
+    st->s = o_clamp_snp(t, st->s + (nuy * t->ks[st->row]), flags);
+    st->tgl = st->tgl + (nuz * t->kt[st->row]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Decoder                                                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t n_tracks, n_attached, n_unattached;
+    const uint8_t *trk_ncls, *trk_sec0, *trk_row0;
+    const uint16_t *trk_pad0;
+    const uint32_t *trk_time0;
+    const int16_t *trk_qpt, *trk_snp, *trk_tgl;
+    const int8_t *cls_row_diff;
+    const uint8_t *cls_sec_diff;
+    const int16_t *cls_pad_res, *cls_time_res;
+    const uint16_t *cls_qtot, *cls_qmax;
+    const uint32_t *un_count; /* [O_NBIN] */
+    const uint32_t *un_time_diff;
+    const uint16_t *un_pad_diff, *un_qtot, *un_qmax;
+} ostream;
+
+typedef struct {
+    uint32_t *row_offset;    /* [O_NBIN + 1] */
+    uint32_t *row_nattached; /* [O_NBIN] */
+    uint32_t *time;
+    uint16_t *pad, *qtot, *qmax;
+    uint64_t capacity;
+} oclusters;
+
+/* Number of clusters of track `it` that lie inside the declared attached
+ * stream: the stream is cut at n_attached if the per-track counts overrun it. */
+static uint32_t o_track_len(uint64_t start, uint32_t ncls, uint32_t n_attached)
+{
+    if (start >= n_attached) return 0;
+    uint64_t room = (uint64_t)n_attached - start;
+    return ncls < room ? ncls : (uint32_t)room;
+}
+
+int oracle_decode(const ostream *in, oclusters *out, float bz, uint32_t *status)
+{
+    if (!in || !out || !status) return O_E_ARG;
+    if ((uint64_t)in->n_attached + in->n_unattached > out->capacity) return O_E_CAPACITY;
+    otab tab;
+    o_tables(bz, &tab);
+    uint32_t flags = 0;
+    const uint32_t nA = in->n_attached, nU = in->n_unattached;
+
+    /* 1. decode every track into per-cluster temporaries, in stream order */
+    uint16_t *key = (uint16_t *)malloc(sizeof(uint16_t) * (nA ? nA : 1));
+    uint32_t *dtime = (uint32_t *)malloc(sizeof(uint32_t) * (nA ? nA : 1));
+    uint16_t *dpad = (uint16_t *)malloc(sizeof(uint16_t) * (nA ? nA : 1));
+    uint8_t *used = (uint8_t *)calloc(nA ? nA : 1, 1);
+    uint64_t start = 0;
+    for (uint32_t it = 0; it < in->n_tracks; it++) {
+        uint32_t ncls = in->trk_ncls[it];
+        uint32_t n = o_track_len(start, ncls, nA);
+        uint64_t c0 = start;
+        start += ncls;
+        if (ncls == 0) flags |= O_F_HDR;
+        ostate st;
+        o_init(&tab, &st, in->trk_sec0[it], in->trk_row0[it], in->trk_pad0[it], in->trk_time0[it],
+               in->trk_qpt[it], in->trk_snp[it], in->trk_tgl[it], &flags);
+        if (n == 0) continue;
+        key[c0] = (uint16_t)(st.sec * O_NROW + st.row);
+        dtime[c0] = (uint32_t)st.t0;
+        dpad[c0] = in->trk_pad0[it];
+        used[c0] = 1;
+        for (uint32_t j = 1; j < n; j++) {
+            uint64_t c = c0 + j;
+            int32_t P, T;
+            o_predict(&tab, &st, in->cls_sec_diff[c], in->cls_row_diff[c], &P, &T, &flags);
+            int32_t padq = P + (int32_t)in->cls_pad_res[c];
+            if (padq < 0) { flags |= O_F_PAD; padq = 0; }
+            if (padq > 65535) { flags |= O_F_PAD; padq = 65535; }
+            int32_t timeq = st.t0 + T + (int32_t)in->cls_time_res[c];
+            if (timeq < 0) { flags |= O_F_TIME; timeq = 0; }
+            if (timeq > O_TIME_LIM - 1) { flags |= O_F_TIME; timeq = O_TIME_LIM - 1; }
+            key[c] = (uint16_t)(st.sec * O_NROW + st.row);
+            dtime[c] = (uint32_t)timeq;
+            dpad[c] = (uint16_t)padq;
+            used[c] = 1;
+            o_update(&tab, &st, in->cls_pad_res[c], in->cls_time_res[c], &flags);
+        }
+    }
+    if (start != nA) flags |= O_F_COUNT;
+
+    /* 2. per-(sector,row) counts: attached from the decode, unattached from the
+     *    stream (cut at n_unattached if the counts overrun it) */
+    uint32_t na[O_NBIN], nu[O_NBIN];
+    memset(na, 0, sizeof(na));
+    for (uint32_t c = 0; c < nA; c++)
+        if (used[c]) na[key[c]]++;
+    uint64_t ustart[O_NBIN];
+    uint64_t usum = 0;
+    for (int b = 0; b < O_NBIN; b++) {
+        ustart[b] = usum;
+        uint32_t cnt = in->un_count[b];
+        uint32_t eff = 0;
+        if (usum < nU) {
+            uint64_t room = (uint64_t)nU - usum;
+            eff = cnt < room ? cnt : (uint32_t)room;
+        }
+        nu[b] = eff;
+        usum += cnt;
+    }
+    if (usum != nU) flags |= O_F_COUNT;
+
+    /* 3. output offsets: exclusive prefix over bins of attached + unattached */
+    uint32_t acc = 0;
+    for (int b = 0; b < O_NBIN; b++) {
+        out->row_offset[b] = acc;
+        out->row_nattached[b] = na[b];
+        acc += na[b] + nu[b];
+    }
+    out->row_offset[O_NBIN] = acc;
+
+    /* 4. attached clusters: inside each bin, in stream order (track, then j) */
+    uint32_t fill[O_NBIN];
+    memset(fill, 0, sizeof(fill));
+    for (uint32_t c = 0; c < nA; c++) {
+        if (!used[c]) continue;
+        uint32_t b = key[c];
+        uint32_t o = out->row_offset[b] + fill[b]++;
+        out->time[o] = dtime[c];
+        out->pad[o] = dpad[c];
+        out->qtot[o] = in->cls_qtot[c];
+        out->qmax[o] = in->cls_qmax[c];
+    }
+
+    /* 5. unattached clusters: running sums of the stored differences within
+     *    each bin, starting from zero; time wraps at 2^32, pad at 2^16 */
+    for (int b = 0; b < O_NBIN; b++) {
+        uint32_t tsum = 0;
+        uint16_t psum = 0;
+        uint64_t src = ustart[b];
+        uint32_t dst = out->row_offset[b] + na[b];
+        for (uint32_t i = 0; i < nu[b]; i++) {
+            tsum = tsum + in->un_time_diff[src + i];
+            psum = (uint16_t)(psum + in->un_pad_diff[src + i]);
+            out->time[dst + i] = tsum;
+            out->pad[dst + i] = psum;
+            out->qtot[dst + i] = in->un_qtot[src + i];
+            out->qmax[dst + i] = in->un_qmax[src + i];
+        }
+    }
+    free(key);
+    free(dtime);
+    free(dpad);
+    free(used);
+    *status = flags;
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Encoder (inverse of the decoder; used only to build round-trip pins)       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t n_tracks;
+    const uint32_t *trk_first; /* [n_tracks + 1]: cluster range of each track */
+    const double *trk_qpt, *trk_tgl;
+    const uint8_t *cl_sec, *cl_row;
+    const double *cl_pad;  /* pad units, 0 at the -y edge of the row */
+    const double *cl_time; /* time bins */
+    const double *cl_snp;  /* local sin(phi) of the track at the cluster */
+    const uint16_t *cl_qtot, *cl_qmax;
+    uint32_t n_un;
+    const uint8_t *un_sec, *un_row;
+    const double *un_pad, *un_time;
+    const uint16_t *un_qtot, *un_qmax;
+} oenc_in;
+
+typedef struct {
+    /* capacities: tracks and attached clusters <= number of input clusters */
+    uint32_t n_tracks, n_attached, n_unattached; /* written */
+    uint8_t *trk_ncls, *trk_sec0, *trk_row0;
+    uint16_t *trk_pad0;
+    uint32_t *trk_time0;
+    int16_t *trk_qpt, *trk_snp, *trk_tgl;
+    int8_t *cls_row_diff;
+    uint8_t *cls_sec_diff;
+    int16_t *cls_pad_res, *cls_time_res;
+    uint16_t *cls_qtot, *cls_qmax;
+    uint32_t *un_count;
+    uint32_t *un_time_diff;
+    uint16_t *un_pad_diff, *un_qtot, *un_qmax;
+    uint32_t n_splits; /* written: headers started in the middle of a track */
+} oenc_out;
+
+static int16_t o_q16(double v, double scale)
+{
+    double q = rint(v * scale);
+    if (q > 32767.0) q = 32767.0;
+    if (q < -32767.0) q = -32767.0;
+    return (int16_t)q;
+}
+
+/* quantisation of an absolute coordinate into 1/32 units */
+static int64_t o_q32(double v) { return (int64_t)rint(v * 32.0); }
+
+typedef struct {
+    uint64_t key;
+    uint32_t tq;
+    uint16_t pq, qt, qm;
+} o_unrec;
+
+/* order of unattached clusters: bin, then time, pad, qTot, qMax */
+static int o_cmp_un(const void *a, const void *b)
+{
+    const o_unrec *x = (const o_unrec *)a, *y = (const o_unrec *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->qt != y->qt) return x->qt < y->qt ? -1 : 1;
+    if (x->qm != y->qm) return x->qm < y->qm ? -1 : 1;
+    return 0;
+}
+
+int oracle_encode(const oenc_in *in, oenc_out *out, float bz)
+{
+    if (!in || !out) return O_E_ARG;
+    otab tab;
+    o_tables(bz, &tab);
+    uint32_t nt = 0, nc = 0, nsplit = 0;
+    for (uint32_t it = 0; it < in->n_tracks; it++) {
+        uint32_t a = in->trk_first[it], e = in->trk_first[it + 1];
+        int16_t qptq = o_q16(in->trk_qpt[it], 1024.0);
+        int16_t tglq = o_q16(in->trk_tgl[it], 4096.0);
+        uint32_t hdr = 0; /* index of the open header */
+        ostate st;
+        for (uint32_t c = a; c < e; c++) {
+            int64_t padq = o_q32(in->cl_pad[c]);
+            int64_t timeq = o_q32(in->cl_time[c]);
+            if (padq < 0 || padq > 65535 || timeq < 0 || timeq >= O_TIME_LIM) return O_E_ARG;
+            int open_new = (c == a);
+            int8_t rd = 0;
+            uint8_t sd = 0;
+            int16_t pres = 0, tres = 0;
+            if (!open_new) {
+                int drow = (int)in->cl_row[c] - (int)in->cl_row[c - 1];
+                int same_side = (in->cl_sec[c] / 18) == (in->cl_sec[c - 1] / 18);
+                if (drow < -128 || drow > 127 || !same_side || out->trk_ncls[hdr] == 255) {
+                    open_new = 1;
+                } else {
+                    rd = (int8_t)drow;
+                    sd = (uint8_t)(((int)(in->cl_sec[c] % 18) - (int)(in->cl_sec[c - 1] % 18) + 18) % 18);
+                    ostate trial = st;
+                    uint32_t fl = 0;
+                    int32_t P, T;
+                    o_predict(&tab, &trial, sd, rd, &P, &T, &fl);
+                    int64_t pr = padq - P;
+                    int64_t tr = timeq - (int64_t)trial.t0 - T;
+                    if (fl || pr < -32768 || pr > 32767 || tr < -32768 || tr > 32767 ||
+                        trial.sec != in->cl_sec[c] || trial.row != in->cl_row[c]) {
+                        open_new = 1;
+                    } else {
+                        pres = (int16_t)pr;
+                        tres = (int16_t)tr;
+                        o_update(&tab, &trial, pres, tres, &fl);
+                        if (fl) open_new = 1;
+                        else st = trial;
+                    }
+                }
+            }
+            if (open_new) {
+                if (c != a) nsplit++;
+                hdr = nt++;
+                out->trk_ncls[hdr] = 1;
+                out->trk_sec0[hdr] = in->cl_sec[c];
+                out->trk_row0[hdr] = in->cl_row[c];
+                out->trk_pad0[hdr] = (uint16_t)padq;
+                out->trk_time0[hdr] = (uint32_t)timeq;
+                out->trk_qpt[hdr] = qptq;
+                out->trk_snp[hdr] = o_q16(in->cl_snp[c], 32768.0);
+                out->trk_tgl[hdr] = tglq;
+                uint32_t fl = 0;
+                o_init(&tab, &st, in->cl_sec[c], in->cl_row[c], (uint16_t)padq, (uint32_t)timeq, qptq,
+                       out->trk_snp[hdr], tglq, &fl);
+                rd = 0;
+                sd = 0;
+                pres = 0;
+                tres = 0;
+            } else {
+                out->trk_ncls[hdr]++;
+            }
+            out->cls_row_diff[nc] = rd;
+            out->cls_sec_diff[nc] = sd;
+            out->cls_pad_res[nc] = pres;
+            out->cls_time_res[nc] = tres;
+            out->cls_qtot[nc] = in->cl_qtot[c];
+            out->cls_qmax[nc] = in->cl_qmax[c];
+            nc++;
+        }
+    }
+    out->n_tracks = nt;
+    out->n_attached = nc;
+    out->n_splits = nsplit;
+
+    /* unattached: group by bin, sort inside a bin by (time, pad, qTot, qMax),
+     * store differences to the predecessor (the first one against zero) */
+    uint32_t nun = in->n_un;
+    o_unrec *rec = (o_unrec *)malloc(sizeof(o_unrec) * (nun ? nun : 1));
+    for (int b = 0; b < O_NBIN; b++) out->un_count[b] = 0;
+    for (uint32_t i = 0; i < nun; i++) {
+        int64_t padq = o_q32(in->un_pad[i]);
+        int64_t timeq = o_q32(in->un_time[i]);
+        if (padq < 0 || padq > 65535 || timeq < 0 || timeq > 0xFFFFFFFFll || in->un_sec[i] >= O_NSEC ||
+            in->un_row[i] >= O_NROW) {
+            free(rec);
+            return O_E_ARG;
+        }
+        uint64_t b = (uint64_t)in->un_sec[i] * O_NROW + in->un_row[i];
+        rec[i].tq = (uint32_t)timeq;
+        rec[i].pq = (uint16_t)padq;
+        rec[i].qt = in->un_qtot[i];
+        rec[i].qm = in->un_qmax[i];
+        /* bin (13 bits) | time (32 bits) | pad (16 bits) */
+        rec[i].key = (b << 48) | ((uint64_t)rec[i].tq << 16) | rec[i].pq;
+        out->un_count[b]++;
+    }
+    qsort(rec, nun, sizeof(o_unrec), o_cmp_un);
+    uint64_t prev_bin = (uint64_t)-1;
+    uint32_t pt = 0;
+    uint16_t pp = 0;
+    for (uint32_t i = 0; i < nun; i++) {
+        uint64_t b = rec[i].key >> 48;
+        if (b != prev_bin) { pt = 0; pp = 0; prev_bin = b; }
+        out->un_time_diff[i] = rec[i].tq - pt;
+        out->un_pad_diff[i] = (uint16_t)(rec[i].pq - pp);
+        out->un_qtot[i] = rec[i].qt;
+        out->un_qmax[i] = rec[i].qm;
+        pt = rec[i].tq;
+        pp = rec[i].pq;
+    }
+    out->n_unattached = nun;
+    free(rec);
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Introspection for the tests                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Tables as float32 values in a fixed order:
+ * x, pw, inv_pw, padoff, pwq, ks, kt (152 each), cosb, sinb (18 each),
+ * kb, vdq, inv_vd32, snp_max.  Returns the number of floats written. */
+int oracle_tables(float bz, float *dst, int cap)
+{
+    otab t;
+    o_tables(bz, &t);
+    const int n = 7 * O_NROW + 2 * 18 + 4;
+    if (cap < n) return -n;
+    int o = 0;
+    const float *rows[7] = {t.x, t.pw, t.inv_pw, t.padoff, t.pwq, t.ks, t.kt};
+    for (int a = 0; a < 7; a++)
+        for (int r = 0; r < O_NROW; r++) dst[o++] = rows[a][r];
+    for (int d = 0; d < 18; d++) dst[o++] = t.cosb[d];
+    for (int d = 0; d < 18; d++) dst[o++] = t.sinb[d];
+    dst[o++] = t.kb;
+    dst[o++] = t.vdq;
+    dst[o++] = t.inv_vd32;
+    dst[o++] = t.snp_max;
+    return o;
+}
+
+int oracle_npads(int *dst)
+{
+    otab t;
+    o_tables(0.0f, &t);
+    for (int r = 0; r < O_NROW; r++) dst[r] = t.npads[r];
+    return O_NROW;
+}
+
+/* a*b+c evaluated as written (two roundings); the canary test checks that the
+ * build did not fuse it. */
+float oracle_fp_canary(float a, float b, float c) { return a * b + c; }
