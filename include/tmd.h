@@ -1,0 +1,202 @@
+/*
+ * tmd.h -- C ABI of libtmd, TPC track-model decoding on AMD MI355X (gfx950).
+ *
+ * The library decodes compressed TPC time frames (arXiv:2411.02206, section 4,
+ * "TPC track-model decoding on GPU"): attached clusters were stored as
+ * residuals to their track, so decoding propagates every track through the
+ * pad rows and adds the residuals (the paper's first GPU kernel, one thread
+ * per track); unattached clusters were sorted by position and stored as
+ * differences to the previous cluster, so decoding sums the differences within
+ * each TPC region (the paper's second kernel, one region per thread).  The
+ * track model (float32 helix propagate-and-update in the local sector frame,
+ * rotation at sector crossings) is this project's own, because the paper does
+ * not define one; its equations are documented with the implementation.
+ *
+ * Memory: every pointer in tmd_frame_in / tmd_frame_out and the workspace is
+ * a DEVICE pointer owned by the caller.  The plan owns only its constant
+ * tables, frame descriptors and status words.  No call blocks on the GPU
+ * except tmd_status, tmd_stage_times and tmd_free.
+ *
+ * Errors: every entry point returns TMD_OK (0) or a negative TMD_E_* code;
+ * tmd_strerror() gives a message.  Argument errors are detected on the host
+ * before anything is enqueued.  Data-dependent problems (inconsistent counts,
+ * streams the model cannot follow) never make the decoder read or write out
+ * of bounds: values are clamped or cut as documented, every output byte is
+ * still defined, and the problem is reported as flag bits by tmd_status.
+ */
+#ifndef TMD_H
+#define TMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TMD_NSEC 36                       /* 2 sides x 18 sectors */
+#define TMD_NROW 152                      /* pad rows per sector */
+#define TMD_NBIN (TMD_NSEC * TMD_NROW)    /* (sector,row) bins, bin = sector*152 + row */
+#define TMD_MAX_TRACKS (1u << 24)         /* per frame */
+
+/* return codes */
+#define TMD_OK 0
+#define TMD_E_ARG (-1)      /* null or misaligned pointer, bad size or shape */
+#define TMD_E_CAPACITY (-2) /* output capacity < n_attached + n_unattached */
+#define TMD_E_INPUT (-3)    /* (tmd_status) counts in the stream disagree with the shape */
+#define TMD_E_STREAM (-4)   /* (tmd_status) the track model had to clamp values */
+#define TMD_E_HIP (-5)      /* HIP runtime error (no device, out of memory, launch failure) */
+
+/* status flag bits reported by tmd_status */
+#define TMD_F_HDR 1u    /* track header out of range: n_clusters 0, sector >= 36 (wrapped), row >= 152 (clamped) */
+#define TMD_F_SEC 2u    /* sector step >= 18 (wrapped modulo 18) */
+#define TMD_F_ROW 4u    /* row left [0, 151] (clamped) */
+#define TMD_F_ROT 8u    /* direction pointed backwards after a sector rotation */
+#define TMD_F_SNP 16u   /* sin(phi) beyond +-0.999 or NaN (clamped, NaN -> 0) */
+#define TMD_F_PAD 32u   /* decoded pad outside [0, 65535] (clamped) */
+#define TMD_F_TIME 64u  /* decoded or header time outside [0, 2^24 - 1] (clamped) */
+#define TMD_F_COUNT 128u /* sum of track lengths != n_attached, or sum of un_count != n_unattached:
+                            streams are cut at the declared sizes */
+
+/* plan flags */
+#define TMD_PLAN_GRAPH 1u   /* capture the launch sequence in a HIP graph and replay it */
+
+typedef struct tmd_plan tmd_plan_t;
+
+/* Sizes of one compressed frame. */
+typedef struct {
+    uint32_t n_tracks;     /* <= TMD_MAX_TRACKS */
+    uint32_t n_attached;   /* clusters attached to tracks (sum of trk_ncls) */
+    uint32_t n_unattached; /* unattached clusters (sum of un_count) */
+} tmd_frame_shape;
+
+/*
+ * One compressed frame, structure of arrays (device pointers, read only).
+ * Track header arrays have n_tracks entries:
+ *   trk_ncls   number of clusters of the track (1..255)
+ *   trk_sec0, trk_row0   sector (0..35) and pad row (0..151) of cluster 0
+ *   trk_pad0   pad of cluster 0 in 1/32 pad (pad 0 is the -y edge of the row)
+ *   trk_time0  time of cluster 0 in 1/32 time bin (< 2^24)
+ *   trk_qpt, trk_snp, trk_tgl   q/pT * 2^10 (c/GeV), sin(phi) * 2^15, tan(lambda) * 2^12
+ * Attached cluster arrays have n_attached entries, track after track, the
+ * clusters of a track in order; entry 0 of a track only supplies qtot/qmax:
+ *   cls_row_diff  row step from the previous cluster
+ *   cls_sec_diff  sector step (0..17, modulo 18, same side) from the previous cluster
+ *   cls_pad_res, cls_time_res   residual to the track prediction, 1/32 pad and 1/32 time bin
+ *   cls_qtot, cls_qmax          charges, copied to the output
+ * Unattached clusters: un_count[TMD_NBIN] per (sector,row) bin, then
+ * n_unattached entries bin after bin; within a bin each value is the
+ * difference to the previous cluster of the bin (the first to zero), time
+ * modulo 2^32 and pad modulo 2^16:
+ *   un_time_diff, un_pad_diff, un_qtot, un_qmax
+ * Alignment: every pointer aligned to its element size.
+ */
+typedef struct {
+    const uint8_t *trk_ncls, *trk_sec0, *trk_row0;
+    const uint16_t *trk_pad0;
+    const uint32_t *trk_time0;
+    const int16_t *trk_qpt, *trk_snp, *trk_tgl;
+    const int8_t *cls_row_diff;
+    const uint8_t *cls_sec_diff;
+    const int16_t *cls_pad_res, *cls_time_res;
+    const uint16_t *cls_qtot, *cls_qmax;
+    const uint32_t *un_count;
+    const uint32_t *un_time_diff;
+    const uint16_t *un_pad_diff, *un_qtot, *un_qmax;
+} tmd_frame_in;
+
+/*
+ * Decoded clusters (device pointers, written).  Clusters are grouped by
+ * (sector,row) bin: bin b occupies [row_offset[b], row_offset[b+1]); inside a
+ * bin come first its row_nattached[b] attached clusters, in stream order
+ * (track, then cluster), then its unattached clusters in stream order.
+ * row_offset has TMD_NBIN + 1 entries, row_nattached TMD_NBIN.
+ *   time  in 1/32 time bin, pad in 1/32 pad, qtot/qmax copied.
+ * capacity: number of entries of time/pad/qtot/qmax, >= n_attached + n_unattached.
+ */
+typedef struct {
+    uint32_t *row_offset, *row_nattached;
+    uint32_t *time;
+    uint16_t *pad, *qtot, *qmax;
+    uint64_t capacity;
+} tmd_frame_out;
+
+typedef struct {
+    float bz_tesla; /* solenoid field; the curvature of a track is q/pT * bz * 0.00299792458 per cm */
+    uint32_t flags; /* TMD_PLAN_* */
+} tmd_params;
+
+/*
+ * Prepare decoding of n_frames frames of the given shapes in one call of
+ * tmd_decode (n_frames = 1: a plain single-frame decode; more: the batched
+ * form, one launch sequence over all frames).  Builds the float32 constant
+ * tables for p->bz_tesla on the host and uploads them to the current device.
+ * *workspace_bytes receives the size of the device workspace tmd_decode needs
+ * (256-byte aligned, caller-allocated, contents need not be initialised).
+ * Errors: TMD_E_ARG (null pointer, n_frames == 0, n_tracks > TMD_MAX_TRACKS),
+ * TMD_E_HIP.
+ */
+int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params *p,
+             tmd_plan_t **plan, size_t *workspace_bytes);
+
+/*
+ * Enqueue the decode of n_frames frames (in[i], out[i] for frame i, shaped as
+ * planned) on `stream` (a hipStream_t; NULL = the default stream) and return.
+ * The kernels: track start offsets (scan of trk_ncls), per-cluster (sector,row)
+ * keys with per-tile counts, per-bin offsets, stable ranks, attached decode,
+ * unattached decode, status reduction.  Calls on one plan must not overlap in
+ * time (the status words are per plan).
+ * Errors: TMD_E_ARG (null plan/in/out/workspace, misaligned pointer),
+ * TMD_E_CAPACITY, TMD_E_HIP.
+ */
+int tmd_decode(tmd_plan_t *plan, const tmd_frame_in *in, tmd_frame_out *out, void *workspace,
+               void *stream);
+
+/*
+ * Flags of frame `frame` from the last tmd_decode on this plan; waits for that
+ * decode to finish.  Returns TMD_OK if no flag is set, TMD_E_INPUT if
+ * TMD_F_COUNT is set, TMD_E_STREAM if another flag is set, TMD_E_ARG for a bad
+ * frame index; *flags receives the bits.
+ */
+int tmd_status(tmd_plan_t *plan, uint32_t frame, uint32_t *flags);
+
+/* Release the plan and its device memory (waits for its work). NULL is a no-op. */
+void tmd_free(tmd_plan_t *plan);
+
+/* Static message for a return code. */
+const char *tmd_strerror(int code);
+
+/* Library version, e.g. "tmd 1.0 gfx950". */
+const char *tmd_version(void);
+
+/*
+ * The float32 constant tables the decoder uses for field bz (host only, no
+ * GPU needed): x, pw, inv_pw, padoff, pwq, ks, kt (152 each), cosb, sinb
+ * (18 each), kb, vdq, inv_vd32, snp_max.  Returns the count written, or
+ * -(count needed) if cap is too small.
+ */
+int tmd_tables(float bz, float *dst, int cap);
+
+/*
+ * Stage timing.  With profiling on, tmd_decode records HIP events around each
+ * stage on its stream.  tmd_stage_times waits for the recorded calls, writes
+ * the summed milliseconds of each stage to ms[0 .. n-1] (stage order as named
+ * by tmd_stage_name), the number of recorded calls to *calls, and clears the
+ * record.  Returns the number of stages.
+ */
+int tmd_set_profiling(tmd_plan_t *plan, int enable);
+int tmd_stage_times(tmd_plan_t *plan, double *ms, uint32_t n, uint32_t *calls);
+const char *tmd_stage_name(uint32_t stage);
+
+/*
+ * Arithmetic self-test on the device (device pointers, n floats each):
+ * out[4i+0] = sqrtf(a[i]), out[4i+1] = a[i] / b[i], out[4i+2] = rintf(a[i]),
+ * out[4i+3] = a[i] * b[i] + a[i] with two roundings.  The decoder relies on
+ * these being the IEEE-754 correctly rounded results, as on the host.
+ */
+int tmd_selftest_fp(const float *a, const float *b, float *out, uint32_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TMD_H */

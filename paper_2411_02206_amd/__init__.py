@@ -1,0 +1,206 @@
+"""TPC track-model decoding on AMD MI355X (arXiv:2411.02206, section 4).
+
+Python front end of libtmd.so.  PyTorch supplies device memory and streams;
+all decoding runs in the library's HIP kernels.
+
+    import paper_2411_02206_amd as tmd
+    dev = tmd.to_device(frame)              # numpy frame dict -> torch tensors on cuda
+    out, flags = tmd.decode(dev, bz=0.5)    # torch tensors on cuda + status flags
+
+Lower level: tmd.Plan(shapes, bz) / plan.decode(ins, outs, workspace, stream).
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (E_ARG, E_CAPACITY, E_HIP, E_INPUT, E_STREAM, F_COUNT, F_HDR, F_PAD, F_ROT,  # noqa: F401
+                   F_ROW, F_SEC, F_SNP, F_TIME, IN_FIELDS, NBIN, NROW, NSEC, OK, OUT_FIELDS, PLAN_GRAPH,
+                   TmdError)
+
+__all__ = ["Plan", "decode", "to_device", "alloc_out", "to_numpy", "version", "tables"]
+
+# element types of the frame arrays; unsigned 16/32-bit data travel in signed
+# torch tensors of the same width (only the bytes matter to the library)
+IN_DTYPES = {
+    "trk_ncls": np.uint8, "trk_sec0": np.uint8, "trk_row0": np.uint8, "trk_pad0": np.uint16,
+    "trk_time0": np.uint32, "trk_qpt": np.int16, "trk_snp": np.int16, "trk_tgl": np.int16,
+    "cls_row_diff": np.int8, "cls_sec_diff": np.uint8, "cls_pad_res": np.int16,
+    "cls_time_res": np.int16, "cls_qtot": np.uint16, "cls_qmax": np.uint16,
+    "un_count": np.uint32, "un_time_diff": np.uint32, "un_pad_diff": np.uint16,
+    "un_qtot": np.uint16, "un_qmax": np.uint16,
+}
+OUT_DTYPES = {"row_offset": np.uint32, "row_nattached": np.uint32, "time": np.uint32,
+              "pad": np.uint16, "qtot": np.uint16, "qmax": np.uint16}
+_SIGNED = {np.dtype(np.uint8): np.uint8, np.dtype(np.int8): np.int8, np.dtype(np.uint16): np.int16,
+           np.dtype(np.int16): np.int16, np.dtype(np.uint32): np.int32, np.dtype(np.int32): np.int32}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def version():
+    return _lib.lib().tmd_version().decode()
+
+
+def tables(bz=0.5):
+    """The library's float32 constant tables (host computation, no GPU)."""
+    buf = (C.c_float * 2048)()
+    n = _lib.lib().tmd_tables(C.c_float(bz), buf, 2048)
+    v = np.frombuffer(buf, np.float32, n).copy()
+    out, o = {}, 0
+    for name in ("x", "pw", "inv_pw", "padoff", "pwq", "ks", "kt"):
+        out[name] = v[o:o + NROW]
+        o += NROW
+    out["cosb"] = v[o:o + 18]; o += 18
+    out["sinb"] = v[o:o + 18]; o += 18
+    out["kb"], out["vdq"], out["inv_vd32"], out["snp_max"] = v[o:o + 4]
+    return out
+
+
+def frame_shape(frame):
+    """(n_tracks, n_attached, n_unattached) of a frame dict (numpy or torch)."""
+    return (int(frame["trk_ncls"].shape[0]), int(frame["cls_qtot"].shape[0]),
+            int(frame["un_qtot"].shape[0]))
+
+
+def to_device(frame, device="cuda"):
+    """Copy a numpy frame dict to torch tensors on `device`."""
+    torch = _torch()
+    out = {}
+    for k in IN_FIELDS:
+        a = np.ascontiguousarray(frame[k], dtype=IN_DTYPES[k])
+        out[k] = torch.from_numpy(a.view(_SIGNED[a.dtype])).to(device)
+    return out
+
+
+def alloc_out(shape, device="cuda", capacity=None):
+    torch = _torch()
+    n = shape[1] + shape[2] if capacity is None else capacity
+    tt = {np.uint32: torch.int32, np.uint16: torch.int16}
+    return {"row_offset": torch.empty(NBIN + 1, dtype=torch.int32, device=device),
+            "row_nattached": torch.empty(NBIN, dtype=torch.int32, device=device),
+            "time": torch.empty(max(n, 1), dtype=tt[np.uint32], device=device),
+            "pad": torch.empty(max(n, 1), dtype=tt[np.uint16], device=device),
+            "qtot": torch.empty(max(n, 1), dtype=tt[np.uint16], device=device),
+            "qmax": torch.empty(max(n, 1), dtype=tt[np.uint16], device=device),
+            "capacity": n}
+
+
+def to_numpy(out):
+    """Device outputs -> numpy arrays with their unsigned types, cut to the
+    decoded size."""
+    res = {k: out[k].cpu().numpy().view(OUT_DTYPES[k]) for k in OUT_FIELDS}
+    n = int(res["row_offset"][NBIN])
+    for k in ("time", "pad", "qtot", "qmax"):
+        res[k] = res[k][:n]
+    return res
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+
+
+class Plan:
+    """A decode plan for frames of fixed shapes (one frame: plain decode; many:
+    batched decode in one launch sequence)."""
+
+    def __init__(self, shapes, bz=0.5, flags=0):
+        L = _lib.lib()
+        shapes = [tuple(int(v) for v in s) for s in shapes]
+        arr = (_lib.FrameShape * len(shapes))(*[_lib.FrameShape(*s) for s in shapes])
+        self._params = _lib.Params(float(bz), int(flags))
+        h = C.c_void_p()
+        ws = C.c_size_t()
+        _lib.check(L.tmd_plan(arr, len(shapes), C.byref(self._params), C.byref(h), C.byref(ws)),
+                   "tmd_plan")
+        self._h = h
+        self.shapes = shapes
+        self.bz = bz
+        self.workspace_bytes = int(ws.value)
+        self._keep = None
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.lib().tmd_free(h)
+            self._h = None
+
+    def alloc_workspace(self, device="cuda"):
+        torch = _torch()
+        return torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=device)
+
+    def decode(self, ins, outs, workspace, stream=None):
+        """Enqueue the decode of len(shapes) frames.  ins/outs: lists of dicts of
+        device tensors (see to_device / alloc_out).  stream: torch stream or
+        None for the current one."""
+        torch = _torch()
+        n = len(self.shapes)
+        if len(ins) != n or len(outs) != n:
+            raise ValueError(f"plan has {n} frames")
+        fin = (_lib.FrameIn * n)()
+        fout = (_lib.FrameOut * n)()
+        for i in range(n):
+            for k in IN_FIELDS:
+                setattr(fin[i], k, _ptr(ins[i][k]))
+            for k in OUT_FIELDS:
+                setattr(fout[i], k, _ptr(outs[i][k]))
+            fout[i].capacity = int(outs[i]["capacity"])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        sp = C.c_void_p(stream.cuda_stream)
+        _lib.check(_lib.lib().tmd_decode(self._h, fin, fout, _ptr(workspace), sp), "tmd_decode")
+
+    def status(self, frame=0):
+        """Flag bits of `frame` from the last decode (waits for it)."""
+        f = C.c_uint32()
+        rc = _lib.lib().tmd_status(self._h, frame, C.byref(f))
+        if rc not in (OK, E_INPUT, E_STREAM):
+            _lib.check(rc, "tmd_status")
+        return int(f.value)
+
+    def set_profiling(self, on=True):
+        _lib.check(_lib.lib().tmd_set_profiling(self._h, 1 if on else 0), "tmd_set_profiling")
+
+    def stage_times(self):
+        """{stage: summed ms} over the profiled calls since the last read, and
+        the number of calls."""
+        L = _lib.lib()
+        buf = (C.c_double * 16)()
+        calls = C.c_uint32()
+        n = L.tmd_stage_times(self._h, buf, 16, C.byref(calls))
+        if n < 0:
+            _lib.check(n, "tmd_stage_times")
+        return {L.tmd_stage_name(i).decode(): buf[i] for i in range(n)}, int(calls.value)
+
+
+def decode(frame, bz=0.5, stream=None):
+    """Decode one frame held in device tensors (see to_device).  Returns
+    (outputs dict of device tensors, status flags)."""
+    shape = frame_shape(frame)
+    dev = frame["trk_ncls"].device
+    plan = Plan([shape], bz)
+    out = alloc_out(shape, dev)
+    ws = plan.alloc_workspace(dev)
+    plan.decode([frame], [out], ws, stream)
+    flags = plan.status(0)
+    plan.free()
+    return out, flags
+
+
+def selftest_fp(a, b, stream=None):
+    """Device arithmetic (sqrt, div, rint, a*b+a with two roundings) of two
+    float32 device tensors; returns a float32 tensor [n, 4]."""
+    torch = _torch()
+    n = a.numel()
+    out = torch.empty(4 * max(n, 1), dtype=torch.float32, device=a.device)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _lib.check(_lib.lib().tmd_selftest_fp(_ptr(a), _ptr(b), _ptr(out), n, C.c_void_p(stream.cuda_stream)),
+               "tmd_selftest_fp")
+    return out[:4 * n].view(n, 4)

@@ -4,4 +4,4 @@ This module draws compressed-frame streams with the shapes of Pb-Pb running;
 it holds none of the decoding arithmetic.  Both the GPU library's tests and
 benchmarks and the CPU oracle consume its frames.  See synth.frames.
 """
-from .frames import CONFIGS, FrameSpec, batch_specs, make_frame, spec_for_config  # noqa: F401
+from .frames import WORKLOADS, FrameSpec, batch_specs, make_frame, spec_for  # noqa: F401

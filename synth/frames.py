@@ -75,25 +75,30 @@ class FrameSpec:
         return self.n_tracks if self.n_tracks > 0 else self.collisions * self.tracks_per_collision
 
 
-# The five workloads.  Seeds follow the workload index.
-CONFIGS = {
-    0: FrameSpec(n_tracks=1000, collisions=1, ncls_min=20, ncls_max=152, crosser_frac=0.0,
-                 sectors=(0,), n_unattached=20000, seed=0),
-    1: FrameSpec(collisions=100, seed=1),
-    2: FrameSpec(collisions=100, seed=2),   # collisions drawn per frame, see batch_specs
-    3: FrameSpec(collisions=100, seed=3),
-    4: FrameSpec(collisions=500, looper_frac=0.15, row_skew=40.0, seed=4),
+# The workloads, each with its own seed:
+#   tiny     one sector, 1000 tracks of 20..152 clusters, 20000 unattached
+#   frame    one Pb-Pb-like time frame: 100 collisions x 2000 tracks
+#   batched  frames of 10..200 collisions (log-uniform), see batch_specs
+#   served   the same frame mix, drawn with another seed
+#   stress   500 collisions, 15% low-pT loopers, rows skewed exp(-row/40)
+WORKLOADS = {
+    "tiny": FrameSpec(n_tracks=1000, collisions=1, ncls_min=20, ncls_max=152, crosser_frac=0.0,
+                      sectors=(0,), n_unattached=20000, seed=0),
+    "frame": FrameSpec(collisions=100, seed=1),
+    "batched": FrameSpec(collisions=100, seed=2),
+    "served": FrameSpec(collisions=100, seed=3),
+    "stress": FrameSpec(collisions=500, looper_frac=0.15, row_skew=40.0, seed=4),
 }
 
 
-def spec_for_config(cfg: int, **over) -> FrameSpec:
-    return dataclasses.replace(CONFIGS[cfg], **over)
+def spec_for(name: str, **over) -> FrameSpec:
+    return dataclasses.replace(WORKLOADS[name], **over)
 
 
-def batch_specs(cfg: int = 2, n_frames: int = 64, seed: int = None, coll_range=(10, 200)):
+def batch_specs(name: str = "batched", n_frames: int = 64, seed: int = None, coll_range=(10, 200)):
     """Frames with collision counts log-uniform in coll_range (batched and
     served workloads)."""
-    base = CONFIGS[cfg]
+    base = WORKLOADS[name]
     seed = base.seed if seed is None else seed
     rng = np.random.default_rng([seed, 7919])
     lo, hi = math.log(coll_range[0]), math.log(coll_range[1])

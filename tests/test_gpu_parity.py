@@ -1,0 +1,188 @@
+"""GPU parity: libtmd (HIP, through the C ABI) against the CPU oracle.
+
+Every output array and the status flags must be bit-identical: the decoder's
+float32 arithmetic is fully specified (fixed operation order, no contraction,
+IEEE division and square root, round-half-even), so there is exactly one
+correct result per stream, including streams the model has to clamp."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import NBIN, build_frame, empty_frame
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tmd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2411_02206_amd as m
+    return m
+
+
+def gpu_decode(tmd, frame, bz=0.5):
+    dev = tmd.to_device(frame)
+    out, flags = tmd.decode(dev, bz=bz)
+    return tmd.to_numpy(out), flags
+
+
+def assert_same(tmd, frame, bz=0.5, label=""):
+    exp, est = oracle.decode(frame, bz=bz)
+    got, gst = gpu_decode(tmd, frame, bz)
+    for k in exp:
+        if not np.array_equal(exp[k], got[k]):
+            bad = np.nonzero(exp[k] != got[k])[0] if exp[k].shape == got[k].shape else None
+            raise AssertionError(f"{label}: {k} differs "
+                                 f"(shape {exp[k].shape} vs {got[k].shape}, first bad {bad[:8] if bad is not None else None})")
+    assert est == gst, f"{label}: status oracle {est:#x} gpu {gst:#x}"
+    return exp, est
+
+
+def test_fp_selftest(tmd):
+    """Device sqrt, division, rint and unfused a*b+a equal the IEEE results."""
+    import torch
+    rng = np.random.default_rng(0)
+    n = 1 << 20
+    a = np.concatenate([rng.uniform(-2, 2, n // 4), rng.uniform(0, 1e-3, n // 4),
+                        (rng.standard_normal(n // 4) * 1e3), np.exp(rng.uniform(-100, 80, n // 4))]).astype(np.float32)
+    a[:64] = np.array([0.0, -0.0, 1e-45, 1e-40, np.inf, -np.inf, 0.5, 1.5, 2.5, -0.5, -1.5, 3.4e38] * 5 +
+                      [np.nan, 1.0, -1.0, 7.0], np.float32)
+    b = rng.uniform(-3, 3, n).astype(np.float32)
+    b[::97] = np.float32(1e-38)
+    with np.errstate(all="ignore"):
+        exp = np.stack([np.sqrt(a), a / b, np.rint(a), (a * b) + a], axis=1).astype(np.float32)
+    got = tmd.selftest_fp(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()).cpu().numpy()
+    both_nan = np.isnan(exp) & np.isnan(got)
+    same = (exp.view(np.uint32) == got.view(np.uint32)) | both_nan
+    assert same.all(), np.argwhere(~same)[:10]
+
+
+def test_tiny_workload(tmd):
+    fr = synth.make_frame(synth.spec_for("tiny"))
+    assert_same(tmd, fr, label="tiny")
+
+
+@pytest.mark.parametrize("coll", [1, 3])
+def test_multi_tile_frames(tmd, coll):
+    """2000 and 6000 tracks: several 256-track tiles with a ragged tail."""
+    fr = synth.make_frame(synth.spec_for("frame", collisions=coll))
+    assert_same(tmd, fr, label=f"{coll} collisions")
+
+
+def test_loopers_and_skew(tmd):
+    fr = synth.make_frame(synth.spec_for("stress", collisions=3))
+    assert_same(tmd, fr, label="stress, 3 collisions")
+
+
+def test_empty_and_tiny(tmd):
+    assert_same(tmd, empty_frame(), label="empty")
+    assert_same(tmd, build_frame([], {5: [(3, 4, 5, 6)], 5471: [(1, 2, 3, 4), (7, 8, 9, 10)]}),
+                label="only unattached")
+    one = dict(sec0=7, row0=20, pad0=1000, time0=5000, qpt=100, snp=200, tgl=300)
+    assert_same(tmd, build_frame([dict(one, cl=[(0, 0, 0, 0, 9, 8)])]), label="one cluster")
+    assert_same(tmd, build_frame([dict(one, cl=[(0, 0, 0, 0, 9, 8), (1, 0, 5, -5, 1, 2)])]), label="two")
+
+
+def test_long_tracks_and_full_bins(tmd):
+    """255-cluster tracks that stay in one bin (row step 0): the largest
+    per-bin counts a 256-track tile can produce."""
+    tr = []
+    for i in range(300):
+        cl = [(0, 0, 0, 0, i & 0xFFFF, 1)] + [(0, 0, (j % 7) - 3, (j % 5) - 2, j, i) for j in range(1, 255)]
+        tr.append(dict(sec0=3, row0=100, pad0=2000, time0=30000, qpt=50, snp=0, tgl=100, cl=cl))
+    assert_same(tmd, build_frame(tr), label="full bins")
+
+
+def _garbage(seed, nt=700, na=60000, nu=30000):
+    rng = np.random.default_rng(seed)
+    fr = {
+        "trk_ncls": rng.integers(0, 256, nt).astype(np.uint8),
+        "trk_sec0": rng.integers(0, 40, nt).astype(np.uint8),
+        "trk_row0": rng.integers(0, 160, nt).astype(np.uint8),
+        "trk_pad0": rng.integers(0, 65536, nt).astype(np.uint16),
+        "trk_time0": rng.integers(0, 2**25, nt).astype(np.uint32),
+        "trk_qpt": rng.integers(-32768, 32768, nt).astype(np.int16),
+        "trk_snp": rng.integers(-32768, 32768, nt).astype(np.int16),
+        "trk_tgl": rng.integers(-32768, 32768, nt).astype(np.int16),
+        "cls_row_diff": rng.integers(-3, 4, na).astype(np.int8),
+        "cls_sec_diff": np.where(rng.random(na) < 0.05, rng.integers(0, 256, na), 0).astype(np.uint8),
+        "cls_pad_res": rng.integers(-3000, 3000, na).astype(np.int16),
+        "cls_time_res": rng.integers(-3000, 3000, na).astype(np.int16),
+        "cls_qtot": rng.integers(0, 65536, na).astype(np.uint16),
+        "cls_qmax": rng.integers(0, 65536, na).astype(np.uint16),
+        "un_count": rng.integers(0, 12, NBIN).astype(np.uint32),
+        "un_time_diff": rng.integers(0, 2**32, nu, dtype=np.uint64).astype(np.uint32),
+        "un_pad_diff": rng.integers(0, 65536, nu).astype(np.uint16),
+        "un_qtot": rng.integers(0, 65536, nu).astype(np.uint16),
+        "un_qmax": rng.integers(0, 65536, nu).astype(np.uint16),
+    }
+    if seed % 2:
+        fr["cls_row_diff"] = rng.integers(-128, 128, na).astype(np.int8)
+    return fr
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_garbage_streams(tmd, seed):
+    """Random streams: clamps, wraps, NaN paths and count mismatches."""
+    for bz in (0.5, 40.0):
+        _, st = assert_same(tmd, _garbage(seed), bz=bz, label=f"garbage {seed}")
+        assert st != 0
+
+
+def test_physical_roundtrip_on_gpu(tmd):
+    """GPU decode of oracle-encoded exact-helix clusters restores the
+    quantised clusters."""
+    from oracle import physgen as pg
+    phys = pg.generate(seed=21, n_tracks=600, n_un=5000, bz=0.5)
+    fr, _ = oracle.encode(phys, bz=0.5)
+    got, st = gpu_decode(tmd, fr, 0.5)
+    exp = pg.expected_clusters(phys)
+    for k in exp:
+        assert np.array_equal(exp[k], got[k]), k
+    assert st == 0
+
+
+def test_frame_workload_full_size(tmd):
+    """The benchmark's workload (one full Pb-Pb-like frame), every cluster."""
+    fr = synth.make_frame(synth.spec_for("frame"))
+    exp, st = assert_same(tmd, fr, label="full frame")
+    assert exp["row_offset"][-1] > 2.4e7
+
+
+def test_batched_plan_equals_single(tmd):
+    """One plan over several frames of different sizes == each frame alone."""
+    import torch
+    specs = synth.batch_specs("batched", n_frames=4, coll_range=(1, 6))
+    frames = [synth.make_frame(s) for s in specs]
+    frames.insert(2, empty_frame())
+    shapes = [tmd.frame_shape(f) for f in frames]
+    plan = tmd.Plan(shapes, bz=0.5)
+    ins = [tmd.to_device(f) for f in frames]
+    outs = [tmd.alloc_out(s) for s in shapes]
+    ws = plan.alloc_workspace()
+    plan.decode(ins, outs, ws)
+    torch.cuda.synchronize()
+    for i, f in enumerate(frames):
+        exp, est = oracle.decode(f)
+        got = tmd.to_numpy(outs[i])
+        for k in exp:
+            assert np.array_equal(exp[k], got[k]), (i, k)
+        assert plan.status(i) == est
+
+
+def test_repeat_is_deterministic(tmd):
+    import torch
+    fr = synth.make_frame(synth.spec_for("frame", collisions=2))
+    shape = tmd.frame_shape(fr)
+    plan = tmd.Plan([shape])
+    dev = tmd.to_device(fr)
+    outs = [tmd.alloc_out(shape) for _ in range(2)]
+    ws = plan.alloc_workspace()
+    for o in outs:
+        plan.decode([dev], [o], ws)
+    torch.cuda.synchronize()
+    a, b = tmd.to_numpy(outs[0]), tmd.to_numpy(outs[1])
+    for k in a:
+        assert np.array_equal(a[k], b[k])

@@ -40,7 +40,7 @@ def _bins_by_walk(fr):
 
 @pytest.fixture(scope="module")
 def frame():
-    fr = synth.make_frame(synth.spec_for_config(1, collisions=3))
+    fr = synth.make_frame(synth.spec_for("frame", collisions=3))
     n = len(fr["cls_qtot"])
     fr["cls_qtot"] = (np.arange(n) & 0xFFFF).astype(np.uint16)   # unique tags
     fr["cls_qmax"] = (np.arange(n) >> 16).astype(np.uint16)

@@ -6,16 +6,16 @@ from synth.frames import NBIN, sizes
 
 
 def test_deterministic():
-    sp = synth.spec_for_config(1, collisions=2)
+    sp = synth.spec_for("frame", collisions=2)
     a, b = synth.make_frame(sp), synth.make_frame(sp)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
-    c = synth.make_frame(synth.spec_for_config(1, collisions=2, frame_index=1))
+    c = synth.make_frame(synth.spec_for("frame", collisions=2, frame_index=1))
     assert not np.array_equal(a["cls_pad_res"][:1000], c["cls_pad_res"][:1000])
 
 
 def test_config0_shape():
-    fr = synth.make_frame(synth.spec_for_config(0))
+    fr = synth.make_frame(synth.spec_for("tiny"))
     nt, na, nu = sizes(fr)
     assert nt == 1000 and nu == 20000
     assert fr["trk_ncls"].min() >= 20 and fr["trk_ncls"].max() <= 152
@@ -25,7 +25,7 @@ def test_config0_shape():
 
 
 def test_config1_like_shape():
-    fr = synth.make_frame(synth.spec_for_config(1, collisions=4))
+    fr = synth.make_frame(synth.spec_for("frame", collisions=4))
     nt, na, nu = sizes(fr)
     assert nt == 8000
     n = fr["trk_ncls"].astype(np.int64)
@@ -39,7 +39,7 @@ def test_config1_like_shape():
 
 
 def test_config4_loopers_and_skew():
-    fr = synth.make_frame(synth.spec_for_config(4, collisions=2))
+    fr = synth.make_frame(synth.spec_for("stress", collisions=2))
     assert (fr["cls_row_diff"] < 0).sum() > 1000          # inward legs of loopers
     rows = np.arange(NBIN) % 152
     cnt = np.bincount(rows, weights=fr["un_count"], minlength=152)
