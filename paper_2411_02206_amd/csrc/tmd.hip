@@ -58,9 +58,19 @@ constexpr uint32_t kTimeLim = 1u << 24;
 // ---------------------------------------------------------------------------
 // constant tables (float32, each the nearest float to a double expression)
 // ---------------------------------------------------------------------------
+struct RowGeo {  // one pad row, read with two 16-byte LDS loads
+    float x;       // local x of the row (cm)
+    float inv_pw;  // 1 / pad width
+    float padoff;  // half the number of pads (pad 0 is the -y edge)
+    float pwq;     // pad quantum: pad width / 32
+    float ks, kt;  // update gains of sin(phi) and tan(lambda): 0.0625 / row pitch
+    float pw;      // pad width (cm)
+    float unused;
+};
+
 struct Geo {
-    float x[NROW], pw[NROW], inv_pw[NROW], padoff[NROW], pwq[NROW], ks[NROW], kt[NROW];
-    float cosb[18], sinb[18];
+    RowGeo row[NROW];
+    float cosb[18], sinb[18];  // rotation by d * 20 degrees
     float kb, vdq, inv_vd32, snp_max;
 };
 
@@ -72,17 +82,19 @@ void build_geo(float bz, Geo *g)
     static const double pitch[4] = {0.75, 1.00, 1.20, 1.50};
     static const double padw[4] = {0.416, 0.608, 0.608, 0.608};
     const double pi = 3.14159265358979323846;
+    memset(g, 0, sizeof(*g));
     for (int g4 = 0; g4 < 4; g4++) {
         for (int r = rs[g4]; r < rs[g4 + 1]; r++) {
             double xd = xs[g4] + ((double)(r - rs[g4]) + 0.5) * pitch[g4];
             int npads = 2 * (int)floor(xd * tan(pi / 18.0) / padw[g4]);
-            g->x[r] = (float)xd;
-            g->pw[r] = (float)padw[g4];
-            g->inv_pw[r] = (float)(1.0 / padw[g4]);
-            g->padoff[r] = (float)(npads / 2);
-            g->pwq[r] = g->pw[r] * 0.03125f;
-            g->ks[r] = (float)(0.0625 / pitch[g4]);
-            g->kt[r] = g->ks[r];
+            RowGeo &R = g->row[r];
+            R.x = (float)xd;
+            R.pw = (float)padw[g4];
+            R.inv_pw = (float)(1.0 / padw[g4]);
+            R.padoff = (float)(npads / 2);
+            R.pwq = R.pw * 0.03125f;
+            R.ks = (float)(0.0625 / pitch[g4]);
+            R.kt = R.ks;
         }
     }
     for (int d = 0; d < 18; d++) {
@@ -99,50 +111,91 @@ void build_geo(float bz, Geo *g)
 }
 
 // ---------------------------------------------------------------------------
-// per-frame descriptor (device copy in the plan)
+// per-frame descriptor.  On the device its pointers are in the global address
+// space, so that loads and stores through them are global (not flat) accesses.
 // ---------------------------------------------------------------------------
-struct FrameDesc {
-    // input
-    const uint8_t *ncls, *sec0, *row0;
-    const uint16_t *pad0;
-    const uint32_t *time0;
-    const int16_t *qpt, *snp, *tgl;
-    const int8_t *rdiff;
-    const uint8_t *sdiff;
-    const int16_t *pres, *tres;
-    const uint16_t *cqtot, *cqmax;
-    const uint32_t *ucount, *utdiff;
-    const uint16_t *updiff, *uqtot, *uqmax;
-    // output
-    uint32_t *roff, *rna, *otime;
-    uint16_t *opad, *oqtot, *oqmax;
-    // workspace
-    uint32_t *start;    // [nT + 1] first cluster of each track
-    uint32_t *tilesum;  // [ntile] clusters per tile
-    uint32_t *hist;     // [ntile][NBIN] per-tile bin counts, then exclusive prefixes
-    uint32_t *uin;      // [NBIN] first unattached input entry of each bin
-    uint32_t *ueff;     // [NBIN] unattached clusters decoded per bin
-    uint32_t *dest;     // [nA] output slot of each attached cluster
-    uint32_t *status;
-    uint64_t cap;  // entries of the output cluster arrays; every store is checked against it
-    uint32_t nT, nA, nU, ntile, tile0;
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLB __attribute__((address_space(1)))
+#else
+#define GLB
+#endif
+
+// scheduling key of a track: home sector (sector of cluster 0) * 3 + direction
+// class (0: rows strictly increasing, 1: strictly decreasing, 2: other)
+constexpr int kNKey = NSEC * 3;
+constexpr int kHRow = NBIN + kNKey;  // per-tile histogram row: bins, then keys
+
+// per-cluster record written by the rank kernel for the decode kernel (16 B):
+// x = output slot, y = pad residual (low 16, signed) | time residual (high 16),
+// z = qTot (low 16) | qMax (high 16), w = row (bits 0-7) | sector (bits 8-15)
+
+// one field list, two views: FrameDesc (device, global pointers) and
+// FrameDescHost (host, plain pointers) have the same layout
+#define TMD_FRAME_FIELDS(Q)                                                                   \
+    /* input */                                                                               \
+    const Q uint8_t *ncls, *sec0, *row0;                                                      \
+    const Q uint16_t *pad0;                                                                   \
+    const Q uint32_t *time0;                                                                  \
+    const Q int16_t *qpt, *snp, *tgl;                                                         \
+    const Q int8_t *rdiff;                                                                    \
+    const Q uint8_t *sdiff;                                                                   \
+    const Q int16_t *pres, *tres;                                                             \
+    const Q uint16_t *cqtot, *cqmax;                                                          \
+    const Q uint32_t *ucount, *utdiff;                                                        \
+    const Q uint16_t *updiff, *uqtot, *uqmax;                                                 \
+    /* output */                                                                              \
+    Q uint32_t *roff, *rna, *otime;                                                           \
+    Q uint16_t *opad, *oqtot, *oqmax;                                                         \
+    /* workspace */                                                                           \
+    Q uint32_t *start;   /* [nT + 1] first cluster of each track */                           \
+    Q uint32_t *tilesum; /* [ntile] clusters per tile */                                      \
+    Q uint32_t *hist;    /* [ntile][NBIN] per-tile bin counts, then exclusive prefixes */     \
+    Q uint32_t *uin;     /* [NBIN] first unattached input entry of each bin */                \
+    Q uint32_t *ueff;    /* [NBIN] unattached clusters decoded per bin */                     \
+    Q uint4 *recs;       /* [nA] per-cluster records for the decode, stream order */          \
+    Q uint32_t *keyinfo; /* [kNKey] tracks per scheduling key, [kNKey] key starts */          \
+    Q uint8_t *tkey;     /* [nT] scheduling key of each track */                              \
+    Q uint32_t *order;   /* [nT] tracks sorted by (key, index): the decode's schedule */      \
+    Q uint32_t *status;                                                                       \
+    uint64_t cap; /* entries of the output cluster arrays; every store is checked */          \
+    uint32_t nT, nA, nU, ntile, tile0;                                                        \
     uint32_t pad_[3];
+
+struct FrameDesc {
+    TMD_FRAME_FIELDS(GLB)
 };
+struct FrameDescHost {
+    TMD_FRAME_FIELDS()
+};
+static_assert(sizeof(FrameDesc) == sizeof(FrameDescHost), "descriptor layouts differ");
 
 // ---------------------------------------------------------------------------
 // wave helpers (wave64)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t dpp(uint32_t v)
+{
+    // lanes without a source keep 0
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xf, false);
+}
+
+// inclusive prefix sum over the 64 lanes (DPP row shifts, then row broadcasts)
 __device__ __forceinline__ uint32_t wave_incl_add(uint32_t v)
 {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t t = __shfl_up(v, (unsigned)d);
-        if (lane >= (uint32_t)d) v += t;
-    }
+    v += dpp<0x111, 0xf>(v);  // row_shr:1
+    v += dpp<0x112, 0xf>(v);  // row_shr:2
+    v += dpp<0x114, 0xf>(v);  // row_shr:4
+    v += dpp<0x118, 0xf>(v);  // row_shr:8
+    v += dpp<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
     return v;
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
 }
 
 __device__ __forceinline__ uint32_t wave_or(uint32_t v)
@@ -150,11 +203,6 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v)
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) v |= __shfl_xor(v, d);
     return v;
-}
-
-__device__ __forceinline__ uint32_t readlane(uint32_t v, int l)
-{
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
 }
 
 // exclusive scan over a block of kTile threads; returns the block total in *tot
@@ -215,8 +263,11 @@ __device__ __forceinline__ void step_pos(int &sec, int &row, int rd, uint32_t sd
 // (sector,row) key of clusters cb + lane of one track, computed by the whole
 // wave; (sec, row) is the position before cluster cb and is advanced to the
 // position of the last cluster of the chunk.  Lanes >= cnt return 0.
+// monotone: the chunk's rows are strictly monotone, so its keys are distinct.
+// fl collects F_SEC (sector step >= 18) and F_ROW (row clamped).
 __device__ __forceinline__ uint32_t chunk_keys(const FrameDesc &F, uint32_t c0, uint32_t cb,
-                                               uint32_t cnt, int &sec, int &row, bool &monotone)
+                                               uint32_t cnt, int &sec, int &row, bool &monotone,
+                                               uint32_t &fl, uint32_t *dir = nullptr)
 {
     const uint32_t lane = lane_id();
     const uint32_t j = cb + lane;
@@ -226,122 +277,157 @@ __device__ __forceinline__ uint32_t chunk_keys(const FrameDesc &F, uint32_t c0, 
     if (act && j > 0) {
         rd = F.rdiff[c0 + j];
         sd = F.sdiff[c0 + j];
-        if (sd >= 18) sd %= 18;
+        if (sd >= 18) {
+            fl |= TMD_F_SEC;
+            sd %= 18;
+        }
     }
     // fast path: prefix sums without clamping
-    int prow = row + (int)wave_incl_add((uint32_t)rd);
-    uint32_t psec = (uint32_t)(sec % 18) + wave_incl_add(sd);
-    bool inrange = !act || (prow >= 0 && prow < NROW);
-    int side = sec / 18;
+    const int prow = row + (int)wave_incl_add((uint32_t)rd);
+    const uint32_t psec = (uint32_t)(sec % 18) + wave_incl_add(sd);
+    const bool inrange = !act || (prow >= 0 && prow < NROW);
+    const bool clamps = __ballot(!inrange) != 0;
+    const int side = sec / 18;
     uint32_t key;
-    if (__ballot(!inrange) == 0) {
-        int s = side * 18 + (int)(psec % 18);
+    if (!clamps) {
+        const int s = side * 18 + (int)(psec % 18);
         key = act ? (uint32_t)(s * NROW + prow) : 0u;
     } else {
         // a row leaves [0, 151] somewhere: walk the chunk in order
+        fl |= TMD_F_ROW;
         int s = sec, r = row;
         key = 0;
         for (uint32_t i = 0; i < cnt; i++) {
-            int rdi = __shfl(rd, (int)i);
-            uint32_t sdi = (uint32_t)__shfl((int)sd, (int)i);
+            const int rdi = __shfl(rd, (int)i);
+            const uint32_t sdi = (uint32_t)__shfl((int)sd, (int)i);
             if (cb + i > 0) step_pos(s, r, rdi, sdi);
             if (i == lane) key = (uint32_t)(s * NROW + r);
         }
     }
-    // rows strictly monotone inside the chunk (and no clamping) => distinct keys
-    uint64_t live = __ballot(act && lane > 0);
-    uint64_t up = __ballot(act && lane > 0 && rd > 0);
-    uint64_t dn = __ballot(act && lane > 0 && rd < 0);
-    monotone = ((up == live) || (dn == live)) && __ballot(!inrange) == 0;
-    uint32_t last = readlane(key, (int)(cnt - 1));
+    const uint64_t live = __ballot(act && lane > 0);
+    const uint64_t up = __ballot(act && lane > 0 && rd > 0);
+    const uint64_t dn = __ballot(act && lane > 0 && rd < 0);
+    monotone = ((up == live) || (dn == live)) && !clamps;
+    if (dir) {
+        // direction of every step of the chunk (bit 0: all up, bit 1: all down)
+        const uint64_t steps = __ballot(act && j > 0);
+        const uint64_t sup = __ballot(act && j > 0 && rd > 0);
+        const uint64_t sdn = __ballot(act && j > 0 && rd < 0);
+        *dir &= clamps ? 0u : ((sup == steps ? 1u : 0u) | (sdn == steps ? 2u : 0u));
+    }
+    const uint32_t last = readlane(key, (int)(cnt - 1));
     sec = (int)(last / NROW);
     row = (int)(last % NROW);
     return key;
 }
 
 // ---------------------------------------------------------------------------
-// K1: clusters per tile; also clears the frame's status word
+// K0: clear the per-frame status word
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWave) void k_setup(const FrameDesc *__restrict__ fd)
+{
+    const FrameDesc F = fd[blockIdx.x];
+    if (threadIdx.x == 0) *F.status = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// K1: clusters per tile
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTile) void k_tilesum(const FrameDesc *__restrict__ fd,
                                                    const uint32_t *__restrict__ tile_frame)
 {
     const uint32_t tile = blockIdx.x;
-    const FrameDesc &F = fd[tile_frame[tile]];
+    const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
     const uint32_t t = lt * kTile + threadIdx.x;
-    uint32_t v = t < F.nT ? F.ncls[t] : 0u;
+    const uint32_t v = t < F.nT ? F.ncls[t] : 0u;
     uint32_t tot;
     block_excl_add(v, &tot);
-    if (threadIdx.x == 0) {
-        F.tilesum[lt] = tot;
-        if (lt == 0) *F.status = 0u;
-    }
+    if (threadIdx.x == 0) F.tilesum[lt] = tot;
 }
 
 // ---------------------------------------------------------------------------
-// K2: track starts and per-tile histogram of cluster bins
+// K2: track starts, per-tile histogram of cluster bins and of scheduling keys.
+// Each wave walks 64 consecutive tracks one at a time, 64 clusters per step
+// (coalesced loads of the row and sector steps).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ fd,
                                                  const uint32_t *__restrict__ tile_frame)
 {
-    __shared__ uint32_t hist[NBIN];
+    __shared__ uint32_t hist[kHRow];
+    __shared__ uint32_t sstart[kTile];
     const uint32_t tile = blockIdx.x;
-    const FrameDesc &F = fd[tile_frame[tile]];
+    const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
     const uint32_t t = lt * kTile + threadIdx.x;
+    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
 
     // clusters of all earlier tiles of the frame
     uint32_t pre = 0;
     for (uint32_t i = threadIdx.x; i < lt; i += kTile) pre += F.tilesum[i];
-    uint32_t dummy;
-    uint32_t pre_excl = block_excl_add(pre, &dummy);
-    (void)pre_excl;
-    const uint32_t before = dummy;
+    uint32_t before;
+    block_excl_add(pre, &before);
 
-    for (uint32_t i = threadIdx.x; i < NBIN; i += kTile) hist[i] = 0;
+    for (uint32_t i = threadIdx.x; i < kHRow; i += kTile) hist[i] = 0;
     const uint32_t nc = t < F.nT ? F.ncls[t] : 0u;
     uint32_t tot;
     const uint32_t start = before + block_excl_add(nc, &tot);  // also syncs
+    sstart[threadIdx.x] = start;
     if (t < F.nT) {
         F.start[t] = start;
         if (t == F.nT - 1) {
             F.start[F.nT] = start + nc;
             if (start + nc != F.nA) atomicOr(F.status, TMD_F_COUNT);
         }
-        const uint32_t n = track_len(start, nc, F.nA);
-        if (n > 0) {
-            HeaderPos h = header_pos(F.sec0[t], F.row0[t]);
-            int sec = h.sec, row = h.row;
-            atomicAdd(&hist[sec * NROW + row], 1u);
-            for (uint32_t j = 1; j < n; j++) {
-                step_pos(sec, row, F.rdiff[start + j], F.sdiff[start + j]);
-                atomicAdd(&hist[sec * NROW + row], 1u);
-            }
+    }
+    __syncthreads();
+    uint32_t fl_unused = 0;
+    for (uint32_t tt = 0; tt < kWave; tt++) {
+        const uint32_t tl = w * kWave + tt;
+        const uint32_t tr = lt * kTile + tl;
+        if (tr >= F.nT) break;
+        const uint32_t c0 = sstart[tl];
+        const uint32_t n = track_len(c0, F.ncls[tr], F.nA);
+        HeaderPos h = header_pos(F.sec0[tr], F.row0[tr]);
+        int sec = h.sec, row = h.row;
+        uint32_t dir = 3u;
+        for (uint32_t cb = 0; cb < n; cb += kWave) {
+            const uint32_t cnt = min(n - cb, (uint32_t)kWave);
+            bool mono;
+            const uint32_t key = chunk_keys(F, c0, cb, cnt, sec, row, mono, fl_unused, &dir);
+            if (lane < cnt) atomicAdd(&hist[key], 1u);
+        }
+        const uint32_t cls = n <= 1 ? 0u : ((dir & 1u) ? 0u : ((dir & 2u) ? 1u : 2u));
+        if (lane == 0) {
+            const uint32_t key = (uint32_t)h.sec * 3u + cls;
+            F.tkey[tr] = (uint8_t)key;
+            atomicAdd(&hist[NBIN + key], 1u);
         }
     }
     __syncthreads();
-    uint32_t *dst = F.hist + (size_t)lt * NBIN;
-    for (uint32_t i = threadIdx.x; i < NBIN; i += kTile) dst[i] = hist[i];
+    GLB uint32_t *dst = F.hist + (size_t)lt * kHRow;
+    for (uint32_t i = threadIdx.x; i < kHRow; i += kTile) dst[i] = hist[i];
 }
 
 // ---------------------------------------------------------------------------
-// K3: per bin, exclusive prefix over the frame's tiles; totals -> row_nattached
-// grid (ceil(NBIN/64), n_frames), block 1024 = 16 waves; lane = bin
+// K3: per histogram column (bin or key), exclusive prefix over the frame's
+// tiles; bin totals -> row_nattached, key totals -> keyinfo
+// grid (ceil(kHRow/64), n_frames), block 1024 = 16 waves; lane = column
 // ---------------------------------------------------------------------------
 constexpr int kScanWaves = 16;
 
 __global__ __launch_bounds__(kWave * kScanWaves) void k_colscan(const FrameDesc *__restrict__ fd)
 {
     __shared__ uint32_t part[kScanWaves][kWave];
-    const FrameDesc &F = fd[blockIdx.y];
+    const FrameDesc F = fd[blockIdx.y];
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     const uint32_t k = blockIdx.x * kWave + lane;
     const uint32_t per = (F.ntile + kScanWaves - 1) / kScanWaves;
     const uint32_t a = w * per;
     const uint32_t b = min(a + per, F.ntile);
     uint32_t sum = 0;
-    if (k < NBIN)
-        for (uint32_t i = a; i < b; i++) sum += F.hist[(size_t)i * NBIN + k];
+    if (k < kHRow)
+        for (uint32_t i = a; i < b; i++) sum += F.hist[(size_t)i * kHRow + k];
     part[w][lane] = sum;
     __syncthreads();
     uint32_t run = 0, total = 0;
@@ -350,19 +436,22 @@ __global__ __launch_bounds__(kWave * kScanWaves) void k_colscan(const FrameDesc 
         if (i < w) run += p;
         total += p;
     }
-    if (k < NBIN) {
+    if (k < kHRow) {
         for (uint32_t i = a; i < b; i++) {
-            uint32_t *h = F.hist + (size_t)i * NBIN + k;
+            GLB uint32_t *h = F.hist + (size_t)i * kHRow + k;
             uint32_t v = *h;
             *h = run;
             run += v;
         }
-        if (w == 0) F.rna[k] = total;
+        if (w == 0) {
+            if (k < NBIN) F.rna[k] = total;
+            else F.keyinfo[k - NBIN] = total;
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// K4: per frame, output offsets and unattached input offsets
+// K4: per frame, output offsets, unattached input offsets, key starts
 // grid n_frames, block 1024; thread i owns bins [6i, 6i + 6)
 // ---------------------------------------------------------------------------
 constexpr int kOffThreads = 1024;
@@ -372,7 +461,7 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(const FrameDesc *__rest
 {
     __shared__ unsigned long long part64[kOffThreads / kWave];
     __shared__ uint32_t part32[kOffThreads / kWave];
-    const FrameDesc &F = fd[blockIdx.x];
+    const FrameDesc F = fd[blockIdx.x];
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     const uint32_t b0 = threadIdx.x * kOffPer;
 
@@ -384,7 +473,6 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(const FrameDesc *__rest
         cnt[i] = b < NBIN ? F.ucount[b] : 0u;
         own += cnt[i];
     }
-    // 64-bit wave scan as two 32-bit halves with carry
     unsigned long long inc = own;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
@@ -432,14 +520,26 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(const FrameDesc *__rest
         o += eff[i];
     }
     if (threadIdx.x == kOffThreads - 1) F.roff[NBIN] = o;
+
+    // start of each scheduling key in the decode order
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int key = 0; key < kNKey; key++) {
+            uint32_t c = F.keyinfo[key];
+            F.keyinfo[kNKey + key] = run;
+            run += c;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
-// K5: unattached clusters; one wave per (bin, frame)
+// K5: unattached clusters; one wave per (bin, frame), 256 clusters per pass
 // ---------------------------------------------------------------------------
+constexpr int kUnroll = 4;
+
 __global__ __launch_bounds__(kWave) void k_unattached(const FrameDesc *__restrict__ fd)
 {
-    const FrameDesc &F = fd[blockIdx.y];
+    const FrameDesc F = fd[blockIdx.y];
     const uint32_t k = blockIdx.x;
     const uint32_t cnt = F.ueff[k];
     if (cnt == 0) return;
@@ -447,46 +547,77 @@ __global__ __launch_bounds__(kWave) void k_unattached(const FrameDesc *__restric
     const uint32_t dst = F.roff[k] + F.rna[k];
     const uint32_t lane = lane_id();
     uint32_t ct = 0, cp = 0;
-    for (uint32_t i = 0; i < cnt; i += kWave) {
-        const uint32_t idx = i + lane;
-        const bool act = idx < cnt;
-        uint32_t td = act ? F.utdiff[src + idx] : 0u;
-        uint32_t pd = act ? (uint32_t)F.updiff[src + idx] : 0u;
-        uint32_t st = ct + wave_incl_add(td);
-        uint32_t sp = cp + wave_incl_add(pd);
-        if (act && dst + idx < F.cap) {
-            F.otime[dst + idx] = st;
-            F.opad[dst + idx] = (uint16_t)sp;
-            F.oqtot[dst + idx] = F.uqtot[src + idx];
-            F.oqmax[dst + idx] = F.uqmax[src + idx];
+    for (uint32_t i = 0; i < cnt; i += kWave * kUnroll) {
+        uint32_t td[kUnroll], pd[kUnroll];
+        uint16_t qt[kUnroll], qm[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const uint32_t idx = i + u * kWave + lane;
+            const bool act = idx < cnt;
+            td[u] = act ? F.utdiff[src + idx] : 0u;
+            pd[u] = act ? (uint32_t)F.updiff[src + idx] : 0u;
+            qt[u] = act ? F.uqtot[src + idx] : (uint16_t)0;
+            qm[u] = act ? F.uqmax[src + idx] : (uint16_t)0;
         }
-        ct = readlane(st, kWave - 1);
-        cp = readlane(sp, kWave - 1);
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const uint32_t idx = i + u * kWave + lane;
+            const uint32_t st = ct + wave_incl_add(td[u]);
+            const uint32_t sp = cp + wave_incl_add(pd[u]);
+            if (idx < cnt && dst + idx < F.cap) {
+                F.otime[dst + idx] = st;
+                F.opad[dst + idx] = (uint16_t)sp;
+                F.oqtot[dst + idx] = qt[u];
+                F.oqmax[dst + idx] = qm[u];
+            }
+            ct = readlane(st, kWave - 1);
+            cp = readlane(sp, kWave - 1);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// K6: stable output slot of every attached cluster.  Within a bin the order is
-// the stream order (track, then cluster).  Block = one tile of 256 tracks;
-// each wave takes 64 consecutive tracks one at a time, 64 clusters per step.
-// LDS: per-wave counters (16 bit: a wave's 64 tracks put at most 64*255
-// clusters in one bin, and three waves' prefix stays below 2^16) and the bin
-// bases of the tile.
+// K6: output slot of every attached cluster, written with the cluster's
+// residuals, charges and (sector,row) as one 16-byte record in stream order;
+// also places the tile's tracks in the decode schedule.  Within a bin the slot
+// order is the stream order (track, then cluster).  Block = one tile of 256
+// tracks; each wave takes 64 consecutive tracks one at a time, 64 clusters per
+// step.  LDS: per-wave counters (16 bit: a wave's 64 tracks put at most
+// 64*255 clusters in one bin, and three waves' prefix stays below 2^16) and
+// the tile's bin bases.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd,
                                                 const uint32_t *__restrict__ tile_frame)
 {
     __shared__ uint32_t wcnt32[kTileWaves * NBIN / 2];  // 16-bit counters, packed
     __shared__ uint32_t base[NBIN];
+    __shared__ uint8_t keys[kTile];
     uint16_t *wcnt = reinterpret_cast<uint16_t *>(wcnt32);
     const uint32_t tile = blockIdx.x;
-    const FrameDesc &F = fd[tile_frame[tile]];
+    const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+    const GLB uint32_t *G = F.hist + (size_t)lt * kHRow;
 
     for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wcnt32[i] = 0;
+    {
+        const uint32_t t = lt * kTile + threadIdx.x;
+        keys[threadIdx.x] = t < F.nT ? F.tkey[t] : (uint8_t)0xFF;
+    }
     __syncthreads();
 
+    // decode schedule: tracks sorted by (key, index), stable
+    {
+        const uint32_t t = lt * kTile + threadIdx.x;
+        if (t < F.nT) {
+            const uint8_t key = keys[threadIdx.x];
+            uint32_t local = 0;
+            for (uint32_t i = 0; i < threadIdx.x; i++) local += keys[i] == key;
+            F.order[F.keyinfo[kNKey + key] + G[NBIN + key] + local] = t;
+        }
+    }
+
+    uint32_t fl = 0;
     const uint32_t t_first = lt * kTile + w * kWave;
     // pass 1: per-wave bin counts
     for (uint32_t tt = 0; tt < kWave; tt++) {
@@ -500,7 +631,7 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
         for (uint32_t cb = 0; cb < n; cb += kWave) {
             const uint32_t cnt = min(n - cb, (uint32_t)kWave);
             bool mono;
-            uint32_t key = chunk_keys(F, c0, cb, cnt, sec, row, mono);
+            uint32_t key = chunk_keys(F, c0, cb, cnt, sec, row, mono, fl);
             if (lane < cnt) {
                 uint32_t idx = w * NBIN + key;
                 atomicAdd(&wcnt32[idx >> 1], 1u << (16 * (idx & 1)));
@@ -509,7 +640,6 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
     }
     __syncthreads();
     // exclusive prefix over the waves; bin base of this tile
-    const uint32_t *G = F.hist + (size_t)lt * NBIN;
     for (uint32_t k = threadIdx.x; k < NBIN; k += kTile) {
         uint32_t run = 0;
         for (uint32_t i = 0; i < kTileWaves; i++) {
@@ -520,7 +650,7 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
         base[k] = F.roff[k] + G[k];
     }
     __syncthreads();
-    // pass 2: slots
+    // pass 2: slots -> records
     for (uint32_t tt = 0; tt < kWave; tt++) {
         const uint32_t t = t_first + tt;
         if (t >= F.nT) break;
@@ -531,9 +661,16 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
         int sec = h.sec, row = h.row;
         for (uint32_t cb = 0; cb < n; cb += kWave) {
             const uint32_t cnt = min(n - cb, (uint32_t)kWave);
-            bool mono;
-            uint32_t key = chunk_keys(F, c0, cb, cnt, sec, row, mono);
             const bool act = lane < cnt;
+            const uint32_t c = c0 + cb + lane;
+            uint32_t res = 0, q = 0;
+            if (act) {
+                res = (uint32_t)(uint16_t)F.pres[c] | ((uint32_t)(uint16_t)F.tres[c] << 16);
+                q = (uint32_t)F.cqtot[c] | ((uint32_t)F.cqmax[c] << 16);
+            }
+            bool mono;
+            uint32_t dummy = 0;
+            uint32_t key = chunk_keys(F, c0, cb, cnt, sec, row, mono, dummy);
             const uint64_t lt_mask = (1ull << lane) - 1ull;
             uint64_t same;
             if (mono) {
@@ -551,36 +688,55 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
             const uint32_t slot_idx = w * NBIN + key;
             uint32_t r = 0;
             if (act) r = wcnt[slot_idx];
-            // every lane reads before any lane writes
+            // every lane reads its counter before any lane updates one
             __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_s_waitcnt(0);
             if (act) {
-                F.dest[c0 + cb + lane] = base[key] + r + below;
+                const uint32_t o = base[key] + r + below;
+                const uint32_t kr = key % NROW, ks = key / NROW;
+                F.recs[c] = make_uint4(o, res, q, kr | (ks << 8));
                 const bool leader = (same >> lane) == 1ull;  // highest lane of its group
                 if (leader) wcnt[slot_idx] = (uint16_t)(r + below + 1);
             }
             __builtin_amdgcn_wave_barrier();
         }
     }
+    fl = wave_or(fl);
+    if (lane == 0 && fl) atomicOr(F.status, fl);
 }
 
 // ---------------------------------------------------------------------------
-// K7: attached decode, one lane per track
+// K7: attached decode, one lane per track.  Tracks come in schedule order
+// (home sector, direction class, index).  A wave whose tracks all move
+// outward (inward) advances row-synchronously: each step processes the lanes
+// whose next cluster lies on the lowest (highest) pending row, so the lanes
+// of a step write neighbouring slots of the same bin.  Other waves advance one
+// cluster per lane per step.  The order of steps never changes a result: each
+// track is decoded cluster after cluster either way.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float clamp_snp(float v, float smax, uint32_t &fl)
 {
-    if (v != v) { fl |= TMD_F_SNP; return 0.0f; }
-    if (v > smax) { fl |= TMD_F_SNP; return smax; }
-    if (v < -smax) { fl |= TMD_F_SNP; return -smax; }
-    return v;
+    const bool nan = v != v;
+    const bool hi = v > smax;
+    const bool lo = v < -smax;
+    fl |= (nan || hi || lo) ? TMD_F_SNP : 0u;
+    float r = hi ? smax : v;
+    r = lo ? -smax : r;
+    return nan ? 0.0f : r;
 }
 
 __device__ __forceinline__ int32_t sat_i32(float v)
 {
-    if (v != v) return 0;
-    if (v > 1073741824.0f) return 1073741824;
-    if (v < -1073741824.0f) return -1073741824;
-    return (int32_t)v;
+    float c = v != v ? 0.0f : v;
+    c = c > 1073741824.0f ? 1073741824.0f : c;
+    c = c < -1073741824.0f ? -1073741824.0f : c;
+    return (int32_t)c;
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) v = min(v, (uint32_t)__shfl_xor(v, d));
+    return v;
 }
 
 __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict__ fd,
@@ -595,88 +751,122 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
     }
     __syncthreads();
     const uint32_t tile = blockIdx.x;
-    const FrameDesc &F = fd[tile_frame[tile]];
-    const uint32_t t = (tile - F.tile0) * kTile + threadIdx.x;
+    const FrameDesc F = fd[tile_frame[tile]];
+    const uint32_t slot = (tile - F.tile0) * kTile + threadIdx.x;
     uint32_t fl = 0;
-    if (t < F.nT) {
+    uint32_t n = 0, c0 = 0, cls = 2;
+    int sec = 0, row = 0;
+    int32_t t0 = 0;
+    uint16_t pad0 = 0;
+    float x = 0.0f, y = 0.0f, z = 0.0f, s = 0.0f, tgl = 0.0f, k = 0.0f;
+    const float smax = geo.snp_max;
+    if (slot < F.nT) {
+        const uint32_t t = F.order[slot];
         const uint32_t ncls = F.ncls[t];
-        const uint32_t c0 = F.start[t];
-        const uint32_t n = track_len(c0, ncls, F.nA);
+        c0 = F.start[t];
+        n = track_len(c0, ncls, F.nA);
+        cls = F.tkey[t] % 3u;
         if (ncls == 0) fl |= TMD_F_HDR;
         HeaderPos h = header_pos(F.sec0[t], F.row0[t]);
         fl |= h.flags;
-        int sec = h.sec, row = h.row;
+        sec = h.sec;
+        row = h.row;
         uint32_t t0u = F.time0[t];
         if (t0u >= kTimeLim) { fl |= TMD_F_TIME; t0u = kTimeLim - 1; }
-        const int32_t t0 = (int32_t)t0u;
-        const uint16_t pad0 = F.pad0[t];
-        const float smax = geo.snp_max;
-        float x = geo.x[row];
-        float y = ((float)pad0 * 0x1p-5f - geo.padoff[row]) * geo.pw[row];
-        float z = 0.0f;
-        float s = clamp_snp((float)F.snp[t] * 0x1p-15f, smax, fl);
-        float tgl = (float)F.tgl[t] * 0x1p-12f;
-        const float k = ((float)F.qpt[t] * 0x1p-10f) * geo.kb;
-        if (n > 0 && F.dest[c0] < F.cap) {
-            uint32_t o = F.dest[c0];
-            F.otime[o] = (uint32_t)t0;
-            F.opad[o] = pad0;
-            F.oqtot[o] = F.cqtot[c0];
-            F.oqmax[o] = F.cqmax[c0];
+        t0 = (int32_t)t0u;
+        pad0 = F.pad0[t];
+        x = geo.row[row].x;
+        y = ((float)pad0 * 0x1p-5f - geo.row[row].padoff) * geo.row[row].pw;
+        s = clamp_snp((float)F.snp[t] * 0x1p-15f, smax, fl);
+        tgl = (float)F.tgl[t] * 0x1p-12f;
+        k = ((float)F.qpt[t] * 0x1p-10f) * geo.kb;
+    }
+    // wave mode: 0 rows ascending, 1 rows descending, 2 one cluster per step
+    const uint64_t any_live = __ballot(n > 0);
+    const uint64_t asc = __ballot(n > 0 && cls == 0);
+    const uint64_t dsc = __ballot(n > 0 && cls == 1);
+    const uint32_t mode = asc == any_live ? 0u : (dsc == any_live ? 1u : 2u);
+
+    uint4 cur = make_uint4(0, 0, 0, 0);
+    if (n > 0) cur = F.recs[c0];
+    uint32_t j = 0;
+    // every step decodes at least one cluster, so 64 * 255 steps always suffice
+    for (uint32_t step = 0; step < (uint32_t)kWave * 256u; step++) {
+        const bool live = j < n;
+        if (__ballot(live) == 0) break;
+        bool ready = live;
+        if (mode != 2) {
+            // rows 0..151; the descending mode works on 255 - row.  The minimum
+            // is taken with all lanes active (it reads other lanes).
+            const uint32_t rr = (cur.w & 0xFFu);
+            const uint32_t v = live ? (mode == 0 ? rr : 255u - rr) : 0xFFFFFFFFu;
+            const uint32_t m = wave_min(v);
+            ready = live && v == m;
         }
-        for (uint32_t j = 1; j < n; j++) {
-            const uint32_t c = c0 + j;
-            uint32_t d = F.sdiff[c];
-            if (d >= 18) { fl |= TMD_F_SEC; d %= 18; }
-            if (d != 0) {
-                const float ca = geo.cosb[d], sa = geo.sinb[d];
-                const float cs = sqrtf((1.0f - s) * (1.0f + s));
-                const float xn = (x * ca) + (y * sa);
-                const float yn = (y * ca) - (x * sa);
-                const float sn = (s * ca) - (cs * sa);
-                const float cn = (cs * ca) + (s * sa);
-                if (!(cn > 0.0f)) fl |= TMD_F_ROT;
-                x = xn;
-                y = yn;
-                s = clamp_snp(sn, smax, fl);
-                sec = (sec / 18) * 18 + (sec % 18 + (int)d) % 18;
+        if (ready) {
+            const uint4 rec = cur;
+            if (j + 1 < n) cur = F.recs[c0 + j + 1];
+            const uint32_t o = rec.x;
+            const uint16_t qt = (uint16_t)(rec.z & 0xFFFFu), qm = (uint16_t)(rec.z >> 16);
+            if (j == 0) {
+                if (o < F.cap) {
+                    F.otime[o] = (uint32_t)t0;
+                    F.opad[o] = pad0;
+                    F.oqtot[o] = qt;
+                    F.oqmax[o] = qm;
+                }
+            } else {
+                const int nsec = (int)((rec.w >> 8) & 0xFFu);
+                int d = nsec % 18 - sec % 18;
+                d = d < 0 ? d + 18 : d;
+                if (d != 0) {
+                    const float ca = geo.cosb[d], sa = geo.sinb[d];
+                    const float cs = sqrtf((1.0f - s) * (1.0f + s));
+                    const float xn = (x * ca) + (y * sa);
+                    const float yn = (y * ca) - (x * sa);
+                    const float sn = (s * ca) - (cs * sa);
+                    const float cn = (cs * ca) + (s * sa);
+                    if (!(cn > 0.0f)) fl |= TMD_F_ROT;
+                    x = xn;
+                    y = yn;
+                    s = clamp_snp(sn, smax, fl);
+                    sec = nsec;
+                }
+                row = (int)(rec.w & 0xFFu);
+                const RowGeo R = geo.row[row];
+                const float dx = R.x - x;
+                const float s1 = clamp_snp(s + (k * dx), smax, fl);
+                const float a0 = sqrtf((1.0f - s) * (1.0f + s));
+                const float a1 = sqrtf((1.0f - s1) * (1.0f + s1));
+                const float dydx = (s + s1) / (a0 + a1);
+                y = y + (dx * dydx);
+                z = z + (tgl * (dx * sqrtf(1.0f + (dydx * dydx))));
+                s = s1;
+                x = R.x;
+                const int32_t P = sat_i32(rintf(((y * R.inv_pw) + R.padoff) * 32.0f));
+                const int32_t T = sat_i32(rintf(z * geo.inv_vd32));
+                const int32_t pres = (int32_t)(int16_t)(rec.y & 0xFFFFu);
+                const int32_t tres = (int32_t)(int16_t)(rec.y >> 16);
+                int32_t padq = P + pres;
+                fl |= (padq < 0 || padq > 65535) ? TMD_F_PAD : 0u;
+                padq = padq < 0 ? 0 : (padq > 65535 ? 65535 : padq);
+                int32_t timeq = t0 + T + tres;
+                fl |= (timeq < 0 || timeq > (int32_t)kTimeLim - 1) ? TMD_F_TIME : 0u;
+                timeq = timeq < 0 ? 0 : (timeq > (int32_t)kTimeLim - 1 ? (int32_t)kTimeLim - 1 : timeq);
+                if (o < F.cap) {
+                    F.otime[o] = (uint32_t)timeq;
+                    F.opad[o] = (uint16_t)padq;
+                    F.oqtot[o] = qt;
+                    F.oqmax[o] = qm;
+                }
+                const float nuy = (float)pres * R.pwq;
+                const float nuz = (float)tres * geo.vdq;
+                y = y + nuy;
+                z = z + nuz;
+                s = clamp_snp(s + (nuy * R.ks), smax, fl);
+                tgl = tgl + (nuz * R.kt);
             }
-            row += F.rdiff[c];
-            if (row < 0) { fl |= TMD_F_ROW; row = 0; }
-            if (row > NROW - 1) { fl |= TMD_F_ROW; row = NROW - 1; }
-            const float xr = geo.x[row];
-            const float dx = xr - x;
-            const float s1 = clamp_snp(s + (k * dx), smax, fl);
-            const float a0 = sqrtf((1.0f - s) * (1.0f + s));
-            const float a1 = sqrtf((1.0f - s1) * (1.0f + s1));
-            const float dydx = (s + s1) / (a0 + a1);
-            y = y + (dx * dydx);
-            z = z + (tgl * (dx * sqrtf(1.0f + (dydx * dydx))));
-            s = s1;
-            x = xr;
-            const int32_t P = sat_i32(rintf(((y * geo.inv_pw[row]) + geo.padoff[row]) * 32.0f));
-            const int32_t T = sat_i32(rintf(z * geo.inv_vd32));
-            const int32_t pres = F.pres[c];
-            const int32_t tres = F.tres[c];
-            int32_t padq = P + pres;
-            if (padq < 0) { fl |= TMD_F_PAD; padq = 0; }
-            if (padq > 65535) { fl |= TMD_F_PAD; padq = 65535; }
-            int32_t timeq = t0 + T + tres;
-            if (timeq < 0) { fl |= TMD_F_TIME; timeq = 0; }
-            if (timeq > (int32_t)kTimeLim - 1) { fl |= TMD_F_TIME; timeq = (int32_t)kTimeLim - 1; }
-            const uint32_t o = F.dest[c];
-            if (o < F.cap) {
-                F.otime[o] = (uint32_t)timeq;
-                F.opad[o] = (uint16_t)padq;
-                F.oqtot[o] = F.cqtot[c];
-                F.oqmax[o] = F.cqmax[c];
-            }
-            const float nuy = (float)pres * geo.pwq[row];
-            const float nuz = (float)tres * geo.vdq;
-            y = y + nuy;
-            z = z + nuz;
-            s = clamp_snp(s + (nuy * geo.ks[row]), smax, fl);
-            tgl = tgl + (nuz * geo.kt[row]);
+            j++;
         }
     }
     fl = wave_or(fl);
@@ -700,14 +890,14 @@ __global__ void k_selftest_fp(const float *a, const float *b, float *out, uint32
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-constexpr int kStages = 7;
-const char *kStageNames[kStages] = {"tilesum", "count", "colscan", "offsets",
+constexpr int kStages = 8;
+const char *kStageNames[kStages] = {"setup", "tilesum", "count", "colscan", "offsets",
                                     "unattached", "rank", "attached"};
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct FrameLayout {
-    size_t start, tilesum, hist, uin, ueff, dest;
+    size_t start, tilesum, hist, uin, ueff, recs, keyinfo, tkey, order;
     uint32_t ntile, tile0;
 };
 
@@ -723,11 +913,11 @@ struct tmd_plan {
     size_t ws_bytes = 0;
     Geo *d_geo = nullptr;
     uint32_t *d_tile_frame = nullptr;
-    FrameDesc *d_desc = nullptr;
+    FrameDesc *d_desc = nullptr;  // device table (FrameDescHost bytes)
     uint32_t *d_status = nullptr;
     uint32_t *h_status = nullptr;  // pinned
-    FrameDesc *h_desc = nullptr;   // pinned staging
-    std::vector<FrameDesc> last_desc;
+    FrameDescHost *h_desc = nullptr;   // pinned staging
+    std::vector<FrameDescHost> last_desc;
     bool desc_valid = false;
     hipEvent_t desc_done = nullptr;
     hipEvent_t done = nullptr;
@@ -774,11 +964,13 @@ int launch_all(tmd_plan_t *P, hipStream_t s, bool record)
         return TMD_OK;
     };
     const uint32_t T = P->total_tiles;
+    hipLaunchKernelGGL(k_setup, dim3(P->n_frames), dim3(kWave), 0, s, P->d_desc);
+    if (mark()) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_tilesum, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
     if (mark()) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_count, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
     if (mark()) return TMD_E_HIP;
-    hipLaunchKernelGGL(k_colscan, dim3((NBIN + kWave - 1) / kWave, P->n_frames), dim3(kWave * kScanWaves), 0,
+    hipLaunchKernelGGL(k_colscan, dim3((kHRow + kWave - 1) / kWave, P->n_frames), dim3(kWave * kScanWaves), 0,
                        s, P->d_desc);
     if (mark()) return TMD_E_HIP;
     hipLaunchKernelGGL(k_offsets, dim3(P->n_frames), dim3(kOffThreads), 0, s, P->d_desc);
@@ -819,10 +1011,14 @@ int tmd_tables(float bz, float *dst, int cap)
     if (!dst || cap < n) return -n;
     Geo g;
     build_geo(bz, &g);
-    const float *rows[7] = {g.x, g.pw, g.inv_pw, g.padoff, g.pwq, g.ks, g.kt};
     int o = 0;
-    for (int a = 0; a < 7; a++)
-        for (int r = 0; r < NROW; r++) dst[o++] = rows[a][r];
+    for (int r = 0; r < NROW; r++) dst[o++] = g.row[r].x;
+    for (int r = 0; r < NROW; r++) dst[o++] = g.row[r].pw;
+    for (int r = 0; r < NROW; r++) dst[o++] = g.row[r].inv_pw;
+    for (int r = 0; r < NROW; r++) dst[o++] = g.row[r].padoff;
+    for (int r = 0; r < NROW; r++) dst[o++] = g.row[r].pwq;
+    for (int r = 0; r < NROW; r++) dst[o++] = g.row[r].ks;
+    for (int r = 0; r < NROW; r++) dst[o++] = g.row[r].kt;
     for (int d = 0; d < 18; d++) dst[o++] = g.cosb[d];
     for (int d = 0; d < 18; d++) dst[o++] = g.sinb[d];
     dst[o++] = g.kb;
@@ -877,10 +1073,13 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
         tile_frame.insert(tile_frame.end(), L.ntile, f);
         L.start = off;   off += align256(4 * ((size_t)S.n_tracks + 1));
         L.tilesum = off; off += align256(4 * (size_t)(L.ntile ? L.ntile : 1));
-        L.hist = off;    off += align256(4 * (size_t)L.ntile * NBIN);
+        L.hist = off;    off += align256(4 * (size_t)L.ntile * kHRow);
         L.uin = off;     off += align256(4 * (size_t)NBIN);
         L.ueff = off;    off += align256(4 * (size_t)NBIN);
-        L.dest = off;    off += align256(4 * (size_t)(S.n_attached ? S.n_attached : 1));
+        L.recs = off;    off += align256(16 * (size_t)(S.n_attached ? S.n_attached : 1));
+        L.keyinfo = off; off += align256(4 * (size_t)(2 * kNKey));
+        L.tkey = off;    off += align256((size_t)(S.n_tracks ? S.n_tracks : 1));
+        L.order = off;   off += align256(4 * (size_t)(S.n_tracks ? S.n_tracks : 1));
         P->layout.push_back(L);
     }
     P->total_tiles = tiles;
@@ -907,7 +1106,7 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
             break;
         }
         memset(P->h_status, 0, sizeof(uint32_t) * n_frames);
-        if (hipHostMalloc((void **)&P->h_desc, sizeof(FrameDesc) * n_frames, 0) != hipSuccess) {
+        if (hipHostMalloc((void **)&P->h_desc, sizeof(FrameDescHost) * n_frames, 0) != hipSuccess) {
             rc = TMD_E_HIP;
             break;
         }
@@ -928,7 +1127,7 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
     if (!P || !in || !out || !workspace) return TMD_E_ARG;
     if ((uintptr_t)workspace % 256) return TMD_E_ARG;
     hipStream_t s = (hipStream_t)stream;
-    std::vector<FrameDesc> desc(P->n_frames);
+    std::vector<FrameDescHost> desc(P->n_frames);
     for (uint32_t f = 0; f < P->n_frames; f++) {
         const tmd_frame_shape &S = P->shapes[f];
         const tmd_frame_in &I = in[f];
@@ -954,7 +1153,7 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
             !aligned(I.un_qmax) || !aligned(O.row_offset) || !aligned(O.row_nattached) ||
             !aligned(O.time) || !aligned(O.pad) || !aligned(O.qtot) || !aligned(O.qmax))
             return TMD_E_ARG;
-        FrameDesc &D = desc[f];
+        FrameDescHost &D = desc[f];
         memset(&D, 0, sizeof(D));
         D.ncls = I.trk_ncls; D.sec0 = I.trk_sec0; D.row0 = I.trk_row0; D.pad0 = I.trk_pad0;
         D.time0 = I.trk_time0; D.qpt = I.trk_qpt; D.snp = I.trk_snp; D.tgl = I.trk_tgl;
@@ -970,7 +1169,10 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
         D.hist = (uint32_t *)(ws + L.hist);
         D.uin = (uint32_t *)(ws + L.uin);
         D.ueff = (uint32_t *)(ws + L.ueff);
-        D.dest = (uint32_t *)(ws + L.dest);
+        D.recs = (uint4 *)(ws + L.recs);
+        D.keyinfo = (uint32_t *)(ws + L.keyinfo);
+        D.tkey = (uint8_t *)(ws + L.tkey);
+        D.order = (uint32_t *)(ws + L.order);
         D.status = P->d_status + f;
         D.cap = O.capacity;
         D.nT = S.n_tracks; D.nA = S.n_attached; D.nU = S.n_unattached;
@@ -981,7 +1183,7 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
     if (cur != P->device) HIP_TRY(hipSetDevice(P->device));
     int rc = TMD_OK;
     do {
-        const size_t dbytes = sizeof(FrameDesc) * P->n_frames;
+        const size_t dbytes = sizeof(FrameDescHost) * P->n_frames;
         if (!P->desc_valid || memcmp(desc.data(), P->last_desc.data(), dbytes) != 0) {
             // the staging buffer may still feed the previous upload
             if (P->desc_valid && hipEventSynchronize(P->desc_done) != hipSuccess) { rc = TMD_E_HIP; break; }
