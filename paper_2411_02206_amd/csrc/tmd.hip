@@ -260,67 +260,6 @@ __device__ __forceinline__ void step_pos(int &sec, int &row, int rd, uint32_t sd
     row = row < 0 ? 0 : (row > NROW - 1 ? NROW - 1 : row);
 }
 
-// (sector,row) key of clusters cb + lane of one track, computed by the whole
-// wave; (sec, row) is the position before cluster cb and is advanced to the
-// position of the last cluster of the chunk.  Lanes >= cnt return 0.
-// monotone: the chunk's rows are strictly monotone, so its keys are distinct.
-// fl collects F_SEC (sector step >= 18) and F_ROW (row clamped).
-__device__ __forceinline__ uint32_t chunk_keys(const FrameDesc &F, uint32_t c0, uint32_t cb,
-                                               uint32_t cnt, int &sec, int &row, bool &monotone,
-                                               uint32_t &fl, uint32_t *dir = nullptr)
-{
-    const uint32_t lane = lane_id();
-    const uint32_t j = cb + lane;
-    const bool act = lane < cnt;
-    int rd = 0;
-    uint32_t sd = 0;
-    if (act && j > 0) {
-        rd = F.rdiff[c0 + j];
-        sd = F.sdiff[c0 + j];
-        if (sd >= 18) {
-            fl |= TMD_F_SEC;
-            sd %= 18;
-        }
-    }
-    // fast path: prefix sums without clamping
-    const int prow = row + (int)wave_incl_add((uint32_t)rd);
-    const uint32_t psec = (uint32_t)(sec % 18) + wave_incl_add(sd);
-    const bool inrange = !act || (prow >= 0 && prow < NROW);
-    const bool clamps = __ballot(!inrange) != 0;
-    const int side = sec / 18;
-    uint32_t key;
-    if (!clamps) {
-        const int s = side * 18 + (int)(psec % 18);
-        key = act ? (uint32_t)(s * NROW + prow) : 0u;
-    } else {
-        // a row leaves [0, 151] somewhere: walk the chunk in order
-        fl |= TMD_F_ROW;
-        int s = sec, r = row;
-        key = 0;
-        for (uint32_t i = 0; i < cnt; i++) {
-            const int rdi = __shfl(rd, (int)i);
-            const uint32_t sdi = (uint32_t)__shfl((int)sd, (int)i);
-            if (cb + i > 0) step_pos(s, r, rdi, sdi);
-            if (i == lane) key = (uint32_t)(s * NROW + r);
-        }
-    }
-    const uint64_t live = __ballot(act && lane > 0);
-    const uint64_t up = __ballot(act && lane > 0 && rd > 0);
-    const uint64_t dn = __ballot(act && lane > 0 && rd < 0);
-    monotone = ((up == live) || (dn == live)) && !clamps;
-    if (dir) {
-        // direction of every step of the chunk (bit 0: all up, bit 1: all down)
-        const uint64_t steps = __ballot(act && j > 0);
-        const uint64_t sup = __ballot(act && j > 0 && rd > 0);
-        const uint64_t sdn = __ballot(act && j > 0 && rd < 0);
-        *dir &= clamps ? 0u : ((sup == steps ? 1u : 0u) | (sdn == steps ? 2u : 0u));
-    }
-    const uint32_t last = readlane(key, (int)(cnt - 1));
-    sec = (int)(last / NROW);
-    row = (int)(last % NROW);
-    return key;
-}
-
 // ---------------------------------------------------------------------------
 // K0: clear the per-frame status word
 // ---------------------------------------------------------------------------
@@ -347,15 +286,164 @@ __global__ __launch_bounds__(kTile) void k_tilesum(const FrameDesc *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// K2: track starts, per-tile histogram of cluster bins and of scheduling keys.
-// Each wave walks 64 consecutive tracks one at a time, 64 clusters per step
-// (coalesced loads of the row and sector steps).
+// Flat walk of a wave's 64 consecutive tracks.  Their decoded clusters form
+// one contiguous range [A, E) of the cluster stream; the wave walks it in
+// chunks of 64 clusters (lane = cluster), loading several chunks at a time.
+// Inside a chunk the rows and sectors are segmented prefix sums: a segment
+// starts at a track's first cluster (its header position) or continues the
+// previous chunk's last track.  If a row would leave [0, 151] the chunk is
+// walked cluster by cluster with the clamps instead.
 // ---------------------------------------------------------------------------
+struct WaveLds {
+    uint8_t hrow[kWave];   // header row of track lane l (clamped)
+    uint8_t hsec[kWave];   // header sector of track lane l (wrapped)
+    uint8_t hm[kWave];     // per chunk: track lane whose first cluster is at lo + i, or 0xFF
+    uint32_t cls[kWave];   // K2: direction bits of track lane l (bit 0 all up, bit 1 all down)
+};
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t dpp_max_step(uint32_t v)
+{
+    return max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xf, false));
+}
+
+// inclusive max over lanes 0..lane
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v)
+{
+    v = dpp_max_step<0x111, 0xf>(v);
+    v = dpp_max_step<0x112, 0xf>(v);
+    v = dpp_max_step<0x114, 0xf>(v);
+    v = dpp_max_step<0x118, 0xf>(v);
+    v = dpp_max_step<0x142, 0xa>(v);
+    v = dpp_max_step<0x143, 0xc>(v);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t bperm(uint32_t v, uint32_t src_lane)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src_lane * 4u), (int)v);
+}
+
+struct WalkState {
+    int csec, crow;     // position of the last cluster of the previous chunk
+    uint32_t ctrack;    // track lane of the last cluster of the previous chunk
+};
+
+// Per-lane track setup; returns the wave's cluster range [A, E).  Lane l holds
+// track tw + l (if < nT): its start, decoded length and header position.
+__device__ __forceinline__ void wave_setup(const FrameDesc &F, uint32_t tw, WaveLds &L, uint32_t start_in,
+                                           uint32_t &start_l, uint32_t &n_l, uint32_t &A, uint32_t &E)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t t = tw + lane;
+    uint32_t nc = 0;
+    start_l = 0xFFFFFFFFu;
+    n_l = 0;
+    uint8_t r = 0, s = 0;
+    if (t < F.nT) {
+        start_l = start_in;
+        nc = F.ncls[t];
+        n_l = track_len(start_l, nc, F.nA);
+        HeaderPos h = header_pos(F.sec0[t], F.row0[t]);
+        r = (uint8_t)h.row;
+        s = (uint8_t)h.sec;
+    }
+    L.hrow[lane] = r;
+    L.hsec[lane] = s;
+    L.cls[lane] = 3u;
+    const uint32_t a = readlane(start_l, 0);  // track tw exists whenever the wave runs
+    const uint32_t sum = readlane(wave_incl_add(nc), kWave - 1);
+    const unsigned long long e = (unsigned long long)a + sum;
+    A = a;
+    E = (uint32_t)(e < F.nA ? e : F.nA);
+    if (A > E) A = E;
+}
+
+// Keys of the chunk [lo, lo + 64) ∩ [lo, E).  rd/sd: this lane's raw row and
+// sector steps (loaded by the caller).  Returns the (sector,row) key (0 for
+// inactive lanes) and, in *tl, the track lane the cluster belongs to.
+__device__ __forceinline__ uint32_t walk_chunk(uint32_t lo, uint32_t E, int rd, uint32_t sd, uint32_t start_l,
+                                               uint32_t n_l, WaveLds &L, WalkState &ws, uint32_t &fl,
+                                               uint32_t &tl, bool &clamped)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t c = lo + lane;
+    const bool act = c < E;
+    // mark the first cluster of every track starting in this chunk
+    L.hm[lane] = 0xFFu;
+    __builtin_amdgcn_wave_barrier();
+    if (n_l > 0 && start_l >= lo && start_l - lo < (uint32_t)kWave) L.hm[start_l - lo] = (uint8_t)lane;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t h = L.hm[lane];
+    const bool head = act && h != 0xFFu;
+    const bool step = act && !head;
+    uint32_t sdm = 0;
+    int rdv = 0;
+    if (step) {
+        rdv = rd;
+        sdm = sd;
+        if (sdm >= 18) {
+            fl |= TMD_F_SEC;
+            sdm %= 18;
+        }
+    }
+    const uint32_t P = wave_incl_add((uint32_t)rdv);
+    const uint32_t Q = wave_incl_add(sdm);
+    const uint32_t H1 = wave_incl_max(head ? lane + 1 : 0u);  // 1 + segment head lane, 0 = continuing
+    const uint32_t src = H1 ? H1 - 1 : 0u;
+    const uint32_t PH = bperm(P, src), QH = bperm(Q, src), TH = bperm(h, src);
+    int row, sec;
+    if (H1) {
+        const int br = L.hrow[TH], bs = L.hsec[TH];
+        row = br + (int)(P - PH);
+        sec = (bs / 18) * 18 + (int)((uint32_t)(bs % 18) + (Q - QH)) % 18;
+        tl = TH;
+    } else {
+        row = ws.crow + (int)P;
+        sec = (ws.csec / 18) * 18 + (int)((uint32_t)(ws.csec % 18) + Q) % 18;
+        tl = ws.ctrack;
+    }
+    clamped = __ballot(act && (row < 0 || row >= NROW)) != 0;
+    if (clamped) {
+        // walk the chunk in order with the clamps
+        fl |= TMD_F_ROW;
+        int s = ws.csec, r = ws.crow;
+        for (uint32_t i = 0; i < (uint32_t)kWave; i++) {
+            if (lo + i >= E) break;
+            const uint32_t hi = (uint32_t)__shfl((int)h, (int)i);
+            const int rdi = __shfl(rd, (int)i);
+            const uint32_t sdi = (uint32_t)__shfl((int)sd, (int)i);
+            if (hi != 0xFFu) {
+                r = L.hrow[hi];
+                s = L.hsec[hi];
+            } else {
+                step_pos(s, r, rdi, sdi);
+            }
+            if (i == lane) {
+                row = r;
+                sec = s;
+            }
+        }
+    }
+    const uint32_t key = act ? (uint32_t)(sec * NROW + row) : 0u;
+    const uint32_t last = (E - lo) < (uint32_t)kWave ? (E - lo - 1) : (uint32_t)(kWave - 1);
+    const uint32_t lk = readlane(key, (int)last);
+    ws.csec = (int)(lk / NROW);
+    ws.crow = (int)(lk % NROW);
+    ws.ctrack = readlane(tl, (int)last);
+    return key;
+}
+
+// ---------------------------------------------------------------------------
+// K2: track starts, per-tile histogram of cluster bins and of scheduling keys
+// ---------------------------------------------------------------------------
+constexpr int kGroup = 4;  // chunks loaded together by a walk
+
 __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ fd,
                                                  const uint32_t *__restrict__ tile_frame)
 {
     __shared__ uint32_t hist[kHRow];
-    __shared__ uint32_t sstart[kTile];
+    __shared__ WaveLds wl[kTileWaves];
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
@@ -372,7 +460,6 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
     const uint32_t nc = t < F.nT ? F.ncls[t] : 0u;
     uint32_t tot;
     const uint32_t start = before + block_excl_add(nc, &tot);  // also syncs
-    sstart[threadIdx.x] = start;
     if (t < F.nT) {
         F.start[t] = start;
         if (t == F.nT - 1) {
@@ -380,27 +467,48 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
             if (start + nc != F.nA) atomicOr(F.status, TMD_F_COUNT);
         }
     }
-    __syncthreads();
-    uint32_t fl_unused = 0;
-    for (uint32_t tt = 0; tt < kWave; tt++) {
-        const uint32_t tl = w * kWave + tt;
-        const uint32_t tr = lt * kTile + tl;
-        if (tr >= F.nT) break;
-        const uint32_t c0 = sstart[tl];
-        const uint32_t n = track_len(c0, F.ncls[tr], F.nA);
-        HeaderPos h = header_pos(F.sec0[tr], F.row0[tr]);
-        int sec = h.sec, row = h.row;
-        uint32_t dir = 3u;
-        for (uint32_t cb = 0; cb < n; cb += kWave) {
-            const uint32_t cnt = min(n - cb, (uint32_t)kWave);
-            bool mono;
-            const uint32_t key = chunk_keys(F, c0, cb, cnt, sec, row, mono, fl_unused, &dir);
-            if (lane < cnt) atomicAdd(&hist[key], 1u);
+    const uint32_t tw = lt * kTile + w * kWave;
+    if (tw < F.nT) {
+        WaveLds &L = wl[w];
+        uint32_t start_l, n_l, A, E;
+        wave_setup(F, tw, L, start, start_l, n_l, A, E);
+        WalkState ws{0, 0, 0};
+        uint32_t fl = 0;
+        for (uint32_t g = A; g < E; g += kWave * kGroup) {
+            int rd[kGroup];
+            uint32_t sd[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; u++) {
+                const uint32_t c = g + u * kWave + lane;
+                rd[u] = c < E ? (int)F.rdiff[c] : 0;
+                sd[u] = c < E ? (uint32_t)F.sdiff[c] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kGroup; u++) {
+                const uint32_t lo = g + u * kWave;
+                if (lo >= E) break;
+                uint32_t tl;
+                bool clamped;
+                const uint32_t key = walk_chunk(lo, E, rd[u], sd[u], start_l, n_l, L, ws, fl, tl, clamped);
+                const uint32_t c = lo + lane;
+                if (c < E) {
+                    atomicAdd(&hist[key], 1u);
+                    // direction of this step for the track's class
+                    const bool head = L.hm[lane] != 0xFFu;
+                    if (clamped) atomicAnd(&L.cls[tl], 0u);
+                    else if (!head) {
+                        if (!(rd[u] > 0)) atomicAnd(&L.cls[tl], ~1u);
+                        if (!(rd[u] < 0)) atomicAnd(&L.cls[tl], ~2u);
+                    }
+                }
+            }
         }
-        const uint32_t cls = n <= 1 ? 0u : ((dir & 1u) ? 0u : ((dir & 2u) ? 1u : 2u));
-        if (lane == 0) {
-            const uint32_t key = (uint32_t)h.sec * 3u + cls;
-            F.tkey[tr] = (uint8_t)key;
+        __builtin_amdgcn_wave_barrier();
+        if (tw + lane < F.nT) {
+            const uint32_t bits = L.cls[lane];
+            const uint32_t cls = n_l <= 1 ? 0u : ((bits & 1u) ? 0u : ((bits & 2u) ? 1u : 2u));
+            const uint32_t key = (uint32_t)L.hsec[lane] * 3u + cls;
+            F.tkey[tw + lane] = (uint8_t)key;
             atomicAdd(&hist[NBIN + key], 1u);
         }
     }
@@ -581,10 +689,10 @@ __global__ __launch_bounds__(kWave) void k_unattached(const FrameDesc *__restric
 // residuals, charges and (sector,row) as one 16-byte record in stream order;
 // also places the tile's tracks in the decode schedule.  Within a bin the slot
 // order is the stream order (track, then cluster).  Block = one tile of 256
-// tracks; each wave takes 64 consecutive tracks one at a time, 64 clusters per
-// step.  LDS: per-wave counters (16 bit: a wave's 64 tracks put at most
-// 64*255 clusters in one bin, and three waves' prefix stays below 2^16) and
-// the tile's bin bases.
+// tracks, wave w walks tracks 64w..64w+63 of the tile (flat walk).  LDS:
+// per-wave bin counters (16 bit: a wave's 64 tracks put at most 64*255
+// clusters in one bin, and three waves' prefix stays below 2^16) and the
+// tile's bin bases.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd,
                                                 const uint32_t *__restrict__ tile_frame)
@@ -592,49 +700,57 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
     __shared__ uint32_t wcnt32[kTileWaves * NBIN / 2];  // 16-bit counters, packed
     __shared__ uint32_t base[NBIN];
     __shared__ uint8_t keys[kTile];
+    __shared__ WaveLds wl[kTileWaves];
     uint16_t *wcnt = reinterpret_cast<uint16_t *>(wcnt32);
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     const GLB uint32_t *G = F.hist + (size_t)lt * kHRow;
+    const uint32_t t = lt * kTile + threadIdx.x;
 
     for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wcnt32[i] = 0;
-    {
-        const uint32_t t = lt * kTile + threadIdx.x;
-        keys[threadIdx.x] = t < F.nT ? F.tkey[t] : (uint8_t)0xFF;
-    }
+    keys[threadIdx.x] = t < F.nT ? F.tkey[t] : (uint8_t)0xFF;
+    const uint32_t my_start = t < F.nT ? F.start[t] : 0u;
     __syncthreads();
 
     // decode schedule: tracks sorted by (key, index), stable
-    {
-        const uint32_t t = lt * kTile + threadIdx.x;
-        if (t < F.nT) {
-            const uint8_t key = keys[threadIdx.x];
-            uint32_t local = 0;
-            for (uint32_t i = 0; i < threadIdx.x; i++) local += keys[i] == key;
-            F.order[F.keyinfo[kNKey + key] + G[NBIN + key] + local] = t;
-        }
+    if (t < F.nT) {
+        const uint8_t key = keys[threadIdx.x];
+        uint32_t local = 0;
+        for (uint32_t i = 0; i < threadIdx.x; i++) local += keys[i] == key;
+        F.order[F.keyinfo[kNKey + key] + G[NBIN + key] + local] = t;
     }
 
+    const uint32_t tw = lt * kTile + w * kWave;
+    const bool wave_on = tw < F.nT;
+    WaveLds &L = wl[w];
+    uint32_t start_l = 0, n_l = 0, A = 0, E = 0;
     uint32_t fl = 0;
-    const uint32_t t_first = lt * kTile + w * kWave;
-    // pass 1: per-wave bin counts
-    for (uint32_t tt = 0; tt < kWave; tt++) {
-        const uint32_t t = t_first + tt;
-        if (t >= F.nT) break;
-        const uint32_t c0 = F.start[t];
-        const uint32_t n = track_len(c0, F.ncls[t], F.nA);
-        if (n == 0) continue;
-        HeaderPos h = header_pos(F.sec0[t], F.row0[t]);
-        int sec = h.sec, row = h.row;
-        for (uint32_t cb = 0; cb < n; cb += kWave) {
-            const uint32_t cnt = min(n - cb, (uint32_t)kWave);
-            bool mono;
-            uint32_t key = chunk_keys(F, c0, cb, cnt, sec, row, mono, fl);
-            if (lane < cnt) {
-                uint32_t idx = w * NBIN + key;
-                atomicAdd(&wcnt32[idx >> 1], 1u << (16 * (idx & 1)));
+    if (wave_on) {
+        wave_setup(F, tw, L, my_start, start_l, n_l, A, E);
+        // pass 1: per-wave bin counts
+        WalkState ws{0, 0, 0};
+        for (uint32_t g = A; g < E; g += kWave * kGroup) {
+            int rd[kGroup];
+            uint32_t sd[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; u++) {
+                const uint32_t c = g + u * kWave + lane;
+                rd[u] = c < E ? (int)F.rdiff[c] : 0;
+                sd[u] = c < E ? (uint32_t)F.sdiff[c] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kGroup; u++) {
+                const uint32_t lo = g + u * kWave;
+                if (lo >= E) break;
+                uint32_t tl;
+                bool clamped;
+                const uint32_t key = walk_chunk(lo, E, rd[u], sd[u], start_l, n_l, L, ws, fl, tl, clamped);
+                if (lo + lane < E) {
+                    const uint32_t idx = w * NBIN + key;
+                    atomicAdd(&wcnt32[idx >> 1], 1u << (16 * (idx & 1)));
+                }
             }
         }
     }
@@ -650,54 +766,52 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
         base[k] = F.roff[k] + G[k];
     }
     __syncthreads();
-    // pass 2: slots -> records
-    for (uint32_t tt = 0; tt < kWave; tt++) {
-        const uint32_t t = t_first + tt;
-        if (t >= F.nT) break;
-        const uint32_t c0 = F.start[t];
-        const uint32_t n = track_len(c0, F.ncls[t], F.nA);
-        if (n == 0) continue;
-        HeaderPos h = header_pos(F.sec0[t], F.row0[t]);
-        int sec = h.sec, row = h.row;
-        for (uint32_t cb = 0; cb < n; cb += kWave) {
-            const uint32_t cnt = min(n - cb, (uint32_t)kWave);
-            const bool act = lane < cnt;
-            const uint32_t c = c0 + cb + lane;
-            uint32_t res = 0, q = 0;
-            if (act) {
-                res = (uint32_t)(uint16_t)F.pres[c] | ((uint32_t)(uint16_t)F.tres[c] << 16);
-                q = (uint32_t)F.cqtot[c] | ((uint32_t)F.cqmax[c] << 16);
+    if (wave_on) {
+        // pass 2: slots -> records
+        WalkState ws{0, 0, 0};
+        uint32_t fl2 = 0;
+        for (uint32_t g = A; g < E; g += kWave * kGroup) {
+            int rd[kGroup];
+            uint32_t sd[kGroup], res[kGroup], q[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; u++) {
+                const uint32_t c = g + u * kWave + lane;
+                const bool a = c < E;
+                rd[u] = a ? (int)F.rdiff[c] : 0;
+                sd[u] = a ? (uint32_t)F.sdiff[c] : 0u;
+                res[u] = a ? ((uint32_t)(uint16_t)F.pres[c] | ((uint32_t)(uint16_t)F.tres[c] << 16)) : 0u;
+                q[u] = a ? ((uint32_t)F.cqtot[c] | ((uint32_t)F.cqmax[c] << 16)) : 0u;
             }
-            bool mono;
-            uint32_t dummy = 0;
-            uint32_t key = chunk_keys(F, c0, cb, cnt, sec, row, mono, dummy);
-            const uint64_t lt_mask = (1ull << lane) - 1ull;
-            uint64_t same;
-            if (mono) {
-                same = 1ull << lane;
-            } else {
+#pragma unroll
+            for (int u = 0; u < kGroup; u++) {
+                const uint32_t lo = g + u * kWave;
+                if (lo >= E) break;
+                uint32_t tl;
+                bool clamped;
+                const uint32_t key = walk_chunk(lo, E, rd[u], sd[u], start_l, n_l, L, ws, fl2, tl, clamped);
+                const uint32_t c = lo + lane;
+                const bool act = c < E;
                 // lanes holding the same key: intersect per-bit ballots
-                same = __ballot(act);
+                uint64_t same = __ballot(act);
 #pragma unroll
                 for (int bit = 0; bit < 13; bit++) {
-                    uint64_t m = __ballot(act && ((key >> bit) & 1u));
+                    const uint64_t m = __ballot(act && ((key >> bit) & 1u));
                     same &= ((key >> bit) & 1u) ? m : ~m;
                 }
+                const uint64_t lt_mask = (1ull << lane) - 1ull;
+                const uint32_t below = (uint32_t)__popcll(same & lt_mask);
+                const uint32_t slot_idx = w * NBIN + key;
+                uint32_t r = 0;
+                if (act) r = wcnt[slot_idx];
+                // every lane reads its counter before any lane updates one
+                __builtin_amdgcn_wave_barrier();
+                if (act) {
+                    const uint32_t o = base[key] + r + below;
+                    F.recs[c] = make_uint4(o, res[u], q[u], (key % NROW) | ((key / NROW) << 8));
+                    if ((same >> lane) == 1ull) wcnt[slot_idx] = (uint16_t)(r + below + 1);
+                }
+                __builtin_amdgcn_wave_barrier();
             }
-            const uint32_t below = (uint32_t)__popcll(same & lt_mask);
-            const uint32_t slot_idx = w * NBIN + key;
-            uint32_t r = 0;
-            if (act) r = wcnt[slot_idx];
-            // every lane reads its counter before any lane updates one
-            __builtin_amdgcn_wave_barrier();
-            if (act) {
-                const uint32_t o = base[key] + r + below;
-                const uint32_t kr = key % NROW, ks = key / NROW;
-                F.recs[c] = make_uint4(o, res, q, kr | (ks << 8));
-                const bool leader = (same >> lane) == 1ull;  // highest lane of its group
-                if (leader) wcnt[slot_idx] = (uint16_t)(r + below + 1);
-            }
-            __builtin_amdgcn_wave_barrier();
         }
     }
     fl = wave_or(fl);
@@ -732,11 +846,23 @@ __device__ __forceinline__ int32_t sat_i32(float v)
     return (int32_t)c;
 }
 
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t dpp_min_step(uint32_t v)
+{
+    // lanes (rows) without a source see the identity 0xFFFFFFFF
+    return min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)v, CTRL, ROWMASK, 0xf, false));
+}
+
+// minimum over all 64 lanes (inclusive min-scan, then lane 63)
 __device__ __forceinline__ uint32_t wave_min(uint32_t v)
 {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) v = min(v, (uint32_t)__shfl_xor(v, d));
-    return v;
+    v = dpp_min_step<0x111, 0xf>(v);
+    v = dpp_min_step<0x112, 0xf>(v);
+    v = dpp_min_step<0x114, 0xf>(v);
+    v = dpp_min_step<0x118, 0xf>(v);
+    v = dpp_min_step<0x142, 0xa>(v);
+    v = dpp_min_step<0x143, 0xc>(v);
+    return readlane(v, kWave - 1);
 }
 
 __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict__ fd,
@@ -787,8 +913,10 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
     const uint64_t dsc = __ballot(n > 0 && cls == 1);
     const uint32_t mode = asc == any_live ? 0u : (dsc == any_live ? 1u : 2u);
 
-    uint4 cur = make_uint4(0, 0, 0, 0);
+    // records of the next two clusters are kept in flight
+    uint4 cur = make_uint4(0, 0, 0, 0), nxt = make_uint4(0, 0, 0, 0);
     if (n > 0) cur = F.recs[c0];
+    if (n > 1) nxt = F.recs[c0 + 1];
     uint32_t j = 0;
     // every step decodes at least one cluster, so 64 * 255 steps always suffice
     for (uint32_t step = 0; step < (uint32_t)kWave * 256u; step++) {
@@ -805,7 +933,8 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
         }
         if (ready) {
             const uint4 rec = cur;
-            if (j + 1 < n) cur = F.recs[c0 + j + 1];
+            cur = nxt;
+            if (j + 2 < n) nxt = F.recs[c0 + j + 2];
             const uint32_t o = rec.x;
             const uint16_t qt = (uint16_t)(rec.z & 0xFFFFu), qm = (uint16_t)(rec.z >> 16);
             if (j == 0) {
