@@ -36,6 +36,10 @@ WORKLOADS = {
     "stress": "high-occupancy stress frame: 500 collisions x 2000 tracks, 15% low-pT loopers, "
               "rows skewed exp(-row/40); plain single launch",
     "tiny": "tiny plain decode: 1 sector, 1000 tracks of 20..152 clusters, 20000 unattached",
+    "batched": "64 time frames of log-uniform 10..200 collisions x 2000 tracks decoded by one plan "
+               "(one HIP-graph launch), compared with 64 plain per-frame decodes",
+    "served": "Poisson arrivals of frames from the batched mix at 25/50/75/100% of the batched peak; "
+              "continuous batching under a 200 GB HBM budget; p50/p99 latency",
 }
 
 
@@ -70,6 +74,8 @@ def main():
     ap.add_argument("--bz", type=float, default=0.5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and check")
+    ap.add_argument("--frames", type=int, default=64, help="frames of the batched/served workloads")
+    ap.add_argument("--seconds-per-load", type=float, default=2.0, help="served: arrival window per load")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build decodes on one GPU only; --gpus {args.gpus} is not supported "
@@ -83,9 +89,12 @@ def main():
     import paper_2411_02206_amd as tmd
     import synth
 
+    if args.workload in ("batched", "served"):
+        return run_batched(args)
+
     spec = synth.spec_for(args.workload)
     t = time.perf_counter()
-    frame = synth.make_frame(spec)
+    frame = synth.make_frame(spec, workers=16)  # forked workers, before any GPU use
     gen_s = time.perf_counter() - t
     nT, nA, nU = tmd.frame_shape(frame)
     n_clusters = nA + nU
@@ -129,7 +138,14 @@ def main():
     att_b, una_b, all_b = algorithmic_bytes(nT, nA, nU)
     avg = {k: v / max(calls, 1) for k, v in stages.items()}
     dominant = max(avg, key=avg.get)
-    dom_bytes = {"attached": att_b, "unattached": una_b}.get(dominant)
+    # algorithmic bytes per launch of each kernel (what its step of the method
+    # must move): attached decode 10 B in + 10 B out per attached cluster and
+    # 15 B per header; unattached 10 + 10 B per cluster; count and rank read
+    # the 2 B of row/sector steps per attached cluster (the rank kernel also
+    # the 8 B of residuals and charges it packs for the decode)
+    kernel_bytes = {"attached": att_b, "unattached": una_b, "count": 2 * nA + nT,
+                    "rank": 10 * nA + nT}
+    dom_bytes = kernel_bytes.get(dominant)
     roof = None
     if dom_bytes is not None and avg[dominant] > 0:
         ach = dom_bytes / (avg[dominant] * 1e-3) / 1e9
@@ -162,6 +178,147 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4)},
     }
+    print(json.dumps(line), flush=True)
+
+
+def _gen(spec):
+    import synth
+    return synth.make_frame(spec)
+
+
+def make_frames(specs, workers=16):
+    """Generate frames in parallel worker processes (forked before any GPU use)."""
+    import multiprocessing as mp
+    n = max(1, min(workers, len(specs), os.cpu_count() or 1))
+    if n == 1:
+        return [_gen(s) for s in specs]
+    with mp.get_context("fork").Pool(n) as pool:
+        return pool.map(_gen, specs, chunksize=1)
+
+
+def run_batched(args):
+    """Batched workload (one plan over all frames, HIP graph) against plain
+    per-frame decodes of the same frames; with --workload served, also the
+    serving loop at several offered loads."""
+    import synth
+    specs = synth.batch_specs(args.workload, n_frames=args.frames)
+    t = time.perf_counter()
+    frames = make_frames(specs)
+    gen_s = time.perf_counter() - t
+
+    import numpy as np
+    import torch
+
+    import paper_2411_02206_amd as tmd
+    from paper_2411_02206_amd import serve
+
+    shapes = [tmd.frame_shape(f) for f in frames]
+    n_clusters = sum(a + u for _, a, u in shapes)
+    print(f"[bench] {args.workload}: {len(frames)} frames, {sum(s[0] for s in shapes)} tracks, {n_clusters} "
+          f"clusters (generated in {gen_s:.1f} s)", file=sys.stderr, flush=True)
+    ins = [tmd.to_device(f) for f in frames]
+    stream = torch.cuda.current_stream()
+
+    # plain: one plan and one launch sequence per frame
+    plans = [tmd.Plan([s], bz=args.bz) for s in shapes]
+    ws_bytes = max(p.workspace_bytes for p in plans)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    outs_plain = [tmd.alloc_out(s) for s in shapes]
+
+    def plain_step():
+        for p, i, o in zip(plans, ins, outs_plain):
+            p.decode([i], [o], ws, stream)
+
+    # batched: one plan over all frames, captured once as a HIP graph
+    bplan = tmd.Plan(shapes, bz=args.bz, flags=tmd.PLAN_GRAPH)
+    bws = bplan.alloc_workspace()
+    outs_b = [tmd.alloc_out(s) for s in shapes]
+
+    def batched_step():
+        bplan.decode(ins, outs_b, bws, stream)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    steps = max(1, args.steps // 10)
+    t_plain = timed(plain_step, steps, 1)
+    t_batch = timed(batched_step, steps, 1)
+    print(f"[bench] plain {1e3 * t_plain:.3f} ms, batched {1e3 * t_batch:.3f} ms per pass over "
+          f"{len(frames)} frames", file=sys.stderr, flush=True)
+    # every frame bit-identical between the two forms
+    def dev_equal(a, b):
+        n = int(a["row_offset"][-1].item())
+        if n != int(b["row_offset"][-1].item()):
+            return False
+        if not (torch.equal(a["row_offset"], b["row_offset"]) and
+                torch.equal(a["row_nattached"], b["row_nattached"])):
+            return False
+        return all(torch.equal(a[k][:n], b[k][:n]) for k in ("time", "pad", "qtot", "qmax"))
+
+    same = all(dev_equal(a, b) for a, b in zip(outs_plain, outs_b))
+    flags_same = all(p.status(0) == bplan.status(i) for i, p in enumerate(plans))
+    oracle_ok = None
+    if not args.no_cpu:
+        import oracle
+        oracle_ok = True
+        for i in (0, len(frames) // 2):
+            exp, est = oracle.decode(frames[i], bz=args.bz)
+            got = tmd.to_numpy(outs_b[i])
+            oracle_ok &= bool(all(np.array_equal(exp[k], got[k]) for k in exp) and est == bplan.status(i))
+
+    line = {
+        "metric": "decoded TPC clusters/s on 1 MI355X (bit-exact) + p50/p99 time-frame latency",
+        "value": n_clusters / t_batch, "unit": "clusters/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": 1e3 * t_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "frames": len(frames),
+                   "n_clusters": n_clusters, "bz_tesla": args.bz},
+        "plain_per_frame": {"ms_per_pass": 1e3 * t_plain, "clusters_per_s": n_clusters / t_plain},
+        "batched_vs_plain_speedup": t_plain / t_batch,
+        "bitexact_batched_vs_plain": bool(same and flags_same),
+        "bitexact_vs_oracle_sampled_frames": oracle_ok,
+    }
+    del outs_plain, plans, ws
+
+    if args.workload == "served":
+        peak_fps = len(frames) / t_batch
+        loads = {}
+        srv = serve.Server(bz=args.bz, hbm_budget=200e9, slots=4, max_batch=8, graph=True)
+        rng = np.random.default_rng(3)
+        for frac in (0.25, 0.5, 0.75, 1.0):
+            rate = frac * peak_fps
+            n_req = max(50, int(rate * args.seconds_per_load))
+            gaps = rng.exponential(1.0 / rate, n_req)
+            picks = rng.integers(0, len(frames), n_req)
+            srv.done = []
+            t0 = time.perf_counter()
+            arrivals = t0 + np.cumsum(gaps)
+            k = 0
+            while len(srv.done) < n_req:
+                now = time.perf_counter()
+                while k < n_req and arrivals[k] <= now:
+                    srv.submit(ins[picks[k]], arrival=float(arrivals[k]))
+                    k += 1
+                srv.step()
+            t1 = time.perf_counter()
+            lat = [1e3 * r.latency for r in srv.done]
+            served_clusters = sum(shapes[p][1] + shapes[p][2] for p in picks)
+            loads[f"{int(frac * 100)}%"] = {
+                "offered_frames_per_s": rate, "requests": n_req,
+                "p50_ms": serve.percentile(lat, 50), "p99_ms": serve.percentile(lat, 99),
+                "clusters_per_s": served_clusters / (t1 - t0)}
+            print(f"[bench] load {frac:.2f}: p50 {loads[f'{int(frac * 100)}%']['p50_ms']:.3f} ms, "
+                  f"p99 {loads[f'{int(frac * 100)}%']['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
+        srv.close()
+        line["served"] = loads
+        line["latency_ms"] = {"p50": loads["100%"]["p50_ms"], "p99": loads["100%"]["p99_ms"]}
     print(json.dumps(line), flush=True)
 
 

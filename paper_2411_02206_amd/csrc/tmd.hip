@@ -149,7 +149,8 @@ constexpr int kHRow = NBIN + kNKey;  // per-tile histogram row: bins, then keys
     /* workspace */                                                                           \
     Q uint32_t *start;   /* [nT + 1] first cluster of each track */                           \
     Q uint32_t *tilesum; /* [ntile] clusters per tile */                                      \
-    Q uint32_t *hist;    /* [ntile][NBIN] per-tile bin counts, then exclusive prefixes */     \
+    Q uint32_t *hist;    /* [ntile][kHRow] per-tile bin/key counts, then exclusive prefixes */ \
+    Q uint32_t *woff;    /* [ntile][4][NBIN] u16 pairs: bin offset of each wave in its tile */ \
     Q uint32_t *uin;     /* [NBIN] first unattached input entry of each bin */                \
     Q uint32_t *ueff;    /* [NBIN] unattached clusters decoded per bin */                     \
     Q uint4 *recs;       /* [nA] per-cluster records for the decode, stream order */          \
@@ -442,8 +443,12 @@ constexpr int kGroup = 4;  // chunks loaded together by a walk
 __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ fd,
                                                  const uint32_t *__restrict__ tile_frame)
 {
-    __shared__ uint32_t hist[kHRow];
+    // per-wave 16-bit bin counters (a wave's 64 tracks put at most 64*255
+    // clusters in one bin; the prefix of three waves stays below 2^16)
+    __shared__ uint32_t wcnt32[kTileWaves * NBIN / 2];
+    __shared__ uint32_t khist[kNKey];
     __shared__ WaveLds wl[kTileWaves];
+    uint16_t *wcnt = reinterpret_cast<uint16_t *>(wcnt32);
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
@@ -456,7 +461,8 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
     uint32_t before;
     block_excl_add(pre, &before);
 
-    for (uint32_t i = threadIdx.x; i < kHRow; i += kTile) hist[i] = 0;
+    for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wcnt32[i] = 0;
+    if (threadIdx.x < kNKey) khist[threadIdx.x] = 0;
     const uint32_t nc = t < F.nT ? F.ncls[t] : 0u;
     uint32_t tot;
     const uint32_t start = before + block_excl_add(nc, &tot);  // also syncs
@@ -492,7 +498,8 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
                 const uint32_t key = walk_chunk(lo, E, rd[u], sd[u], start_l, n_l, L, ws, fl, tl, clamped);
                 const uint32_t c = lo + lane;
                 if (c < E) {
-                    atomicAdd(&hist[key], 1u);
+                    const uint32_t idx = w * NBIN + key;
+                    atomicAdd(&wcnt32[idx >> 1], 1u << (16 * (idx & 1)));
                     // direction of this step for the track's class
                     const bool head = L.hm[lane] != 0xFFu;
                     if (clamped) atomicAnd(&L.cls[tl], 0u);
@@ -503,18 +510,33 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
                 }
             }
         }
+        fl = wave_or(fl);
+        if (lane == 0 && fl) atomicOr(F.status, fl);
         __builtin_amdgcn_wave_barrier();
         if (tw + lane < F.nT) {
             const uint32_t bits = L.cls[lane];
             const uint32_t cls = n_l <= 1 ? 0u : ((bits & 1u) ? 0u : ((bits & 2u) ? 1u : 2u));
             const uint32_t key = (uint32_t)L.hsec[lane] * 3u + cls;
             F.tkey[tw + lane] = (uint8_t)key;
-            atomicAdd(&hist[NBIN + key], 1u);
+            atomicAdd(&khist[key], 1u);
         }
     }
     __syncthreads();
+    // per bin: offsets of the waves inside the tile, and the tile total
     GLB uint32_t *dst = F.hist + (size_t)lt * kHRow;
-    for (uint32_t i = threadIdx.x; i < kHRow; i += kTile) dst[i] = hist[i];
+    for (uint32_t k = threadIdx.x; k < NBIN; k += kTile) {
+        uint32_t run = 0;
+        for (uint32_t i = 0; i < kTileWaves; i++) {
+            const uint32_t v = wcnt[i * NBIN + k];
+            wcnt[i * NBIN + k] = (uint16_t)run;
+            run += v;
+        }
+        dst[k] = run;
+    }
+    if (threadIdx.x < kNKey) dst[NBIN + threadIdx.x] = khist[threadIdx.x];
+    __syncthreads();
+    GLB uint32_t *wo = F.woff + (size_t)lt * (kTileWaves * NBIN / 2);
+    for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wo[i] = wcnt32[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -690,9 +712,8 @@ __global__ __launch_bounds__(kWave) void k_unattached(const FrameDesc *__restric
 // also places the tile's tracks in the decode schedule.  Within a bin the slot
 // order is the stream order (track, then cluster).  Block = one tile of 256
 // tracks, wave w walks tracks 64w..64w+63 of the tile (flat walk).  LDS:
-// per-wave bin counters (16 bit: a wave's 64 tracks put at most 64*255
-// clusters in one bin, and three waves' prefix stays below 2^16) and the
-// tile's bin bases.
+// per-wave bin counters, starting at the wave's in-tile offsets from the count
+// kernel, and the tile's bin bases.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd,
                                                 const uint32_t *__restrict__ tile_frame)
@@ -709,7 +730,9 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
     const GLB uint32_t *G = F.hist + (size_t)lt * kHRow;
     const uint32_t t = lt * kTile + threadIdx.x;
 
-    for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wcnt32[i] = 0;
+    const GLB uint32_t *wo = F.woff + (size_t)lt * (kTileWaves * NBIN / 2);
+    for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wcnt32[i] = wo[i];
+    for (uint32_t k = threadIdx.x; k < NBIN; k += kTile) base[k] = F.roff[k] + G[k];
     keys[threadIdx.x] = t < F.nT ? F.tkey[t] : (uint8_t)0xFF;
     const uint32_t my_start = t < F.nT ? F.start[t] : 0u;
     __syncthreads();
@@ -726,48 +749,9 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
     const bool wave_on = tw < F.nT;
     WaveLds &L = wl[w];
     uint32_t start_l = 0, n_l = 0, A = 0, E = 0;
-    uint32_t fl = 0;
+    if (wave_on) wave_setup(F, tw, L, my_start, start_l, n_l, A, E);
     if (wave_on) {
-        wave_setup(F, tw, L, my_start, start_l, n_l, A, E);
-        // pass 1: per-wave bin counts
-        WalkState ws{0, 0, 0};
-        for (uint32_t g = A; g < E; g += kWave * kGroup) {
-            int rd[kGroup];
-            uint32_t sd[kGroup];
-#pragma unroll
-            for (int u = 0; u < kGroup; u++) {
-                const uint32_t c = g + u * kWave + lane;
-                rd[u] = c < E ? (int)F.rdiff[c] : 0;
-                sd[u] = c < E ? (uint32_t)F.sdiff[c] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < kGroup; u++) {
-                const uint32_t lo = g + u * kWave;
-                if (lo >= E) break;
-                uint32_t tl;
-                bool clamped;
-                const uint32_t key = walk_chunk(lo, E, rd[u], sd[u], start_l, n_l, L, ws, fl, tl, clamped);
-                if (lo + lane < E) {
-                    const uint32_t idx = w * NBIN + key;
-                    atomicAdd(&wcnt32[idx >> 1], 1u << (16 * (idx & 1)));
-                }
-            }
-        }
-    }
-    __syncthreads();
-    // exclusive prefix over the waves; bin base of this tile
-    for (uint32_t k = threadIdx.x; k < NBIN; k += kTile) {
-        uint32_t run = 0;
-        for (uint32_t i = 0; i < kTileWaves; i++) {
-            uint32_t v = wcnt[i * NBIN + k];
-            wcnt[i * NBIN + k] = (uint16_t)run;
-            run += v;
-        }
-        base[k] = F.roff[k] + G[k];
-    }
-    __syncthreads();
-    if (wave_on) {
-        // pass 2: slots -> records
+        // slots -> records
         WalkState ws{0, 0, 0};
         uint32_t fl2 = 0;
         for (uint32_t g = A; g < E; g += kWave * kGroup) {
@@ -814,8 +798,6 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
             }
         }
     }
-    fl = wave_or(fl);
-    if (lane == 0 && fl) atomicOr(F.status, fl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1026,7 +1008,7 @@ const char *kStageNames[kStages] = {"setup", "tilesum", "count", "colscan", "off
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct FrameLayout {
-    size_t start, tilesum, hist, uin, ueff, recs, keyinfo, tkey, order;
+    size_t start, tilesum, hist, woff, uin, ueff, recs, keyinfo, tkey, order;
     uint32_t ntile, tile0;
 };
 
@@ -1050,11 +1032,12 @@ struct tmd_plan {
     bool desc_valid = false;
     hipEvent_t desc_done = nullptr;
     hipEvent_t done = nullptr;
+    hipStream_t side = nullptr;  // default priority, non-blocking
+    hipEvent_t fork = nullptr, join = nullptr;
     bool profiling = false;
     std::vector<std::vector<hipEvent_t>> prof_events;
-    hipGraphExec_t graph = nullptr;
-    hipStream_t graph_stream = nullptr;
-    void *graph_ws = nullptr;
+    hipGraphExec_t graph = nullptr;   // TMD_PLAN_GRAPH: the captured launch sequence
+    hipStream_t capture = nullptr;    // stream the graph is captured on
 };
 
 namespace {
@@ -1077,39 +1060,51 @@ bool aligned(const T *p)
     return ((uintptr_t)p % alignof(T)) == 0;
 }
 
+// Enqueue the pipeline on stream s.  The unattached kernel depends only on
+// the offsets kernel, so it runs on the plan's side stream, concurrently with
+// the rank and attached kernels; the main stream waits for it at the end.
+// With profiling on, every stage is bracketed by its own pair of events on
+// the stream it runs on.
 int launch_all(tmd_plan_t *P, hipStream_t s, bool record)
 {
     std::vector<hipEvent_t> ev;
     if (record) {
-        ev.resize(kStages + 1);
+        ev.resize(2 * kStages);
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-        HIP_TRY(hipEventRecord(ev[0], s));
     }
-    int st = 0;
-    auto mark = [&]() -> int {
-        if (record) {
-            if (hipEventRecord(ev[++st], s) != hipSuccess) return TMD_E_HIP;
-        }
-        return TMD_OK;
+    auto begin = [&](int st, hipStream_t q) -> int {
+        return (record && hipEventRecord(ev[2 * st], q) != hipSuccess) ? TMD_E_HIP : TMD_OK;
+    };
+    auto end = [&](int st, hipStream_t q) -> int {
+        return (record && hipEventRecord(ev[2 * st + 1], q) != hipSuccess) ? TMD_E_HIP : TMD_OK;
     };
     const uint32_t T = P->total_tiles;
+    hipStream_t s2 = P->side;
+    if (begin(0, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_setup, dim3(P->n_frames), dim3(kWave), 0, s, P->d_desc);
-    if (mark()) return TMD_E_HIP;
+    if (end(0, s) || begin(1, s)) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_tilesum, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
-    if (mark()) return TMD_E_HIP;
+    if (end(1, s) || begin(2, s)) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_count, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
-    if (mark()) return TMD_E_HIP;
+    if (end(2, s) || begin(3, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_colscan, dim3((kHRow + kWave - 1) / kWave, P->n_frames), dim3(kWave * kScanWaves), 0,
                        s, P->d_desc);
-    if (mark()) return TMD_E_HIP;
+    if (end(3, s) || begin(4, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_offsets, dim3(P->n_frames), dim3(kOffThreads), 0, s, P->d_desc);
-    if (mark()) return TMD_E_HIP;
-    hipLaunchKernelGGL(k_unattached, dim3(NBIN, P->n_frames), dim3(kWave), 0, s, P->d_desc);
-    if (mark()) return TMD_E_HIP;
+    if (end(4, s)) return TMD_E_HIP;
+    // fork: unattached decode on the side stream
+    HIP_TRY(hipEventRecord(P->fork, s));
+    HIP_TRY(hipStreamWaitEvent(s2, P->fork, 0));
+    if (begin(5, s2)) return TMD_E_HIP;
+    hipLaunchKernelGGL(k_unattached, dim3(NBIN, P->n_frames), dim3(kWave), 0, s2, P->d_desc);
+    if (end(5, s2)) return TMD_E_HIP;
+    HIP_TRY(hipEventRecord(P->join, s2));
+    if (begin(6, s)) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_rank, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
-    if (mark()) return TMD_E_HIP;
+    if (end(6, s) || begin(7, s)) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_attached, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame, P->d_geo);
-    if (mark()) return TMD_E_HIP;
+    if (end(7, s)) return TMD_E_HIP;
+    HIP_TRY(hipStreamWaitEvent(s, P->join, 0));
     HIP_TRY(hipGetLastError());
     if (record) P->prof_events.push_back(ev);
     return TMD_OK;
@@ -1166,6 +1161,11 @@ void tmd_free(tmd_plan_t *P)
     for (auto &v : P->prof_events)
         for (auto e : v) (void)hipEventDestroy(e);
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
+    if (P->side) (void)hipStreamSynchronize(P->side);
+    if (P->fork) (void)hipEventDestroy(P->fork);
+    if (P->join) (void)hipEventDestroy(P->join);
+    if (P->side) (void)hipStreamDestroy(P->side);
+    if (P->capture) (void)hipStreamDestroy(P->capture);
     if (P->desc_done) (void)hipEventDestroy(P->desc_done);
     if (P->done) (void)hipEventDestroy(P->done);
     if (P->d_geo) (void)hipFree(P->d_geo);
@@ -1203,6 +1203,7 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
         L.start = off;   off += align256(4 * ((size_t)S.n_tracks + 1));
         L.tilesum = off; off += align256(4 * (size_t)(L.ntile ? L.ntile : 1));
         L.hist = off;    off += align256(4 * (size_t)L.ntile * kHRow);
+        L.woff = off;    off += align256(2 * (size_t)L.ntile * kTileWaves * NBIN);
         L.uin = off;     off += align256(4 * (size_t)NBIN);
         L.ueff = off;    off += align256(4 * (size_t)NBIN);
         L.recs = off;    off += align256(16 * (size_t)(S.n_attached ? S.n_attached : 1));
@@ -1241,6 +1242,14 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
         }
         if (hipEventCreateWithFlags(&P->desc_done, hipEventDisableTiming) != hipSuccess) { rc = TMD_E_HIP; break; }
         if (hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if (hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if (hipEventCreateWithFlags(&P->join, hipEventDisableTiming) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if ((p->flags & TMD_PLAN_GRAPH) &&
+            hipStreamCreateWithFlags(&P->capture, hipStreamNonBlocking) != hipSuccess) {
+            rc = TMD_E_HIP;
+            break;
+        }
     } while (0);
     if (rc != TMD_OK) {
         tmd_free(P);
@@ -1296,6 +1305,7 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
         D.start = (uint32_t *)(ws + L.start);
         D.tilesum = (uint32_t *)(ws + L.tilesum);
         D.hist = (uint32_t *)(ws + L.hist);
+        D.woff = (uint32_t *)(ws + L.woff);
         D.uin = (uint32_t *)(ws + L.uin);
         D.ueff = (uint32_t *)(ws + L.ueff);
         D.recs = (uint4 *)(ws + L.recs);
@@ -1325,8 +1335,35 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
             P->last_desc = desc;
             P->desc_valid = true;
         }
-        rc = launch_all(P, s, P->profiling);
-        if (rc != TMD_OK) break;
+        if (P->params.flags & TMD_PLAN_GRAPH) {
+            // the kernels read only plan-owned buffers (descriptor table,
+            // tables, tile map), so one captured graph serves every call
+            if (!P->graph) {
+                hipGraph_t g = nullptr;
+                if (hipStreamBeginCapture(P->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                    rc = TMD_E_HIP;
+                    break;
+                }
+                rc = launch_all(P, P->capture, false);
+                hipError_t ec = hipStreamEndCapture(P->capture, &g);
+                if (rc != TMD_OK || ec != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    rc = TMD_E_HIP;
+                    break;
+                }
+                hipError_t ei = hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ei != hipSuccess) {
+                    P->graph = nullptr;
+                    rc = TMD_E_HIP;
+                    break;
+                }
+            }
+            if (hipGraphLaunch(P->graph, s) != hipSuccess) { rc = TMD_E_HIP; break; }
+        } else {
+            rc = launch_all(P, s, P->profiling);
+            if (rc != TMD_OK) break;
+        }
         if (hipMemcpyAsync(P->h_status, P->d_status, sizeof(uint32_t) * P->n_frames, hipMemcpyDeviceToHost,
                            s) != hipSuccess) {
             rc = TMD_E_HIP;
@@ -1361,10 +1398,10 @@ int tmd_stage_times(tmd_plan_t *P, double *ms, uint32_t n, uint32_t *calls)
     if (!P || (!ms && n)) return TMD_E_ARG;
     std::vector<double> acc(kStages, 0.0);
     for (auto &ev : P->prof_events) {
-        HIP_TRY(hipEventSynchronize(ev[kStages]));
         for (int i = 0; i < kStages; i++) {
+            HIP_TRY(hipEventSynchronize(ev[2 * i + 1]));
             float t = 0.0f;
-            HIP_TRY(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+            HIP_TRY(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
             acc[i] += t;
         }
     }

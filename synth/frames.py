@@ -322,10 +322,25 @@ def _quant_header_s(s):
     return np.clip(np.rint(np.asarray(s) * 32768.0), -32767, 32767).astype(np.int16)
 
 
-def make_frame(spec: FrameSpec) -> dict:
-    """Draw one compressed frame (dict of numpy arrays, see FIELDS)."""
-    rng = np.random.default_rng([spec.seed, spec.frame_index, 104729])
-    nt_total = spec.tracks()
+CHUNK_COLLISIONS = 25  # collisions per generation chunk (each chunk has its own random stream)
+
+
+def _chunks(spec):
+    """(chunk id, collisions, tracks) of a frame; chunks are generated
+    independently and concatenated in order."""
+    if spec.n_tracks > 0:
+        return [(0, max(spec.collisions, 1), spec.n_tracks)]
+    out = []
+    for c, lo in enumerate(range(0, spec.collisions, CHUNK_COLLISIONS)):
+        n = min(CHUNK_COLLISIONS, spec.collisions - lo)
+        out.append((c, n, n * spec.tracks_per_collision))
+    return out
+
+
+def _attached_chunk(args):
+    """Tracks and attached-cluster streams of one chunk of collisions."""
+    spec, chunk_id, ncoll, nt_total = args
+    rng = np.random.default_rng([spec.seed, spec.frame_index, chunk_id, 104729])
     n_loop = int(round(nt_total * spec.looper_frac))
     n_norm = nt_total - n_loop
     ncls, hdr, fl, steps, secstep = _normal_tracks(rng, spec, n_norm)
@@ -333,9 +348,9 @@ def make_frame(spec: FrameSpec) -> dict:
     jj = np.arange(NROW)[None, :]
     mask = jj < ncls[:, None]
 
-    # per-track collision assignment and times (in time bins)
-    ncoll = max(spec.collisions, 1)
-    span_bins = 100.0 * ncoll
+    # per-track collision assignment and times (in time bins); collision times
+    # are uniform over the whole frame's span
+    span_bins = 100.0 * max(spec.collisions, 1)
     coll_t = rng.uniform(0.0, span_bins, ncoll)
     legs = _looper_legs(rng, spec, n_loop) if n_loop > 0 else []
 
@@ -436,6 +451,25 @@ def make_frame(spec: FrameSpec) -> dict:
     fr["cls_time_res"] = np.clip(time_res, -32768, 32767).astype(np.int16)
     del pad_res, time_res
     fr["cls_qmax"], fr["cls_qtot"] = _charges(rng, nA)
+    return fr
+
+
+def make_frame(spec: FrameSpec, workers: int = 1) -> dict:
+    """Draw one compressed frame (dict of numpy arrays, see FIELDS).  With
+    workers > 1 the chunks of collisions are generated in forked worker
+    processes (call this before the process uses a GPU)."""
+    chunks = [(spec, c, n, t) for c, n, t in _chunks(spec)]
+    if workers > 1 and len(chunks) > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, len(chunks))) as pool:
+            parts = pool.map(_attached_chunk, chunks, chunksize=1)
+    else:
+        parts = [_attached_chunk(c) for c in chunks]
+    fr = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+    del parts
+    nA = int(fr["cls_qtot"].shape[0])
+    rng = np.random.default_rng([spec.seed, spec.frame_index, 1 << 20, 104729])
+    span_bins = 100.0 * max(spec.collisions, 1)
 
     # --- unattached clusters ---
     nU = spec.n_unattached if spec.n_unattached >= 0 else int(round(nA * spec.unattached_ratio))
