@@ -149,9 +149,15 @@ def main():
     roof = None
     if dom_bytes is not None and avg[dominant] > 0:
         ach = dom_bytes / (avg[dominant] * 1e-3) / 1e9
+        # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+        # copy-calibrated), only if taken with the current kernel source
+        from paper_2411_02206_amd import traffic as _traffic
+        summ = _traffic.load_summary(args.workload)
+        kt = summ["kernels"].get(f"k_{dominant}") if summ else None
         roof = {"bound": "hbm", "kernel": f"k_{dominant}", "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": dom_bytes, "avg_ms": round(avg[dominant], 4)}
+                "traffic": kt["traffic_bytes"] if kt else None, "bytes_per_launch": dom_bytes,
+                "avg_ms": round(avg[dominant], 4)}
     step_gbs = all_b / (ms_per_step * 1e-3) / 1e9
 
     cpu = None

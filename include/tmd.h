@@ -144,8 +144,10 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
  * planned) on `stream` (a hipStream_t; NULL = the default stream) and return.
  * The kernels: track start offsets (scan of trk_ncls), per-cluster (sector,row)
  * keys with per-tile counts, per-bin offsets, stable ranks, attached decode,
- * unattached decode, status reduction.  Calls on one plan must not overlap in
- * time (the status words are per plan).
+ * unattached decode, status reduction.  Calls on one plan are serialised on
+ * the device: a call enqueued on any stream waits for the previous call on the
+ * same plan to finish (they share the plan's descriptor table and status
+ * words), so independent work that should overlap needs plans of its own.
  * Errors: TMD_E_ARG (null plan/in/out/workspace, misaligned pointer),
  * TMD_E_CAPACITY, TMD_E_HIP.
  */

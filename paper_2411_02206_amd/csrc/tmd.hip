@@ -121,7 +121,11 @@ void build_geo(float bz, Geo *g)
 #endif
 
 // scheduling key of a track: home sector (sector of cluster 0) * 3 + direction
-// class (0: rows strictly increasing, 1: strictly decreasing, 2: other)
+// class (0: rows strictly increasing, 1: strictly decreasing, 2: other).  In
+// schedule order (key, index) the tracks of a wave are neighbours in the
+// stream, so their clusters on one row fill neighbouring output slots of one
+// bin; ordering by anything that separates stream neighbours (such as the rows
+// a track spans) scatters the decode's stores.
 constexpr int kNKey = NSEC * 3;
 constexpr int kHRow = NBIN + kNKey;  // per-tile histogram row: bins, then keys
 
@@ -154,8 +158,9 @@ constexpr int kHRow = NBIN + kNKey;  // per-tile histogram row: bins, then keys
     Q uint32_t *uin;     /* [NBIN] first unattached input entry of each bin */                \
     Q uint32_t *ueff;    /* [NBIN] unattached clusters decoded per bin */                     \
     Q uint4 *recs;       /* [nA] per-cluster records for the decode, stream order */          \
+    Q uint16_t *ckey;    /* [nA] (sector,row) bin of each attached cluster, stream order */    \
     Q uint32_t *keyinfo; /* [kNKey] tracks per scheduling key, [kNKey] key starts */          \
-    Q uint8_t *tkey;     /* [nT] scheduling key of each track */                              \
+    Q uint16_t *tkey;    /* [nT] scheduling key of each track */                              \
     Q uint32_t *order;   /* [nT] tracks sorted by (key, index): the decode's schedule */      \
     Q uint32_t *status;                                                                       \
     uint64_t cap; /* entries of the output cluster arrays; every store is checked */          \
@@ -252,6 +257,8 @@ __device__ __forceinline__ uint32_t track_len(uint32_t start, uint32_t ncls, uin
     uint32_t room = nA - start;
     return ncls < room ? ncls : room;
 }
+
+__device__ __forceinline__ uint32_t key_class(uint32_t key) { return key % 3u; }
 
 __device__ __forceinline__ void step_pos(int &sec, int &row, int rd, uint32_t sd)
 {
@@ -462,7 +469,7 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
     block_excl_add(pre, &before);
 
     for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wcnt32[i] = 0;
-    if (threadIdx.x < kNKey) khist[threadIdx.x] = 0;
+    for (uint32_t i = threadIdx.x; i < kNKey; i += kTile) khist[i] = 0;
     const uint32_t nc = t < F.nT ? F.ncls[t] : 0u;
     uint32_t tot;
     const uint32_t start = before + block_excl_add(nc, &tot);  // also syncs
@@ -497,17 +504,26 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
                 bool clamped;
                 const uint32_t key = walk_chunk(lo, E, rd[u], sd[u], start_l, n_l, L, ws, fl, tl, clamped);
                 const uint32_t c = lo + lane;
-                if (c < E) {
+                const bool act = c < E;
+                // direction of this step for the track's class: the bits it
+                // clears (1: not all up, 2: not all down)
+                uint32_t clr = 0;
+                if (act) {
+                    F.ckey[c] = (uint16_t)key;
                     const uint32_t idx = w * NBIN + key;
                     atomicAdd(&wcnt32[idx >> 1], 1u << (16 * (idx & 1)));
-                    // direction of this step for the track's class
                     const bool head = L.hm[lane] != 0xFFu;
-                    if (clamped) atomicAnd(&L.cls[tl], 0u);
-                    else if (!head) {
-                        if (!(rd[u] > 0)) atomicAnd(&L.cls[tl], ~1u);
-                        if (!(rd[u] < 0)) atomicAnd(&L.cls[tl], ~2u);
-                    }
+                    if (clamped) clr = 3u;
+                    else if (!head) clr = (rd[u] > 0 ? 0u : 1u) | (rd[u] < 0 ? 0u : 2u);
                 }
+                // one LDS atomic per run of lanes with the same track and bits
+                // (row_shr:1 within each row of 16 lanes; row starts count as
+                // run starts)
+                const uint32_t ptl = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)tl, 0x111, 0xf,
+                                                                           0xf, false);
+                const uint32_t pclr = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)clr, 0x111,
+                                                                            0xf, 0xf, false);
+                if (clr && (ptl != tl || pclr != clr)) atomicAnd(&L.cls[tl], ~clr);
             }
         }
         fl = wave_or(fl);
@@ -517,7 +533,7 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
             const uint32_t bits = L.cls[lane];
             const uint32_t cls = n_l <= 1 ? 0u : ((bits & 1u) ? 0u : ((bits & 2u) ? 1u : 2u));
             const uint32_t key = (uint32_t)L.hsec[lane] * 3u + cls;
-            F.tkey[tw + lane] = (uint8_t)key;
+            F.tkey[tw + lane] = (uint16_t)key;
             atomicAdd(&khist[key], 1u);
         }
     }
@@ -533,7 +549,7 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
         }
         dst[k] = run;
     }
-    if (threadIdx.x < kNKey) dst[NBIN + threadIdx.x] = khist[threadIdx.x];
+    for (uint32_t i = threadIdx.x; i < kNKey; i += kTile) dst[NBIN + i] = khist[i];
     __syncthreads();
     GLB uint32_t *wo = F.woff + (size_t)lt * (kTileWaves * NBIN / 2);
     for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wo[i] = wcnt32[i];
@@ -586,6 +602,7 @@ __global__ __launch_bounds__(kWave * kScanWaves) void k_colscan(const FrameDesc 
 // ---------------------------------------------------------------------------
 constexpr int kOffThreads = 1024;
 constexpr int kOffPer = (NBIN + kOffThreads - 1) / kOffThreads;  // 6
+constexpr int kKeyPer = (kNKey + kOffThreads - 1) / kOffThreads;
 
 __global__ __launch_bounds__(kOffThreads) void k_offsets(const FrameDesc *__restrict__ fd)
 {
@@ -652,13 +669,24 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(const FrameDesc *__rest
     if (threadIdx.x == kOffThreads - 1) F.roff[NBIN] = o;
 
     // start of each scheduling key in the decode order
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int key = 0; key < kNKey; key++) {
-            uint32_t c = F.keyinfo[key];
-            F.keyinfo[kNKey + key] = run;
-            run += c;
-        }
+    __syncthreads();  // part32 is reused
+    uint32_t kc[kKeyPer];
+    uint32_t kown = 0;
+    for (int i = 0; i < kKeyPer; i++) {
+        const uint32_t key = threadIdx.x * kKeyPer + i;
+        kc[i] = key < (uint32_t)kNKey ? F.keyinfo[key] : 0u;
+        kown += kc[i];
+    }
+    const uint32_t kinc = wave_incl_add(kown);
+    if (lane == kWave - 1) part32[w] = kinc;
+    __syncthreads();
+    uint32_t krun = 0;
+    for (uint32_t i = 0; i < w; i++) krun += part32[i];
+    krun += kinc - kown;
+    for (int i = 0; i < kKeyPer; i++) {
+        const uint32_t key = threadIdx.x * kKeyPer + i;
+        if (key < (uint32_t)kNKey) F.keyinfo[kNKey + key] = krun;
+        krun += kc[i];
     }
 }
 
@@ -711,18 +739,17 @@ __global__ __launch_bounds__(kWave) void k_unattached(const FrameDesc *__restric
 // residuals, charges and (sector,row) as one 16-byte record in stream order;
 // also places the tile's tracks in the decode schedule.  Within a bin the slot
 // order is the stream order (track, then cluster).  Block = one tile of 256
-// tracks, wave w walks tracks 64w..64w+63 of the tile (flat walk).  LDS:
-// per-wave bin counters, starting at the wave's in-tile offsets from the count
-// kernel, and the tile's bin bases.
+// tracks; wave w takes the clusters of tracks 64w..64w+63 of the tile (one
+// contiguous range of the stream, with the bins the count kernel stored), 64
+// per chunk.  LDS: per-wave 16-bit bin counters, starting at the wave's
+// in-tile offsets from the count kernel, and the tile's bin bases.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd,
                                                 const uint32_t *__restrict__ tile_frame)
 {
     __shared__ uint32_t wcnt32[kTileWaves * NBIN / 2];  // 16-bit counters, packed
     __shared__ uint32_t base[NBIN];
-    __shared__ uint8_t keys[kTile];
-    __shared__ WaveLds wl[kTileWaves];
-    uint16_t *wcnt = reinterpret_cast<uint16_t *>(wcnt32);
+    __shared__ uint16_t keys[kTile];
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
@@ -733,69 +760,62 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
     const GLB uint32_t *wo = F.woff + (size_t)lt * (kTileWaves * NBIN / 2);
     for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wcnt32[i] = wo[i];
     for (uint32_t k = threadIdx.x; k < NBIN; k += kTile) base[k] = F.roff[k] + G[k];
-    keys[threadIdx.x] = t < F.nT ? F.tkey[t] : (uint8_t)0xFF;
-    const uint32_t my_start = t < F.nT ? F.start[t] : 0u;
+    keys[threadIdx.x] = t < F.nT ? F.tkey[t] : (uint16_t)0xFFFF;
     __syncthreads();
 
     // decode schedule: tracks sorted by (key, index), stable
     if (t < F.nT) {
-        const uint8_t key = keys[threadIdx.x];
+        const uint16_t key = keys[threadIdx.x];
         uint32_t local = 0;
         for (uint32_t i = 0; i < threadIdx.x; i++) local += keys[i] == key;
         F.order[F.keyinfo[kNKey + key] + G[NBIN + key] + local] = t;
     }
 
     const uint32_t tw = lt * kTile + w * kWave;
-    const bool wave_on = tw < F.nT;
-    WaveLds &L = wl[w];
-    uint32_t start_l = 0, n_l = 0, A = 0, E = 0;
-    if (wave_on) wave_setup(F, tw, L, my_start, start_l, n_l, A, E);
-    if (wave_on) {
-        // slots -> records
-        WalkState ws{0, 0, 0};
-        uint32_t fl2 = 0;
-        for (uint32_t g = A; g < E; g += kWave * kGroup) {
-            int rd[kGroup];
-            uint32_t sd[kGroup], res[kGroup], q[kGroup];
+    if (tw >= F.nT) return;
+    // the wave's clusters: [start of track tw, start of track tw + 64) within nA
+    const uint32_t te = tw + kWave < F.nT ? tw + kWave : F.nT;
+    const uint32_t A = F.start[tw] < F.nA ? F.start[tw] : F.nA;
+    const uint32_t E = F.start[te] < F.nA ? F.start[te] : F.nA;
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+    for (uint32_t g = A; g < E; g += kWave * kGroup) {
+        uint32_t key[kGroup], res[kGroup], q[kGroup];
 #pragma unroll
-            for (int u = 0; u < kGroup; u++) {
-                const uint32_t c = g + u * kWave + lane;
-                const bool a = c < E;
-                rd[u] = a ? (int)F.rdiff[c] : 0;
-                sd[u] = a ? (uint32_t)F.sdiff[c] : 0u;
-                res[u] = a ? ((uint32_t)(uint16_t)F.pres[c] | ((uint32_t)(uint16_t)F.tres[c] << 16)) : 0u;
-                q[u] = a ? ((uint32_t)F.cqtot[c] | ((uint32_t)F.cqmax[c] << 16)) : 0u;
-            }
+        for (int u = 0; u < kGroup; u++) {
+            const uint32_t c = g + u * kWave + lane;
+            const bool a = c < E;
+            key[u] = a ? (uint32_t)F.ckey[c] : 0u;
+            res[u] = a ? ((uint32_t)(uint16_t)F.pres[c] | ((uint32_t)(uint16_t)F.tres[c] << 16)) : 0u;
+            q[u] = a ? ((uint32_t)F.cqtot[c] | ((uint32_t)F.cqmax[c] << 16)) : 0u;
+        }
 #pragma unroll
-            for (int u = 0; u < kGroup; u++) {
-                const uint32_t lo = g + u * kWave;
-                if (lo >= E) break;
-                uint32_t tl;
-                bool clamped;
-                const uint32_t key = walk_chunk(lo, E, rd[u], sd[u], start_l, n_l, L, ws, fl2, tl, clamped);
-                const uint32_t c = lo + lane;
-                const bool act = c < E;
-                // lanes holding the same key: intersect per-bit ballots
+        for (int u = 0; u < kGroup; u++) {
+            const uint32_t lo = g + u * kWave;
+            if (lo >= E) break;
+            const uint32_t c = lo + lane;
+            const bool act = c < E;
+            const uint32_t k = key[u] < (uint32_t)NBIN ? key[u] : 0u;
+            const uint32_t idx = w * NBIN + k;
+            const uint32_t sh = (idx & 1u) * 16u;
+            // count this cluster; the returned value is its rank if no other
+            // lane of the chunk has the same bin
+            uint32_t r = 0, fin = 0;
+            if (act) r = (atomicAdd(&wcnt32[idx >> 1], 1u << sh) >> sh) & 0xFFFFu;
+            __builtin_amdgcn_wave_barrier();
+            if (act) fin = (wcnt32[idx >> 1] >> sh) & 0xFFFFu;
+            if (__ballot(act && fin - r != 1u)) {
+                // some bin occurs more than once in the chunk: rank those
+                // lanes in lane (= stream) order
                 uint64_t same = __ballot(act);
 #pragma unroll
                 for (int bit = 0; bit < 13; bit++) {
-                    const uint64_t m = __ballot(act && ((key >> bit) & 1u));
-                    same &= ((key >> bit) & 1u) ? m : ~m;
+                    const uint64_t m = __ballot(act && ((k >> bit) & 1u));
+                    same &= ((k >> bit) & 1u) ? m : ~m;
                 }
-                const uint64_t lt_mask = (1ull << lane) - 1ull;
-                const uint32_t below = (uint32_t)__popcll(same & lt_mask);
-                const uint32_t slot_idx = w * NBIN + key;
-                uint32_t r = 0;
-                if (act) r = wcnt[slot_idx];
-                // every lane reads its counter before any lane updates one
-                __builtin_amdgcn_wave_barrier();
-                if (act) {
-                    const uint32_t o = base[key] + r + below;
-                    F.recs[c] = make_uint4(o, res[u], q[u], (key % NROW) | ((key / NROW) << 8));
-                    if ((same >> lane) == 1ull) wcnt[slot_idx] = (uint16_t)(r + below + 1);
-                }
-                __builtin_amdgcn_wave_barrier();
+                r = fin - (uint32_t)__popcll(same) + (uint32_t)__popcll(same & lt_mask);
             }
+            if (act) F.recs[c] = make_uint4(base[k] + r, res[u], q[u], (k % NROW) | ((k / NROW) << 8));
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }
@@ -805,9 +825,10 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
 // (home sector, direction class, index).  A wave whose tracks all move
 // outward (inward) advances row-synchronously: each step processes the lanes
 // whose next cluster lies on the lowest (highest) pending row, so the lanes
-// of a step write neighbouring slots of the same bin.  Other waves advance one
-// cluster per lane per step.  The order of steps never changes a result: each
-// track is decoded cluster after cluster either way.
+// of a step write neighbouring slots of the same bin and read the same table
+// row.  Other waves advance one cluster per lane per step.  The order of steps
+// never changes a result: each track is decoded cluster after cluster either
+// way.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float clamp_snp(float v, float smax, uint32_t &fl)
 {
@@ -847,11 +868,24 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v)
     return readlane(v, kWave - 1);
 }
 
+// Record staging: each lane keeps a ring of kRing records of its track in LDS.
+// The decode runs in blocks of kBlk steps; at each block boundary the records
+// loaded (into registers) at the previous boundary enter the ring, the block's
+// decoded clusters (staged in LDS) are stored, and the next records are
+// loaded.  Between boundaries the decode issues no global memory instruction,
+// so no step waits for memory: every load and store has a whole block to
+// complete.  A lane holds at least kBlk unread records at every boundary (or
+// all that remain), enough for the kBlk steps that follow.
+constexpr int kBlk = 4;
+constexpr int kRing = 2 * kBlk;
+
 __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict__ fd,
                                                     const uint32_t *__restrict__ tile_frame,
                                                     const Geo *__restrict__ geo_g)
 {
     __shared__ Geo geo;
+    __shared__ uint4 ring[kTileWaves][kRing][kWave];
+    __shared__ uint2 stg[kTileWaves][kBlk][kWave];  // decoded (time, pad) of the block's clusters
     {
         const uint32_t *s = reinterpret_cast<const uint32_t *>(geo_g);
         uint32_t *d = reinterpret_cast<uint32_t *>(&geo);
@@ -861,6 +895,7 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t slot = (tile - F.tile0) * kTile + threadIdx.x;
+    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     uint32_t fl = 0;
     uint32_t n = 0, c0 = 0, cls = 2;
     int sec = 0, row = 0;
@@ -873,7 +908,7 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
         const uint32_t ncls = F.ncls[t];
         c0 = F.start[t];
         n = track_len(c0, ncls, F.nA);
-        cls = F.tkey[t] % 3u;
+        cls = key_class(F.tkey[t]);
         if (ncls == 0) fl |= TMD_F_HDR;
         HeaderPos h = header_pos(F.sec0[t], F.row0[t]);
         fl |= h.flags;
@@ -895,93 +930,139 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
     const uint64_t dsc = __ballot(n > 0 && cls == 1);
     const uint32_t mode = asc == any_live ? 0u : (dsc == any_live ? 1u : 2u);
 
-    // records of the next two clusters are kept in flight
-    uint4 cur = make_uint4(0, 0, 0, 0), nxt = make_uint4(0, 0, 0, 0);
-    if (n > 0) cur = F.recs[c0];
-    if (n > 1) nxt = F.recs[c0 + 1];
-    uint32_t j = 0;
-    // every step decodes at least one cluster, so 64 * 255 steps always suffice
-    for (uint32_t step = 0; step < (uint32_t)kWave * 256u; step++) {
-        const bool live = j < n;
-        if (__ballot(live) == 0) break;
-        bool ready = live;
-        if (mode != 2) {
-            // rows 0..151; the descending mode works on 255 - row.  The minimum
-            // is taken with all lanes active (it reads other lanes).
-            const uint32_t rr = (cur.w & 0xFFu);
-            const uint32_t v = live ? (mode == 0 ? rr : 255u - rr) : 0xFFFFFFFFu;
-            const uint32_t m = wave_min(v);
-            ready = live && v == m;
-        }
-        if (ready) {
-            const uint4 rec = cur;
-            cur = nxt;
-            if (j + 2 < n) nxt = F.recs[c0 + j + 2];
-            const uint32_t o = rec.x;
-            const uint16_t qt = (uint16_t)(rec.z & 0xFFFFu), qm = (uint16_t)(rec.z >> 16);
-            if (j == 0) {
-                if (o < F.cap) {
-                    F.otime[o] = (uint32_t)t0;
-                    F.opad[o] = pad0;
-                    F.oqtot[o] = qt;
-                    F.oqmax[o] = qm;
-                }
-            } else {
-                const int nsec = (int)((rec.w >> 8) & 0xFFu);
-                int d = nsec % 18 - sec % 18;
-                d = d < 0 ? d + 18 : d;
-                if (d != 0) {
-                    const float ca = geo.cosb[d], sa = geo.sinb[d];
-                    const float cs = sqrtf((1.0f - s) * (1.0f + s));
-                    const float xn = (x * ca) + (y * sa);
-                    const float yn = (y * ca) - (x * sa);
-                    const float sn = (s * ca) - (cs * sa);
-                    const float cn = (cs * ca) + (s * sa);
-                    if (!(cn > 0.0f)) fl |= TMD_F_ROT;
-                    x = xn;
-                    y = yn;
-                    s = clamp_snp(sn, smax, fl);
-                    sec = nsec;
-                }
-                row = (int)(rec.w & 0xFFu);
-                const RowGeo R = geo.row[row];
-                const float dx = R.x - x;
-                const float s1 = clamp_snp(s + (k * dx), smax, fl);
-                const float a0 = sqrtf((1.0f - s) * (1.0f + s));
-                const float a1 = sqrtf((1.0f - s1) * (1.0f + s1));
-                const float dydx = (s + s1) / (a0 + a1);
-                y = y + (dx * dydx);
-                z = z + (tgl * (dx * sqrtf(1.0f + (dydx * dydx))));
-                s = s1;
-                x = R.x;
-                const int32_t P = sat_i32(rintf(((y * R.inv_pw) + R.padoff) * 32.0f));
-                const int32_t T = sat_i32(rintf(z * geo.inv_vd32));
-                const int32_t pres = (int32_t)(int16_t)(rec.y & 0xFFFFu);
-                const int32_t tres = (int32_t)(int16_t)(rec.y >> 16);
-                int32_t padq = P + pres;
-                fl |= (padq < 0 || padq > 65535) ? TMD_F_PAD : 0u;
-                padq = padq < 0 ? 0 : (padq > 65535 ? 65535 : padq);
-                int32_t timeq = t0 + T + tres;
-                fl |= (timeq < 0 || timeq > (int32_t)kTimeLim - 1) ? TMD_F_TIME : 0u;
-                timeq = timeq < 0 ? 0 : (timeq > (int32_t)kTimeLim - 1 ? (int32_t)kTimeLim - 1 : timeq);
-                if (o < F.cap) {
-                    F.otime[o] = (uint32_t)timeq;
-                    F.opad[o] = (uint16_t)padq;
-                    F.oqtot[o] = qt;
-                    F.oqmax[o] = qm;
-                }
-                const float nuy = (float)pres * R.pwq;
-                const float nuz = (float)tres * geo.vdq;
-                y = y + nuy;
-                z = z + nuz;
-                s = clamp_snp(s + (nuy * R.ks), smax, fl);
-                tgl = tgl + (nuz * R.kt);
+    // first records straight into the ring
+    uint32_t L = n < (uint32_t)kRing ? n : (uint32_t)kRing;  // records [0, L) have entered the ring
+    {
+        uint4 first[kRing];
+#pragma unroll
+        for (int i = 0; i < kRing; i++) first[i] = (uint32_t)i < L ? F.recs[c0 + i] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < kRing; i++)
+            if ((uint32_t)i < L) ring[w][i][lane] = first[i];
+    }
+    uint4 nb[kBlk];  // records [L, L + m), loaded at the last boundary
+#pragma unroll
+    for (int i = 0; i < kBlk; i++) nb[i] = make_uint4(0, 0, 0, 0);
+    uint32_t m = 0;
+    uint4 cur = make_uint4(0, 0, 0, 0);  // record j (valid while j < L)
+    if (L > 0) cur = ring[w][0][lane];
+    uint32_t j = 0, jb = 0;  // next record; first record of the block
+    // of two consecutive blocks at least one decodes a cluster (a block in
+    // which no lane has a record in its ring refills them), so 2 * 64 * 255
+    // blocks always suffice
+    for (uint32_t blk = 0; blk < 2u * (uint32_t)kWave * 256u; blk++) {
+        for (int st = 0; st < kBlk; st++) {
+            const bool live = j < L;
+            if (__ballot(live) == 0) break;
+            bool ready = live;
+            if (mode != 2) {
+                // rows 0..151; the descending mode works on 255 - row.  The minimum
+                // is taken with all lanes active (it reads other lanes).
+                const uint32_t rr = (cur.w & 0xFFu);
+                const uint32_t v = live ? (mode == 0 ? rr : 255u - rr) : 0xFFFFFFFFu;
+                const uint32_t mn = wave_min(v);
+                ready = live && v == mn;
             }
-            j++;
+            if (ready) {
+                const uint4 rec = cur;
+                uint32_t otime = (uint32_t)t0, opad = pad0;
+                if (j > 0) {
+                    const int nsec = (int)((rec.w >> 8) & 0xFFu);
+                    int d = nsec % 18 - sec % 18;
+                    d = d < 0 ? d + 18 : d;
+                    if (d != 0) {
+                        const float ca = geo.cosb[d], sa = geo.sinb[d];
+                        const float cs = sqrtf((1.0f - s) * (1.0f + s));
+                        const float xn = (x * ca) + (y * sa);
+                        const float yn = (y * ca) - (x * sa);
+                        const float sn = (s * ca) - (cs * sa);
+                        const float cn = (cs * ca) + (s * sa);
+                        if (!(cn > 0.0f)) fl |= TMD_F_ROT;
+                        x = xn;
+                        y = yn;
+                        s = clamp_snp(sn, smax, fl);
+                        sec = nsec;
+                    }
+                    row = (int)(rec.w & 0xFFu);
+                    const RowGeo R = geo.row[row];
+                    const float dx = R.x - x;
+                    const float s1 = clamp_snp(s + (k * dx), smax, fl);
+                    const float a0 = sqrtf((1.0f - s) * (1.0f + s));
+                    const float a1 = sqrtf((1.0f - s1) * (1.0f + s1));
+                    const float dydx = (s + s1) / (a0 + a1);
+                    y = y + (dx * dydx);
+                    z = z + (tgl * (dx * sqrtf(1.0f + (dydx * dydx))));
+                    s = s1;
+                    x = R.x;
+                    const int32_t P = sat_i32(rintf(((y * R.inv_pw) + R.padoff) * 32.0f));
+                    const int32_t T = sat_i32(rintf(z * geo.inv_vd32));
+                    const int32_t pres = (int32_t)(int16_t)(rec.y & 0xFFFFu);
+                    const int32_t tres = (int32_t)(int16_t)(rec.y >> 16);
+                    int32_t padq = P + pres;
+                    fl |= (padq < 0 || padq > 65535) ? TMD_F_PAD : 0u;
+                    padq = padq < 0 ? 0 : (padq > 65535 ? 65535 : padq);
+                    int32_t timeq = t0 + T + tres;
+                    fl |= (timeq < 0 || timeq > (int32_t)kTimeLim - 1) ? TMD_F_TIME : 0u;
+                    timeq = timeq < 0 ? 0 : (timeq > (int32_t)kTimeLim - 1 ? (int32_t)kTimeLim - 1 : timeq);
+                    otime = (uint32_t)timeq;
+                    opad = (uint32_t)padq;
+                    const float nuy = (float)pres * R.pwq;
+                    const float nuz = (float)tres * geo.vdq;
+                    y = y + nuy;
+                    z = z + nuz;
+                    s = clamp_snp(s + (nuy * R.ks), smax, fl);
+                    tgl = tgl + (nuz * R.kt);
+                }
+                stg[w][j - jb][lane] = make_uint2(otime, opad);
+                j++;
+                if (j < L) cur = ring[w][j % kRing][lane];
+            }
         }
+        // block boundary.  Records loaded at the last boundary enter the ring:
+        // they end below jb + kRing (refill bound below), so their slots are
+        // not those of records [jb, L), which hold this block's decoded
+        // clusters (stored next) and the unread ones.
+        const bool starved = j == L;
+#pragma unroll
+        for (int i = 0; i < kBlk; i++)
+            if ((uint32_t)i < m) ring[w][(L + i) % kRing][lane] = nb[i];
+        L += m;
+        if (starved && j < L) cur = ring[w][j % kRing][lane];
+        // store the block's clusters: slot and charges from the ring, time and
+        // pad from the staging area
+        const uint32_t done = j - jb;
+        uint4 r[kBlk];
+        uint2 o[kBlk];
+#pragma unroll
+        for (int i = 0; i < kBlk; i++) {  // all reads first: one LDS round trip
+            r[i] = ring[w][(jb + i) % kRing][lane];
+            o[i] = stg[w][i][lane];
+        }
+#pragma unroll
+        for (int i = 0; i < kBlk; i++) {
+            if ((uint32_t)i < done && r[i].x < F.cap) {
+                F.otime[r[i].x] = o[i].x;
+                F.opad[r[i].x] = (uint16_t)o[i].y;
+                F.oqtot[r[i].x] = (uint16_t)(r[i].z & 0xFFFFu);
+                F.oqmax[r[i].x] = (uint16_t)(r[i].z >> 16);
+            }
+        }
+        jb = j;
+        // next records: at most kBlk, and no more than the ring can take
+        // without overwriting a record >= j (records [j, L + m) span at most
+        // kRing slots), so at the next boundary the ring again holds at least
+        // kBlk unread records or all that remain
+        m = n - L;
+        if (m > (uint32_t)kBlk) m = kBlk;
+        const uint32_t room = (uint32_t)kRing - (L - j);
+        if (m > room) m = room;
+#pragma unroll
+        for (int i = 0; i < kBlk; i++)
+            if ((uint32_t)i < m) nb[i] = F.recs[c0 + L + i];
+        if (__ballot(j < n) == 0) break;
     }
     fl = wave_or(fl);
-    if (lane_id() == 0 && fl) atomicOr(F.status, fl);
+    if (lane == 0 && fl) atomicOr(F.status, fl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1008,7 +1089,7 @@ const char *kStageNames[kStages] = {"setup", "tilesum", "count", "colscan", "off
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct FrameLayout {
-    size_t start, tilesum, hist, woff, uin, ueff, recs, keyinfo, tkey, order;
+    size_t start, tilesum, hist, woff, uin, ueff, recs, ckey, keyinfo, tkey, order;
     uint32_t ntile, tile0;
 };
 
@@ -1032,6 +1113,7 @@ struct tmd_plan {
     bool desc_valid = false;
     hipEvent_t desc_done = nullptr;
     hipEvent_t done = nullptr;
+    bool called = false;  // `done` has been recorded at least once
     hipStream_t side = nullptr;  // default priority, non-blocking
     hipEvent_t fork = nullptr, join = nullptr;
     bool profiling = false;
@@ -1207,8 +1289,9 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
         L.uin = off;     off += align256(4 * (size_t)NBIN);
         L.ueff = off;    off += align256(4 * (size_t)NBIN);
         L.recs = off;    off += align256(16 * (size_t)(S.n_attached ? S.n_attached : 1));
+        L.ckey = off;    off += align256(2 * (size_t)(S.n_attached ? S.n_attached : 1));
         L.keyinfo = off; off += align256(4 * (size_t)(2 * kNKey));
-        L.tkey = off;    off += align256((size_t)(S.n_tracks ? S.n_tracks : 1));
+        L.tkey = off;    off += align256(2 * (size_t)(S.n_tracks ? S.n_tracks : 1));
         L.order = off;   off += align256(4 * (size_t)(S.n_tracks ? S.n_tracks : 1));
         P->layout.push_back(L);
     }
@@ -1309,8 +1392,9 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
         D.uin = (uint32_t *)(ws + L.uin);
         D.ueff = (uint32_t *)(ws + L.ueff);
         D.recs = (uint4 *)(ws + L.recs);
+        D.ckey = (uint16_t *)(ws + L.ckey);
         D.keyinfo = (uint32_t *)(ws + L.keyinfo);
-        D.tkey = (uint8_t *)(ws + L.tkey);
+        D.tkey = (uint16_t *)(ws + L.tkey);
         D.order = (uint32_t *)(ws + L.order);
         D.status = P->d_status + f;
         D.cap = O.capacity;
@@ -1322,6 +1406,9 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
     if (cur != P->device) HIP_TRY(hipSetDevice(P->device));
     int rc = TMD_OK;
     do {
+        // calls on one plan share its descriptor table and status words:
+        // a call issued on another stream starts after the previous one ends
+        if (P->called && hipStreamWaitEvent(s, P->done, 0) != hipSuccess) { rc = TMD_E_HIP; break; }
         const size_t dbytes = sizeof(FrameDescHost) * P->n_frames;
         if (!P->desc_valid || memcmp(desc.data(), P->last_desc.data(), dbytes) != 0) {
             // the staging buffer may still feed the previous upload
@@ -1370,6 +1457,7 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
             break;
         }
         if (hipEventRecord(P->done, s) != hipSuccess) { rc = TMD_E_HIP; break; }
+        P->called = true;
     } while (0);
     if (cur != P->device) (void)hipSetDevice(cur);
     return rc;

@@ -9,7 +9,9 @@ batches are still running overlap with them on the device.  A request's
 latency runs from its arrival to the completion event of its batch.
 
 All decoding is done by libtmd (through paper_2411_02206_amd.Plan); this
-module only schedules.  Plans are cached by their tuple of frame shapes.
+module only schedules.  Plans are cached per slot by their tuple of frame
+shapes: calls on one plan are serialised by the library, so slots never share
+one.
 """
 import collections
 import threading
@@ -108,8 +110,8 @@ class Server:
         return r
 
     # -- scheduler -----------------------------------------------------------
-    def _plan(self, shapes):
-        key = tuple(shapes)
+    def _plan(self, slot, shapes):
+        key = (slot, tuple(shapes))
         p = self._plans.get(key)
         if p is not None:
             self._plans.move_to_end(key)
@@ -165,7 +167,7 @@ class Server:
         torch = self._torch
         stream = self._streams[slot]
         shapes = [r.shape for r in batch]
-        plan = self._plan(shapes)
+        plan = self._plan(slot, shapes)
         with torch.cuda.stream(stream):
             ins = [r.frame if r.on_device else to_device(r.frame, self.device) for r in batch]
             outs = [alloc_out(r.shape, self.device) for r in batch]
