@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and check")
     ap.add_argument("--frames", type=int, default=64, help="frames of the batched/served workloads")
     ap.add_argument("--seconds-per-load", type=float, default=2.0, help="served: arrival window per load")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="forked processes generating the synthetic frames (1 under a profiler that "
+                         "initialises the GPU before the program starts)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build decodes on one GPU only; --gpus {args.gpus} is not supported "
@@ -94,7 +97,7 @@ def main():
 
     spec = synth.spec_for(args.workload)
     t = time.perf_counter()
-    frame = synth.make_frame(spec, workers=16)  # forked workers, before any GPU use
+    frame = synth.make_frame(spec, workers=args.gen_workers)  # forked workers, before any GPU use
     gen_s = time.perf_counter() - t
     nT, nA, nU = tmd.frame_shape(frame)
     n_clusters = nA + nU
@@ -209,7 +212,7 @@ def run_batched(args):
     import synth
     specs = synth.batch_specs(args.workload, n_frames=args.frames)
     t = time.perf_counter()
-    frames = make_frames(specs)
+    frames = make_frames(specs, workers=args.gen_workers)
     gen_s = time.perf_counter() - t
 
     import numpy as np

@@ -131,7 +131,9 @@ constexpr int kHRow = NBIN + kNKey;  // per-tile histogram row: bins, then keys
 
 // per-cluster record written by the rank kernel for the decode kernel (16 B):
 // x = output slot, y = pad residual (low 16, signed) | time residual (high 16),
-// z = qTot (low 16) | qMax (high 16), w = row (bits 0-7) | sector (bits 8-15)
+// z = qTot (low 16) | qMax (high 16), w = row (bits 0-7) | rotation (bits
+// 8-15: the cluster's sector step modulo 18, the number of 20-degree turns
+// from the previous cluster's frame)
 
 // one field list, two views: FrameDesc (device, global pointers) and
 // FrameDescHost (host, plain pointers) have the same layout
@@ -229,6 +231,28 @@ __device__ uint32_t block_excl_add(uint32_t v, uint32_t *tot)
     __syncthreads();
     *tot = all;
     return base + inc - v;
+}
+
+// Copy n 16-byte vectors from global memory to LDS, all loads of a batch in
+// flight before the first LDS write (a load-then-store loop would wait for
+// every load in turn).
+template <int BATCH, int NT>
+__device__ __forceinline__ void copy_to_lds(uint4 *dst, const GLB uint4 *src, uint32_t n)
+{
+    for (uint32_t i0 = threadIdx.x; i0 < n; i0 += BATCH * NT) {
+        uint4 v[BATCH];
+#pragma unroll
+        for (int b = 0; b < BATCH; b++) {
+            const uint32_t i = i0 + b * NT;
+            v[b] = make_uint4(0, 0, 0, 0);
+            if (i < n) v[b] = src[i];
+        }
+#pragma unroll
+        for (int b = 0; b < BATCH; b++) {
+            const uint32_t i = i0 + b * NT;
+            if (i < n) dst[i] = v[b];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -487,22 +511,31 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
         wave_setup(F, tw, L, start, start_l, n_l, A, E);
         WalkState ws{0, 0, 0};
         uint32_t fl = 0;
-        for (uint32_t g = A; g < E; g += kWave * kGroup) {
+        // groups of kGroup chunks; two groups alternate so that the loads of
+        // one are in flight while the other is walked.  Loads are
+        // unconditional: lanes past E read cluster E - 1, and the walk ignores
+        // their steps.
+        struct Group {
             int rd[kGroup];
             uint32_t sd[kGroup];
+        };
+        auto load = [&](uint32_t g, Group &P) {
 #pragma unroll
             for (int u = 0; u < kGroup; u++) {
                 const uint32_t c = g + u * kWave + lane;
-                rd[u] = c < E ? (int)F.rdiff[c] : 0;
-                sd[u] = c < E ? (uint32_t)F.sdiff[c] : 0u;
+                const uint32_t cc = c < E ? c : E - 1;
+                P.rd[u] = (int)F.rdiff[cc];
+                P.sd[u] = (uint32_t)F.sdiff[cc];
             }
+        };
+        auto walk = [&](uint32_t g, const Group &P) {
 #pragma unroll
             for (int u = 0; u < kGroup; u++) {
                 const uint32_t lo = g + u * kWave;
                 if (lo >= E) break;
                 uint32_t tl;
                 bool clamped;
-                const uint32_t key = walk_chunk(lo, E, rd[u], sd[u], start_l, n_l, L, ws, fl, tl, clamped);
+                const uint32_t key = walk_chunk(lo, E, P.rd[u], P.sd[u], start_l, n_l, L, ws, fl, tl, clamped);
                 const uint32_t c = lo + lane;
                 const bool act = c < E;
                 // direction of this step for the track's class: the bits it
@@ -514,7 +547,7 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
                     atomicAdd(&wcnt32[idx >> 1], 1u << (16 * (idx & 1)));
                     const bool head = L.hm[lane] != 0xFFu;
                     if (clamped) clr = 3u;
-                    else if (!head) clr = (rd[u] > 0 ? 0u : 1u) | (rd[u] < 0 ? 0u : 2u);
+                    else if (!head) clr = (P.rd[u] > 0 ? 0u : 1u) | (P.rd[u] < 0 ? 0u : 2u);
                 }
                 // one LDS atomic per run of lanes with the same track and bits
                 // (row_shr:1 within each row of 16 lanes; row starts count as
@@ -525,6 +558,16 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
                                                                             0xf, 0xf, false);
                 if (clr && (ptl != tl || pclr != clr)) atomicAnd(&L.cls[tl], ~clr);
             }
+        };
+        constexpr uint32_t kStep = kWave * kGroup;
+        Group P0, P1;
+        if (A < E) load(A, P0);
+        for (uint32_t g = A; g < E; g += 2 * kStep) {
+            load(g + kStep, P1);
+            walk(g, P0);
+            if (g + kStep >= E) break;
+            load(g + 2 * kStep, P0);
+            walk(g + kStep, P1);
         }
         fl = wave_or(fl);
         if (lane == 0 && fl) atomicOr(F.status, fl);
@@ -561,6 +604,7 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
 // grid (ceil(kHRow/64), n_frames), block 1024 = 16 waves; lane = column
 // ---------------------------------------------------------------------------
 constexpr int kScanWaves = 16;
+constexpr int kColBatch = 8;
 
 __global__ __launch_bounds__(kWave * kScanWaves) void k_colscan(const FrameDesc *__restrict__ fd)
 {
@@ -571,9 +615,17 @@ __global__ __launch_bounds__(kWave * kScanWaves) void k_colscan(const FrameDesc 
     const uint32_t per = (F.ntile + kScanWaves - 1) / kScanWaves;
     const uint32_t a = w * per;
     const uint32_t b = min(a + per, F.ntile);
+    // loads in batches of kColBatch, so that a batch is in flight together
     uint32_t sum = 0;
-    if (k < kHRow)
-        for (uint32_t i = a; i < b; i++) sum += F.hist[(size_t)i * kHRow + k];
+    if (k < kHRow) {
+        for (uint32_t i0 = a; i0 < b; i0 += kColBatch) {
+            uint32_t v[kColBatch];
+#pragma unroll
+            for (int u = 0; u < kColBatch; u++) v[u] = i0 + u < b ? F.hist[(size_t)(i0 + u) * kHRow + k] : 0u;
+#pragma unroll
+            for (int u = 0; u < kColBatch; u++) sum += v[u];
+        }
+    }
     part[w][lane] = sum;
     __syncthreads();
     uint32_t run = 0, total = 0;
@@ -583,11 +635,15 @@ __global__ __launch_bounds__(kWave * kScanWaves) void k_colscan(const FrameDesc 
         total += p;
     }
     if (k < kHRow) {
-        for (uint32_t i = a; i < b; i++) {
-            GLB uint32_t *h = F.hist + (size_t)i * kHRow + k;
-            uint32_t v = *h;
-            *h = run;
-            run += v;
+        for (uint32_t i0 = a; i0 < b; i0 += kColBatch) {
+            uint32_t v[kColBatch];
+#pragma unroll
+            for (int u = 0; u < kColBatch; u++) v[u] = i0 + u < b ? F.hist[(size_t)(i0 + u) * kHRow + k] : 0u;
+#pragma unroll
+            for (int u = 0; u < kColBatch; u++) {
+                if (i0 + u < b) F.hist[(size_t)(i0 + u) * kHRow + k] = run;
+                run += v[u];
+            }
         }
         if (w == 0) {
             if (k < NBIN) F.rna[k] = total;
@@ -749,26 +805,54 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
 {
     __shared__ uint32_t wcnt32[kTileWaves * NBIN / 2];  // 16-bit counters, packed
     __shared__ uint32_t base[NBIN];
-    __shared__ uint16_t keys[kTile];
+    __shared__ uint32_t kcnt[kTileWaves][kNKey];  // tracks per (wave, scheduling key)
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     const GLB uint32_t *G = F.hist + (size_t)lt * kHRow;
     const uint32_t t = lt * kTile + threadIdx.x;
+    static_assert(kNKey <= 128, "schedule keys are matched on 7 bits");
 
-    const GLB uint32_t *wo = F.woff + (size_t)lt * (kTileWaves * NBIN / 2);
-    for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wcnt32[i] = wo[i];
-    for (uint32_t k = threadIdx.x; k < NBIN; k += kTile) base[k] = F.roff[k] + G[k];
-    keys[threadIdx.x] = t < F.nT ? F.tkey[t] : (uint16_t)0xFFFF;
+    // the tile's in-tile wave offsets (16-byte aligned: 43776 bytes per tile)
+    constexpr uint32_t kWoffVec = kTileWaves * NBIN / 8;
+    copy_to_lds<(kWoffVec + kTile - 1) / kTile, kTile>(
+        reinterpret_cast<uint4 *>(wcnt32),
+        reinterpret_cast<const GLB uint4 *>(F.woff + (size_t)lt * (kTileWaves * NBIN / 2)), kWoffVec);
+    {
+        constexpr int kPer = (NBIN + kTile - 1) / kTile;
+        uint32_t ro[kPer], gg[kPer];
+#pragma unroll
+        for (int b = 0; b < kPer; b++) {
+            const uint32_t k = threadIdx.x + b * kTile;
+            ro[b] = k < NBIN ? F.roff[k] : 0u;
+            gg[b] = k < NBIN ? G[k] : 0u;
+        }
+#pragma unroll
+        for (int b = 0; b < kPer; b++) {
+            const uint32_t k = threadIdx.x + b * kTile;
+            if (k < NBIN) base[k] = ro[b] + gg[b];
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < kTileWaves * kNKey; i += kTile) (&kcnt[0][0])[i] = 0;
+    const bool tv = t < F.nT;
+    const uint32_t tk = tv ? (uint32_t)F.tkey[t] : 0u;
+    __syncthreads();
+    if (tv) atomicAdd(&kcnt[w][tk], 1u);
+    // rank among the wave's tracks with the same key (keys < 128: 7 bits)
+    uint64_t same = __ballot(tv);
+#pragma unroll
+    for (int bit = 0; bit < 7; bit++) {
+        const uint64_t m = __ballot(tv && ((tk >> bit) & 1u));
+        same &= ((tk >> bit) & 1u) ? m : ~m;
+    }
+    uint32_t local = (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
     __syncthreads();
 
     // decode schedule: tracks sorted by (key, index), stable
-    if (t < F.nT) {
-        const uint16_t key = keys[threadIdx.x];
-        uint32_t local = 0;
-        for (uint32_t i = 0; i < threadIdx.x; i++) local += keys[i] == key;
-        F.order[F.keyinfo[kNKey + key] + G[NBIN + key] + local] = t;
+    if (tv) {
+        for (uint32_t v = 0; v < w; v++) local += kcnt[v][tk];
+        F.order[F.keyinfo[kNKey + tk] + G[NBIN + tk] + local] = t;
     }
 
     const uint32_t tw = lt * kTile + w * kWave;
@@ -778,23 +862,35 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
     const uint32_t A = F.start[tw] < F.nA ? F.start[tw] : F.nA;
     const uint32_t E = F.start[te] < F.nA ? F.start[te] : F.nA;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    for (uint32_t g = A; g < E; g += kWave * kGroup) {
-        uint32_t key[kGroup], res[kGroup], q[kGroup];
+    // a group of kGroup chunks: its loads, then its ranks and records.  Two
+    // groups alternate so that the loads of one are in flight while the other
+    // is ranked.
+    // Loads are unconditional (lanes past E read cluster E - 1 and ignore it)
+    // and raw, so that nothing waits for them until the group is ranked.
+    struct Group {
+        uint32_t key[kGroup], sd[kGroup], pr[kGroup], tr[kGroup], qt[kGroup], qm[kGroup];
+    };
+    auto load = [&](uint32_t g, Group &P) {
 #pragma unroll
         for (int u = 0; u < kGroup; u++) {
             const uint32_t c = g + u * kWave + lane;
-            const bool a = c < E;
-            key[u] = a ? (uint32_t)F.ckey[c] : 0u;
-            res[u] = a ? ((uint32_t)(uint16_t)F.pres[c] | ((uint32_t)(uint16_t)F.tres[c] << 16)) : 0u;
-            q[u] = a ? ((uint32_t)F.cqtot[c] | ((uint32_t)F.cqmax[c] << 16)) : 0u;
+            const uint32_t cc = c < E ? c : E - 1;
+            P.key[u] = F.ckey[cc];
+            P.sd[u] = F.sdiff[cc];
+            P.pr[u] = (uint16_t)F.pres[cc];
+            P.tr[u] = (uint16_t)F.tres[cc];
+            P.qt[u] = F.cqtot[cc];
+            P.qm[u] = F.cqmax[cc];
         }
+    };
+    auto rank = [&](uint32_t g, const Group &P) {
 #pragma unroll
         for (int u = 0; u < kGroup; u++) {
             const uint32_t lo = g + u * kWave;
             if (lo >= E) break;
             const uint32_t c = lo + lane;
             const bool act = c < E;
-            const uint32_t k = key[u] < (uint32_t)NBIN ? key[u] : 0u;
+            const uint32_t k = P.key[u] < (uint32_t)NBIN ? P.key[u] : 0u;
             const uint32_t idx = w * NBIN + k;
             const uint32_t sh = (idx & 1u) * 16u;
             // count this cluster; the returned value is its rank if no other
@@ -814,9 +910,23 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
                 }
                 r = fin - (uint32_t)__popcll(same) + (uint32_t)__popcll(same & lt_mask);
             }
-            if (act) F.recs[c] = make_uint4(base[k] + r, res[u], q[u], (k % NROW) | ((k / NROW) << 8));
+            if (act) {
+                const uint32_t rot = P.sd[u] < 18u ? P.sd[u] : P.sd[u] % 18u;
+                F.recs[c] = make_uint4(base[k] + r, P.pr[u] | (P.tr[u] << 16), P.qt[u] | (P.qm[u] << 16),
+                                       (k % NROW) | (rot << 8));
+            }
             __builtin_amdgcn_wave_barrier();
         }
+    };
+    constexpr uint32_t kStep = kWave * kGroup;
+    Group P0, P1;
+    if (A < E) load(A, P0);
+    for (uint32_t g = A; g < E; g += 2 * kStep) {
+        load(g + kStep, P1);
+        rank(g, P0);
+        if (g + kStep >= E) break;
+        load(g + 2 * kStep, P0);
+        rank(g + kStep, P1);
     }
 }
 
@@ -879,57 +989,24 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v)
 constexpr int kBlk = 4;
 constexpr int kRing = 2 * kBlk;
 
-__global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict__ fd,
-                                                    const uint32_t *__restrict__ tile_frame,
-                                                    const Geo *__restrict__ geo_g)
-{
-    __shared__ Geo geo;
-    __shared__ uint4 ring[kTileWaves][kRing][kWave];
-    __shared__ uint2 stg[kTileWaves][kBlk][kWave];  // decoded (time, pad) of the block's clusters
-    {
-        const uint32_t *s = reinterpret_cast<const uint32_t *>(geo_g);
-        uint32_t *d = reinterpret_cast<uint32_t *>(&geo);
-        for (uint32_t i = threadIdx.x; i < sizeof(Geo) / 4; i += kTile) d[i] = s[i];
-    }
-    __syncthreads();
-    const uint32_t tile = blockIdx.x;
-    const FrameDesc F = fd[tile_frame[tile]];
-    const uint32_t slot = (tile - F.tile0) * kTile + threadIdx.x;
-    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
-    uint32_t fl = 0;
-    uint32_t n = 0, c0 = 0, cls = 2;
-    int sec = 0, row = 0;
-    int32_t t0 = 0;
-    uint16_t pad0 = 0;
-    float x = 0.0f, y = 0.0f, z = 0.0f, s = 0.0f, tgl = 0.0f, k = 0.0f;
-    const float smax = geo.snp_max;
-    if (slot < F.nT) {
-        const uint32_t t = F.order[slot];
-        const uint32_t ncls = F.ncls[t];
-        c0 = F.start[t];
-        n = track_len(c0, ncls, F.nA);
-        cls = key_class(F.tkey[t]);
-        if (ncls == 0) fl |= TMD_F_HDR;
-        HeaderPos h = header_pos(F.sec0[t], F.row0[t]);
-        fl |= h.flags;
-        sec = h.sec;
-        row = h.row;
-        uint32_t t0u = F.time0[t];
-        if (t0u >= kTimeLim) { fl |= TMD_F_TIME; t0u = kTimeLim - 1; }
-        t0 = (int32_t)t0u;
-        pad0 = F.pad0[t];
-        x = geo.row[row].x;
-        y = ((float)pad0 * 0x1p-5f - geo.row[row].padoff) * geo.row[row].pw;
-        s = clamp_snp((float)F.snp[t] * 0x1p-15f, smax, fl);
-        tgl = (float)F.tgl[t] * 0x1p-12f;
-        k = ((float)F.qpt[t] * 0x1p-10f) * geo.kb;
-    }
-    // wave mode: 0 rows ascending, 1 rows descending, 2 one cluster per step
-    const uint64_t any_live = __ballot(n > 0);
-    const uint64_t asc = __ballot(n > 0 && cls == 0);
-    const uint64_t dsc = __ballot(n > 0 && cls == 1);
-    const uint32_t mode = asc == any_live ? 0u : (dsc == any_live ? 1u : 2u);
+// per-lane decode state of one track
+struct LaneTrack {
+    float x, y, z, s, tgl, k;
+    int32_t t0;
+    uint32_t pad0, fl, n, c0;
+};
 
+// The decode loop of one wave.  MODE 0: rows ascending, 1: descending (both
+// row-synchronous), 2: one cluster per lane per step.  In modes 0 and 1 all
+// lanes processing a step are on one row, so its table entry is read once per
+// wave through the scalar cache.
+template <int MODE>
+__device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__restrict__ geo,
+                                              uint4 (*ring)[kWave], uint2 (*stg)[kWave], LaneTrack &T)
+{
+    const uint32_t lane = lane_id();
+    const float smax = geo->snp_max;
+    const uint32_t n = T.n, c0 = T.c0;
     // first records straight into the ring
     uint32_t L = n < (uint32_t)kRing ? n : (uint32_t)kRing;  // records [0, L) have entered the ring
     {
@@ -938,15 +1015,20 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
         for (int i = 0; i < kRing; i++) first[i] = (uint32_t)i < L ? F.recs[c0 + i] : make_uint4(0, 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < kRing; i++)
-            if ((uint32_t)i < L) ring[w][i][lane] = first[i];
+            if ((uint32_t)i < L) ring[i][lane] = first[i];
     }
     uint4 nb[kBlk];  // records [L, L + m), loaded at the last boundary
 #pragma unroll
     for (int i = 0; i < kBlk; i++) nb[i] = make_uint4(0, 0, 0, 0);
     uint32_t m = 0;
     uint4 cur = make_uint4(0, 0, 0, 0);  // record j (valid while j < L)
-    if (L > 0) cur = ring[w][0][lane];
-    uint32_t j = 0, jb = 0;  // next record; first record of the block
+    if (L > 0) cur = ring[0][lane];
+    uint32_t j = 0, jb = 0;       // next record; first record of the block
+    uint32_t vrow = 0xFFFFFFFFu;  // modes 0 and 1: the last row processed
+    float x = T.x, y = T.y, z = T.z, s = T.s, tgl = T.tgl;
+    const float k = T.k;
+    const int32_t t0 = T.t0;
+    uint32_t fl = T.fl;
     // of two consecutive blocks at least one decodes a cluster (a block in
     // which no lane has a record in its ring refills them), so 2 * 64 * 255
     // blocks always suffice
@@ -955,23 +1037,37 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
             const bool live = j < L;
             if (__ballot(live) == 0) break;
             bool ready = live;
-            if (mode != 2) {
-                // rows 0..151; the descending mode works on 255 - row.  The minimum
-                // is taken with all lanes active (it reads other lanes).
+            if (MODE != 2) {
+                // rows 0..151; the descending mode works on 255 - row.  The
+                // pending minimum is usually the row after the last one; only
+                // if no lane is there is the minimum taken over all lanes
+                // (with all lanes active: it reads other lanes).
                 const uint32_t rr = (cur.w & 0xFFu);
-                const uint32_t v = live ? (mode == 0 ? rr : 255u - rr) : 0xFFFFFFFFu;
-                const uint32_t mn = wave_min(v);
-                ready = live && v == mn;
+                const uint32_t v = live ? (MODE == 0 ? rr : 255u - rr) : 0xFFFFFFFFu;
+                vrow += 1u;
+                ready = live && v == vrow;
+                if (__ballot(ready) == 0) {
+                    vrow = wave_min(v);
+                    ready = live && v == vrow;
+                }
             }
             if (ready) {
                 const uint4 rec = cur;
-                uint32_t otime = (uint32_t)t0, opad = pad0;
+                uint32_t otime = (uint32_t)t0, opad = T.pad0;
                 if (j > 0) {
-                    const int nsec = (int)((rec.w >> 8) & 0xFFu);
-                    int d = nsec % 18 - sec % 18;
-                    d = d < 0 ? d + 18 : d;
+                    const uint32_t d = (rec.w >> 8) & 0xFFu;  // 0..17
                     if (d != 0) {
-                        const float ca = geo.cosb[d], sa = geo.sinb[d];
+                        // table entry through the scalar cache, once per
+                        // distinct d among the rotating lanes
+                        float ca = 0.0f, sa = 0.0f;
+                        for (;;) {
+                            const uint32_t ud = __builtin_amdgcn_readfirstlane(d);
+                            if (d == ud) {
+                                ca = geo->cosb[ud];
+                                sa = geo->sinb[ud];
+                                break;
+                            }
+                        }
                         const float cs = sqrtf((1.0f - s) * (1.0f + s));
                         const float xn = (x * ca) + (y * sa);
                         const float yn = (y * ca) - (x * sa);
@@ -981,10 +1077,9 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
                         x = xn;
                         y = yn;
                         s = clamp_snp(sn, smax, fl);
-                        sec = nsec;
                     }
-                    row = (int)(rec.w & 0xFFu);
-                    const RowGeo R = geo.row[row];
+                    const uint32_t row = rec.w & 0xFFu;
+                    const RowGeo R = geo->row[MODE != 2 ? __builtin_amdgcn_readfirstlane(row) : row];
                     const float dx = R.x - x;
                     const float s1 = clamp_snp(s + (k * dx), smax, fl);
                     const float a0 = sqrtf((1.0f - s) * (1.0f + s));
@@ -995,27 +1090,27 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
                     s = s1;
                     x = R.x;
                     const int32_t P = sat_i32(rintf(((y * R.inv_pw) + R.padoff) * 32.0f));
-                    const int32_t T = sat_i32(rintf(z * geo.inv_vd32));
+                    const int32_t Tq = sat_i32(rintf(z * geo->inv_vd32));
                     const int32_t pres = (int32_t)(int16_t)(rec.y & 0xFFFFu);
                     const int32_t tres = (int32_t)(int16_t)(rec.y >> 16);
                     int32_t padq = P + pres;
                     fl |= (padq < 0 || padq > 65535) ? TMD_F_PAD : 0u;
                     padq = padq < 0 ? 0 : (padq > 65535 ? 65535 : padq);
-                    int32_t timeq = t0 + T + tres;
+                    int32_t timeq = t0 + Tq + tres;
                     fl |= (timeq < 0 || timeq > (int32_t)kTimeLim - 1) ? TMD_F_TIME : 0u;
                     timeq = timeq < 0 ? 0 : (timeq > (int32_t)kTimeLim - 1 ? (int32_t)kTimeLim - 1 : timeq);
                     otime = (uint32_t)timeq;
                     opad = (uint32_t)padq;
                     const float nuy = (float)pres * R.pwq;
-                    const float nuz = (float)tres * geo.vdq;
+                    const float nuz = (float)tres * geo->vdq;
                     y = y + nuy;
                     z = z + nuz;
                     s = clamp_snp(s + (nuy * R.ks), smax, fl);
                     tgl = tgl + (nuz * R.kt);
                 }
-                stg[w][j - jb][lane] = make_uint2(otime, opad);
+                stg[j - jb][lane] = make_uint2(otime, opad);
                 j++;
-                if (j < L) cur = ring[w][j % kRing][lane];
+                if (j < L) cur = ring[j % kRing][lane];
             }
         }
         // block boundary.  Records loaded at the last boundary enter the ring:
@@ -1025,9 +1120,9 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
         const bool starved = j == L;
 #pragma unroll
         for (int i = 0; i < kBlk; i++)
-            if ((uint32_t)i < m) ring[w][(L + i) % kRing][lane] = nb[i];
+            if ((uint32_t)i < m) ring[(L + i) % kRing][lane] = nb[i];
         L += m;
-        if (starved && j < L) cur = ring[w][j % kRing][lane];
+        if (starved && j < L) cur = ring[j % kRing][lane];
         // store the block's clusters: slot and charges from the ring, time and
         // pad from the staging area
         const uint32_t done = j - jb;
@@ -1035,8 +1130,8 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
         uint2 o[kBlk];
 #pragma unroll
         for (int i = 0; i < kBlk; i++) {  // all reads first: one LDS round trip
-            r[i] = ring[w][(jb + i) % kRing][lane];
-            o[i] = stg[w][i][lane];
+            r[i] = ring[(jb + i) % kRing][lane];
+            o[i] = stg[i][lane];
         }
 #pragma unroll
         for (int i = 0; i < kBlk; i++) {
@@ -1061,7 +1156,51 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
             if ((uint32_t)i < m) nb[i] = F.recs[c0 + L + i];
         if (__ballot(j < n) == 0) break;
     }
-    fl = wave_or(fl);
+    T.fl = fl;
+}
+
+__global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict__ fd,
+                                                    const uint32_t *__restrict__ tile_frame,
+                                                    const Geo *__restrict__ geo)
+{
+    // LDS holds only the record rings and staging (40 KB per block, so four
+    // blocks fit a CU); the tables stay in global memory.
+    __shared__ uint4 ring[kTileWaves][kRing][kWave];
+    __shared__ uint2 stg[kTileWaves][kBlk][kWave];  // decoded (time, pad) of the block's clusters
+    const uint32_t tile = blockIdx.x;
+    const FrameDesc F = fd[tile_frame[tile]];
+    const uint32_t slot = (tile - F.tile0) * kTile + threadIdx.x;
+    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+    LaneTrack T = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0, 0u, 0u, 0u, 0u};
+    uint32_t cls = 2;
+    if (slot < F.nT) {
+        const uint32_t t = F.order[slot];
+        const uint32_t ncls = F.ncls[t];
+        T.c0 = F.start[t];
+        T.n = track_len(T.c0, ncls, F.nA);
+        cls = key_class(F.tkey[t]);
+        if (ncls == 0) T.fl |= TMD_F_HDR;
+        HeaderPos h = header_pos(F.sec0[t], F.row0[t]);
+        T.fl |= h.flags;
+        uint32_t t0u = F.time0[t];
+        if (t0u >= kTimeLim) { T.fl |= TMD_F_TIME; t0u = kTimeLim - 1; }
+        T.t0 = (int32_t)t0u;
+        T.pad0 = F.pad0[t];
+        const RowGeo R = geo->row[h.row];
+        T.x = R.x;
+        T.y = ((float)T.pad0 * 0x1p-5f - R.padoff) * R.pw;
+        T.s = clamp_snp((float)F.snp[t] * 0x1p-15f, geo->snp_max, T.fl);
+        T.tgl = (float)F.tgl[t] * 0x1p-12f;
+        T.k = ((float)F.qpt[t] * 0x1p-10f) * geo->kb;
+    }
+    // wave mode: 0 rows ascending, 1 rows descending, 2 one cluster per step
+    const uint64_t any_live = __ballot(T.n > 0);
+    const uint64_t asc = __ballot(T.n > 0 && cls == 0);
+    const uint64_t dsc = __ballot(T.n > 0 && cls == 1);
+    if (asc == any_live) attached_loop<0>(F, geo, ring[w], stg[w], T);
+    else if (dsc == any_live) attached_loop<1>(F, geo, ring[w], stg[w], T);
+    else attached_loop<2>(F, geo, ring[w], stg[w], T);
+    const uint32_t fl = wave_or(T.fl);
     if (lane == 0 && fl) atomicOr(F.status, fl);
 }
 

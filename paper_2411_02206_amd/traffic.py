@@ -100,7 +100,7 @@ def main():
         return
     py = sys.executable
     bench = [py, "-u", os.path.join(ROOT, "bench.py"), "--workload", args.workload, "--steps", "3",
-             "--warmup", "1", "--no-cpu"]
+             "--warmup", "1", "--no-cpu", "--gen-workers", "1"]
     copyp = [py, "-u", "-m", "paper_2411_02206_amd.traffic", "--copy", str(COPY_MIB)]
     res = {}
     for tag, prog in (("bench", bench), ("copy", copyp)):
