@@ -198,6 +198,24 @@ const char *tmd_stage_name(uint32_t stage);
  */
 int tmd_selftest_fp(const float *a, const float *b, float *out, uint32_t n, void *stream);
 
+/*
+ * Self-test of the decode loop's own forms of three operations (device
+ * pointers; a[n] in, out[4n] out, as raw 32-bit words):
+ * out[4i+0] = square root of a[i] (meaningful for positive normal a[i], the
+ * only arguments the loop gives it), out[4i+1] = a[i] clamped to the decoder's
+ * |sin phi| limit with NaN -> 0, out[4i+2] = 1 if that clamp changed a[i] or
+ * a[i] was NaN, else 0, out[4i+3] = rint(a[i]) as int32 clamped to
+ * [-2^30, 2^30] with NaN -> 0.  Each must equal the plain definition.
+ */
+int tmd_selftest_math(const float *a, uint32_t *out, uint32_t n, void *stream);
+
+/*
+ * Counts into *mismatches (a device word, added to, not cleared) the floats
+ * whose bit patterns lie in [lo_bits, hi_bits) for which the decode loop's
+ * square root differs from the IEEE square root on the device.
+ */
+int tmd_selftest_sqrt(uint32_t lo_bits, uint32_t hi_bits, uint32_t *mismatches, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -204,3 +204,29 @@ def selftest_fp(a, b, stream=None):
     _lib.check(_lib.lib().tmd_selftest_fp(_ptr(a), _ptr(b), _ptr(out), n, C.c_void_p(stream.cuda_stream)),
                "tmd_selftest_fp")
     return out[:4 * n].view(n, 4)
+
+
+def selftest_math(a, stream=None):
+    """The decode loop's square root, |sin phi| clamp (+ flag) and rounding to
+    int32 of a float32 device tensor; returns an int32 tensor [n, 4] of raw
+    words (see tmd_selftest_math)."""
+    torch = _torch()
+    n = a.numel()
+    out = torch.empty(4 * max(n, 1), dtype=torch.int32, device=a.device)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _lib.check(_lib.lib().tmd_selftest_math(_ptr(a), _ptr(out), n, C.c_void_p(stream.cuda_stream)),
+               "tmd_selftest_math")
+    return out[:4 * n].view(n, 4)
+
+
+def selftest_sqrt(lo_bits, hi_bits, device="cuda", stream=None):
+    """Number of floats with bit patterns in [lo_bits, hi_bits) where the
+    decode loop's square root differs from the IEEE one."""
+    torch = _torch()
+    cnt = torch.zeros(1, dtype=torch.int32, device=device)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _lib.check(_lib.lib().tmd_selftest_sqrt(lo_bits, hi_bits, _ptr(cnt), C.c_void_p(stream.cuda_stream)),
+               "tmd_selftest_sqrt")
+    return int(cnt.item())

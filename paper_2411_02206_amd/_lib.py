@@ -75,6 +75,10 @@ def lib():
         L.tmd_stage_name.restype = C.c_char_p
         L.tmd_selftest_fp.argtypes = [P, P, P, C.c_uint32, P]
         L.tmd_selftest_fp.restype = C.c_int
+        L.tmd_selftest_math.argtypes = [P, P, C.c_uint32, P]
+        L.tmd_selftest_math.restype = C.c_int
+        L.tmd_selftest_sqrt.argtypes = [C.c_uint32, C.c_uint32, P, P]
+        L.tmd_selftest_sqrt.restype = C.c_int
         _LIB = L
     return _LIB
 

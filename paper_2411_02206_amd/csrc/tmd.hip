@@ -233,6 +233,18 @@ __device__ uint32_t block_excl_add(uint32_t v, uint32_t *tot)
     return base + inc - v;
 }
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round robin by
+// workgroup id.  This maps workgroup b to a tile so that each XCD gets one
+// contiguous range of tiles: neighbouring tiles, whose stores share cache
+// lines, then meet in the same L2.  A bijection for any grid size.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n)
+{
+    const uint32_t x = b % kXcds, i = b / kXcds;
+    const uint32_t q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // Copy n 16-byte vectors from global memory to LDS, all loads of a batch in
 // flight before the first LDS write (a load-then-store loop would wait for
 // every load in turn).
@@ -951,12 +963,42 @@ __device__ __forceinline__ float clamp_snp(float v, float smax, uint32_t &fl)
     return nan ? 0.0f : r;
 }
 
-__device__ __forceinline__ int32_t sat_i32(float v)
+// The decode loop's forms of the same operations, shorter on this hardware and
+// equal bit for bit on the arguments it sees (checked on the device by
+// tmd_selftest_math and tmd_selftest_sqrt):
+//
+// clamp to [-smax, smax] with NaN -> 0; `flag` is set if v was outside or
+// NaN.  The median of (v, -smax, smax) is the clamp of every non-NaN v.
+__device__ __forceinline__ float clamp_snp_b(float v, float smax, bool &flag)
 {
-    float c = v != v ? 0.0f : v;
-    c = c > 1073741824.0f ? 1073741824.0f : c;
-    c = c < -1073741824.0f ? -1073741824.0f : c;
-    return (int32_t)c;
+    const float c = __builtin_amdgcn_fmed3f(v, -smax, smax);
+    flag |= c != v;  // also for NaN
+    return v != v ? 0.0f : c;
+}
+
+// rint(v) as int32 clamped to [-2^30, 2^30], NaN -> 0.  v_cvt_i32_f32 turns
+// NaN into 0 and saturates values outside int32, so an integer median ends it.
+__device__ __forceinline__ int32_t sat_rint(float v)
+{
+    int32_t i;
+    asm("v_cvt_i32_f32 %0, %1" : "=v"(i) : "v"(__builtin_rintf(v)));
+    return min(max(i, -(1 << 30)), 1 << 30);
+}
+
+// IEEE square root of a positive normal float.  v_sqrt_f32 is within one ulp;
+// of its result and the two neighbours, the residuals x - r' * r (one fused
+// multiply-add each) pick the correctly rounded one.  Every square root in the
+// decode loop has its argument in [2^-9, 2^9]: (1 - s)(1 + s) with |s| <=
+// 0.999, and 1 + (dy/dx)^2 with |dy/dx| <= 1.998 / (2 sqrt(0.001999)).
+__device__ __forceinline__ float sqrt_pos(float x)
+{
+    const float r = __builtin_amdgcn_sqrtf(x);
+    const float rm = __uint_as_float(__float_as_uint(r) - 1u);
+    const float rp = __uint_as_float(__float_as_uint(r) + 1u);
+    const float em = __builtin_fmaf(-rm, r, x);
+    const float ep = __builtin_fmaf(-rp, r, x);
+    const float q = em <= 0.0f ? rm : r;
+    return ep > 0.0f ? rp : q;
 }
 
 template <int CTRL, int ROWMASK>
@@ -1028,7 +1070,7 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
     float x = T.x, y = T.y, z = T.z, s = T.s, tgl = T.tgl;
     const float k = T.k;
     const int32_t t0 = T.t0;
-    uint32_t fl = T.fl;
+    bool f_snp = false, f_rot = false, f_pad = false, f_time = false;
     // of two consecutive blocks at least one decodes a cluster (a block in
     // which no lane has a record in its ring refills them), so 2 * 64 * 255
     // blocks always suffice
@@ -1068,36 +1110,36 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
                                 break;
                             }
                         }
-                        const float cs = sqrtf((1.0f - s) * (1.0f + s));
+                        const float cs = sqrt_pos((1.0f - s) * (1.0f + s));
                         const float xn = (x * ca) + (y * sa);
                         const float yn = (y * ca) - (x * sa);
                         const float sn = (s * ca) - (cs * sa);
                         const float cn = (cs * ca) + (s * sa);
-                        if (!(cn > 0.0f)) fl |= TMD_F_ROT;
+                        f_rot |= !(cn > 0.0f);
                         x = xn;
                         y = yn;
-                        s = clamp_snp(sn, smax, fl);
+                        s = clamp_snp_b(sn, smax, f_snp);
                     }
                     const uint32_t row = rec.w & 0xFFu;
                     const RowGeo R = geo->row[MODE != 2 ? __builtin_amdgcn_readfirstlane(row) : row];
                     const float dx = R.x - x;
-                    const float s1 = clamp_snp(s + (k * dx), smax, fl);
-                    const float a0 = sqrtf((1.0f - s) * (1.0f + s));
-                    const float a1 = sqrtf((1.0f - s1) * (1.0f + s1));
+                    const float s1 = clamp_snp_b(s + (k * dx), smax, f_snp);
+                    const float a0 = sqrt_pos((1.0f - s) * (1.0f + s));
+                    const float a1 = sqrt_pos((1.0f - s1) * (1.0f + s1));
                     const float dydx = (s + s1) / (a0 + a1);
                     y = y + (dx * dydx);
-                    z = z + (tgl * (dx * sqrtf(1.0f + (dydx * dydx))));
+                    z = z + (tgl * (dx * sqrt_pos(1.0f + (dydx * dydx))));
                     s = s1;
                     x = R.x;
-                    const int32_t P = sat_i32(rintf(((y * R.inv_pw) + R.padoff) * 32.0f));
-                    const int32_t Tq = sat_i32(rintf(z * geo->inv_vd32));
+                    const int32_t P = sat_rint(((y * R.inv_pw) + R.padoff) * 32.0f);
+                    const int32_t Tq = sat_rint(z * geo->inv_vd32);
                     const int32_t pres = (int32_t)(int16_t)(rec.y & 0xFFFFu);
                     const int32_t tres = (int32_t)(int16_t)(rec.y >> 16);
                     int32_t padq = P + pres;
-                    fl |= (padq < 0 || padq > 65535) ? TMD_F_PAD : 0u;
+                    f_pad |= padq < 0 || padq > 65535;
                     padq = padq < 0 ? 0 : (padq > 65535 ? 65535 : padq);
                     int32_t timeq = t0 + Tq + tres;
-                    fl |= (timeq < 0 || timeq > (int32_t)kTimeLim - 1) ? TMD_F_TIME : 0u;
+                    f_time |= timeq < 0 || timeq > (int32_t)kTimeLim - 1;
                     timeq = timeq < 0 ? 0 : (timeq > (int32_t)kTimeLim - 1 ? (int32_t)kTimeLim - 1 : timeq);
                     otime = (uint32_t)timeq;
                     opad = (uint32_t)padq;
@@ -1105,7 +1147,7 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
                     const float nuz = (float)tres * geo->vdq;
                     y = y + nuy;
                     z = z + nuz;
-                    s = clamp_snp(s + (nuy * R.ks), smax, fl);
+                    s = clamp_snp_b(s + (nuy * R.ks), smax, f_snp);
                     tgl = tgl + (nuz * R.kt);
                 }
                 stg[j - jb][lane] = make_uint2(otime, opad);
@@ -1156,7 +1198,8 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
             if ((uint32_t)i < m) nb[i] = F.recs[c0 + L + i];
         if (__ballot(j < n) == 0) break;
     }
-    T.fl = fl;
+    T.fl |= (f_snp ? TMD_F_SNP : 0u) | (f_rot ? TMD_F_ROT : 0u) | (f_pad ? TMD_F_PAD : 0u) |
+            (f_time ? TMD_F_TIME : 0u);
 }
 
 __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict__ fd,
@@ -1167,7 +1210,7 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
     // blocks fit a CU); the tables stay in global memory.
     __shared__ uint4 ring[kTileWaves][kRing][kWave];
     __shared__ uint2 stg[kTileWaves][kBlk][kWave];  // decoded (time, pad) of the block's clusters
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t slot = (tile - F.tile0) * kTile + threadIdx.x;
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
@@ -1207,6 +1250,33 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
 // ---------------------------------------------------------------------------
 // arithmetic self-test
 // ---------------------------------------------------------------------------
+__global__ void k_selftest_math(const float *a, float smax, uint32_t *out, uint32_t n)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = a[i];
+    bool f = false;
+    const float c = clamp_snp_b(x, smax, f);
+    out[4 * i + 0] = __float_as_uint(sqrt_pos(x));
+    out[4 * i + 1] = __float_as_uint(c);
+    out[4 * i + 2] = f ? 1u : 0u;
+    out[4 * i + 3] = (uint32_t)sat_rint(x);
+}
+
+// count the floats with bit patterns in [lo, hi) where sqrt_pos differs from
+// the IEEE square root
+__global__ void k_selftest_sqrt(uint32_t lo, uint32_t hi, uint32_t *count)
+{
+    uint32_t bad = 0;
+    for (uint64_t b = (uint64_t)lo + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < hi;
+         b += (uint64_t)gridDim.x * blockDim.x) {
+        const float x = __uint_as_float((uint32_t)b);
+        bad += __float_as_uint(sqrt_pos(x)) != __float_as_uint(sqrtf(x));
+    }
+    bad = wave_incl_add(bad);
+    if (lane_id() == kWave - 1 && bad) atomicAdd(count, bad);
+}
+
 __global__ void k_selftest_fp(const float *a, const float *b, float *out, uint32_t n)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1641,6 +1711,27 @@ int tmd_stage_times(tmd_plan_t *P, double *ms, uint32_t n, uint32_t *calls)
 }
 
 const char *tmd_stage_name(uint32_t stage) { return stage < (uint32_t)kStages ? kStageNames[stage] : ""; }
+
+int tmd_selftest_math(const float *a, uint32_t *out, uint32_t n, void *stream)
+{
+    if (!a || !out) return TMD_E_ARG;
+    if (n == 0) return TMD_OK;
+    Geo g;
+    build_geo(0.5f, &g);
+    hipLaunchKernelGGL(k_selftest_math, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, a, g.snp_max,
+                       out, n);
+    HIP_TRY(hipGetLastError());
+    return TMD_OK;
+}
+
+int tmd_selftest_sqrt(uint32_t lo_bits, uint32_t hi_bits, uint32_t *mismatches, void *stream)
+{
+    if (!mismatches || lo_bits > hi_bits) return TMD_E_ARG;
+    hipLaunchKernelGGL(k_selftest_sqrt, dim3(4096), dim3(256), 0, (hipStream_t)stream, lo_bits, hi_bits,
+                       mismatches);
+    HIP_TRY(hipGetLastError());
+    return TMD_OK;
+}
 
 int tmd_selftest_fp(const float *a, const float *b, float *out, uint32_t n, void *stream)
 {

@@ -59,6 +59,46 @@ def test_fp_selftest(tmd):
     assert same.all(), np.argwhere(~same)[:10]
 
 
+def test_decoder_math_forms(tmd):
+    """The decode loop's square root, clamp and float->int rounding equal
+    their plain definitions (numpy) on random and edge-case inputs."""
+    import torch
+    rng = np.random.default_rng(1)
+    f32 = np.float32
+    smax = f32(0.999)
+    pos = np.exp2(rng.uniform(-12, 12, 1 << 18)).astype(f32)
+    mixed = np.concatenate([rng.uniform(-2, 2, 1 << 16), rng.standard_normal(1 << 16) * 4e9,
+                            rng.uniform(-40, 40, 1 << 16)]).astype(f32)
+    edge = np.array([0.0, -0.0, np.nan, -np.nan, np.inf, -np.inf, smax, -smax, np.nextafter(smax, f32(2)),
+                     np.nextafter(-smax, f32(-2)), 0.5, 1.5, 2.5, -0.5, -1.5, -2.5, 2.0 ** 30, -2.0 ** 30,
+                     2.0 ** 30 + 128, -2.0 ** 30 - 128, 2.0 ** 31, -2.0 ** 31, 2.0 ** 32, 3.4e38, -3.4e38,
+                     1e-45, -1e-45, 1073741823.5, 8388607.5, -8388607.5], f32)
+    a = np.concatenate([pos, mixed, edge]).astype(f32)
+    out = tmd.selftest_math(torch.from_numpy(a).cuda()).cpu().numpy().view(np.uint32)
+    # square root: positive normal arguments only
+    got_sqrt = out[:pos.size, 0].view(f32)
+    assert np.array_equal(got_sqrt.view(np.uint32), np.sqrt(pos).view(np.uint32))
+    # clamp to [-smax, smax], NaN -> 0, flag when changed or NaN
+    nan = np.isnan(a)
+    with np.errstate(invalid="ignore"):
+        exp_c = np.where(nan, f32(0), np.clip(a, -smax, smax)).astype(f32)
+        exp_f = (nan | (a > smax) | (a < -smax)).astype(np.uint32)
+        r = np.rint(a)
+        exp_i = np.where(nan, 0, np.clip(r, -2.0 ** 30, 2.0 ** 30)).astype(np.int64).astype(np.int32)
+    assert np.array_equal(out[:, 1], exp_c.view(np.uint32))
+    assert np.array_equal(out[:, 2], exp_f)
+    assert np.array_equal(out[:, 3].view(np.int32), exp_i)
+
+
+def test_decoder_sqrt_exhaustive(tmd):
+    """Every float in [2^-12, 2^12) (the decode loop uses [2^-9, 2^9]): the
+    loop's square root equals the IEEE one (itself checked against the host in
+    test_fp_selftest)."""
+    lo = int(np.float32(2.0 ** -12).view(np.uint32))
+    hi = int(np.float32(2.0 ** 12).view(np.uint32))
+    assert tmd.selftest_sqrt(lo, hi) == 0
+
+
 def test_tiny_workload(tmd):
     fr = synth.make_frame(synth.spec_for("tiny"))
     assert_same(tmd, fr, label="tiny")

@@ -59,6 +59,9 @@ def test_bad_arguments_rejected_on_host():
     st = C.c_uint32()
     assert L.tmd_status(None, 0, C.byref(st)) == _lib.E_ARG
     assert L.tmd_selftest_fp(None, None, None, 4, None) == _lib.E_ARG
+    assert L.tmd_selftest_math(None, None, 4, None) == _lib.E_ARG
+    assert L.tmd_selftest_sqrt(0, 1, None, None) == _lib.E_ARG
+    assert L.tmd_selftest_sqrt(5, 4, C.c_void_p(1), None) == _lib.E_ARG
     L.tmd_free(None)  # no-op
 
 
