@@ -1020,16 +1020,24 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v)
     return readlane(v, kWave - 1);
 }
 
-// Record staging: each lane keeps a ring of kRing records of its track in LDS.
+// Record staging: each lane keeps a ring of kRing records of its track in LDS,
+// split in two arrays indexed [slot][lane]: rb = (residuals, row | rotation),
+// read at every step, and ra = (output slot, charges), read when storing.
 // The decode runs in blocks of kBlk steps; at each block boundary the records
-// loaded (into registers) at the previous boundary enter the ring, the block's
-// decoded clusters (staged in LDS) are stored, and the next records are
-// loaded.  Between boundaries the decode issues no global memory instruction,
-// so no step waits for memory: every load and store has a whole block to
-// complete.  A lane holds at least kBlk unread records at every boundary (or
-// all that remain), enough for the kBlk steps that follow.
+// loaded at the previous boundary enter the ring, the block's decoded clusters
+// (staged in LDS) are stored, and the next records are loaded.  Between
+// boundaries the decode issues no global memory instruction, so no step waits
+// for memory: every load and store has a whole block to complete.  A lane
+// holds at least kBlk unread records at every boundary (or all that remain),
+// enough for the kBlk steps that follow.
+//
+// Loads are cooperative: the next kBlk records of a track are contiguous, so
+// kBlk neighbouring lanes fetch them with one instruction (lane l of load k
+// fetches record l % 4 for track lane 16 k + l / 4): 64 contiguous bytes per
+// group of four lanes instead of one cache line per lane.
 constexpr int kBlk = 4;
 constexpr int kRing = 2 * kBlk;
+static_assert(kBlk == 4 && kWave == 64, "cooperative loads: 4 records per track, 16 tracks per load");
 
 // per-lane decode state of one track
 struct LaneTrack {
@@ -1038,34 +1046,72 @@ struct LaneTrack {
     uint32_t pad0, fl, n, c0;
 };
 
+// records fetched by one cooperative load round, and where they go
+struct CoopLoad {
+    uint4 v[kBlk];
+    uint32_t dst[kBlk];  // ring slot | track lane << 8, or ~0u: nothing to place
+};
+
+// Fetch records [L_t, L_t + m_t) of every track lane t (L and m: this lane's
+// values; base = c0 + L).  m_t <= kBlk.
+__device__ __forceinline__ void coop_load(const FrameDesc &F, uint32_t base, uint32_t L, uint32_t m,
+                                          CoopLoad &C)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t q = lane & 3u;
+    const uint32_t lm = (L << 8) | m;  // L <= 255, m <= 4
+#pragma unroll
+    for (int k = 0; k < kBlk; k++) {
+        const uint32_t t = 16u * k + (lane >> 2);
+        const uint32_t bt = bperm(base, t), lmt = bperm(lm, t);
+        const bool ok = q < (lmt & 0xFFu);
+        C.v[k] = F.recs[ok ? bt + q : 0u];
+        C.dst[k] = ok ? (((lmt >> 8) + q) % kRing) | (t << 8) : ~0u;
+    }
+}
+
+__device__ __forceinline__ void coop_place(const CoopLoad &C, uint2 (*ra)[kWave], uint2 (*rb)[kWave])
+{
+#pragma unroll
+    for (int k = 0; k < kBlk; k++) {
+        if (C.dst[k] != ~0u) {
+            const uint32_t sl = C.dst[k] & 0xFFu, t = C.dst[k] >> 8;
+            ra[sl][t] = make_uint2(C.v[k].x, C.v[k].z);
+            rb[sl][t] = make_uint2(C.v[k].y, C.v[k].w);
+        }
+    }
+}
+
 // The decode loop of one wave.  MODE 0: rows ascending, 1: descending (both
 // row-synchronous), 2: one cluster per lane per step.  In modes 0 and 1 all
 // lanes processing a step are on one row, so its table entry is read once per
 // wave through the scalar cache.
 template <int MODE>
 __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__restrict__ geo,
-                                              uint4 (*ring)[kWave], uint2 (*stg)[kWave], LaneTrack &T)
+                                              uint2 (*ra)[kWave], uint2 (*rb)[kWave], uint2 (*stg)[kWave],
+                                              LaneTrack &T)
 {
     const uint32_t lane = lane_id();
     const float smax = geo->snp_max;
     const uint32_t n = T.n, c0 = T.c0;
-    // first records straight into the ring
+    // first records straight into the ring: two rounds of kBlk
     uint32_t L = n < (uint32_t)kRing ? n : (uint32_t)kRing;  // records [0, L) have entered the ring
     {
-        uint4 first[kRing];
-#pragma unroll
-        for (int i = 0; i < kRing; i++) first[i] = (uint32_t)i < L ? F.recs[c0 + i] : make_uint4(0, 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < kRing; i++)
-            if ((uint32_t)i < L) ring[i][lane] = first[i];
+        CoopLoad C0, C1;
+        const uint32_t m0 = n < (uint32_t)kBlk ? n : (uint32_t)kBlk;
+        coop_load(F, c0, 0, m0, C0);
+        coop_load(F, c0 + kBlk, kBlk, L - m0, C1);
+        coop_place(C0, ra, rb);
+        coop_place(C1, ra, rb);
     }
-    uint4 nb[kBlk];  // records [L, L + m), loaded at the last boundary
+    CoopLoad nb;  // records [L, L + m), loaded at the last boundary
 #pragma unroll
-    for (int i = 0; i < kBlk; i++) nb[i] = make_uint4(0, 0, 0, 0);
+    for (int i = 0; i < kBlk; i++) nb.dst[i] = ~0u;
     uint32_t m = 0;
-    uint4 cur = make_uint4(0, 0, 0, 0);  // record j (valid while j < L)
-    if (L > 0) cur = ring[0][lane];
+    uint2 cur = make_uint2(0, 0);  // record j (valid while j < L)
+    if (L > 0) cur = rb[0][lane];
     uint32_t j = 0, jb = 0;       // next record; first record of the block
+    uint32_t rmask = 0;           // steps of the block at which this lane decoded
     uint32_t vrow = 0xFFFFFFFFu;  // modes 0 and 1: the last row processed
     float x = T.x, y = T.y, z = T.z, s = T.s, tgl = T.tgl;
     const float k = T.k;
@@ -1084,7 +1130,7 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
                 // pending minimum is usually the row after the last one; only
                 // if no lane is there is the minimum taken over all lanes
                 // (with all lanes active: it reads other lanes).
-                const uint32_t rr = (cur.w & 0xFFu);
+                const uint32_t rr = (cur.y & 0xFFu);
                 const uint32_t v = live ? (MODE == 0 ? rr : 255u - rr) : 0xFFFFFFFFu;
                 vrow += 1u;
                 ready = live && v == vrow;
@@ -1094,10 +1140,10 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
                 }
             }
             if (ready) {
-                const uint4 rec = cur;
+                const uint2 rec = cur;  // x = residuals, y = row | rotation << 8
                 uint32_t otime = (uint32_t)t0, opad = T.pad0;
                 if (j > 0) {
-                    const uint32_t d = (rec.w >> 8) & 0xFFu;  // 0..17
+                    const uint32_t d = (rec.y >> 8) & 0xFFu;  // 0..17
                     if (d != 0) {
                         // table entry through the scalar cache, once per
                         // distinct d among the rotating lanes
@@ -1120,7 +1166,7 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
                         y = yn;
                         s = clamp_snp_b(sn, smax, f_snp);
                     }
-                    const uint32_t row = rec.w & 0xFFu;
+                    const uint32_t row = rec.y & 0xFFu;
                     const RowGeo R = geo->row[MODE != 2 ? __builtin_amdgcn_readfirstlane(row) : row];
                     const float dx = R.x - x;
                     const float s1 = clamp_snp_b(s + (k * dx), smax, f_snp);
@@ -1133,8 +1179,8 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
                     x = R.x;
                     const int32_t P = sat_rint(((y * R.inv_pw) + R.padoff) * 32.0f);
                     const int32_t Tq = sat_rint(z * geo->inv_vd32);
-                    const int32_t pres = (int32_t)(int16_t)(rec.y & 0xFFFFu);
-                    const int32_t tres = (int32_t)(int16_t)(rec.y >> 16);
+                    const int32_t pres = (int32_t)(int16_t)(rec.x & 0xFFFFu);
+                    const int32_t tres = (int32_t)(int16_t)(rec.x >> 16);
                     int32_t padq = P + pres;
                     f_pad |= padq < 0 || padq > 65535;
                     padq = padq < 0 ? 0 : (padq > 65535 ? 65535 : padq);
@@ -1150,9 +1196,10 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
                     s = clamp_snp_b(s + (nuy * R.ks), smax, f_snp);
                     tgl = tgl + (nuz * R.kt);
                 }
-                stg[j - jb][lane] = make_uint2(otime, opad);
+                stg[st][lane] = make_uint2(otime, opad);
+                rmask |= 1u << st;
                 j++;
-                if (j < L) cur = ring[j % kRing][lane];
+                if (j < L) cur = rb[j % kRing][lane];
             }
         }
         // block boundary.  Records loaded at the last boundary enter the ring:
@@ -1160,30 +1207,30 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
         // not those of records [jb, L), which hold this block's decoded
         // clusters (stored next) and the unread ones.
         const bool starved = j == L;
-#pragma unroll
-        for (int i = 0; i < kBlk; i++)
-            if ((uint32_t)i < m) ring[(L + i) % kRing][lane] = nb[i];
+        coop_place(nb, ra, rb);
         L += m;
-        if (starved && j < L) cur = ring[j % kRing][lane];
-        // store the block's clusters: slot and charges from the ring, time and
-        // pad from the staging area
-        const uint32_t done = j - jb;
-        uint4 r[kBlk];
-        uint2 o[kBlk];
+        if (starved && j < L) cur = rb[j % kRing][lane];
+        // store the block's clusters step by step: the lanes that decoded at
+        // one step share its row, so their slots are neighbours and each
+        // store instruction covers a short run of a bin.  Slot and charges
+        // come from the ring, time and pad from the staging area.
+        uint2 r[kBlk], o[kBlk];
 #pragma unroll
-        for (int i = 0; i < kBlk; i++) {  // all reads first: one LDS round trip
-            r[i] = ring[(jb + i) % kRing][lane];
-            o[i] = stg[i][lane];
+        for (int st = 0; st < kBlk; st++) {  // all reads first: one LDS round trip
+            const uint32_t idx = jb + (uint32_t)__popc(rmask & ((1u << st) - 1u));
+            r[st] = ra[idx % kRing][lane];
+            o[st] = stg[st][lane];
         }
 #pragma unroll
-        for (int i = 0; i < kBlk; i++) {
-            if ((uint32_t)i < done && r[i].x < F.cap) {
-                F.otime[r[i].x] = o[i].x;
-                F.opad[r[i].x] = (uint16_t)o[i].y;
-                F.oqtot[r[i].x] = (uint16_t)(r[i].z & 0xFFFFu);
-                F.oqmax[r[i].x] = (uint16_t)(r[i].z >> 16);
+        for (int st = 0; st < kBlk; st++) {
+            if (((rmask >> st) & 1u) && r[st].x < F.cap) {
+                F.otime[r[st].x] = o[st].x;
+                F.opad[r[st].x] = (uint16_t)o[st].y;
+                F.oqtot[r[st].x] = (uint16_t)(r[st].y & 0xFFFFu);
+                F.oqmax[r[st].x] = (uint16_t)(r[st].y >> 16);
             }
         }
+        rmask = 0;
         jb = j;
         // next records: at most kBlk, and no more than the ring can take
         // without overwriting a record >= j (records [j, L + m) span at most
@@ -1193,10 +1240,8 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
         if (m > (uint32_t)kBlk) m = kBlk;
         const uint32_t room = (uint32_t)kRing - (L - j);
         if (m > room) m = room;
-#pragma unroll
-        for (int i = 0; i < kBlk; i++)
-            if ((uint32_t)i < m) nb[i] = F.recs[c0 + L + i];
         if (__ballot(j < n) == 0) break;
+        coop_load(F, c0 + L, L, m, nb);
     }
     T.fl |= (f_snp ? TMD_F_SNP : 0u) | (f_rot ? TMD_F_ROT : 0u) | (f_pad ? TMD_F_PAD : 0u) |
             (f_time ? TMD_F_TIME : 0u);
@@ -1208,8 +1253,9 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
 {
     // LDS holds only the record rings and staging (40 KB per block, so four
     // blocks fit a CU); the tables stay in global memory.
-    __shared__ uint4 ring[kTileWaves][kRing][kWave];
-    __shared__ uint2 stg[kTileWaves][kBlk][kWave];  // decoded (time, pad) of the block's clusters
+    __shared__ uint2 ra[kTileWaves][kRing][kWave];  // record rings: (output slot, charges)
+    __shared__ uint2 rb[kTileWaves][kRing][kWave];  // (residuals, row | rotation << 8)
+    __shared__ uint2 stg[kTileWaves][kBlk][kWave];  // per step of the block: the decoded (time, pad)
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t slot = (tile - F.tile0) * kTile + threadIdx.x;
@@ -1240,9 +1286,9 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
     const uint64_t any_live = __ballot(T.n > 0);
     const uint64_t asc = __ballot(T.n > 0 && cls == 0);
     const uint64_t dsc = __ballot(T.n > 0 && cls == 1);
-    if (asc == any_live) attached_loop<0>(F, geo, ring[w], stg[w], T);
-    else if (dsc == any_live) attached_loop<1>(F, geo, ring[w], stg[w], T);
-    else attached_loop<2>(F, geo, ring[w], stg[w], T);
+    if (asc == any_live) attached_loop<0>(F, geo, ra[w], rb[w], stg[w], T);
+    else if (dsc == any_live) attached_loop<1>(F, geo, ra[w], rb[w], stg[w], T);
+    else attached_loop<2>(F, geo, ra[w], rb[w], stg[w], T);
     const uint32_t fl = wave_or(T.fl);
     if (lane == 0 && fl) atomicOr(F.status, fl);
 }
