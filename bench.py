@@ -310,12 +310,17 @@ def run_batched(args):
             t0 = time.perf_counter()
             arrivals = t0 + np.cumsum(gaps)
             k = 0
+            nd = 0
             while len(srv.done) < n_req:
                 now = time.perf_counter()
                 while k < n_req and arrivals[k] <= now:
                     srv.submit(ins[picks[k]], arrival=float(arrivals[k]))
                     k += 1
                 srv.step()
+                # the client takes each result as it completes: its buffers go
+                for r in srv.done[nd:]:
+                    r.out = None
+                nd = len(srv.done)
             t1 = time.perf_counter()
             lat = [1e3 * r.latency for r in srv.done]
             served_clusters = sum(shapes[p][1] + shapes[p][2] for p in picks)

@@ -155,6 +155,20 @@ int tmd_decode(tmd_plan_t *plan, const tmd_frame_in *in, tmd_frame_out *out, voi
                void *stream);
 
 /*
+ * As tmd_decode, for frames whose shapes (shapes[i], n_frames entries) are no
+ * larger than the planned ones in every count: the plan's shapes are then
+ * capacities, and one plan (and its workspace, and in TMD_PLAN_GRAPH mode its
+ * captured graph) serves frames of any smaller shape, e.g. a serving loop's
+ * changing batches.  A frame of shape (0, 0, 0) is an idle entry: it needs
+ * only un_count (5472 zero words), row_offset and row_nattached.  The kernels
+ * launched are those of the planned shapes; tiles beyond a frame's own track
+ * count return at once.
+ * Errors: those of tmd_decode, and TMD_E_ARG if a shape exceeds the plan's.
+ */
+int tmd_decode_shapes(tmd_plan_t *plan, const tmd_frame_shape *shapes, const tmd_frame_in *in,
+                      tmd_frame_out *out, void *workspace, void *stream);
+
+/*
  * Flags of frame `frame` from the last tmd_decode on this plan; waits for that
  * decode to finish.  Returns TMD_OK if no flag is set, TMD_E_INPUT if
  * TMD_F_COUNT is set, TMD_E_STREAM if another flag is set, TMD_E_ARG for a bad

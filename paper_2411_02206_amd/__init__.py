@@ -135,10 +135,11 @@ class Plan:
         torch = _torch()
         return torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=device)
 
-    def decode(self, ins, outs, workspace, stream=None):
+    def decode(self, ins, outs, workspace, stream=None, shapes=None):
         """Enqueue the decode of len(shapes) frames.  ins/outs: lists of dicts of
         device tensors (see to_device / alloc_out).  stream: torch stream or
-        None for the current one."""
+        None for the current one.  shapes: the frames' own shapes if they are
+        smaller than the planned ones (tmd_decode_shapes); None: as planned."""
         torch = _torch()
         n = len(self.shapes)
         if len(ins) != n or len(outs) != n:
@@ -154,7 +155,14 @@ class Plan:
         if stream is None:
             stream = torch.cuda.current_stream()
         sp = C.c_void_p(stream.cuda_stream)
-        _lib.check(_lib.lib().tmd_decode(self._h, fin, fout, _ptr(workspace), sp), "tmd_decode")
+        if shapes is None:
+            _lib.check(_lib.lib().tmd_decode(self._h, fin, fout, _ptr(workspace), sp), "tmd_decode")
+        else:
+            if len(shapes) != n:
+                raise ValueError(f"plan has {n} frames")
+            arr = (_lib.FrameShape * n)(*[_lib.FrameShape(*(int(v) for v in sh)) for sh in shapes])
+            _lib.check(_lib.lib().tmd_decode_shapes(self._h, arr, fin, fout, _ptr(workspace), sp),
+                       "tmd_decode_shapes")
 
     def status(self, frame=0):
         """Flag bits of `frame` from the last decode (waits for it)."""

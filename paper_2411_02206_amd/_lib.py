@@ -57,6 +57,8 @@ def lib():
         L.tmd_plan.restype = C.c_int
         L.tmd_decode.argtypes = [P, C.POINTER(FrameIn), C.POINTER(FrameOut), P, P]
         L.tmd_decode.restype = C.c_int
+        L.tmd_decode_shapes.argtypes = [P, C.POINTER(FrameShape), C.POINTER(FrameIn), C.POINTER(FrameOut), P, P]
+        L.tmd_decode_shapes.restype = C.c_int
         L.tmd_status.argtypes = [P, C.c_uint32, C.POINTER(C.c_uint32)]
         L.tmd_status.restype = C.c_int
         L.tmd_free.argtypes = [P]

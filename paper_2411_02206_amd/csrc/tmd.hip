@@ -322,6 +322,7 @@ __global__ __launch_bounds__(kTile) void k_tilesum(const FrameDesc *__restrict__
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
+    if (lt >= F.ntile) return;  // a tile of the planned capacity beyond this call's frame
     const uint32_t t = lt * kTile + threadIdx.x;
     const uint32_t v = t < F.nT ? F.ncls[t] : 0u;
     uint32_t tot;
@@ -495,6 +496,7 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
+    if (lt >= F.ntile) return;  // a tile of the planned capacity beyond this call's frame
     const uint32_t t = lt * kTile + threadIdx.x;
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
 
@@ -821,6 +823,7 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
+    if (lt >= F.ntile) return;  // a tile of the planned capacity beyond this call's frame
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     const GLB uint32_t *G = F.hist + (size_t)lt * kHRow;
     const uint32_t t = lt * kTile + threadIdx.x;
@@ -1258,6 +1261,7 @@ __global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict_
     __shared__ uint2 stg[kTileWaves][kBlk][kWave];  // per step of the block: the decoded (time, pad)
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const FrameDesc F = fd[tile_frame[tile]];
+    if (tile - F.tile0 >= F.ntile) return;  // a tile of the planned capacity beyond this call's frame
     const uint32_t slot = (tile - F.tile0) * kTile + threadIdx.x;
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     LaneTrack T = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0, 0u, 0u, 0u, 0u};
@@ -1600,12 +1604,24 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
 
 int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *workspace, void *stream)
 {
-    if (!P || !in || !out || !workspace) return TMD_E_ARG;
+    if (!P) return TMD_E_ARG;
+    return tmd_decode_shapes(P, P->shapes.data(), in, out, workspace, stream);
+}
+
+int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
+                      void *workspace, void *stream)
+{
+    if (!P || !shapes || !in || !out || !workspace) return TMD_E_ARG;
     if ((uintptr_t)workspace % 256) return TMD_E_ARG;
+    for (uint32_t f = 0; f < P->n_frames; f++) {
+        const tmd_frame_shape &C = P->shapes[f], &S = shapes[f];
+        if (S.n_tracks > C.n_tracks || S.n_attached > C.n_attached || S.n_unattached > C.n_unattached)
+            return TMD_E_ARG;
+    }
     hipStream_t s = (hipStream_t)stream;
     std::vector<FrameDescHost> desc(P->n_frames);
     for (uint32_t f = 0; f < P->n_frames; f++) {
-        const tmd_frame_shape &S = P->shapes[f];
+        const tmd_frame_shape &S = shapes[f];
         const tmd_frame_in &I = in[f];
         const tmd_frame_out &O = out[f];
         const FrameLayout &L = P->layout[f];
@@ -1654,7 +1670,8 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
         D.status = P->d_status + f;
         D.cap = O.capacity;
         D.nT = S.n_tracks; D.nA = S.n_attached; D.nU = S.n_unattached;
-        D.ntile = L.ntile; D.tile0 = L.tile0;
+        D.ntile = (S.n_tracks + kTile - 1) / kTile;  // <= the planned L.ntile
+        D.tile0 = L.tile0;
     }
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));

@@ -4,41 +4,46 @@ Requests (one frame each, device-resident or host arrays) arrive at any time.
 The scheduler keeps up to `slots` batches in flight, each on its own stream
 (default priority).  Whenever a slot is free it admits the oldest waiting
 requests whose buffers fit the HBM budget -- up to `max_batch` of them -- and
-decodes them together with one multi-frame plan; frames admitted while other
-batches are still running overlap with them on the device.  A request's
+decodes them together with one launch sequence; batches admitted while
+others are still running overlap with them on the device.  A request's
 latency runs from its arrival to the completion event of its batch.
 
-All decoding is done by libtmd (through paper_2411_02206_amd.Plan); this
-module only schedules.  Plans are cached per slot by their tuple of frame
-shapes: calls on one plan are serialised by the library, so slots never share
-one.
+Each slot owns one plan whose frame shapes are capacities (tmd_decode_shapes):
+max_batch entries of the server's per-frame capacity.  A batch fills the
+first entries and leaves the rest idle, so the plan, its workspace and (with
+graph=True) its captured HIP graph are made once and reused for every batch.
+The capacity starts at the first frame's shape times 1.25 (or is given) and
+grows by the same factor when a larger frame arrives; a slot rebuilds its plan
+when it is next idle.  All decoding is done by libtmd; this module schedules.
 """
 import collections
 import threading
 import time
 
-from . import Plan, alloc_out, frame_shape, to_device
+from . import IN_FIELDS, NBIN, Plan, alloc_out, frame_shape, to_device
 
-# bytes of the device buffers of one frame: inputs, outputs and workspace (the
-# workspace is taken from the plan once known; this estimate is used for
-# admission before the plan exists)
+# bytes of the device buffers of one request: inputs (when copied in) and outputs
 IN_BYTES_TRACK = 15
 IN_BYTES_CLUSTER = 10
 OUT_BYTES_CLUSTER = 10
-WS_BYTES_ATTACHED = 16 + 4        # records + start
-WS_BYTES_TRACK = 4 + 4 + 1 + 90   # start, order, key, histogram rows
-FIXED_BYTES = 5472 * 16 + (1 << 20)
+FIXED_BYTES = (2 * NBIN + 1) * 4 + (1 << 12)
+GROWTH = 1.25
 
 
-def frame_bytes(shape):
+def frame_bytes(shape, inputs=True):
     nT, nA, nU = shape
-    return (nT * IN_BYTES_TRACK + (nA + nU) * (IN_BYTES_CLUSTER + OUT_BYTES_CLUSTER)
-            + nA * WS_BYTES_ATTACHED + nT * WS_BYTES_TRACK + FIXED_BYTES)
+    b = (nA + nU) * OUT_BYTES_CLUSTER + FIXED_BYTES
+    if inputs:
+        b += nT * IN_BYTES_TRACK + (nA + nU) * IN_BYTES_CLUSTER
+    return b
+
+
+def _grow(cap, shape):
+    return tuple(max(c, int(s * GROWTH) + 1) if s > c else c for c, s in zip(cap, shape))
 
 
 class Request:
-    __slots__ = ("frame", "shape", "arrival", "admitted", "done_time", "out", "flags", "event", "nbytes",
-                 "on_device")
+    __slots__ = ("frame", "shape", "arrival", "admitted", "done_time", "out", "flags", "nbytes", "on_device")
 
     def __init__(self, frame, arrival):
         self.frame = frame
@@ -48,55 +53,59 @@ class Request:
         self.done_time = None
         self.out = None
         self.flags = None
-        self.event = None
-        self.nbytes = frame_bytes(self.shape)
         self.on_device = bool(getattr(frame["trk_ncls"], "is_cuda", False))
+        self.nbytes = frame_bytes(self.shape, inputs=not self.on_device)
 
     @property
     def latency(self):
         return None if self.done_time is None else self.done_time - self.arrival
 
 
-class _Batch:
-    def __init__(self, reqs, plan, stream, event, ws, keep, slot):
-        self.slot = slot
-        self.reqs = reqs
-        self.plan = plan
+class _Slot:
+    """A stream with its capacity plan, workspace and idle-entry buffers."""
+
+    def __init__(self, stream):
         self.stream = stream
-        self.event = event
-        self.ws = ws
-        self.keep = keep
+        self.plan = None
+        self.ws = None
+        self.cap = None
+        self.idle_in = None
+        self.idle_out = None
+        self.reqs = None   # the batch in flight, if any
+        self.event = None
+        self.keep = None   # its input buffers
 
 
 class Server:
     """Continuous-batching decoder.  submit() may be called from any thread;
     the scheduling runs in step()/run_until() on the calling thread (or
-    start() for a background thread)."""
+    start() for a background thread).  capacity: per-frame (n_tracks,
+    n_attached, n_unattached) of the slot plans, or None to size them from
+    the frames that arrive."""
 
     def __init__(self, bz=0.5, hbm_budget=200e9, slots=4, max_batch=8, graph=False, device="cuda",
-                 plan_cache=64, executor=None):
+                 capacity=None, executor=None):
         self.bz = bz
         self.budget = float(hbm_budget)
         self.max_batch = max_batch
-        self.peak_in_use = 0.0
         self.graph = graph
         self.device = device
+        self.capacity = tuple(capacity) if capacity is not None else None
+        self.peak_in_use = 0.0
         self.in_use = 0.0
         self.waiting = collections.deque()
         self.done = []
         self.lock = threading.Lock()
-        self._plans = collections.OrderedDict()
-        self._plan_cache = plan_cache
-        self._busy = []
         self._executor = executor  # test hook: decodes a list of requests without a GPU
         if executor is None:
             import torch
             self._torch = torch
-            self._streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
+            self._slots = [_Slot(torch.cuda.Stream(device=device)) for _ in range(slots)]
         else:
             self._torch = None
-            self._streams = [None] * slots
+            self._slots = [_Slot(None) for _ in range(slots)]
         self._free = list(range(slots))
+        self._busy = []  # slot indices with a batch in flight
         self._thread = None
         self._stop = False
 
@@ -110,35 +119,44 @@ class Server:
         return r
 
     # -- scheduler -----------------------------------------------------------
-    def _plan(self, slot, shapes):
-        key = (slot, tuple(shapes))
-        p = self._plans.get(key)
-        if p is not None:
-            self._plans.move_to_end(key)
-            return p
+    def _slot_ready(self, S):
+        """Make slot S's plan match the current capacity (S is idle)."""
+        if S.plan is not None and S.cap == self.capacity:
+            return
+        torch = self._torch
         from . import PLAN_GRAPH
-        p = Plan(shapes, bz=self.bz, flags=PLAN_GRAPH if self.graph else 0)
-        self._plans[key] = p
-        while len(self._plans) > self._plan_cache:
-            _, old = self._plans.popitem(last=False)
-            old.free()
-        return p
+        if S.plan is not None:
+            self.in_use -= S.ws.numel()
+            S.plan.free()
+        S.cap = self.capacity
+        S.plan = Plan([S.cap] * self.max_batch, bz=self.bz, flags=PLAN_GRAPH if self.graph else 0)
+        with torch.cuda.stream(S.stream):
+            S.ws = S.plan.alloc_workspace(self.device)
+            if S.idle_in is None:
+                S.idle_in = {k: None for k in IN_FIELDS}
+                S.idle_in["un_count"] = torch.zeros(NBIN, dtype=torch.int32, device=self.device)
+                o = alloc_out((0, 0, 0), self.device)
+                S.idle_out = {k: (o[k] if k in ("row_offset", "row_nattached") else None) for k in o}
+                S.idle_out["capacity"] = 0
+        self.in_use += S.ws.numel()
+        self.peak_in_use = max(self.peak_in_use, self.in_use)
 
     def _retire(self):
         still = []
-        for b in self._busy:
-            finished = b.event is None or b.event.query()
-            if finished:
+        for si in self._busy:
+            S = self._slots[si]
+            if S.event is None or S.event.query():
                 now = time.perf_counter()
-                for i, r in enumerate(b.reqs):
+                for i, r in enumerate(S.reqs):
                     r.done_time = now
-                    if b.plan is not None:
-                        r.flags = b.plan.status(i)
+                    if S.plan is not None and self._executor is None:
+                        r.flags = S.plan.status(i)
                     self.in_use -= r.nbytes
                     self.done.append(r)
-                self._free.append(b.slot)
+                S.reqs, S.event, S.keep = None, None, None
+                self._free.append(si)
             else:
-                still.append(b)
+                still.append(si)
         self._busy = still
 
     def _admit(self):
@@ -156,28 +174,34 @@ class Server:
                 batch.append(r)
         if not batch:
             return False
-        slot = self._free.pop()
+        for r in batch:
+            if self.capacity is None:
+                self.capacity = _grow((0, 0, 0), r.shape)
+            elif any(s > c for s, c in zip(r.shape, self.capacity)):
+                self.capacity = _grow(self.capacity, r.shape)
+        si = self._free.pop()
+        S = self._slots[si]
         now = time.perf_counter()
         for r in batch:
             r.admitted = now
+        S.reqs = batch
+        self._busy.append(si)
         if self._executor is not None:
             self._executor(batch)
-            self._busy.append(_Batch(batch, None, None, None, None, None, slot))
             return True
+        self._slot_ready(S)
         torch = self._torch
-        stream = self._streams[slot]
-        shapes = [r.shape for r in batch]
-        plan = self._plan(slot, shapes)
-        with torch.cuda.stream(stream):
+        idle = self.max_batch - len(batch)
+        with torch.cuda.stream(S.stream):
             ins = [r.frame if r.on_device else to_device(r.frame, self.device) for r in batch]
             outs = [alloc_out(r.shape, self.device) for r in batch]
-            ws = plan.alloc_workspace(self.device)
-            plan.decode(ins, outs, ws, stream)
-            ev = torch.cuda.Event()
-            ev.record(stream)
+            S.plan.decode(ins + [S.idle_in] * idle, outs + [S.idle_out] * idle, S.ws, S.stream,
+                          shapes=[r.shape for r in batch] + [(0, 0, 0)] * idle)
+            S.event = torch.cuda.Event()
+            S.event.record(S.stream)
         for r, o in zip(batch, outs):
             r.out = o
-        self._busy.append(_Batch(batch, plan, stream, ev, ws, ins, slot))
+        S.keep = ins
         return True
 
     def step(self):
@@ -215,9 +239,13 @@ class Server:
 
     def close(self):
         self.stop()
-        for p in self._plans.values():
-            p.free()
-        self._plans.clear()
+        if self._torch is not None:
+            self._torch.cuda.synchronize()
+        for S in self._slots:
+            if S.plan is not None:
+                S.plan.free()
+                S.plan = None
+            S.ws = None
 
 
 def percentile(values, q):

@@ -79,3 +79,47 @@ def test_served_host_frames(tmd, frames):
     for i, r in enumerate(reqs):
         assert same(ref[i][0], tmd.to_numpy(r.out)), i
     srv.close()
+
+
+def test_capacity_plan_changing_shapes(tmd, frames):
+    """One plan with capacity shapes (tmd_decode_shapes) decodes batches of
+    different, smaller frames and idle entries, eagerly and replayed as a
+    graph, bit-identically to plain single-frame decodes."""
+    import torch
+    ref = [plain(tmd, f) for f in frames]
+    shapes = [tmd.frame_shape(f) for f in frames]
+    cap = tuple(max(s[i] for s in shapes) + 7 for i in range(3))
+    nent = 3
+    for flags in (0, tmd.PLAN_GRAPH):
+        plan = tmd.Plan([cap] * nent, flags=flags)
+        ws = plan.alloc_workspace()
+        idle_in = {k: None for k in tmd.IN_FIELDS}
+        idle_in["un_count"] = torch.zeros(tmd.NBIN, dtype=torch.int32, device="cuda")
+        idle_out = tmd.alloc_out((0, 0, 0))
+        for k in ("time", "pad", "qtot", "qmax"):
+            idle_out[k] = None
+        idle_out["capacity"] = 0
+        groups = [[0, 1, 2], [3], [4, 5], [5, 0]]
+        for rep in range(2):
+            for g in groups:
+                ins = [tmd.to_device(frames[i]) for i in g] + [idle_in] * (nent - len(g))
+                outs = [tmd.alloc_out(shapes[i]) for i in g] + [idle_out] * (nent - len(g))
+                plan.decode(ins, outs, ws, shapes=[shapes[i] for i in g] + [(0, 0, 0)] * (nent - len(g)))
+                torch.cuda.synchronize()
+                for e, i in enumerate(g):
+                    assert same(ref[i][0], tmd.to_numpy(outs[e])), (flags, rep, g, i)
+                    assert plan.status(e) == ref[i][1]
+                for e in range(len(g), nent):
+                    assert plan.status(e) == 0
+                    assert int(idle_out["row_offset"][-1].item()) == 0
+        plan.free()
+
+
+def test_capacity_plan_rejects_larger_shape(tmd, frames):
+    shapes = [tmd.frame_shape(f) for f in frames]
+    plan = tmd.Plan([shapes[0]])
+    ws = plan.alloc_workspace()
+    big = tuple(v + 1 for v in shapes[0])
+    with pytest.raises(tmd.TmdError):
+        plan.decode([tmd.to_device(frames[0])], [tmd.alloc_out(big)], ws, shapes=[big])
+    plan.free()

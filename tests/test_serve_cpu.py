@@ -47,3 +47,15 @@ def test_admission_waits_for_memory():
 def test_percentile():
     assert serve.percentile([3, 1, 2], 50) == 2
     assert serve.percentile(list(range(101)), 99) == 99
+
+
+def test_capacity_growth():
+    """Plan capacity starts at 1.25x the first frame and grows by 1.25x past
+    any larger frame, per count."""
+    assert serve._grow((0, 0, 0), (100, 1000, 10)) == (126, 1251, 13)
+    assert serve._grow((126, 1251, 13), (100, 2000, 10)) == (126, 2501, 13)
+    srv = serve.Server(slots=1, max_batch=2, executor=lambda b: None)
+    srv.submit(fake_frame(100, 1000, 10))
+    srv.submit(fake_frame(50, 3000, 5))
+    srv.run_until(2, timeout=10)
+    assert srv.capacity == (126, 3751, 13)
