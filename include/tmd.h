@@ -194,13 +194,15 @@ const char *tmd_version(void);
 int tmd_tables(float bz, float *dst, int cap);
 
 /*
- * Stage timing.  With profiling on, tmd_decode records HIP events around each
+ * Stage timing.  tmd_set_profiling selects stages by bit (bit i = stage i as
+ * named by tmd_stage_name; 0 = off, ~0u = all); tmd_decode (not in
+ * TMD_PLAN_GRAPH mode) then records a pair of HIP events around each selected
  * stage on its stream.  tmd_stage_times waits for the recorded calls, writes
- * the summed milliseconds of each stage to ms[0 .. n-1] (stage order as named
- * by tmd_stage_name), the number of recorded calls to *calls, and clears the
- * record.  Returns the number of stages.
+ * the summed milliseconds of each stage to ms[0 .. n-1] (0 for unselected
+ * stages), the number of recorded calls to *calls, and clears the record.
+ * Returns the number of stages.
  */
-int tmd_set_profiling(tmd_plan_t *plan, int enable);
+int tmd_set_profiling(tmd_plan_t *plan, uint32_t stage_mask);
 int tmd_stage_times(tmd_plan_t *plan, double *ms, uint32_t n, uint32_t *calls);
 const char *tmd_stage_name(uint32_t stage);
 

@@ -172,8 +172,16 @@ class Plan:
             _lib.check(rc, "tmd_status")
         return int(f.value)
 
-    def set_profiling(self, on=True):
-        _lib.check(_lib.lib().tmd_set_profiling(self._h, 1 if on else 0), "tmd_set_profiling")
+    def set_profiling(self, on=True, stages=None):
+        """Record events around every stage (on=True), none (False), or the
+        named stages only (stages: iterable of stage names)."""
+        L = _lib.lib()
+        if stages is not None:
+            names = [L.tmd_stage_name(i).decode() for i in range(16)]
+            mask = sum(1 << names.index(st) for st in stages)
+        else:
+            mask = 0xFFFFFFFF if on else 0
+        _lib.check(L.tmd_set_profiling(self._h, mask), "tmd_set_profiling")
 
     def stage_times(self):
         """{stage: summed ms} over the profiled calls since the last read, and

@@ -69,7 +69,7 @@ def lib():
         L.tmd_version.restype = C.c_char_p
         L.tmd_tables.argtypes = [C.c_float, C.POINTER(C.c_float), C.c_int]
         L.tmd_tables.restype = C.c_int
-        L.tmd_set_profiling.argtypes = [P, C.c_int]
+        L.tmd_set_profiling.argtypes = [P, C.c_uint32]
         L.tmd_set_profiling.restype = C.c_int
         L.tmd_stage_times.argtypes = [P, C.POINTER(C.c_double), C.c_uint32, C.POINTER(C.c_uint32)]
         L.tmd_stage_times.restype = C.c_int

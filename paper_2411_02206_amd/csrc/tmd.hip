@@ -1375,8 +1375,9 @@ struct tmd_plan {
     bool called = false;  // `done` has been recorded at least once
     hipStream_t side = nullptr;  // default priority, non-blocking
     hipEvent_t fork = nullptr, join = nullptr;
-    bool profiling = false;
-    std::vector<std::vector<hipEvent_t>> prof_events;
+    uint32_t profiling = 0;                            // stage mask
+    std::vector<std::vector<hipEvent_t>> prof_events;  // per recorded call: 2 per stage (unrecorded: null)
+    std::vector<hipEvent_t> event_pool;                // events ready for reuse
     hipGraphExec_t graph = nullptr;   // TMD_PLAN_GRAPH: the captured launch sequence
     hipStream_t capture = nullptr;    // stream the graph is captured on
 };
@@ -1402,22 +1403,35 @@ bool aligned(const T *p)
 }
 
 // Enqueue the pipeline on stream s.  The unattached kernel depends only on
-// the offsets kernel, so it runs on the plan's side stream, concurrently with
-// the rank and attached kernels; the main stream waits for it at the end.
-// With profiling on, every stage is bracketed by its own pair of events on
-// the stream it runs on.
-int launch_all(tmd_plan_t *P, hipStream_t s, bool record)
+// the offsets kernel; it runs on the plan's side stream, forked after the rank
+// kernel so that it shares the GPU with the latency-bound attached kernel
+// rather than with the bandwidth-bound rank kernel; the main stream waits for
+// it at the end.
+// Each stage in the profiling mask is bracketed by its own pair of events on
+// the stream it runs on (events come from the plan's pool).
+int launch_all(tmd_plan_t *P, hipStream_t s, uint32_t mask)
 {
     std::vector<hipEvent_t> ev;
-    if (record) {
-        ev.resize(2 * kStages);
-        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    if (mask) {
+        ev.assign(2 * kStages, nullptr);
+        for (int st = 0; st < kStages; st++) {
+            if (!((mask >> st) & 1u)) continue;
+            for (int e = 0; e < 2; e++) {
+                if (!P->event_pool.empty()) {
+                    ev[2 * st + e] = P->event_pool.back();
+                    P->event_pool.pop_back();
+                } else {
+                    HIP_TRY(hipEventCreate(&ev[2 * st + e]));
+                }
+            }
+        }
     }
     auto begin = [&](int st, hipStream_t q) -> int {
-        return (record && hipEventRecord(ev[2 * st], q) != hipSuccess) ? TMD_E_HIP : TMD_OK;
+        return (ev.size() && ev[2 * st] && hipEventRecord(ev[2 * st], q) != hipSuccess) ? TMD_E_HIP : TMD_OK;
     };
     auto end = [&](int st, hipStream_t q) -> int {
-        return (record && hipEventRecord(ev[2 * st + 1], q) != hipSuccess) ? TMD_E_HIP : TMD_OK;
+        return (ev.size() && ev[2 * st + 1] && hipEventRecord(ev[2 * st + 1], q) != hipSuccess) ? TMD_E_HIP
+                                                                                              : TMD_OK;
     };
     const uint32_t T = P->total_tiles;
     hipStream_t s2 = P->side;
@@ -1433,21 +1447,23 @@ int launch_all(tmd_plan_t *P, hipStream_t s, bool record)
     if (end(3, s) || begin(4, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_offsets, dim3(P->n_frames), dim3(kOffThreads), 0, s, P->d_desc);
     if (end(4, s)) return TMD_E_HIP;
-    // fork: unattached decode on the side stream
+    if (begin(6, s)) return TMD_E_HIP;
+    if (T) hipLaunchKernelGGL(k_rank, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
+    if (end(6, s)) return TMD_E_HIP;
+    // fork: unattached decode on the side stream, beside the attached decode
+    // (which leaves memory bandwidth and issue slots free)
     HIP_TRY(hipEventRecord(P->fork, s));
     HIP_TRY(hipStreamWaitEvent(s2, P->fork, 0));
     if (begin(5, s2)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_unattached, dim3(NBIN, P->n_frames), dim3(kWave), 0, s2, P->d_desc);
     if (end(5, s2)) return TMD_E_HIP;
     HIP_TRY(hipEventRecord(P->join, s2));
-    if (begin(6, s)) return TMD_E_HIP;
-    if (T) hipLaunchKernelGGL(k_rank, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
-    if (end(6, s) || begin(7, s)) return TMD_E_HIP;
+    if (begin(7, s)) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_attached, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame, P->d_geo);
     if (end(7, s)) return TMD_E_HIP;
     HIP_TRY(hipStreamWaitEvent(s, P->join, 0));
     HIP_TRY(hipGetLastError());
-    if (record) P->prof_events.push_back(ev);
+    if (mask) P->prof_events.push_back(ev);
     return TMD_OK;
 }
 
@@ -1500,7 +1516,9 @@ void tmd_free(tmd_plan_t *P)
     if (hipGetDevice(&cur) == hipSuccess && cur != P->device) (void)hipSetDevice(P->device);
     if (P->done) (void)hipEventSynchronize(P->done);
     for (auto &v : P->prof_events)
-        for (auto e : v) (void)hipEventDestroy(e);
+        for (auto e : v)
+            if (e) (void)hipEventDestroy(e);
+    for (auto e : P->event_pool) (void)hipEventDestroy(e);
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
     if (P->side) (void)hipStreamSynchronize(P->side);
     if (P->fork) (void)hipEventDestroy(P->fork);
@@ -1703,7 +1721,7 @@ int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_fr
                     rc = TMD_E_HIP;
                     break;
                 }
-                rc = launch_all(P, P->capture, false);
+                rc = launch_all(P, P->capture, 0u);
                 hipError_t ec = hipStreamEndCapture(P->capture, &g);
                 if (rc != TMD_OK || ec != hipSuccess) {
                     if (g) (void)hipGraphDestroy(g);
@@ -1746,10 +1764,10 @@ int tmd_status(tmd_plan_t *P, uint32_t frame, uint32_t *flags)
     return TMD_OK;
 }
 
-int tmd_set_profiling(tmd_plan_t *P, int enable)
+int tmd_set_profiling(tmd_plan_t *P, uint32_t stage_mask)
 {
     if (!P) return TMD_E_ARG;
-    P->profiling = enable != 0;
+    P->profiling = stage_mask & ((1u << kStages) - 1u);
     return TMD_OK;
 }
 
@@ -1759,6 +1777,7 @@ int tmd_stage_times(tmd_plan_t *P, double *ms, uint32_t n, uint32_t *calls)
     std::vector<double> acc(kStages, 0.0);
     for (auto &ev : P->prof_events) {
         for (int i = 0; i < kStages; i++) {
+            if (!ev[2 * i]) continue;
             HIP_TRY(hipEventSynchronize(ev[2 * i + 1]));
             float t = 0.0f;
             HIP_TRY(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
@@ -1767,7 +1786,8 @@ int tmd_stage_times(tmd_plan_t *P, double *ms, uint32_t n, uint32_t *calls)
     }
     if (calls) *calls = (uint32_t)P->prof_events.size();
     for (auto &ev : P->prof_events)
-        for (auto e : ev) (void)hipEventDestroy(e);
+        for (auto e : ev)
+            if (e) P->event_pool.push_back(e);
     P->prof_events.clear();
     for (uint32_t i = 0; i < n && i < (uint32_t)kStages; i++) ms[i] = acc[i];
     return kStages;
