@@ -53,12 +53,13 @@ namespace {
 constexpr int kTile = 256;  // tracks per tile: K2, K6, K7 blocks
 constexpr int kWave = 64;
 constexpr int kTileWaves = kTile / kWave;
+constexpr int kAttWaves = 1;  // waves per workgroup of the attached decode
 constexpr uint32_t kTimeLim = 1u << 24;
 
 // ---------------------------------------------------------------------------
 // constant tables (float32, each the nearest float to a double expression)
 // ---------------------------------------------------------------------------
-struct RowGeo {  // one pad row, read with two 16-byte LDS loads
+struct RowGeo {  // one pad row (32 bytes)
     float x;       // local x of the row (cm)
     float inv_pw;  // 1 / pad width
     float padoff;  // half the number of pads (pad 0 is the -y edge)
@@ -67,6 +68,7 @@ struct RowGeo {  // one pad row, read with two 16-byte LDS loads
     float pw;      // pad width (cm)
     float unused;
 };
+static_assert(sizeof(RowGeo) == 32 && offsetof(RowGeo, ks) == 16, "row table layout");
 
 struct Geo {
     RowGeo row[NROW];
@@ -1089,13 +1091,38 @@ __device__ __forceinline__ void coop_place(const CoopLoad &C, uint2 (*ra)[kWave]
 // row-synchronous), 2: one cluster per lane per step.  In modes 0 and 1 all
 // lanes processing a step are on one row, so its table entry is read once per
 // wave through the scalar cache.
+// a wave-uniform row's table entry through the vector memory path: used when
+// the entry requested through the scalar cache one step ahead is not the
+// needed one, so that no second scalar load to the same registers is in
+// flight (which would make the next request wait for every LDS access)
+__device__ __forceinline__ RowGeo row_geo_vmem(const Geo *__restrict__ geo, uint32_t row)
+{
+    uint32_t r = row;
+    asm volatile("" : "+v"(r));  // a per-lane index: a vector load
+    const float4 a = *(const GLB float4 *)(&geo->row[r].x);
+    const float2 b = *(const GLB float2 *)(&geo->row[r].ks);
+    RowGeo R;
+    R.x = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(a.x)));
+    R.inv_pw = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(a.y)));
+    R.padoff = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(a.z)));
+    R.pwq = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(a.w)));
+    R.ks = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(b.x)));
+    R.kt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(b.y)));
+    R.pw = 0.0f;
+    return R;
+}
+
 template <int MODE>
 __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__restrict__ geo,
                                               uint2 (*ra)[kWave], uint2 (*rb)[kWave], uint2 (*stg)[kWave],
                                               LaneTrack &T)
 {
     const uint32_t lane = lane_id();
-    const float smax = geo->snp_max;
+    // constants in registers (loaded once: the loop's stores could alias them
+    // as far as the compiler knows); the rotation table one entry per lane,
+    // read with ds_bpermute
+    const float smax = geo->snp_max, vdq = geo->vdq, inv_vd32 = geo->inv_vd32;
+    const float rcos = lane < 18u ? geo->cosb[lane] : 0.0f, rsin = lane < 18u ? geo->sinb[lane] : 0.0f;
     const uint32_t n = T.n, c0 = T.c0;
     // first records straight into the ring: two rounds of kBlk
     uint32_t L = n < (uint32_t)kRing ? n : (uint32_t)kRing;  // records [0, L) have entered the ring
@@ -1119,7 +1146,16 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
     float x = T.x, y = T.y, z = T.z, s = T.s, tgl = T.tgl;
     const float k = T.k;
     const int32_t t0 = T.t0;
-    bool f_snp = false, f_rot = false, f_pad = false, f_time = false;
+    // status checks accumulate in registers and are turned into flags once,
+    // after the loop: out-of-range pads and times leave high bits in an OR of
+    // the raw values; a clamped |sin phi| (or a NaN) leaves |v - clamp(v)| > 0
+    // (or NaN) in a sum
+    uint32_t pad_or = 0, time_or = 0, rot_bad = 0;
+    float snp_dev = 0.0f;
+    // modes 0 and 1: the table entry of the row after the last one, requested
+    // one step ahead (the step's row is that row unless the wave skips rows)
+    uint32_t grow = MODE == 0 ? 0u : (uint32_t)NROW - 1u;
+    RowGeo Rn = geo->row[grow];
     // of two consecutive blocks at least one decodes a cluster (a block in
     // which no lane has a record in its ring refills them), so 2 * 64 * 255
     // blocks always suffice
@@ -1128,6 +1164,7 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
             const bool live = j < L;
             if (__ballot(live) == 0) break;
             bool ready = live;
+            RowGeo R;
             if (MODE != 2) {
                 // rows 0..151; the descending mode works on 255 - row.  The
                 // pending minimum is usually the row after the last one; only
@@ -1141,68 +1178,75 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
                     vrow = wave_min(v);
                     ready = live && v == vrow;
                 }
+                const uint32_t urow = MODE == 0 ? vrow : 255u - vrow;  // the row of every ready lane
+                R = Rn;
+                if (urow != grow) R = row_geo_vmem(geo, urow);
+            }
+            // rotation by d sectors, rare: a wave-uniform branch, the table
+            // entry from lane d (read while every lane is active)
+            const uint32_t d = (cur.y >> 8) & 0xFFu;  // 0..17
+            const bool rot = ready && j > 0 && d != 0;
+            if (__ballot(rot) != 0) {
+                const float ca = __uint_as_float(bperm(__float_as_uint(rcos), d));
+                const float sa = __uint_as_float(bperm(__float_as_uint(rsin), d));
+                if (rot) {
+                    const float cs = sqrt_pos((1.0f - s) * (1.0f + s));
+                    const float xn = (x * ca) + (y * sa);
+                    const float yn = (y * ca) - (x * sa);
+                    const float sn = (s * ca) - (cs * sa);
+                    const float cn = (cs * ca) + (s * sa);
+                    rot_bad |= (cn > 0.0f) ? 0u : 1u;
+                    x = xn;
+                    y = yn;
+                    const float sc = __builtin_amdgcn_fmed3f(sn, -smax, smax);
+                    snp_dev = snp_dev + fabsf(sn - sc);
+                    s = sn != sn ? 0.0f : sc;
+                }
             }
             if (ready) {
                 const uint2 rec = cur;  // x = residuals, y = row | rotation << 8
                 uint32_t otime = (uint32_t)t0, opad = T.pad0;
                 if (j > 0) {
-                    const uint32_t d = (rec.y >> 8) & 0xFFu;  // 0..17
-                    if (d != 0) {
-                        // table entry through the scalar cache, once per
-                        // distinct d among the rotating lanes
-                        float ca = 0.0f, sa = 0.0f;
-                        for (;;) {
-                            const uint32_t ud = __builtin_amdgcn_readfirstlane(d);
-                            if (d == ud) {
-                                ca = geo->cosb[ud];
-                                sa = geo->sinb[ud];
-                                break;
-                            }
-                        }
-                        const float cs = sqrt_pos((1.0f - s) * (1.0f + s));
-                        const float xn = (x * ca) + (y * sa);
-                        const float yn = (y * ca) - (x * sa);
-                        const float sn = (s * ca) - (cs * sa);
-                        const float cn = (cs * ca) + (s * sa);
-                        f_rot |= !(cn > 0.0f);
-                        x = xn;
-                        y = yn;
-                        s = clamp_snp_b(sn, smax, f_snp);
-                    }
-                    const uint32_t row = rec.y & 0xFFu;
-                    const RowGeo R = geo->row[MODE != 2 ? __builtin_amdgcn_readfirstlane(row) : row];
+                    if (MODE == 2) R = geo->row[rec.y & 0xFFu];
                     const float dx = R.x - x;
-                    const float s1 = clamp_snp_b(s + (k * dx), smax, f_snp);
+                    const float s1r = s + (k * dx);
+                    const float s1c = __builtin_amdgcn_fmed3f(s1r, -smax, smax);
+                    const float s1 = s1r != s1r ? 0.0f : s1c;
                     const float a0 = sqrt_pos((1.0f - s) * (1.0f + s));
                     const float a1 = sqrt_pos((1.0f - s1) * (1.0f + s1));
                     const float dydx = (s + s1) / (a0 + a1);
                     y = y + (dx * dydx);
                     z = z + (tgl * (dx * sqrt_pos(1.0f + (dydx * dydx))));
-                    s = s1;
                     x = R.x;
                     const int32_t P = sat_rint(((y * R.inv_pw) + R.padoff) * 32.0f);
-                    const int32_t Tq = sat_rint(z * geo->inv_vd32);
+                    const int32_t Tq = sat_rint(z * inv_vd32);
                     const int32_t pres = (int32_t)(int16_t)(rec.x & 0xFFFFu);
                     const int32_t tres = (int32_t)(int16_t)(rec.x >> 16);
-                    int32_t padq = P + pres;
-                    f_pad |= padq < 0 || padq > 65535;
-                    padq = padq < 0 ? 0 : (padq > 65535 ? 65535 : padq);
-                    int32_t timeq = t0 + Tq + tres;
-                    f_time |= timeq < 0 || timeq > (int32_t)kTimeLim - 1;
-                    timeq = timeq < 0 ? 0 : (timeq > (int32_t)kTimeLim - 1 ? (int32_t)kTimeLim - 1 : timeq);
-                    otime = (uint32_t)timeq;
-                    opad = (uint32_t)padq;
+                    const int32_t padq = P + pres;
+                    const int32_t timeq = t0 + Tq + tres;
+                    pad_or |= (uint32_t)padq;
+                    time_or |= (uint32_t)timeq;
+                    otime = (uint32_t)min(max(timeq, 0), (int32_t)kTimeLim - 1);
+                    opad = (uint32_t)min(max(padq, 0), 65535);
                     const float nuy = (float)pres * R.pwq;
-                    const float nuz = (float)tres * geo->vdq;
+                    const float nuz = (float)tres * vdq;
                     y = y + nuy;
                     z = z + nuz;
-                    s = clamp_snp_b(s + (nuy * R.ks), smax, f_snp);
+                    const float s2r = s1 + (nuy * R.ks);
+                    const float s2c = __builtin_amdgcn_fmed3f(s2r, -smax, smax);
+                    snp_dev = snp_dev + (fabsf(s1r - s1c) + fabsf(s2r - s2c));
+                    s = s2r != s2r ? 0.0f : s2c;
                     tgl = tgl + (nuz * R.kt);
                 }
                 stg[st][lane] = make_uint2(otime, opad);
                 rmask |= 1u << st;
                 j++;
                 if (j < L) cur = rb[j % kRing][lane];
+            }
+            if (MODE != 2) {
+                const uint32_t g = MODE == 0 ? vrow + 1u : 254u - vrow;
+                grow = g < (uint32_t)NROW ? g : (uint32_t)NROW - 1u;
+                Rn = geo->row[grow];
             }
         }
         // block boundary.  Records loaded at the last boundary enter the ring:
@@ -1246,24 +1290,27 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
         if (__ballot(j < n) == 0) break;
         coop_load(F, c0 + L, L, m, nb);
     }
-    T.fl |= (f_snp ? TMD_F_SNP : 0u) | (f_rot ? TMD_F_ROT : 0u) | (f_pad ? TMD_F_PAD : 0u) |
-            (f_time ? TMD_F_TIME : 0u);
+    T.fl |= (snp_dev != 0.0f ? TMD_F_SNP : 0u) | (rot_bad ? TMD_F_ROT : 0u) |
+            ((pad_or & 0xFFFF0000u) ? TMD_F_PAD : 0u) | ((time_or & ~(kTimeLim - 1u)) ? TMD_F_TIME : 0u);
 }
 
-__global__ __launch_bounds__(kTile) void k_attached(const FrameDesc *__restrict__ fd,
-                                                    const uint32_t *__restrict__ tile_frame,
-                                                    const Geo *__restrict__ geo)
+__global__ __launch_bounds__(kAttWaves * kWave) void k_attached(const FrameDesc *__restrict__ fd,
+                                                               const uint32_t *__restrict__ tile_frame,
+                                                               const Geo *__restrict__ geo)
 {
-    // LDS holds only the record rings and staging (40 KB per block, so four
-    // blocks fit a CU); the tables stay in global memory.
-    __shared__ uint2 ra[kTileWaves][kRing][kWave];  // record rings: (output slot, charges)
-    __shared__ uint2 rb[kTileWaves][kRing][kWave];  // (residuals, row | rotation << 8)
-    __shared__ uint2 stg[kTileWaves][kBlk][kWave];  // per step of the block: the decoded (time, pad)
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    // LDS holds only the record rings and staging (10 KB per wave); the
+    // tables stay in global memory.  Workgroups of kAttWaves waves: the
+    // grid's waves are all resident at once, and small workgroups let the
+    // dispatcher spread them evenly over the CUs.
+    __shared__ uint2 ra[kAttWaves][kRing][kWave];  // record rings: (output slot, charges)
+    __shared__ uint2 rb[kAttWaves][kRing][kWave];  // (residuals, row | rotation << 8)
+    __shared__ uint2 stg[kAttWaves][kBlk][kWave];  // per step of the block: the decoded (time, pad)
+    const uint32_t gw = xcd_tile(blockIdx.x, gridDim.x) * kAttWaves + threadIdx.x / kWave;  // wave of the grid
+    const uint32_t tile = gw / kTileWaves;
     const FrameDesc F = fd[tile_frame[tile]];
     if (tile - F.tile0 >= F.ntile) return;  // a tile of the planned capacity beyond this call's frame
-    const uint32_t slot = (tile - F.tile0) * kTile + threadIdx.x;
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+    const uint32_t slot = (tile - F.tile0) * kTile + (gw % kTileWaves) * kWave + lane;
     LaneTrack T = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0, 0u, 0u, 0u, 0u};
     uint32_t cls = 2;
     if (slot < F.nT) {
@@ -1459,7 +1506,9 @@ int launch_all(tmd_plan_t *P, hipStream_t s, uint32_t mask)
     if (end(5, s2)) return TMD_E_HIP;
     HIP_TRY(hipEventRecord(P->join, s2));
     if (begin(7, s)) return TMD_E_HIP;
-    if (T) hipLaunchKernelGGL(k_attached, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame, P->d_geo);
+    if (T)
+        hipLaunchKernelGGL(k_attached, dim3(T * (kTileWaves / kAttWaves)), dim3(kAttWaves * kWave), 0, s, P->d_desc,
+                           P->d_tile_frame, P->d_geo);
     if (end(7, s)) return TMD_E_HIP;
     HIP_TRY(hipStreamWaitEvent(s, P->join, 0));
     HIP_TRY(hipGetLastError());
