@@ -158,7 +158,6 @@ constexpr int kHRow = NBIN + kNKey;  // per-tile histogram row: bins, then keys
     Q uint32_t *start;   /* [nT + 1] first cluster of each track */                           \
     Q uint32_t *tilesum; /* [ntile] clusters per tile */                                      \
     Q uint32_t *hist;    /* [ntile][kHRow] per-tile bin/key counts, then exclusive prefixes */ \
-    Q uint32_t *woff;    /* [ntile][4][NBIN] u16 pairs: bin offset of each wave in its tile */ \
     Q uint32_t *uin;     /* [NBIN] first unattached input entry of each bin */                \
     Q uint32_t *ueff;    /* [NBIN] unattached clusters decoded per bin */                     \
     Q uint4 *recs;       /* [nA] per-cluster records for the decode, stream order */          \
@@ -489,12 +488,13 @@ constexpr int kGroup = 4;  // chunks loaded together by a walk
 __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ fd,
                                                  const uint32_t *__restrict__ tile_frame)
 {
-    // per-wave 16-bit bin counters (a wave's 64 tracks put at most 64*255
-    // clusters in one bin; the prefix of three waves stays below 2^16)
-    __shared__ uint32_t wcnt32[kTileWaves * NBIN / 2];
+    // the tile's 16-bit bin counters, shared by its waves (256 tracks put at
+    // most 256 * 255 < 2^16 clusters in one bin); 13 KB of LDS in all, so
+    // that every tile of a frame can be resident at once
+    __shared__ uint32_t wcnt32[NBIN / 2];
     __shared__ uint32_t khist[kNKey];
     __shared__ WaveLds wl[kTileWaves];
-    uint16_t *wcnt = reinterpret_cast<uint16_t *>(wcnt32);
+    const uint16_t *wcnt = reinterpret_cast<const uint16_t *>(wcnt32);
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
     uint32_t before;
     block_excl_add(pre, &before);
 
-    for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wcnt32[i] = 0;
+    for (uint32_t i = threadIdx.x; i < NBIN / 2; i += kTile) wcnt32[i] = 0;
     for (uint32_t i = threadIdx.x; i < kNKey; i += kTile) khist[i] = 0;
     const uint32_t nc = t < F.nT ? F.ncls[t] : 0u;
     uint32_t tot;
@@ -559,8 +559,7 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
                 uint32_t clr = 0;
                 if (act) {
                     F.ckey[c] = (uint16_t)key;
-                    const uint32_t idx = w * NBIN + key;
-                    atomicAdd(&wcnt32[idx >> 1], 1u << (16 * (idx & 1)));
+                    atomicAdd(&wcnt32[key >> 1], 1u << (16 * (key & 1)));
                     const bool head = L.hm[lane] != 0xFFu;
                     if (clamped) clr = 3u;
                     else if (!head) clr = (P.rd[u] > 0 ? 0u : 1u) | (P.rd[u] < 0 ? 0u : 2u);
@@ -597,21 +596,10 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
         }
     }
     __syncthreads();
-    // per bin: offsets of the waves inside the tile, and the tile total
+    // the tile's row of the histogram: bin counts, then key counts
     GLB uint32_t *dst = F.hist + (size_t)lt * kHRow;
-    for (uint32_t k = threadIdx.x; k < NBIN; k += kTile) {
-        uint32_t run = 0;
-        for (uint32_t i = 0; i < kTileWaves; i++) {
-            const uint32_t v = wcnt[i * NBIN + k];
-            wcnt[i * NBIN + k] = (uint16_t)run;
-            run += v;
-        }
-        dst[k] = run;
-    }
+    for (uint32_t k = threadIdx.x; k < NBIN; k += kTile) dst[k] = wcnt[k];
     for (uint32_t i = threadIdx.x; i < kNKey; i += kTile) dst[NBIN + i] = khist[i];
-    __syncthreads();
-    GLB uint32_t *wo = F.woff + (size_t)lt * (kTileWaves * NBIN / 2);
-    for (uint32_t i = threadIdx.x; i < kTileWaves * NBIN / 2; i += kTile) wo[i] = wcnt32[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -811,17 +799,23 @@ __global__ __launch_bounds__(kWave) void k_unattached(const FrameDesc *__restric
 // residuals, charges and (sector,row) as one 16-byte record in stream order;
 // also places the tile's tracks in the decode schedule.  Within a bin the slot
 // order is the stream order (track, then cluster).  Block = one tile of 256
-// tracks; wave w takes the clusters of tracks 64w..64w+63 of the tile (one
-// contiguous range of the stream, with the bins the count kernel stored), 64
-// per chunk.  LDS: per-wave 16-bit bin counters, starting at the wave's
-// in-tile offsets from the count kernel, and the tile's bin bases.
+// tracks, whose clusters are one contiguous range of the stream (with the
+// bins the count kernel stored).  LDS holds one running slot per bin (bin
+// base + tile prefix, advanced by atomic adds): 24 KB, so that every tile of
+// a frame can be resident at once.  The range is cut into groups of 256
+// clusters, taken by the four waves in turn (group q by wave q % 4).  A
+// group's slots are taken in stream order: the wave waits until the tile's
+// turn counter reaches q, issues its four chunks' atomic adds (each followed
+// by a read-back of the counters), and sets the turn to q + 1.  LDS executes
+// one wave's operations in issue order, so the next wave can only see the new
+// turn once the atomics are done; no wait is needed in between.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd,
                                                 const uint32_t *__restrict__ tile_frame)
 {
-    __shared__ uint32_t wcnt32[kTileWaves * NBIN / 2];  // 16-bit counters, packed
-    __shared__ uint32_t base[NBIN];
+    __shared__ uint32_t base[NBIN];                // next slot of each bin
     __shared__ uint32_t kcnt[kTileWaves][kNKey];  // tracks per (wave, scheduling key)
+    __shared__ uint32_t turn;                      // the group whose slots are taken next
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
@@ -831,11 +825,6 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
     const uint32_t t = lt * kTile + threadIdx.x;
     static_assert(kNKey <= 128, "schedule keys are matched on 7 bits");
 
-    // the tile's in-tile wave offsets (16-byte aligned: 43776 bytes per tile)
-    constexpr uint32_t kWoffVec = kTileWaves * NBIN / 8;
-    copy_to_lds<(kWoffVec + kTile - 1) / kTile, kTile>(
-        reinterpret_cast<uint4 *>(wcnt32),
-        reinterpret_cast<const GLB uint4 *>(F.woff + (size_t)lt * (kTileWaves * NBIN / 2)), kWoffVec);
     {
         constexpr int kPer = (NBIN + kTile - 1) / kTile;
         uint32_t ro[kPer], gg[kPer];
@@ -852,6 +841,7 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
         }
     }
     for (uint32_t i = threadIdx.x; i < kTileWaves * kNKey; i += kTile) (&kcnt[0][0])[i] = 0;
+    if (threadIdx.x == 0) turn = 0;
     const bool tv = t < F.nT;
     const uint32_t tk = tv ? (uint32_t)F.tkey[t] : 0u;
     __syncthreads();
@@ -872,18 +862,17 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
         F.order[F.keyinfo[kNKey + tk] + G[NBIN + tk] + local] = t;
     }
 
-    const uint32_t tw = lt * kTile + w * kWave;
-    if (tw >= F.nT) return;
-    // the wave's clusters: [start of track tw, start of track tw + 64) within nA
-    const uint32_t te = tw + kWave < F.nT ? tw + kWave : F.nT;
-    const uint32_t A = F.start[tw] < F.nA ? F.start[tw] : F.nA;
+    // the tile's clusters: [start of its first track, start of the next tile)
+    // within nA
+    const uint32_t tf = lt * kTile;
+    const uint32_t te = tf + kTile < F.nT ? tf + kTile : F.nT;
+    const uint32_t A = F.start[tf] < F.nA ? F.start[tf] : F.nA;
     const uint32_t E = F.start[te] < F.nA ? F.start[te] : F.nA;
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    // a group of kGroup chunks: its loads, then its ranks and records.  Two
-    // groups alternate so that the loads of one are in flight while the other
-    // is ranked.
-    // Loads are unconditional (lanes past E read cluster E - 1 and ignore it)
-    // and raw, so that nothing waits for them until the group is ranked.
+    // a group of kGroup chunks: its loads, then its ranks and records.  A
+    // wave's next group is loaded while the current one is ranked.  Loads are
+    // unconditional (lanes past E read cluster E - 1 and ignore it) and raw,
+    // so that nothing waits for them until the group is ranked.
     struct Group {
         uint32_t key[kGroup], sd[kGroup], pr[kGroup], tr[kGroup], qt[kGroup], qm[kGroup];
     };
@@ -900,50 +889,92 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
             P.qm[u] = F.cqmax[cc];
         }
     };
-    auto rank = [&](uint32_t g, const Group &P) {
+    auto rank = [&](uint32_t q, uint32_t g, const Group &P) {
+        uint32_t k[kGroup], r[kGroup], fin[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; u++) k[u] = P.key[u] < (uint32_t)NBIN ? P.key[u] : 0u;
+        // the bins are in registers before the turn is taken (no load is
+        // waited for while the turn is held)
+        asm volatile("" ::"v"(k[0]), "v"(k[1]), "v"(k[2]), "v"(k[3]));
+        static_assert(kGroup == 4, "four chunks per group");
+        // wait for this group's turn (bounded: the waves of the block are all
+        // resident and every turn is passed on, so the bound is never reached
+        // unless something is broken; then the frame is flagged)
+        for (uint32_t spin = 0; __hip_atomic_load(&turn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != q;
+             spin++) {
+            if (spin == (1u << 22)) {
+                if (lane == 0) atomicOr(F.status, TMD_F_COUNT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        // slots in stream order: per chunk, one atomic add per lane and a
+        // read-back of the counters after it (the returned value is the rank
+        // if no other lane of the chunk has the same bin)
+#pragma unroll
+        for (int u = 0; u < kGroup; u++) {
+            r[u] = 0;
+            fin[u] = 0;
+            const uint32_t c = g + u * kWave + lane;
+            if (c < E) r[u] = atomicAdd(&base[k[u]], 1u);
+            __builtin_amdgcn_wave_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (c < E) fin[u] = __hip_atomic_load(&base[k[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __builtin_amdgcn_wave_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (lane == 0) __hip_atomic_store(&turn, q + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
         for (int u = 0; u < kGroup; u++) {
             const uint32_t lo = g + u * kWave;
             if (lo >= E) break;
             const uint32_t c = lo + lane;
             const bool act = c < E;
-            const uint32_t k = P.key[u] < (uint32_t)NBIN ? P.key[u] : 0u;
-            const uint32_t idx = w * NBIN + k;
-            const uint32_t sh = (idx & 1u) * 16u;
-            // count this cluster; the returned value is its rank if no other
-            // lane of the chunk has the same bin
-            uint32_t r = 0, fin = 0;
-            if (act) r = (atomicAdd(&wcnt32[idx >> 1], 1u << sh) >> sh) & 0xFFFFu;
-            __builtin_amdgcn_wave_barrier();
-            if (act) fin = (wcnt32[idx >> 1] >> sh) & 0xFFFFu;
-            if (__ballot(act && fin - r != 1u)) {
+            uint32_t slot = r[u];
+            if (__ballot(act && fin[u] - r[u] != 1u)) {
                 // some bin occurs more than once in the chunk: rank those
                 // lanes in lane (= stream) order
                 uint64_t same = __ballot(act);
 #pragma unroll
                 for (int bit = 0; bit < 13; bit++) {
-                    const uint64_t m = __ballot(act && ((k >> bit) & 1u));
-                    same &= ((k >> bit) & 1u) ? m : ~m;
+                    const uint64_t m = __ballot(act && ((k[u] >> bit) & 1u));
+                    same &= ((k[u] >> bit) & 1u) ? m : ~m;
                 }
-                r = fin - (uint32_t)__popcll(same) + (uint32_t)__popcll(same & lt_mask);
+                slot = fin[u] - (uint32_t)__popcll(same) + (uint32_t)__popcll(same & lt_mask);
             }
             if (act) {
                 const uint32_t rot = P.sd[u] < 18u ? P.sd[u] : P.sd[u] % 18u;
-                F.recs[c] = make_uint4(base[k] + r, P.pr[u] | (P.tr[u] << 16), P.qt[u] | (P.qm[u] << 16),
-                                       (k % NROW) | (rot << 8));
+                F.recs[c] = make_uint4(slot, P.pr[u] | (P.tr[u] << 16), P.qt[u] | (P.qm[u] << 16),
+                                       (k[u] % NROW) | (rot << 8));
             }
-            __builtin_amdgcn_wave_barrier();
         }
     };
     constexpr uint32_t kStep = kWave * kGroup;
-    Group P0, P1;
-    if (A < E) load(A, P0);
-    for (uint32_t g = A; g < E; g += 2 * kStep) {
-        load(g + kStep, P1);
-        rank(g, P0);
-        if (g + kStep >= E) break;
-        load(g + 2 * kStep, P0);
-        rank(g + kStep, P1);
+    const uint32_t nq = (E - A + kStep - 1) / kStep;  // groups of the tile
+    // Each wave loads two of its groups ahead (its turns come every fourth
+    // group, and a turn should not wait for loads).  Loads of groups past the
+    // end read cluster E - 1: unconditional, so that waiting for one group
+    // never waits for a later one's loads.
+    Group P0, P1, P2;
+    constexpr uint32_t kW = kTileWaves;
+    uint32_t q = w;
+    if (q < nq) {
+        load(A + q * kStep, P0);
+        load(A + (q + kW) * kStep, P1);
+        for (;; q += 3 * kW) {
+            load(A + (q + 2 * kW) * kStep, P2);
+            rank(q, A + q * kStep, P0);
+            if (q + kW >= nq) break;
+            load(A + (q + 3 * kW) * kStep, P0);
+            rank(q + kW, A + (q + kW) * kStep, P1);
+            if (q + 2 * kW >= nq) break;
+            load(A + (q + 4 * kW) * kStep, P1);
+            rank(q + 2 * kW, A + (q + 2 * kW) * kStep, P2);
+            if (q + 3 * kW >= nq) break;
+        }
     }
 }
 
@@ -1395,7 +1426,7 @@ const char *kStageNames[kStages] = {"setup", "tilesum", "count", "colscan", "off
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct FrameLayout {
-    size_t start, tilesum, hist, woff, uin, ueff, recs, ckey, keyinfo, tkey, order;
+    size_t start, tilesum, hist, uin, ueff, recs, ckey, keyinfo, tkey, order;
     uint32_t ntile, tile0;
 };
 
@@ -1611,7 +1642,6 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
         L.start = off;   off += align256(4 * ((size_t)S.n_tracks + 1));
         L.tilesum = off; off += align256(4 * (size_t)(L.ntile ? L.ntile : 1));
         L.hist = off;    off += align256(4 * (size_t)L.ntile * kHRow);
-        L.woff = off;    off += align256(2 * (size_t)L.ntile * kTileWaves * NBIN);
         L.uin = off;     off += align256(4 * (size_t)NBIN);
         L.ueff = off;    off += align256(4 * (size_t)NBIN);
         L.recs = off;    off += align256(16 * (size_t)(S.n_attached ? S.n_attached : 1));
@@ -1726,7 +1756,6 @@ int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_fr
         D.start = (uint32_t *)(ws + L.start);
         D.tilesum = (uint32_t *)(ws + L.tilesum);
         D.hist = (uint32_t *)(ws + L.hist);
-        D.woff = (uint32_t *)(ws + L.woff);
         D.uin = (uint32_t *)(ws + L.uin);
         D.ueff = (uint32_t *)(ws + L.ueff);
         D.recs = (uint4 *)(ws + L.recs);
