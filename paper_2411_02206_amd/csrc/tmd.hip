@@ -1499,7 +1499,9 @@ int launch_all(tmd_plan_t *P, hipStream_t s, uint32_t mask)
                     ev[2 * st + e] = P->event_pool.back();
                     P->event_pool.pop_back();
                 } else {
-                    HIP_TRY(hipEventCreate(&ev[2 * st + e]));
+                    // timing only: no system-scope fence (no cache write-back
+                    // and invalidation around the timed kernels)
+                    HIP_TRY(hipEventCreateWithFlags(&ev[2 * st + e], hipEventDisableSystemFence));
                 }
             }
         }
@@ -1681,8 +1683,12 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
         }
         if (hipEventCreateWithFlags(&P->desc_done, hipEventDisableTiming) != hipSuccess) { rc = TMD_E_HIP; break; }
         if (hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess) { rc = TMD_E_HIP; break; }
-        if (hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) != hipSuccess) { rc = TMD_E_HIP; break; }
-        if (hipEventCreateWithFlags(&P->join, hipEventDisableTiming) != hipSuccess) { rc = TMD_E_HIP; break; }
+        // fork and join only order the plan's two streams on one device: no
+        // system-scope fence.  done (the host reads the status copy after it)
+        // and desc_done keep theirs.
+        constexpr unsigned kDevOnly = hipEventDisableTiming | hipEventDisableSystemFence;
+        if (hipEventCreateWithFlags(&P->fork, kDevOnly) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if (hipEventCreateWithFlags(&P->join, kDevOnly) != hipSuccess) { rc = TMD_E_HIP; break; }
         if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess) { rc = TMD_E_HIP; break; }
         if ((p->flags & TMD_PLAN_GRAPH) &&
             hipStreamCreateWithFlags(&P->capture, hipStreamNonBlocking) != hipSuccess) {
