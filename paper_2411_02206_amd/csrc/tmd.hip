@@ -1451,8 +1451,6 @@ struct tmd_plan {
     hipEvent_t desc_done = nullptr;
     hipEvent_t done = nullptr;
     bool called = false;  // `done` has been recorded at least once
-    hipStream_t side = nullptr;  // default priority, non-blocking
-    hipEvent_t fork = nullptr, join = nullptr;
     uint32_t profiling = 0;                            // stage mask
     std::vector<std::vector<hipEvent_t>> prof_events;  // per recorded call: 2 per stage (unrecorded: null)
     std::vector<hipEvent_t> event_pool;                // events ready for reuse
@@ -1480,13 +1478,9 @@ bool aligned(const T *p)
     return ((uintptr_t)p % alignof(T)) == 0;
 }
 
-// Enqueue the pipeline on stream s.  The unattached kernel depends only on
-// the offsets kernel; it runs on the plan's side stream, forked after the rank
-// kernel so that it shares the GPU with the latency-bound attached kernel
-// rather than with the bandwidth-bound rank kernel; the main stream waits for
-// it at the end.
-// Each stage in the profiling mask is bracketed by its own pair of events on
-// the stream it runs on (events come from the plan's pool).
+// Enqueue the pipeline on stream s, one kernel after the other.  Each stage
+// in the profiling mask is bracketed by its own pair of events (from the
+// plan's pool).
 int launch_all(tmd_plan_t *P, hipStream_t s, uint32_t mask)
 {
     std::vector<hipEvent_t> ev;
@@ -1514,7 +1508,6 @@ int launch_all(tmd_plan_t *P, hipStream_t s, uint32_t mask)
                                                                                               : TMD_OK;
     };
     const uint32_t T = P->total_tiles;
-    hipStream_t s2 = P->side;
     if (begin(0, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_setup, dim3(P->n_frames), dim3(kWave), 0, s, P->d_desc);
     if (end(0, s) || begin(1, s)) return TMD_E_HIP;
@@ -1530,20 +1523,17 @@ int launch_all(tmd_plan_t *P, hipStream_t s, uint32_t mask)
     if (begin(6, s)) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_rank, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
     if (end(6, s)) return TMD_E_HIP;
-    // fork: unattached decode on the side stream, beside the attached decode
-    // (which leaves memory bandwidth and issue slots free)
-    HIP_TRY(hipEventRecord(P->fork, s));
-    HIP_TRY(hipStreamWaitEvent(s2, P->fork, 0));
-    if (begin(5, s2)) return TMD_E_HIP;
-    hipLaunchKernelGGL(k_unattached, dim3(NBIN, P->n_frames), dim3(kWave), 0, s2, P->d_desc);
-    if (end(5, s2)) return TMD_E_HIP;
-    HIP_TRY(hipEventRecord(P->join, s2));
+    // attached decode, then the unattached one.  (Run side by side on two
+    // streams they take as long in all: the unattached waves slow the attached
+    // decode by about what they take alone.)
     if (begin(7, s)) return TMD_E_HIP;
     if (T)
         hipLaunchKernelGGL(k_attached, dim3(T * (kTileWaves / kAttWaves)), dim3(kAttWaves * kWave), 0, s, P->d_desc,
                            P->d_tile_frame, P->d_geo);
     if (end(7, s)) return TMD_E_HIP;
-    HIP_TRY(hipStreamWaitEvent(s, P->join, 0));
+    if (begin(5, s)) return TMD_E_HIP;
+    hipLaunchKernelGGL(k_unattached, dim3(NBIN, P->n_frames), dim3(kWave), 0, s, P->d_desc);
+    if (end(5, s)) return TMD_E_HIP;
     HIP_TRY(hipGetLastError());
     if (mask) P->prof_events.push_back(ev);
     return TMD_OK;
@@ -1602,10 +1592,6 @@ void tmd_free(tmd_plan_t *P)
             if (e) (void)hipEventDestroy(e);
     for (auto e : P->event_pool) (void)hipEventDestroy(e);
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
-    if (P->side) (void)hipStreamSynchronize(P->side);
-    if (P->fork) (void)hipEventDestroy(P->fork);
-    if (P->join) (void)hipEventDestroy(P->join);
-    if (P->side) (void)hipStreamDestroy(P->side);
     if (P->capture) (void)hipStreamDestroy(P->capture);
     if (P->desc_done) (void)hipEventDestroy(P->desc_done);
     if (P->done) (void)hipEventDestroy(P->done);
@@ -1683,13 +1669,6 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
         }
         if (hipEventCreateWithFlags(&P->desc_done, hipEventDisableTiming) != hipSuccess) { rc = TMD_E_HIP; break; }
         if (hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess) { rc = TMD_E_HIP; break; }
-        // fork and join only order the plan's two streams on one device: no
-        // system-scope fence.  done (the host reads the status copy after it)
-        // and desc_done keep theirs.
-        constexpr unsigned kDevOnly = hipEventDisableTiming | hipEventDisableSystemFence;
-        if (hipEventCreateWithFlags(&P->fork, kDevOnly) != hipSuccess) { rc = TMD_E_HIP; break; }
-        if (hipEventCreateWithFlags(&P->join, kDevOnly) != hipSuccess) { rc = TMD_E_HIP; break; }
-        if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess) { rc = TMD_E_HIP; break; }
         if ((p->flags & TMD_PLAN_GRAPH) &&
             hipStreamCreateWithFlags(&P->capture, hipStreamNonBlocking) != hipSuccess) {
             rc = TMD_E_HIP;
