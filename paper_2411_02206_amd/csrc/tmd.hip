@@ -21,16 +21,17 @@
 // the result is bit-identical to any other implementation of the same
 // equations under the same rules.
 //
-// Pipeline (all frames of a plan in each launch):
-//   K1 k_tilesum     sum of track lengths per tile of 256 tracks
+// Pipeline (all frames of a plan in each launch, in this order):
+//   K1 k_tilesum     sum of track lengths per tile of 256 tracks; clears the
+//                    frames' status words
 //   K2 k_count       track start offsets (scan), per-cluster (sector,row) walk,
 //                    per-tile bin histogram
 //   K3 k_colscan     per bin, exclusive prefix of the tile histograms
 //   K4 k_offsets     per frame, bin offsets of the output and of the
 //                    unattached input (flags count mismatches)
-//   K5 k_unattached  per bin, running sums of the differences (one wave)
 //   K6 k_rank        per tile, stable slot of every attached cluster
 //   K7 k_attached    one lane per track: the float32 propagate-and-update
+//   K5 k_unattached  per bin, running sums of the differences (one wave)
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -306,20 +307,16 @@ __device__ __forceinline__ void step_pos(int &sec, int &row, int rd, uint32_t sd
 }
 
 // ---------------------------------------------------------------------------
-// K0: clear the per-frame status word
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWave) void k_setup(const FrameDesc *__restrict__ fd)
-{
-    const FrameDesc F = fd[blockIdx.x];
-    if (threadIdx.x == 0) *F.status = 0u;
-}
-
-// ---------------------------------------------------------------------------
-// K1: clusters per tile
+// K1: clusters per tile (the extra blocks after the tiles clear the status
+// word of each frame)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTile) void k_tilesum(const FrameDesc *__restrict__ fd,
-                                                   const uint32_t *__restrict__ tile_frame)
+                                                   const uint32_t *__restrict__ tile_frame, uint32_t ntiles)
 {
+    if (blockIdx.x >= ntiles) {  // one extra block per frame: clear its status word
+        if (threadIdx.x == 0) *fd[blockIdx.x - ntiles].status = 0u;
+        return;
+    }
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
@@ -609,6 +606,7 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
 // ---------------------------------------------------------------------------
 constexpr int kScanWaves = 16;
 constexpr int kColBatch = 8;
+constexpr int kColKeep = 64;  // column entries per wave kept in registers (a frame of 64 * 16 tiles)
 
 __global__ __launch_bounds__(kWave * kScanWaves) void k_colscan(const FrameDesc *__restrict__ fd)
 {
@@ -619,10 +617,19 @@ __global__ __launch_bounds__(kWave * kScanWaves) void k_colscan(const FrameDesc 
     const uint32_t per = (F.ntile + kScanWaves - 1) / kScanWaves;
     const uint32_t a = w * per;
     const uint32_t b = min(a + per, F.ntile);
-    // loads in batches of kColBatch, so that a batch is in flight together
+    // a wave's share of the column: up to kColKeep entries stay in registers
+    // between the sum and the prefix (read once); longer shares are read again
+    uint32_t keep[kColKeep];
     uint32_t sum = 0;
     if (k < kHRow) {
-        for (uint32_t i0 = a; i0 < b; i0 += kColBatch) {
+#pragma unroll
+        for (int u = 0; u < kColKeep; u++) {
+            keep[u] = a + u < b ? F.hist[(size_t)(a + u) * kHRow + k] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kColKeep; u++) sum += keep[u];
+        // loads in batches of kColBatch, so that a batch is in flight together
+        for (uint32_t i0 = a + kColKeep; i0 < b; i0 += kColBatch) {
             uint32_t v[kColBatch];
 #pragma unroll
             for (int u = 0; u < kColBatch; u++) v[u] = i0 + u < b ? F.hist[(size_t)(i0 + u) * kHRow + k] : 0u;
@@ -639,7 +646,12 @@ __global__ __launch_bounds__(kWave * kScanWaves) void k_colscan(const FrameDesc 
         total += p;
     }
     if (k < kHRow) {
-        for (uint32_t i0 = a; i0 < b; i0 += kColBatch) {
+#pragma unroll
+        for (int u = 0; u < kColKeep; u++) {
+            if (a + u < b) F.hist[(size_t)(a + u) * kHRow + k] = run;
+            run += keep[u];
+        }
+        for (uint32_t i0 = a + kColKeep; i0 < b; i0 += kColBatch) {
             uint32_t v[kColBatch];
 #pragma unroll
             for (int u = 0; u < kColBatch; u++) v[u] = i0 + u < b ? F.hist[(size_t)(i0 + u) * kHRow + k] : 0u;
@@ -1419,9 +1431,8 @@ __global__ void k_selftest_fp(const float *a, const float *b, float *out, uint32
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-constexpr int kStages = 8;
-const char *kStageNames[kStages] = {"setup", "tilesum", "count", "colscan", "offsets",
-                                    "unattached", "rank", "attached"};
+constexpr int kStages = 7;
+const char *kStageNames[kStages] = {"tilesum", "count", "colscan", "offsets", "rank", "attached", "unattached"};
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -1509,31 +1520,27 @@ int launch_all(tmd_plan_t *P, hipStream_t s, uint32_t mask)
     };
     const uint32_t T = P->total_tiles;
     if (begin(0, s)) return TMD_E_HIP;
-    hipLaunchKernelGGL(k_setup, dim3(P->n_frames), dim3(kWave), 0, s, P->d_desc);
+    hipLaunchKernelGGL(k_tilesum, dim3(T + P->n_frames), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame, T);
     if (end(0, s) || begin(1, s)) return TMD_E_HIP;
-    if (T) hipLaunchKernelGGL(k_tilesum, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
-    if (end(1, s) || begin(2, s)) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_count, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
-    if (end(2, s) || begin(3, s)) return TMD_E_HIP;
+    if (end(1, s) || begin(2, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_colscan, dim3((kHRow + kWave - 1) / kWave, P->n_frames), dim3(kWave * kScanWaves), 0,
                        s, P->d_desc);
-    if (end(3, s) || begin(4, s)) return TMD_E_HIP;
+    if (end(2, s) || begin(3, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_offsets, dim3(P->n_frames), dim3(kOffThreads), 0, s, P->d_desc);
-    if (end(4, s)) return TMD_E_HIP;
-    if (begin(6, s)) return TMD_E_HIP;
+    if (end(3, s) || begin(4, s)) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_rank, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
-    if (end(6, s)) return TMD_E_HIP;
+    if (end(4, s)) return TMD_E_HIP;
     // attached decode, then the unattached one.  (Run side by side on two
     // streams they take as long in all: the unattached waves slow the attached
     // decode by about what they take alone.)
-    if (begin(7, s)) return TMD_E_HIP;
+    if (begin(5, s)) return TMD_E_HIP;
     if (T)
         hipLaunchKernelGGL(k_attached, dim3(T * (kTileWaves / kAttWaves)), dim3(kAttWaves * kWave), 0, s, P->d_desc,
                            P->d_tile_frame, P->d_geo);
-    if (end(7, s)) return TMD_E_HIP;
-    if (begin(5, s)) return TMD_E_HIP;
+    if (end(5, s) || begin(6, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_unattached, dim3(NBIN, P->n_frames), dim3(kWave), 0, s, P->d_desc);
-    if (end(5, s)) return TMD_E_HIP;
+    if (end(6, s)) return TMD_E_HIP;
     HIP_TRY(hipGetLastError());
     if (mask) P->prof_events.push_back(ev);
     return TMD_OK;
