@@ -216,16 +216,17 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v)
 }
 
 // exclusive scan over a block of kTile threads; returns the block total in *tot
+template <int NW = kTileWaves>  // waves of the block
 __device__ uint32_t block_excl_add(uint32_t v, uint32_t *tot)
 {
-    __shared__ uint32_t part[kTileWaves];
+    __shared__ uint32_t part[NW];
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     uint32_t inc = wave_incl_add(v);
     if (lane == kWave - 1) part[w] = inc;
     __syncthreads();
     uint32_t base = 0, all = 0;
 #pragma unroll
-    for (int i = 0; i < kTileWaves; i++) {
+    for (int i = 0; i < NW; i++) {
         uint32_t p = part[i];
         if (i < (int)w) base += p;
         all += p;
@@ -372,10 +373,11 @@ struct WalkState {
     uint32_t ctrack;    // track lane of the last cluster of the previous chunk
 };
 
-// Per-lane track setup; returns the wave's cluster range [A, E).  Lane l holds
-// track tw + l (if < nT): its start, decoded length and header position.
-__device__ __forceinline__ void wave_setup(const FrameDesc &F, uint32_t tw, WaveLds &L, uint32_t start_in,
-                                           uint32_t &start_l, uint32_t &n_l, uint32_t &A, uint32_t &E)
+// Per-lane track setup; returns the wave's cluster range [A, E).  Lane l < ntr
+// holds track tw + l (if < nT): its start, decoded length and header position.
+__device__ __forceinline__ void wave_setup(const FrameDesc &F, uint32_t tw, uint32_t ntr, WaveLds &L,
+                                           uint32_t start_in, uint32_t &start_l, uint32_t &n_l, uint32_t &A,
+                                           uint32_t &E)
 {
     const uint32_t lane = lane_id();
     const uint32_t t = tw + lane;
@@ -383,7 +385,7 @@ __device__ __forceinline__ void wave_setup(const FrameDesc &F, uint32_t tw, Wave
     start_l = 0xFFFFFFFFu;
     n_l = 0;
     uint8_t r = 0, s = 0;
-    if (t < F.nT) {
+    if (lane < ntr && t < F.nT) {
         start_l = start_in;
         nc = F.ncls[t];
         n_l = track_len(start_l, nc, F.nA);
@@ -481,47 +483,55 @@ __device__ __forceinline__ uint32_t walk_chunk(uint32_t lo, uint32_t E, int rd, 
 // K2: track starts, per-tile histogram of cluster bins and of scheduling keys
 // ---------------------------------------------------------------------------
 constexpr int kGroup = 4;  // chunks loaded together by a walk
+// the count kernel: 8 waves per tile of 256 tracks, 32 tracks per wave (the
+// walk still covers 64 clusters per step; more waves per tile hide more of
+// its latency)
+constexpr int kCountWaves = 8;
+constexpr int kCountTracks = kTile / kCountWaves;
+constexpr int kCountThreads = kCountWaves * kWave;
 
-__global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ fd,
-                                                 const uint32_t *__restrict__ tile_frame)
+__global__ __launch_bounds__(kCountThreads) void k_count(const FrameDesc *__restrict__ fd,
+                                                         const uint32_t *__restrict__ tile_frame)
 {
     // the tile's 16-bit bin counters, shared by its waves (256 tracks put at
-    // most 256 * 255 < 2^16 clusters in one bin); 13 KB of LDS in all, so
+    // most 256 * 255 < 2^16 clusters in one bin); 17 KB of LDS in all, so
     // that every tile of a frame can be resident at once
     __shared__ uint32_t wcnt32[NBIN / 2];
     __shared__ uint32_t khist[kNKey];
-    __shared__ WaveLds wl[kTileWaves];
+    __shared__ WaveLds wl[kCountWaves];
     const uint16_t *wcnt = reinterpret_cast<const uint16_t *>(wcnt32);
     const uint32_t tile = blockIdx.x;
     const FrameDesc F = fd[tile_frame[tile]];
     const uint32_t lt = tile - F.tile0;
     if (lt >= F.ntile) return;  // a tile of the planned capacity beyond this call's frame
-    const uint32_t t = lt * kTile + threadIdx.x;
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+    // wave w takes tracks [32 w, 32 w + 32) of the tile in lanes 0..31
+    const bool tl_ok = lane < (uint32_t)kCountTracks;
+    const uint32_t t = lt * kTile + w * kCountTracks + lane;
 
     // clusters of all earlier tiles of the frame
     uint32_t pre = 0;
-    for (uint32_t i = threadIdx.x; i < lt; i += kTile) pre += F.tilesum[i];
+    for (uint32_t i = threadIdx.x; i < lt; i += kCountThreads) pre += F.tilesum[i];
     uint32_t before;
-    block_excl_add(pre, &before);
+    block_excl_add<kCountWaves>(pre, &before);
 
-    for (uint32_t i = threadIdx.x; i < NBIN / 2; i += kTile) wcnt32[i] = 0;
-    for (uint32_t i = threadIdx.x; i < kNKey; i += kTile) khist[i] = 0;
-    const uint32_t nc = t < F.nT ? F.ncls[t] : 0u;
+    for (uint32_t i = threadIdx.x; i < NBIN / 2; i += kCountThreads) wcnt32[i] = 0;
+    for (uint32_t i = threadIdx.x; i < kNKey; i += kCountThreads) khist[i] = 0;
+    const uint32_t nc = tl_ok && t < F.nT ? F.ncls[t] : 0u;
     uint32_t tot;
-    const uint32_t start = before + block_excl_add(nc, &tot);  // also syncs
-    if (t < F.nT) {
+    const uint32_t start = before + block_excl_add<kCountWaves>(nc, &tot);  // also syncs
+    if (tl_ok && t < F.nT) {
         F.start[t] = start;
         if (t == F.nT - 1) {
             F.start[F.nT] = start + nc;
             if (start + nc != F.nA) atomicOr(F.status, TMD_F_COUNT);
         }
     }
-    const uint32_t tw = lt * kTile + w * kWave;
+    const uint32_t tw = lt * kTile + w * kCountTracks;
     if (tw < F.nT) {
         WaveLds &L = wl[w];
         uint32_t start_l, n_l, A, E;
-        wave_setup(F, tw, L, start, start_l, n_l, A, E);
+        wave_setup(F, tw, kCountTracks, L, start, start_l, n_l, A, E);
         WalkState ws{0, 0, 0};
         uint32_t fl = 0;
         // groups of kGroup chunks; two groups alternate so that the loads of
@@ -584,7 +594,7 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
         fl = wave_or(fl);
         if (lane == 0 && fl) atomicOr(F.status, fl);
         __builtin_amdgcn_wave_barrier();
-        if (tw + lane < F.nT) {
+        if (tl_ok && tw + lane < F.nT) {
             const uint32_t bits = L.cls[lane];
             const uint32_t cls = n_l <= 1 ? 0u : ((bits & 1u) ? 0u : ((bits & 2u) ? 1u : 2u));
             const uint32_t key = (uint32_t)L.hsec[lane] * 3u + cls;
@@ -595,8 +605,8 @@ __global__ __launch_bounds__(kTile) void k_count(const FrameDesc *__restrict__ f
     __syncthreads();
     // the tile's row of the histogram: bin counts, then key counts
     GLB uint32_t *dst = F.hist + (size_t)lt * kHRow;
-    for (uint32_t k = threadIdx.x; k < NBIN; k += kTile) dst[k] = wcnt[k];
-    for (uint32_t i = threadIdx.x; i < kNKey; i += kTile) dst[NBIN + i] = khist[i];
+    for (uint32_t k = threadIdx.x; k < NBIN; k += kCountThreads) dst[k] = wcnt[k];
+    for (uint32_t i = threadIdx.x; i < kNKey; i += kCountThreads) dst[NBIN + i] = khist[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1522,7 +1532,7 @@ int launch_all(tmd_plan_t *P, hipStream_t s, uint32_t mask)
     if (begin(0, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_tilesum, dim3(T + P->n_frames), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame, T);
     if (end(0, s) || begin(1, s)) return TMD_E_HIP;
-    if (T) hipLaunchKernelGGL(k_count, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
+    if (T) hipLaunchKernelGGL(k_count, dim3(T), dim3(kCountThreads), 0, s, P->d_desc, P->d_tile_frame);
     if (end(1, s) || begin(2, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_colscan, dim3((kHRow + kWave - 1) / kWave, P->n_frames), dim3(kWave * kScanWaves), 0,
                        s, P->d_desc);
