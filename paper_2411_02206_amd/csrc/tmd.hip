@@ -169,7 +169,8 @@ constexpr int kHRow = NBIN + kNKey;  // per-tile histogram row: bins, then keys
     Q uint32_t *status;                                                                       \
     uint64_t cap; /* entries of the output cluster arrays; every store is checked */          \
     uint32_t nT, nA, nU, ntile, tile0;                                                        \
-    uint32_t pad_[3];
+    uint32_t awaves; /* waves of the attached decode */                                       \
+    uint32_t pad_[2];
 
 struct FrameDesc {
     TMD_FRAME_FIELDS(GLB)
@@ -1078,6 +1079,9 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v)
     return readlane(v, kWave - 1);
 }
 
+// maximum over all 64 lanes
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) { return ~wave_min(~v); }
+
 // Record staging: each lane keeps a ring of kRing records of its track in LDS,
 // split in two arrays indexed [slot][lane]: rb = (residuals, row | rotation),
 // read at every step, and ra = (output slot, charges), read when storing.
@@ -1097,11 +1101,16 @@ constexpr int kBlk = 4;
 constexpr int kRing = 2 * kBlk;
 static_assert(kBlk == 4 && kWave == 64, "cooperative loads: 4 records per track, 16 tracks per load");
 
-// per-lane decode state of one track
+// per-lane decode state: one track, or two decoded one after the other (the
+// second, B, starts at record nA; its initial state waits in the B fields)
 struct LaneTrack {
     float x, y, z, s, tgl, k;
     int32_t t0;
     uint32_t pad0, fl, n, c0;
+    uint32_t nA, c0B;  // records of the first track (n if there is no second); start of the second
+    float xB, yB, sB, tglB, kB;
+    int32_t t0B;
+    uint32_t pad0B;
 };
 
 // records fetched by one cooperative load round, and where they go
@@ -1110,20 +1119,25 @@ struct CoopLoad {
     uint32_t dst[kBlk];  // ring slot | track lane << 8, or ~0u: nothing to place
 };
 
-// Fetch records [L_t, L_t + m_t) of every track lane t (L and m: this lane's
-// values; base = c0 + L).  m_t <= kBlk.
-__device__ __forceinline__ void coop_load(const FrameDesc &F, uint32_t base, uint32_t L, uint32_t m,
-                                          CoopLoad &C)
+// Fetch records [L_t, L_t + m_t) of every lane t (L and m: this lane's
+// values; m_t <= kBlk).  A lane's records j < nA are those of its first track
+// (from c0), the rest those of its second (from c0B).
+__device__ __forceinline__ void coop_load(const FrameDesc &F, uint32_t L, uint32_t m, uint32_t c0, uint32_t nA,
+                                          uint32_t c0B, CoopLoad &C)
 {
     const uint32_t lane = lane_id();
     const uint32_t q = lane & 3u;
-    const uint32_t lm = (L << 8) | m;  // L <= 255, m <= 4
+    const uint32_t baseA = c0 + L;
+    const uint32_t baseB = c0B + L - nA;  // (wraps while L < nA; used only for records >= nA)
+    const uint32_t sp = nA > L ? min(nA - L, (uint32_t)kBlk) : 0u;  // of the kBlk, those of the first track
+    const uint32_t lm = (L << 8) | (sp << 4) | m;  // L < 2^24, sp, m <= 4
 #pragma unroll
     for (int k = 0; k < kBlk; k++) {
         const uint32_t t = 16u * k + (lane >> 2);
-        const uint32_t bt = bperm(base, t), lmt = bperm(lm, t);
-        const bool ok = q < (lmt & 0xFFu);
-        C.v[k] = F.recs[ok ? bt + q : 0u];
+        const uint32_t bA = bperm(baseA, t), bB = bperm(baseB, t), lmt = bperm(lm, t);
+        const bool ok = q < (lmt & 0xFu);
+        const uint32_t a = q < ((lmt >> 4) & 0xFu) ? bA + q : bB + q;
+        C.v[k] = F.recs[ok ? a : 0u];
         C.dst[k] = ok ? (((lmt >> 8) + q) % kRing) | (t << 8) : ~0u;
     }
 }
@@ -1176,14 +1190,14 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
     // read with ds_bpermute
     const float smax = geo->snp_max, vdq = geo->vdq, inv_vd32 = geo->inv_vd32;
     const float rcos = lane < 18u ? geo->cosb[lane] : 0.0f, rsin = lane < 18u ? geo->sinb[lane] : 0.0f;
-    const uint32_t n = T.n, c0 = T.c0;
+    const uint32_t n = T.n, c0 = T.c0, nA = T.nA, c0B = T.c0B;
     // first records straight into the ring: two rounds of kBlk
     uint32_t L = n < (uint32_t)kRing ? n : (uint32_t)kRing;  // records [0, L) have entered the ring
     {
         CoopLoad C0, C1;
         const uint32_t m0 = n < (uint32_t)kBlk ? n : (uint32_t)kBlk;
-        coop_load(F, c0, 0, m0, C0);
-        coop_load(F, c0 + kBlk, kBlk, L - m0, C1);
+        coop_load(F, 0, m0, c0, nA, c0B, C0);
+        coop_load(F, kBlk, L - m0, c0, nA, c0B, C1);
         coop_place(C0, ra, rb);
         coop_place(C1, ra, rb);
     }
@@ -1197,8 +1211,9 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
     uint32_t rmask = 0;           // steps of the block at which this lane decoded
     uint32_t vrow = 0xFFFFFFFFu;  // modes 0 and 1: the last row processed
     float x = T.x, y = T.y, z = T.z, s = T.s, tgl = T.tgl;
-    const float k = T.k;
-    const int32_t t0 = T.t0;
+    float k = T.k;
+    int32_t t0 = T.t0;
+    uint32_t pad0 = T.pad0;
     // status checks accumulate in registers and are turned into flags once,
     // after the loop: out-of-range pads and times leave high bits in an OR of
     // the raw values; a clamped |sin phi| (or a NaN) leaves |v - clamp(v)| > 0
@@ -1238,7 +1253,7 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
             // rotation by d sectors, rare: a wave-uniform branch, the table
             // entry from lane d (read while every lane is active)
             const uint32_t d = (cur.y >> 8) & 0xFFu;  // 0..17
-            const bool rot = ready && j > 0 && d != 0;
+            const bool rot = ready && j > 0 && j != nA && d != 0;
             if (__ballot(rot) != 0) {
                 const float ca = __uint_as_float(bperm(__float_as_uint(rcos), d));
                 const float sa = __uint_as_float(bperm(__float_as_uint(rsin), d));
@@ -1258,8 +1273,8 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
             }
             if (ready) {
                 const uint2 rec = cur;  // x = residuals, y = row | rotation << 8
-                uint32_t otime = (uint32_t)t0, opad = T.pad0;
-                if (j > 0) {
+                uint32_t otime = (uint32_t)t0, opad = pad0;
+                if (j > 0 && j != nA) {  // (records 0 and nA: the tracks' header clusters)
                     if (MODE == 2) R = geo->row[rec.y & 0xFFu];
                     const float dx = R.x - x;
                     const float s1r = s + (k * dx);
@@ -1294,6 +1309,16 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
                 stg[st][lane] = make_uint2(otime, opad);
                 rmask |= 1u << st;
                 j++;
+                if (j == nA && j < n) {  // the second track starts
+                    x = T.xB;
+                    y = T.yB;
+                    z = 0.0f;
+                    s = T.sB;
+                    tgl = T.tglB;
+                    k = T.kB;
+                    t0 = T.t0B;
+                    pad0 = T.pad0B;
+                }
                 if (j < L) cur = rb[j % kRing][lane];
             }
             if (MODE != 2) {
@@ -1341,58 +1366,195 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
         const uint32_t room = (uint32_t)kRing - (L - j);
         if (m > room) m = room;
         if (__ballot(j < n) == 0) break;
-        coop_load(F, c0 + L, L, m, nb);
+        coop_load(F, L, m, c0, nA, c0B, nb);
     }
     T.fl |= (snp_dev != 0.0f ? TMD_F_SNP : 0u) | (rot_bad ? TMD_F_ROT : 0u) |
             ((pad_or & 0xFFFF0000u) ? TMD_F_PAD : 0u) | ((time_or & ~(kTimeLim - 1u)) ? TMD_F_TIME : 0u);
 }
 
+// initial state of track t (header position, time, pad, angles, curvature)
+struct TrackInit {
+    float x, y, s, tgl, k;
+    int32_t t0;
+    uint32_t pad0, fl, n, c0, cls, row;
+};
+
+__device__ __forceinline__ void track_init(const FrameDesc &F, const Geo *__restrict__ geo, uint32_t t,
+                                           TrackInit &I)
+{
+    const uint32_t ncls = F.ncls[t];
+    I.c0 = F.start[t];
+    I.n = track_len(I.c0, ncls, F.nA);
+    I.cls = key_class(F.tkey[t]);
+    I.fl = ncls == 0 ? TMD_F_HDR : 0u;
+    const HeaderPos h = header_pos(F.sec0[t], F.row0[t]);
+    I.fl |= h.flags;
+    I.row = (uint32_t)h.row;
+    uint32_t t0u = F.time0[t];
+    if (t0u >= kTimeLim) {
+        I.fl |= TMD_F_TIME;
+        t0u = kTimeLim - 1;
+    }
+    I.t0 = (int32_t)t0u;
+    I.pad0 = F.pad0[t];
+    const RowGeo R = geo->row[h.row];
+    I.x = R.x;
+    I.y = ((float)I.pad0 * 0x1p-5f - R.padoff) * R.pw;
+    I.s = clamp_snp((float)F.snp[t] * 0x1p-15f, geo->snp_max, I.fl);
+    I.tgl = (float)F.tgl[t] * 0x1p-12f;
+    I.k = ((float)F.qpt[t] * 0x1p-10f) * geo->kb;
+}
+
+// lane `src`'s TrackInit, in every lane
+__device__ __forceinline__ TrackInit track_init_from(const TrackInit &I, uint32_t src)
+{
+    TrackInit R;
+    R.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(I.x), (int)src));
+    R.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(I.y), (int)src));
+    R.s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(I.s), (int)src));
+    R.tgl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(I.tgl), (int)src));
+    R.k = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(I.k), (int)src));
+    R.t0 = __builtin_amdgcn_readlane(I.t0, (int)src);
+    R.pad0 = readlane(I.pad0, (int)src);
+    R.fl = readlane(I.fl, (int)src);
+    R.n = readlane(I.n, (int)src);
+    R.c0 = readlane(I.c0, (int)src);
+    R.cls = readlane(I.cls, (int)src);
+    R.row = readlane(I.row, (int)src);
+    return R;
+}
+
+// Waves: a frame's decode uses F.awaves waves; wave fw takes the tracks at
+// schedule positions [fw nT / awaves, (fw + 1) nT / awaves).  Normally that is
+// at most 64 (awaves = ceil(nT / 64)).  When ceil(nT / 64) is just above a
+// multiple of the number of SIMDs, the host picks that multiple instead (every
+// SIMD then runs the same number of decode waves, where a few would run one
+// more): a wave then has up to 66 tracks, and one or two of them are decoded
+// each after another track of the wave.  Those are the tracks that start last
+// (in the wave's row order; the shortest ones if its rows are mixed), and each
+// follows the track that ends first, so that the lane's rows stay in step with
+// the wave's.  A single-frame call uses the first awaves workgroups, dealt
+// evenly to the XCDs.
 __global__ __launch_bounds__(kAttWaves * kWave) void k_attached(const FrameDesc *__restrict__ fd,
                                                                const uint32_t *__restrict__ tile_frame,
-                                                               const Geo *__restrict__ geo)
+                                                               const Geo *__restrict__ geo, uint32_t single)
 {
+    static_assert(kAttWaves == 1, "one wave per workgroup: the wave index is the workgroup index");
     // LDS holds only the record rings and staging (10 KB per wave); the
-    // tables stay in global memory.  Workgroups of kAttWaves waves: the
-    // grid's waves are all resident at once, and small workgroups let the
-    // dispatcher spread them evenly over the CUs.
-    __shared__ uint2 ra[kAttWaves][kRing][kWave];  // record rings: (output slot, charges)
-    __shared__ uint2 rb[kAttWaves][kRing][kWave];  // (residuals, row | rotation << 8)
-    __shared__ uint2 stg[kAttWaves][kBlk][kWave];  // per step of the block: the decoded (time, pad)
-    const uint32_t gw = xcd_tile(blockIdx.x, gridDim.x) * kAttWaves + threadIdx.x / kWave;  // wave of the grid
-    const uint32_t tile = gw / kTileWaves;
-    const FrameDesc F = fd[tile_frame[tile]];
-    if (tile - F.tile0 >= F.ntile) return;  // a tile of the planned capacity beyond this call's frame
-    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
-    const uint32_t slot = (tile - F.tile0) * kTile + (gw % kTileWaves) * kWave + lane;
-    LaneTrack T = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0, 0u, 0u, 0u, 0u};
-    uint32_t cls = 2;
-    if (slot < F.nT) {
-        const uint32_t t = F.order[slot];
-        const uint32_t ncls = F.ncls[t];
-        T.c0 = F.start[t];
-        T.n = track_len(T.c0, ncls, F.nA);
-        cls = key_class(F.tkey[t]);
-        if (ncls == 0) T.fl |= TMD_F_HDR;
-        HeaderPos h = header_pos(F.sec0[t], F.row0[t]);
-        T.fl |= h.flags;
-        uint32_t t0u = F.time0[t];
-        if (t0u >= kTimeLim) { T.fl |= TMD_F_TIME; t0u = kTimeLim - 1; }
-        T.t0 = (int32_t)t0u;
-        T.pad0 = F.pad0[t];
-        const RowGeo R = geo->row[h.row];
-        T.x = R.x;
-        T.y = ((float)T.pad0 * 0x1p-5f - R.padoff) * R.pw;
-        T.s = clamp_snp((float)F.snp[t] * 0x1p-15f, geo->snp_max, T.fl);
-        T.tgl = (float)F.tgl[t] * 0x1p-12f;
-        T.k = ((float)F.qpt[t] * 0x1p-10f) * geo->kb;
+    // tables stay in global memory.  One-wave workgroups: the grid's waves
+    // are all resident at once, and small workgroups let the dispatcher spread
+    // them evenly over the CUs.
+    __shared__ uint2 ra[kRing][kWave];  // record rings: (output slot, charges)
+    __shared__ uint2 rb[kRing][kWave];  // (residuals, row | rotation << 8)
+    __shared__ uint2 stg[kBlk][kWave];  // per step of the block: the decoded (time, pad)
+    const uint32_t W1 = single ? fd[0].awaves : 0u;
+    if (single && blockIdx.x >= W1) return;
+    const uint32_t gw = single ? xcd_tile(blockIdx.x, W1) : xcd_tile(blockIdx.x, gridDim.x);
+    const FrameDesc F = fd[single ? 0u : tile_frame[gw / kTileWaves]];
+    const uint32_t fw = gw - F.tile0 * kTileWaves;  // wave of the frame
+    if (fw >= F.awaves) return;  // beyond this call's frame (capacity plans)
+    const uint32_t lane = lane_id();
+    const uint32_t b0 = (uint32_t)((uint64_t)fw * F.nT / F.awaves);
+    const uint32_t b1 = (uint32_t)((uint64_t)(fw + 1) * F.nT / F.awaves);
+    TrackInit I = {};
+    const bool own = b0 + lane < b1;
+    if (own) track_init(F, geo, F.order[b0 + lane], I);
+    // tracks beyond the 64th (at most two; wave-uniform)
+    const uint32_t nx = b1 - b0 > (uint32_t)kWave ? min(b1 - b0 - (uint32_t)kWave, 2u) : 0u;
+    TrackInit X[2] = {};
+    bool live_x = false, x0 = true, x1 = true;
+#pragma unroll
+    for (uint32_t e = 0; e < 2; e++) {
+        if (e >= nx) break;
+        track_init(F, geo, F.order[b0 + kWave + e], X[e]);
+        if (X[e].n > 0) {
+            live_x = true;
+            x0 = x0 && X[e].cls == 0;
+            x1 = x1 && X[e].cls == 1;
+        }
     }
     // wave mode: 0 rows ascending, 1 rows descending, 2 one cluster per step
-    const uint64_t any_live = __ballot(T.n > 0);
-    const uint64_t asc = __ballot(T.n > 0 && cls == 0);
-    const uint64_t dsc = __ballot(T.n > 0 && cls == 1);
-    if (asc == any_live) attached_loop<0>(F, geo, ra[w], rb[w], stg[w], T);
-    else if (dsc == any_live) attached_loop<1>(F, geo, ra[w], rb[w], stg[w], T);
-    else attached_loop<2>(F, geo, ra[w], rb[w], stg[w], T);
+    const uint64_t any_live = __ballot(I.n > 0);
+    const uint64_t asc = __ballot(I.n > 0 && I.cls == 0);
+    const uint64_t dsc = __ballot(I.n > 0 && I.cls == 1);
+    const int mode = (asc == any_live && (!live_x || x0)) ? 0 : ((dsc == any_live && (!live_x || x1)) ? 1 : 2);
+    LaneTrack T = {};
+    if (nx > 0) {
+        // the tracks decoded second: those that start last (largest start key)
+        auto start_key = [&](const TrackInit &J) -> uint32_t {
+            if (J.n == 0) return 0u;
+            return mode == 0 ? J.row + 1u : (mode == 1 ? 256u - J.row : 256u - J.n);
+        };
+#pragma unroll
+        for (uint32_t e = 0; e < 2; e++) {
+            if (e >= nx) break;
+            const uint32_t best = wave_max_u32(own ? (start_key(I) << 6) | lane : 0u);
+            const uint32_t src = best & 63u;
+            if ((best >> 6) > start_key(X[e])) {  // swap with lane src's track
+                const TrackInit Y = track_init_from(I, src);
+                if (lane == src) I = X[e];
+                X[e] = Y;
+            }
+        }
+        // each follows the track that ends first (smallest end key; lanes
+        // without records first)
+        uint32_t end_key = 0;
+        if (I.n > 0) {
+            if (mode == 2) {
+                end_key = I.n;
+            } else {
+                const uint32_t lr = F.recs[I.c0 + I.n - 1].w & 0xFFu;  // row of the last cluster
+                end_key = mode == 0 ? lr + 1u : 256u - lr;
+            }
+        }
+        bool taken = false;
+#pragma unroll
+        for (uint32_t e = 0; e < 2; e++) {
+            if (e >= nx) break;
+            const uint32_t pick = wave_min(taken ? 0xFFFFFFFFu : ((end_key << 6) | lane)) & 63u;
+            if (lane == pick) {
+                taken = true;
+                const TrackInit &J = X[e];
+                if (I.n == 0) {  // a lane without records: the track becomes its own
+                    const uint32_t fl0 = I.fl;
+                    I = J;
+                    I.fl |= fl0;
+                } else {
+                    T.fl |= J.fl;
+                    if (J.n > 0) {
+                        T.nA = I.n;
+                        T.c0B = J.c0;
+                        T.n = J.n;  // (added below)
+                        T.xB = J.x;
+                        T.yB = J.y;
+                        T.sB = J.s;
+                        T.tglB = J.tgl;
+                        T.kB = J.k;
+                        T.t0B = J.t0;
+                        T.pad0B = J.pad0;
+                    }
+                }
+            }
+        }
+    }
+    T.x = I.x;
+    T.y = I.y;
+    T.s = I.s;
+    T.tgl = I.tgl;
+    T.k = I.k;
+    T.t0 = I.t0;
+    T.pad0 = I.pad0;
+    T.fl |= I.fl;
+    T.c0 = I.c0;
+    if (T.n > 0) {  // two tracks: n of the second was set above
+        T.n += I.n;
+    } else {
+        T.n = I.n;
+        T.nA = I.n;
+    }
+    if (mode == 0) attached_loop<0>(F, geo, ra, rb, stg, T);
+    else if (mode == 1) attached_loop<1>(F, geo, ra, rb, stg, T);
+    else attached_loop<2>(F, geo, ra, rb, stg, T);
     const uint32_t fl = wave_or(T.fl);
     if (lane == 0 && fl) atomicOr(F.status, fl);
 }
@@ -1455,6 +1617,7 @@ struct FrameLayout {
 
 struct tmd_plan {
     int device = 0;
+    uint32_t simds = 1024;  // SIMDs of the device (CUs x 4): the attached decode balances its waves over them
     uint32_t n_frames = 0;
     uint32_t total_tiles = 0;
     tmd_params params{};
@@ -1497,6 +1660,18 @@ template <class T>
 bool aligned(const T *p)
 {
     return ((uintptr_t)p % alignof(T)) == 0;
+}
+
+// Waves of the attached decode for a frame of nT tracks: ceil(nT / 64), or,
+// for a single-frame call whose count is just above a multiple of the SIMD
+// count, that multiple (tracks per wave up to 66: at most two decoded after
+// another track of the wave; see k_attached).
+uint32_t attached_waves(uint32_t nT, bool single, uint32_t simds)
+{
+    const uint32_t w0 = (uint32_t)(((uint64_t)nT + kWave - 1) / kWave);
+    if (!single || simds == 0 || w0 <= simds || w0 % simds == 0) return w0;
+    const uint32_t w = w0 / simds * simds;
+    return (uint64_t)nT <= (uint64_t)(kWave + 2) * w ? w : w0;
 }
 
 // Enqueue the pipeline on stream s, one kernel after the other.  Each stage
@@ -1547,7 +1722,7 @@ int launch_all(tmd_plan_t *P, hipStream_t s, uint32_t mask)
     if (begin(5, s)) return TMD_E_HIP;
     if (T)
         hipLaunchKernelGGL(k_attached, dim3(T * (kTileWaves / kAttWaves)), dim3(kAttWaves * kWave), 0, s, P->d_desc,
-                           P->d_tile_frame, P->d_geo);
+                           P->d_tile_frame, P->d_geo, P->n_frames == 1 ? 1u : 0u);
     if (end(5, s) || begin(6, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_unattached, dim3(NBIN, P->n_frames), dim3(kWave), 0, s, P->d_desc);
     if (end(6, s)) return TMD_E_HIP;
@@ -1661,6 +1836,19 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
     int rc = TMD_OK;
     do {
         if (hipGetDevice(&P->device) != hipSuccess) { rc = TMD_E_HIP; break; }
+        {
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess) {
+                rc = TMD_E_HIP;
+                break;
+            }
+            P->simds = cus > 0 ? 4u * (uint32_t)cus : 4u;
+            // (tests set a small count to exercise the wave balancing on small frames)
+            if (const char *e = getenv("TMD_ATTACHED_SIMDS")) {
+                const long v = strtol(e, nullptr, 10);
+                if (v > 0 && v < (1L << 20)) P->simds = (uint32_t)v;
+            }
+        }
         Geo g;
         build_geo(p->bz_tesla, &g);
         if (hipMalloc(&P->d_geo, sizeof(Geo)) != hipSuccess) { rc = TMD_E_HIP; break; }
@@ -1770,6 +1958,7 @@ int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_fr
         D.nT = S.n_tracks; D.nA = S.n_attached; D.nU = S.n_unattached;
         D.ntile = (S.n_tracks + kTile - 1) / kTile;  // <= the planned L.ntile
         D.tile0 = L.tile0;
+        D.awaves = attached_waves(S.n_tracks, P->n_frames == 1, P->simds);
     }
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));

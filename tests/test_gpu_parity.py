@@ -171,6 +171,42 @@ def test_garbage_streams(tmd, seed):
         assert st != 0
 
 
+def _cut(fr, nt):
+    """The first nt tracks of a frame with their clusters (unattached kept)."""
+    na = int(fr["trk_ncls"][:nt].astype(np.int64).sum())
+    return {k: (v[:nt] if k.startswith("trk_") else v[:na] if k.startswith("cls_") else v) for k, v in fr.items()}
+
+
+def _balanced(nt, simds):
+    """Waves the attached decode uses for one frame of nt tracks (its rule:
+    ceil(nt / 64), or the multiple of the SIMD count just below when that
+    leaves at most 66 tracks per wave)."""
+    w0 = -(-nt // 64)
+    if w0 <= simds or w0 % simds == 0:
+        return w0
+    w = w0 // simds * simds
+    return w if nt <= 66 * w else w0
+
+
+@pytest.mark.parametrize("case", ["frame", "stress", "garbage0", "garbage1", "garbage3"])
+def test_chained_tracks(tmd, monkeypatch, case):
+    """Waves with 65 or 66 tracks (the extra ones decoded after another track
+    of the wave), forced on small frames by a small SIMD count: ascending
+    waves (frame), descending and mixed ones (loopers), and lanes without
+    records (garbage streams whose tracks run past the cluster count)."""
+    if case == "frame":
+        fr, simds = _cut(synth.make_frame(synth.spec_for("frame", collisions=2)), 64 * 60 + 100), 30
+    elif case == "stress":
+        fr, simds = _cut(synth.make_frame(synth.spec_for("stress", collisions=3)), 64 * 90 + 150), 45
+    else:
+        fr, simds = _garbage(int(case[-1]), nt=650), 5
+    nt = int(fr["trk_ncls"].shape[0])
+    assert _balanced(nt, simds) < -(-nt // 64)  # the case does chain tracks
+    monkeypatch.setenv("TMD_ATTACHED_SIMDS", str(simds))
+    for bz in ((0.5, 40.0) if case.startswith("garbage") else (0.5,)):
+        assert_same(tmd, fr, bz=bz, label=f"chained {case} bz {bz}")
+
+
 def test_physical_roundtrip_on_gpu(tmd):
     """GPU decode of oracle-encoded exact-helix clusters restores the
     quantised clusters."""
