@@ -133,6 +133,11 @@ typedef struct {
  * tables for p->bz_tesla on the host and uploads them to the current device.
  * *workspace_bytes receives the size of the device workspace tmd_decode needs
  * (256-byte aligned, caller-allocated, contents need not be initialised).
+ * The plan reads the device's compute-unit count: a single-frame decode
+ * balances its attached-decode waves over the device's SIMDs (results do not
+ * depend on it).  The environment variable TMD_ATTACHED_SIMDS, if set to a
+ * positive count, replaces that SIMD count (tests use it to exercise the
+ * balancing on small frames).
  * Errors: TMD_E_ARG (null pointer, n_frames == 0, n_tracks > TMD_MAX_TRACKS),
  * TMD_E_HIP.
  */
