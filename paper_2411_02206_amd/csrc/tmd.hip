@@ -346,24 +346,6 @@ struct WaveLds {
     uint32_t cls[kWave];   // K2: direction bits of track lane l (bit 0 all up, bit 1 all down)
 };
 
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ uint32_t dpp_max_step(uint32_t v)
-{
-    return max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xf, false));
-}
-
-// inclusive max over lanes 0..lane
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v)
-{
-    v = dpp_max_step<0x111, 0xf>(v);
-    v = dpp_max_step<0x112, 0xf>(v);
-    v = dpp_max_step<0x114, 0xf>(v);
-    v = dpp_max_step<0x118, 0xf>(v);
-    v = dpp_max_step<0x142, 0xa>(v);
-    v = dpp_max_step<0x143, 0xc>(v);
-    return v;
-}
-
 __device__ __forceinline__ uint32_t bperm(uint32_t v, uint32_t src_lane)
 {
     return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src_lane * 4u), (int)v);
@@ -433,20 +415,25 @@ __device__ __forceinline__ uint32_t walk_chunk(uint32_t lo, uint32_t E, int rd, 
             sdm %= 18;
         }
     }
-    const uint32_t P = wave_incl_add((uint32_t)rdv);
-    const uint32_t Q = wave_incl_add(sdm);
-    const uint32_t H1 = wave_incl_max(head ? lane + 1 : 0u);  // 1 + segment head lane, 0 = continuing
-    const uint32_t src = H1 ? H1 - 1 : 0u;
-    const uint32_t PH = bperm(P, src), QH = bperm(Q, src), TH = bperm(h, src);
+    // row and sector steps in one inclusive sum: low half row step + 128
+    // (0..255), high half sector step (0..17); over 64 lanes neither half
+    // carries into the other
+    const uint32_t PK = wave_incl_add(step ? (uint32_t)(rdv + 128) | (sdm << 16) : 0u);
+    // the segment's head: the last head lane at or below this lane (every lane
+    // between it and this one is a step, since inactive lanes come last)
+    const uint64_t hm = __ballot(head);
+    const uint64_t upto = hm & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull));
+    const uint32_t hl = upto ? (uint32_t)(kWave - 1) - (uint32_t)__clzll(upto) : 0u;
+    const uint32_t PKH = bperm(PK, hl), TH = bperm(h, hl);
     int row, sec;
-    if (H1) {
+    if (upto) {
         const int br = L.hrow[TH], bs = L.hsec[TH];
-        row = br + (int)(P - PH);
-        sec = (bs / 18) * 18 + (int)((uint32_t)(bs % 18) + (Q - QH)) % 18;
+        row = br + ((int)(PK & 0xFFFFu) - (int)(PKH & 0xFFFFu)) - 128 * (int)(lane - hl);
+        sec = (bs / 18) * 18 + (int)((uint32_t)(bs % 18) + ((PK >> 16) - (PKH >> 16))) % 18;
         tl = TH;
     } else {
-        row = ws.crow + (int)P;
-        sec = (ws.csec / 18) * 18 + (int)((uint32_t)(ws.csec % 18) + Q) % 18;
+        row = ws.crow + (int)(PK & 0xFFFFu) - 128 * (int)(lane + 1u);
+        sec = (ws.csec / 18) * 18 + (int)((uint32_t)(ws.csec % 18) + (PK >> 16)) % 18;
         tl = ws.ctrack;
     }
     clamped = __ballot(act && (row < 0 || row >= NROW)) != 0;
