@@ -30,7 +30,8 @@
 //   K4 k_offsets     per frame, bin offsets of the output and of the
 //                    unattached input (flags count mismatches)
 //   K6 k_rank        per tile, stable slot of every attached cluster
-//   K7 k_attached    one lane per track: the float32 propagate-and-update
+//   K7 k_attached    one lane per track (a few lanes take a second track
+//                    after the first): the float32 propagate-and-update
 //   K5 k_unattached  per bin, running sums of the differences (one wave)
 #include <hip/hip_runtime.h>
 
@@ -331,9 +332,10 @@ __global__ __launch_bounds__(kTile) void k_tilesum(const FrameDesc *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Flat walk of a wave's 64 consecutive tracks.  Their decoded clusters form
-// one contiguous range [A, E) of the cluster stream; the wave walks it in
-// chunks of 64 clusters (lane = cluster), loading several chunks at a time.
+// Flat walk of a wave's consecutive tracks (32 in the count kernel).  Their
+// decoded clusters form one contiguous range [A, E) of the cluster stream; the
+// wave walks it in chunks of 64 clusters (lane = cluster), loading several
+// chunks at a time.
 // Inside a chunk the rows and sectors are segmented prefix sums: a segment
 // starts at a track's first cluster (its header position) or continues the
 // previous chunk's last track.  If a row would leave [0, 151] the chunk is

@@ -115,6 +115,41 @@ def test_capacity_plan_changing_shapes(tmd, frames):
         plan.free()
 
 
+def test_single_frame_capacity_plan_with_chained_tracks(tmd, frames, monkeypatch):
+    """A single-frame capacity plan whose calls change the decode's wave count
+    and whether tracks are chained (two per lane in a few lanes; forced by a
+    SIMD count of 2): eager and graph replays against the oracle."""
+    import torch
+    import oracle
+    monkeypatch.setenv("TMD_ATTACHED_SIMDS", "2")
+    big = max(frames, key=lambda f: f["trk_ncls"].shape[0])
+
+    def cut(fr, nt):
+        na = int(fr["trk_ncls"][:nt].astype(np.int64).sum())
+        return {k: (v[:nt] if k.startswith("trk_") else v[:na] if k.startswith("cls_") else v)
+                for k, v in fr.items()}
+
+    # 2100, 4000, 3000 tracks: 33, 63, 47 waves -> 32, 62, 46 with chained
+    # tracks; 2048: 32 waves, none chained
+    cuts = [cut(big, nt) for nt in (2100, 2048, 4000, 3000) if nt <= big["trk_ncls"].shape[0]]
+    assert len(cuts) == 4
+    exp = [oracle.decode(f) for f in cuts]
+    shapes = [tmd.frame_shape(f) for f in cuts]
+    cap = tuple(max(s[i] for s in shapes) + 5 for i in range(3))
+    for flags in (0, tmd.PLAN_GRAPH):
+        plan = tmd.Plan([cap], flags=flags)
+        ws = plan.alloc_workspace()
+        for rep in range(2):
+            for i, f in enumerate(cuts):
+                out = tmd.alloc_out(shapes[i])
+                plan.decode([tmd.to_device(f)], [out], ws, shapes=[shapes[i]])
+                torch.cuda.synchronize()
+                got = tmd.to_numpy(out)
+                assert all(np.array_equal(exp[i][0][k], got[k]) for k in exp[i][0]), (flags, rep, i)
+                assert plan.status(0) == exp[i][1], (flags, rep, i)
+        plan.free()
+
+
 def test_capacity_plan_rejects_larger_shape(tmd, frames):
     shapes = [tmd.frame_shape(f) for f in frames]
     plan = tmd.Plan([shapes[0]])
