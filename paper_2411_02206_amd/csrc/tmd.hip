@@ -162,7 +162,7 @@ constexpr int kHRow = NBIN + kNKey;  // per-tile histogram row: bins, then keys
     Q uint32_t *hist;    /* [ntile][kHRow] per-tile bin/key counts, then exclusive prefixes */ \
     Q uint32_t *uin;     /* [NBIN] first unattached input entry of each bin */                \
     Q uint32_t *ueff;    /* [NBIN] unattached clusters decoded per bin */                     \
-    Q uint4 *recs;       /* [nA] per-cluster records for the decode, stream order */          \
+    Q uint4 *recs;       /* [nA] (slot, charges, residuals, row|rot), stream order */         \
     Q uint16_t *ckey;    /* [nA] (sector,row) bin of each attached cluster, stream order */    \
     Q uint32_t *keyinfo; /* [kNKey] tracks per scheduling key, [kNKey] key starts */          \
     Q uint16_t *tkey;    /* [nT] scheduling key of each track */                              \
@@ -959,7 +959,7 @@ __global__ __launch_bounds__(kTile) void k_rank(const FrameDesc *__restrict__ fd
             }
             if (act) {
                 const uint32_t rot = P.sd[u] < 18u ? P.sd[u] : P.sd[u] % 18u;
-                F.recs[c] = make_uint4(slot, P.pr[u] | (P.tr[u] << 16), P.qt[u] | (P.qm[u] << 16),
+                F.recs[c] = make_uint4(slot, P.qt[u] | (P.qm[u] << 16), P.pr[u] | (P.tr[u] << 16),
                                        (k[u] % NROW) | (rot << 8));
             }
         }
@@ -1137,8 +1137,8 @@ __device__ __forceinline__ void coop_place(const CoopLoad &C, uint2 (*ra)[kWave]
     for (int k = 0; k < kBlk; k++) {
         if (C.dst[k] != ~0u) {
             const uint32_t sl = C.dst[k] & 0xFFu, t = C.dst[k] >> 8;
-            ra[sl][t] = make_uint2(C.v[k].x, C.v[k].z);
-            rb[sl][t] = make_uint2(C.v[k].y, C.v[k].w);
+            ra[sl][t] = make_uint2(C.v[k].x, C.v[k].y);
+            rb[sl][t] = make_uint2(C.v[k].z, C.v[k].w);
         }
     }
 }
