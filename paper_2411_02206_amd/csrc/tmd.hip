@@ -1217,24 +1217,29 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
     // which no lane has a record in its ring refills them), so 2 * 64 * 255
     // blocks always suffice
     for (uint32_t blk = 0; blk < 2u * (uint32_t)kWave * 256u; blk++) {
+        // (lane masks of compound conditions are ANDs of one-comparison
+        // ballots: a ballot of an && costs two more vector instructions)
         for (int st = 0; st < kBlk; st++) {
             const bool live = j < L;
-            if (__ballot(live) == 0) break;
+            uint64_t rdy = __ballot(live);
+            if (rdy == 0) break;
             bool ready = live;
             RowGeo R;
             if (MODE != 2) {
                 // rows 0..151; the descending mode works on 255 - row.  The
                 // pending minimum is usually the row after the last one; only
                 // if no lane is there is the minimum taken over all lanes
-                // (with all lanes active: it reads other lanes).
+                // (with all lanes active: it reads other lanes).  Lanes with
+                // no record left hold v = ~0, which no row matches.
                 const uint32_t rr = (cur.y & 0xFFu);
                 const uint32_t v = live ? (MODE == 0 ? rr : 255u - rr) : 0xFFFFFFFFu;
                 vrow += 1u;
-                ready = live && v == vrow;
-                if (__ballot(ready) == 0) {
+                rdy = __ballot(v == vrow);
+                if (rdy == 0) {
                     vrow = wave_min(v);
-                    ready = live && v == vrow;
+                    rdy = __ballot(v == vrow);
                 }
+                ready = v == vrow;
                 const uint32_t urow = MODE == 0 ? vrow : 255u - vrow;  // the row of every ready lane
                 R = Rn;
                 if (urow != grow) R = row_geo_vmem(geo, urow);
@@ -1243,7 +1248,7 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
             // entry from lane d (read while every lane is active)
             const uint32_t d = (cur.y >> 8) & 0xFFu;  // 0..17
             const bool rot = ready && j > 0 && j != nA && d != 0;
-            if (__ballot(rot) != 0) {
+            if ((rdy & __ballot(j > 0) & __ballot(j != nA) & __ballot(d != 0)) != 0) {
                 const float ca = __uint_as_float(bperm(__float_as_uint(rcos), d));
                 const float sa = __uint_as_float(bperm(__float_as_uint(rsin), d));
                 if (rot) {
@@ -1298,7 +1303,12 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
                 stg[st][lane] = make_uint2(otime, opad);
                 rmask |= 1u << st;
                 j++;
-                if (j == nA && j < n) {  // the second track starts
+                if (j < L) cur = rb[j % kRing][lane];
+            }
+            // the second track starts (once per lane at most: a wave-uniform
+            // branch keeps the copies out of every other step)
+            if (__builtin_expect((rdy & __ballot(j == nA) & __ballot(j < n)) != 0, 0)) {
+                if (ready && j == nA && j < n) {
                     x = T.xB;
                     y = T.yB;
                     z = 0.0f;
@@ -1308,7 +1318,6 @@ __device__ __forceinline__ void attached_loop(const FrameDesc &F, const Geo *__r
                     t0 = T.t0B;
                     pad0 = T.pad0B;
                 }
-                if (j < L) cur = rb[j % kRing][lane];
             }
             if (MODE != 2) {
                 const uint32_t g = MODE == 0 ? vrow + 1u : 254u - vrow;
