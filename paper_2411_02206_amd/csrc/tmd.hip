@@ -684,14 +684,26 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(const FrameDesc *__rest
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     const uint32_t b0 = threadIdx.x * kOffPer;
 
-    // unattached input: exclusive prefix of un_count in 64 bits, cut at nU
+    // every input read up front (one memory round trip): unattached counts,
+    // attached counts and tracks per scheduling key, all per bin or key
     unsigned long long cnt[kOffPer];
+    uint32_t na[kOffPer];
     unsigned long long own = 0;
     for (int i = 0; i < kOffPer; i++) {
         uint32_t b = b0 + i;
         cnt[i] = b < NBIN ? F.ucount[b] : 0u;
+        na[i] = b < NBIN ? F.rna[b] : 0u;
         own += cnt[i];
     }
+    uint32_t kc[kKeyPer];
+    uint32_t kown = 0;
+    for (int i = 0; i < kKeyPer; i++) {
+        const uint32_t key = threadIdx.x * kKeyPer + i;
+        kc[i] = key < (uint32_t)kNKey ? F.keyinfo[key] : 0u;
+        kown += kc[i];
+    }
+
+    // unattached input: exclusive prefix of un_count in 64 bits, cut at nU
     unsigned long long inc = own;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
@@ -718,7 +730,7 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(const FrameDesc *__rest
         if (b < NBIN) {
             F.uin[b] = (uint32_t)(us < F.nU ? us : F.nU);
             F.ueff[b] = e;
-            eff[i] = e + F.rna[b];
+            eff[i] = e + na[i];
         } else {
             eff[i] = 0;
         }
@@ -742,13 +754,6 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(const FrameDesc *__rest
 
     // start of each scheduling key in the decode order
     __syncthreads();  // part32 is reused
-    uint32_t kc[kKeyPer];
-    uint32_t kown = 0;
-    for (int i = 0; i < kKeyPer; i++) {
-        const uint32_t key = threadIdx.x * kKeyPer + i;
-        kc[i] = key < (uint32_t)kNKey ? F.keyinfo[key] : 0u;
-        kown += kc[i];
-    }
     const uint32_t kinc = wave_incl_add(kown);
     if (lane == kWave - 1) part32[w] = kinc;
     __syncthreads();
