@@ -184,6 +184,46 @@ int tmd_status(tmd_plan_t *plan, uint32_t frame, uint32_t *flags);
 /* Release the plan and its device memory (waits for its work). NULL is a no-op. */
 void tmd_free(tmd_plan_t *plan);
 
+/*
+ * Host-resident frames (paper section 4, Fig. 2: per-stream transfers to the
+ * GPU, decode kernels, transfers back, with the transfers of one stream
+ * overlapping the kernels of another).  A pipeline owns `depth` slots
+ * (1..TMD_PIPE_MAX_DEPTH); each slot has its own stream, a capacity plan for
+ * frames up to *capacity, its workspace, and device buffers for one frame's
+ * inputs and outputs, all allocated here (hipMalloc) and released by
+ * tmd_pipe_free.  p->flags is ignored (the slots launch eagerly).
+ * Errors: TMD_E_ARG (null pointer, depth out of range, n_tracks >
+ * TMD_MAX_TRACKS), TMD_E_HIP (no device, out of memory).
+ */
+#define TMD_PIPE_MAX_DEPTH 8u
+typedef struct tmd_pipe tmd_pipe_t;
+int tmd_pipe_create(const tmd_frame_shape *capacity, uint32_t depth, const tmd_params *p, tmd_pipe_t **pipe);
+
+/*
+ * Decode n_frames frames held in HOST memory: in[i] has host pointers laid
+ * out as tmd_frame_in describes, shaped shapes[i] (no count above the
+ * pipeline's capacity), and out[i] host pointers for the outputs as
+ * tmd_frame_out describes (row_offset, row_nattached, and n_attached +
+ * n_unattached entries of time/pad/qtot/qmax; capacity >= that sum).  Frame i
+ * goes to slot i % depth: on the slot's stream its inputs are copied to the
+ * device, decoded (tmd_decode_shapes), and the outputs copied back; a slot is
+ * reused once its previous frame is back.  Page-locked host memory
+ * (hipHostMalloc, or a pinned torch tensor) lets the copies of one slot run
+ * during another slot's kernels; pageable memory gives the same results
+ * without that overlap.  Returns when every frame is back; flags[i] receives
+ * frame i's status bits (as tmd_status).  The caller owns all host buffers;
+ * they must stay valid and unchanged until the call returns.
+ * Returns TMD_OK if no frame has a flag, TMD_E_INPUT if any has TMD_F_COUNT,
+ * TMD_E_STREAM if any has another flag; errors: TMD_E_ARG (null pipeline,
+ * null or misaligned pointer, a shape above the capacity; checked before
+ * anything is enqueued), TMD_E_CAPACITY, TMD_E_HIP.
+ */
+int tmd_pipe_run(tmd_pipe_t *pipe, uint32_t n_frames, const tmd_frame_shape *shapes, const tmd_frame_in *in,
+                 tmd_frame_out *out, uint32_t *flags);
+
+/* Release a pipeline (waits for its streams). NULL is a no-op. */
+void tmd_pipe_free(tmd_pipe_t *pipe);
+
 /* Static message for a return code. */
 const char *tmd_strerror(int code);
 

@@ -18,7 +18,8 @@ from ._lib import (E_ARG, E_CAPACITY, E_HIP, E_INPUT, E_STREAM, F_COUNT, F_HDR, 
                    F_ROW, F_SEC, F_SNP, F_TIME, IN_FIELDS, NBIN, NROW, NSEC, OK, OUT_FIELDS, PLAN_GRAPH,
                    TmdError)
 
-__all__ = ["Plan", "decode", "to_device", "alloc_out", "to_numpy", "version", "tables"]
+__all__ = ["Plan", "Pipeline", "decode", "to_device", "to_host", "alloc_out", "alloc_host_out", "to_numpy",
+           "version", "tables"]
 
 # element types of the frame arrays; unsigned 16/32-bit data travel in signed
 # torch tensors of the same width (only the bytes matter to the library)
@@ -193,6 +194,82 @@ class Plan:
         if n < 0:
             _lib.check(n, "tmd_stage_times")
         return {L.tmd_stage_name(i).decode(): buf[i] for i in range(n)}, int(calls.value)
+
+
+def to_host(frame, pin=True):
+    """Copy a numpy frame dict to torch CPU tensors, page-locked if `pin`
+    (what lets a Pipeline's transfers overlap its kernels)."""
+    torch = _torch()
+    out = {}
+    for k in IN_FIELDS:
+        a = np.ascontiguousarray(frame[k], dtype=IN_DTYPES[k])
+        t = torch.from_numpy(a.view(_SIGNED[a.dtype]))
+        out[k] = t.pin_memory() if pin else t.clone()
+    return out
+
+
+def alloc_host_out(shape, pin=True, capacity=None):
+    """Host output buffers (torch CPU tensors, page-locked if `pin`) for a
+    frame of `shape`; same keys and types as alloc_out."""
+    torch = _torch()
+    n = shape[1] + shape[2] if capacity is None else capacity
+    tt = {np.uint32: torch.int32, np.uint16: torch.int16}
+    mk = (lambda m, dt: torch.empty(m, dtype=dt, pin_memory=True)) if pin else \
+        (lambda m, dt: torch.empty(m, dtype=dt))
+    return {"row_offset": mk(NBIN + 1, torch.int32), "row_nattached": mk(NBIN, torch.int32),
+            "time": mk(max(n, 1), tt[np.uint32]), "pad": mk(max(n, 1), tt[np.uint16]),
+            "qtot": mk(max(n, 1), tt[np.uint16]), "qmax": mk(max(n, 1), tt[np.uint16]), "capacity": n}
+
+
+class Pipeline:
+    """Decoding of host-resident frames through `depth` slots (stream, plan,
+    device buffers each) used in turn: frame i is copied in, decoded and
+    copied back on slot i % depth, so transfers overlap other slots' kernels
+    (tmd_pipe_create / tmd_pipe_run)."""
+
+    def __init__(self, capacity, depth=3, bz=0.5):
+        L = _lib.lib()
+        self._params = _lib.Params(float(bz), 0)
+        cap = _lib.FrameShape(*(int(v) for v in capacity))
+        h = C.c_void_p()
+        _lib.check(L.tmd_pipe_create(C.byref(cap), int(depth), C.byref(self._params), C.byref(h)),
+                   "tmd_pipe_create")
+        self._h = h
+        self.capacity = tuple(int(v) for v in capacity)
+        self.depth = int(depth)
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.lib().tmd_pipe_free(h)
+            self._h = None
+
+    def run(self, frames, outs, shapes=None):
+        """Decode host frames (dicts of CPU tensors, see to_host) into host
+        outputs (see alloc_host_out).  Returns the list of status flags; raises
+        TmdError on an argument or runtime error."""
+        n = len(frames)
+        if len(outs) != n:
+            raise ValueError("one output dict per frame")
+        if shapes is None:
+            shapes = [frame_shape(f) for f in frames]
+        sh = (_lib.FrameShape * max(n, 1))(*[_lib.FrameShape(*(int(v) for v in s)) for s in shapes])
+        fin = (_lib.FrameIn * max(n, 1))()
+        fout = (_lib.FrameOut * max(n, 1))()
+        for i in range(n):
+            for k in IN_FIELDS:
+                setattr(fin[i], k, _ptr(frames[i][k]))
+            for k in OUT_FIELDS:
+                setattr(fout[i], k, _ptr(outs[i][k]))
+            fout[i].capacity = int(outs[i]["capacity"])
+        flags = (C.c_uint32 * max(n, 1))()
+        rc = _lib.lib().tmd_pipe_run(self._h, n, sh, fin, fout, flags)
+        if rc not in (OK, E_INPUT, E_STREAM):
+            _lib.check(rc, "tmd_pipe_run")
+        return [int(flags[i]) for i in range(n)]
 
 
 def decode(frame, bz=0.5, stream=None):

@@ -16,6 +16,7 @@ MAX_TRACKS = 1 << 24
 OK, E_ARG, E_CAPACITY, E_INPUT, E_STREAM, E_HIP = 0, -1, -2, -3, -4, -5
 F_HDR, F_SEC, F_ROW, F_ROT, F_SNP, F_PAD, F_TIME, F_COUNT = 1, 2, 4, 8, 16, 32, 64, 128
 PLAN_GRAPH = 1
+PIPE_MAX_DEPTH = 8
 
 P = C.c_void_p
 
@@ -81,6 +82,13 @@ def lib():
         L.tmd_selftest_math.restype = C.c_int
         L.tmd_selftest_sqrt.argtypes = [C.c_uint32, C.c_uint32, P, P]
         L.tmd_selftest_sqrt.restype = C.c_int
+        L.tmd_pipe_create.argtypes = [C.POINTER(FrameShape), C.c_uint32, C.POINTER(Params), C.POINTER(P)]
+        L.tmd_pipe_create.restype = C.c_int
+        L.tmd_pipe_run.argtypes = [P, C.c_uint32, C.POINTER(FrameShape), C.POINTER(FrameIn), C.POINTER(FrameOut),
+                                   C.POINTER(C.c_uint32)]
+        L.tmd_pipe_run.restype = C.c_int
+        L.tmd_pipe_free.argtypes = [P]
+        L.tmd_pipe_free.restype = None
         _LIB = L
     return _LIB
 

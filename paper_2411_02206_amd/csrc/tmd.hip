@@ -36,10 +36,12 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -2094,6 +2096,237 @@ int tmd_selftest_fp(const float *a, const float *b, float *out, uint32_t n, void
     if (n == 0) return TMD_OK;
     hipLaunchKernelGGL(k_selftest_fp, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, a, b, out, n);
     HIP_TRY(hipGetLastError());
+    return TMD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Host-resident frames (the transfer-hiding scheme of the paper's Fig. 2):
+// frames in host memory are decoded through `depth` slots used in turn.  A
+// slot owns a stream, a capacity plan with its workspace, and device copies of
+// one frame's inputs and outputs; on its stream it uploads a frame, decodes it
+// and downloads the result, so one frame's transfers run while another slot's
+// frame is decoded (the copy engines and the compute units work side by side).
+// ---------------------------------------------------------------------------
+namespace {
+
+enum CountKind { kCntT, kCntA, kCntU, kCntBin };
+struct ArrSpec {
+    size_t off;     // offset of the pointer in tmd_frame_in
+    uint32_t elem;  // element size in bytes
+    CountKind kind;
+};
+#define TMD_IN(f, e, k) {offsetof(tmd_frame_in, f), e, k}
+const ArrSpec kPipeIn[] = {
+    TMD_IN(trk_ncls, 1, kCntT),     TMD_IN(trk_sec0, 1, kCntT),      TMD_IN(trk_row0, 1, kCntT),
+    TMD_IN(trk_pad0, 2, kCntT),     TMD_IN(trk_time0, 4, kCntT),     TMD_IN(trk_qpt, 2, kCntT),
+    TMD_IN(trk_snp, 2, kCntT),      TMD_IN(trk_tgl, 2, kCntT),       TMD_IN(cls_row_diff, 1, kCntA),
+    TMD_IN(cls_sec_diff, 1, kCntA), TMD_IN(cls_pad_res, 2, kCntA),   TMD_IN(cls_time_res, 2, kCntA),
+    TMD_IN(cls_qtot, 2, kCntA),     TMD_IN(cls_qmax, 2, kCntA),      TMD_IN(un_count, 4, kCntBin),
+    TMD_IN(un_time_diff, 4, kCntU), TMD_IN(un_pad_diff, 2, kCntU),   TMD_IN(un_qtot, 2, kCntU),
+    TMD_IN(un_qmax, 2, kCntU),
+};
+#undef TMD_IN
+
+size_t pipe_count(CountKind k, const tmd_frame_shape &S)
+{
+    switch (k) {
+    case kCntT: return S.n_tracks;
+    case kCntA: return S.n_attached;
+    case kCntU: return S.n_unattached;
+    default: return NBIN;
+    }
+}
+
+const void *in_ptr(const tmd_frame_in &I, size_t off)
+{
+    const void *p;
+    memcpy(&p, (const char *)&I + off, sizeof(p));
+    return p;
+}
+
+void set_in_ptr(tmd_frame_in &I, size_t off, const void *p) { memcpy((char *)&I + off, &p, sizeof(p)); }
+
+struct PipeSlot {
+    hipStream_t stream = nullptr;
+    tmd_plan_t *plan = nullptr;
+    void *ws = nullptr;
+    void *din = nullptr;  // device inputs, one allocation
+    void *dout = nullptr;  // device outputs, one allocation
+    tmd_frame_in in{};
+    tmd_frame_out out{};
+    int64_t frame = -1;  // frame of the current run whose result is still in flight
+};
+
+}  // namespace
+
+struct tmd_pipe {
+    int device = 0;
+    tmd_frame_shape cap{};
+    std::vector<PipeSlot> slots;
+};
+
+extern "C" {
+
+void tmd_pipe_free(tmd_pipe_t *Q)
+{
+    if (!Q) return;
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != Q->device) (void)hipSetDevice(Q->device);
+    for (PipeSlot &sl : Q->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        tmd_free(sl.plan);
+        if (sl.ws) (void)hipFree(sl.ws);
+        if (sl.din) (void)hipFree(sl.din);
+        if (sl.dout) (void)hipFree(sl.dout);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    if (cur != Q->device) (void)hipSetDevice(cur);
+    delete Q;
+}
+
+int tmd_pipe_create(const tmd_frame_shape *capacity, uint32_t depth, const tmd_params *p, tmd_pipe_t **pipe)
+{
+    if (!capacity || !p || !pipe || depth == 0 || depth > TMD_PIPE_MAX_DEPTH) return TMD_E_ARG;
+    if (capacity->n_tracks > TMD_MAX_TRACKS) return TMD_E_ARG;
+    *pipe = nullptr;
+    tmd_pipe_t *Q = new (std::nothrow) tmd_pipe_t();
+    if (!Q) return TMD_E_HIP;
+    Q->cap = *capacity;
+    const tmd_params pp = {p->bz_tesla, 0u};  // eager launches: the slots' streams overlap
+    int rc = TMD_OK;
+    if (hipGetDevice(&Q->device) != hipSuccess) rc = TMD_E_HIP;
+    Q->slots.resize(rc == TMD_OK ? depth : 0);
+    for (PipeSlot &sl : Q->slots) {
+        size_t wsb = 0;
+        if ((rc = tmd_plan(capacity, 1, &pp, &sl.plan, &wsb)) != TMD_OK) break;
+        if (hipMalloc(&sl.ws, wsb > 256 ? wsb : 256) != hipSuccess) { rc = TMD_E_HIP; break; }
+        auto in_bytes = [&](const ArrSpec &a) {
+            return align256((size_t)a.elem * std::max<size_t>(pipe_count(a.kind, Q->cap), 1));
+        };
+        size_t ib = 0;
+        for (const ArrSpec &a : kPipeIn) ib += in_bytes(a);
+        if (hipMalloc(&sl.din, ib) != hipSuccess) { rc = TMD_E_HIP; break; }
+        size_t o = 0;
+        for (const ArrSpec &a : kPipeIn) {
+            set_in_ptr(sl.in, a.off, (char *)sl.din + o);
+            o += in_bytes(a);
+        }
+        const size_t n = std::max<size_t>((size_t)Q->cap.n_attached + Q->cap.n_unattached, 1);
+        const size_t ob = align256(4 * (size_t)(NBIN + 1)) + align256(4 * (size_t)NBIN) + align256(4 * n) +
+                          3 * align256(2 * n);
+        if (hipMalloc(&sl.dout, ob) != hipSuccess) { rc = TMD_E_HIP; break; }
+        char *b = (char *)sl.dout;
+        sl.out.row_offset = (uint32_t *)b; b += align256(4 * (size_t)(NBIN + 1));
+        sl.out.row_nattached = (uint32_t *)b; b += align256(4 * (size_t)NBIN);
+        sl.out.time = (uint32_t *)b; b += align256(4 * n);
+        sl.out.pad = (uint16_t *)b; b += align256(2 * n);
+        sl.out.qtot = (uint16_t *)b; b += align256(2 * n);
+        sl.out.qmax = (uint16_t *)b;
+        sl.out.capacity = n;
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) { rc = TMD_E_HIP; break; }
+    }
+    if (rc != TMD_OK) {
+        tmd_pipe_free(Q);
+        return rc;
+    }
+    *pipe = Q;
+    return TMD_OK;
+}
+
+int tmd_pipe_run(tmd_pipe_t *Q, uint32_t n_frames, const tmd_frame_shape *shapes, const tmd_frame_in *in,
+                 tmd_frame_out *out, uint32_t *flags)
+{
+    if (!Q) return TMD_E_ARG;
+    if (n_frames == 0) return TMD_OK;
+    if (!shapes || !in || !out || !flags) return TMD_E_ARG;
+    // host-side checks of every frame before anything is enqueued
+    for (uint32_t i = 0; i < n_frames; i++) {
+        const tmd_frame_shape &S = shapes[i];
+        if (S.n_tracks > Q->cap.n_tracks || S.n_attached > Q->cap.n_attached ||
+            S.n_unattached > Q->cap.n_unattached)
+            return TMD_E_ARG;
+        const uint64_t nn = (uint64_t)S.n_attached + S.n_unattached;
+        if (out[i].capacity < nn) return TMD_E_CAPACITY;
+        for (const ArrSpec &a : kPipeIn) {
+            const void *h = in_ptr(in[i], a.off);
+            if (pipe_count(a.kind, S) && (!h || (uintptr_t)h % a.elem)) return TMD_E_ARG;
+        }
+        const tmd_frame_out &O = out[i];
+        if (!O.row_offset || !O.row_nattached || !aligned(O.row_offset) || !aligned(O.row_nattached))
+            return TMD_E_ARG;
+        if (nn && (!O.time || !O.pad || !O.qtot || !O.qmax || !aligned(O.time) || !aligned(O.pad) ||
+                   !aligned(O.qtot) || !aligned(O.qmax)))
+            return TMD_E_ARG;
+        flags[i] = 0;
+    }
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != Q->device) HIP_TRY(hipSetDevice(Q->device));
+    uint32_t any = 0;
+    // wait for a slot's frame and collect its flags
+    auto finish = [&](PipeSlot &sl) -> int {
+        if (sl.frame < 0) return TMD_OK;
+        if (hipStreamSynchronize(sl.stream) != hipSuccess) return TMD_E_HIP;
+        uint32_t f = 0;
+        const int r = tmd_status(sl.plan, 0, &f);
+        if (r == TMD_E_ARG || r == TMD_E_HIP) return r;
+        flags[sl.frame] = f;
+        any |= f;
+        sl.frame = -1;
+        return TMD_OK;
+    };
+    const uint32_t depth = (uint32_t)Q->slots.size();
+    int rc = TMD_OK;
+    for (uint32_t i = 0; i < n_frames && rc == TMD_OK; i++) {
+        PipeSlot &sl = Q->slots[i % depth];
+        if ((rc = finish(sl)) != TMD_OK) break;
+        const tmd_frame_shape &S = shapes[i];
+        for (const ArrSpec &a : kPipeIn) {
+            const size_t cnt = pipe_count(a.kind, S);
+            if (!cnt) continue;
+            if (hipMemcpyAsync((void *)in_ptr(sl.in, a.off), in_ptr(in[i], a.off), cnt * a.elem,
+                               hipMemcpyHostToDevice, sl.stream) != hipSuccess) {
+                rc = TMD_E_HIP;
+                break;
+            }
+        }
+        if (rc != TMD_OK) break;
+        tmd_frame_out dev = sl.out;
+        if ((rc = tmd_decode_shapes(sl.plan, &S, &sl.in, &dev, sl.ws, sl.stream)) != TMD_OK) break;
+        const size_t nn = (size_t)S.n_attached + S.n_unattached;
+        const tmd_frame_out &O = out[i];
+        struct {
+            void *dst;
+            const void *src;
+            size_t bytes;
+        } dl[6] = {{O.row_offset, sl.out.row_offset, 4 * (size_t)(NBIN + 1)},
+                   {O.row_nattached, sl.out.row_nattached, 4 * (size_t)NBIN},
+                   {O.time, sl.out.time, 4 * nn},
+                   {O.pad, sl.out.pad, 2 * nn},
+                   {O.qtot, sl.out.qtot, 2 * nn},
+                   {O.qmax, sl.out.qmax, 2 * nn}};
+        for (auto &d : dl) {
+            if (!d.bytes) continue;
+            if (hipMemcpyAsync(d.dst, d.src, d.bytes, hipMemcpyDeviceToHost, sl.stream) != hipSuccess) {
+                rc = TMD_E_HIP;
+                break;
+            }
+        }
+        sl.frame = i;
+    }
+    // drain every slot (also after an error, so that no copy is left running)
+    for (PipeSlot &sl : Q->slots) {
+        int r = hipStreamSynchronize(sl.stream) == hipSuccess ? TMD_OK : TMD_E_HIP;
+        if (r == TMD_OK) r = finish(sl);
+        if (rc == TMD_OK) rc = r;
+        sl.frame = -1;
+    }
+    if (cur != Q->device) (void)hipSetDevice(cur);
+    if (rc != TMD_OK) return rc;
+    if (any & TMD_F_COUNT) return TMD_E_INPUT;
+    if (any) return TMD_E_STREAM;
     return TMD_OK;
 }
 

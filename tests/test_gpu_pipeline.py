@@ -1,0 +1,89 @@
+"""Host-resident frames through the native pipeline (tmd_pipe_*): frames in
+host memory are copied in, decoded and copied back on several streams, and
+every output must be bit-identical to the oracle's decode of the same frame,
+whatever the depth, and with page-locked or pageable host memory."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import build_frame, empty_frame
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tmd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2411_02206_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def frames():
+    specs = synth.batch_specs("batched", n_frames=5, coll_range=(1, 6), seed=7)
+    fr = [synth.make_frame(s) for s in specs]
+    # a frame without clusters, and one with a single one-cluster track
+    one = build_frame([{"sec0": 3, "row0": 40, "pad0": 1000, "time0": 5000, "qpt": 100, "snp": 0, "tgl": 0,
+                        "cl": [(0, 0, 0, 0, 11, 12)]}], {7: [(5, 6, 7, 8)]})
+    return fr[:3] + [empty_frame()] + fr[3:] + [one]
+
+
+@pytest.fixture(scope="module")
+def expected(frames):
+    return [oracle.decode(f, bz=0.5) for f in frames]
+
+
+def cap_of(tmd, frames):
+    sh = [tmd.frame_shape(f) for f in frames]
+    return tuple(max(s[i] for s in sh) for i in range(3))
+
+
+def check(tmd, frames, expected, outs, flags):
+    for i, (exp, est) in enumerate(expected):
+        got = tmd.to_numpy(outs[i])
+        for k in exp:
+            assert np.array_equal(exp[k], got[k]), (i, k)
+        assert flags[i] == est, (i, flags[i], est)
+
+
+@pytest.mark.parametrize("depth", [1, 3])
+def test_pipeline_pinned_matches_oracle(tmd, frames, expected, depth):
+    pipe = tmd.Pipeline(cap_of(tmd, frames), depth=depth)
+    host = [tmd.to_host(f, pin=True) for f in frames]
+    outs = [tmd.alloc_host_out(tmd.frame_shape(f), pin=True) for f in frames]
+    for rep in range(2):  # the slots are reused across calls
+        for o in outs:
+            for k in tmd.OUT_FIELDS:
+                o[k].fill_(-1)
+        flags = pipe.run(host, outs)
+        check(tmd, frames, expected, outs, flags)
+    pipe.free()
+
+
+def test_pipeline_pageable_matches_oracle(tmd, frames, expected):
+    pipe = tmd.Pipeline(cap_of(tmd, frames), depth=2)
+    host = [tmd.to_host(f, pin=False) for f in frames]
+    outs = [tmd.alloc_host_out(tmd.frame_shape(f), pin=False) for f in frames]
+    flags = pipe.run(host, outs)
+    check(tmd, frames, expected, outs, flags)
+    pipe.free()
+
+
+def test_pipeline_rejects_oversized_frames(tmd, frames):
+    small = tmd.frame_shape(frames[0])
+    big_i = max(range(len(frames)), key=lambda i: tmd.frame_shape(frames[i])[1])
+    pipe = tmd.Pipeline(small, depth=2)
+    host = [tmd.to_host(frames[big_i])]
+    if tmd.frame_shape(frames[big_i])[1] > small[1]:
+        with pytest.raises(tmd.TmdError) as e:
+            pipe.run(host, [tmd.alloc_host_out(tmd.frame_shape(frames[big_i]))])
+        assert e.value.code == tmd.E_ARG
+    # output capacity below the frame's cluster count
+    f0 = tmd.to_host(frames[0])
+    n = small[1] + small[2]
+    with pytest.raises(tmd.TmdError) as e:
+        pipe.run([f0], [tmd.alloc_host_out(small, capacity=max(n - 1, 0))])
+    assert e.value.code == tmd.E_CAPACITY
+    pipe.free()

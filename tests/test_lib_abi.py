@@ -63,6 +63,16 @@ def test_bad_arguments_rejected_on_host():
     assert L.tmd_selftest_sqrt(0, 1, None, None) == _lib.E_ARG
     assert L.tmd_selftest_sqrt(5, 4, C.c_void_p(1), None) == _lib.E_ARG
     L.tmd_free(None)  # no-op
+    # host pipeline: argument checks that come before any device call
+    q = C.c_void_p()
+    assert L.tmd_pipe_create(None, 2, C.byref(p), C.byref(q)) == _lib.E_ARG
+    assert L.tmd_pipe_create(shape, 0, C.byref(p), C.byref(q)) == _lib.E_ARG
+    assert L.tmd_pipe_create(shape, _lib.PIPE_MAX_DEPTH + 1, C.byref(p), C.byref(q)) == _lib.E_ARG
+    assert L.tmd_pipe_create(big, 2, C.byref(p), C.byref(q)) == _lib.E_ARG
+    assert L.tmd_pipe_create(shape, 2, None, C.byref(q)) == _lib.E_ARG
+    flags = (C.c_uint32 * 1)()
+    assert L.tmd_pipe_run(None, 1, shape, None, None, flags) == _lib.E_ARG
+    L.tmd_pipe_free(None)  # no-op
 
 
 def test_table_size_query():
