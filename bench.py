@@ -41,8 +41,8 @@ WORKLOADS = {
     "served": "Poisson arrivals of frames from the batched mix at 25/50/75/100% of the batched peak; "
               "continuous batching under a 200 GB HBM budget; p50/p99 latency",
     "pipeline": "the frame workload held in page-locked host memory, decoded through the native pipeline "
-                "(per slot stream: copy in over PCIe, decode, copy back), 3 slots against 1 (no overlap); "
-                "rate includes the transfers",
+                "(one upload stream, a decode stream per slot, one download stream, ordered by events), "
+                "3 slots against 1 (no overlap); rate includes the PCIe transfers",
 }
 
 

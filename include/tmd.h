@@ -188,10 +188,11 @@ void tmd_free(tmd_plan_t *plan);
  * Host-resident frames (paper section 4, Fig. 2: per-stream transfers to the
  * GPU, decode kernels, transfers back, with the transfers of one stream
  * overlapping the kernels of another).  A pipeline owns `depth` slots
- * (1..TMD_PIPE_MAX_DEPTH); each slot has its own stream, a capacity plan for
- * frames up to *capacity, its workspace, and device buffers for one frame's
- * inputs and outputs, all allocated here (hipMalloc) and released by
- * tmd_pipe_free.  p->flags is ignored (the slots launch eagerly).
+ * (1..TMD_PIPE_MAX_DEPTH); each slot has its own decode stream, a capacity
+ * plan for frames up to *capacity, its workspace, and device buffers for one
+ * frame's inputs and outputs.  One more stream carries every upload and
+ * another every download.  All of it is allocated here (hipMalloc) and
+ * released by tmd_pipe_free.  p->flags is ignored (the slots launch eagerly).
  * Errors: TMD_E_ARG (null pointer, depth out of range, n_tracks >
  * TMD_MAX_TRACKS), TMD_E_HIP (no device, out of memory).
  */
@@ -205,9 +206,11 @@ int tmd_pipe_create(const tmd_frame_shape *capacity, uint32_t depth, const tmd_p
  * pipeline's capacity), and out[i] host pointers for the outputs as
  * tmd_frame_out describes (row_offset, row_nattached, and n_attached +
  * n_unattached entries of time/pad/qtot/qmax; capacity >= that sum).  Frame i
- * goes to slot i % depth: on the slot's stream its inputs are copied to the
- * device, decoded (tmd_decode_shapes), and the outputs copied back; a slot is
- * reused once its previous frame is back.  Page-locked host memory
+ * goes to slot i % depth: its inputs are copied to the slot's buffers on the
+ * upload stream, decoded on the slot's stream (tmd_decode_shapes), and the
+ * outputs copied back on the download stream, each step ordered after the
+ * previous one by events; a slot is reused once its previous frame is back.
+ * Page-locked host memory
  * (hipHostMalloc, or a pinned torch tensor) lets the copies of one slot run
  * during another slot's kernels; pageable memory gives the same results
  * without that overlap.  Returns when every frame is back; flags[i] receives

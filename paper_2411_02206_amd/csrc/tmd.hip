@@ -2104,10 +2104,11 @@ int tmd_selftest_fp(const float *a, const float *b, float *out, uint32_t n, void
 // ---------------------------------------------------------------------------
 // Host-resident frames (the transfer-hiding scheme of the paper's Fig. 2):
 // frames in host memory are decoded through `depth` slots used in turn.  A
-// slot owns a stream, a capacity plan with its workspace, and device copies of
-// one frame's inputs and outputs; on its stream it uploads a frame, decodes it
-// and downloads the result, so one frame's transfers run while another slot's
-// frame is decoded (the copy engines and the compute units work side by side).
+// slot owns a decode stream, a capacity plan with its workspace, and device
+// copies of one frame's inputs and outputs.  All uploads go through one
+// stream and all downloads through another, ordered against the decodes by
+// events, so that at any time one upload, one decode and one download can run
+// side by side (PCIe carries both directions at once).
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -2149,7 +2150,9 @@ const void *in_ptr(const tmd_frame_in &I, size_t off)
 void set_in_ptr(tmd_frame_in &I, size_t off, const void *p) { memcpy((char *)&I + off, &p, sizeof(p)); }
 
 struct PipeSlot {
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // decode
+    hipEvent_t up = nullptr, dec = nullptr, down = nullptr;  // this slot's last upload, decode, download
+    bool used = false;              // the events have been recorded
     tmd_plan_t *plan = nullptr;
     void *ws = nullptr;
     void *din = nullptr;  // device inputs, one allocation
@@ -2165,6 +2168,7 @@ struct tmd_pipe {
     int device = 0;
     tmd_frame_shape cap{};
     std::vector<PipeSlot> slots;
+    hipStream_t up = nullptr, down = nullptr;  // all uploads; all downloads
 };
 
 extern "C" {
@@ -2174,14 +2178,20 @@ void tmd_pipe_free(tmd_pipe_t *Q)
     if (!Q) return;
     int cur = 0;
     if (hipGetDevice(&cur) == hipSuccess && cur != Q->device) (void)hipSetDevice(Q->device);
+    if (Q->up) (void)hipStreamSynchronize(Q->up);
+    if (Q->down) (void)hipStreamSynchronize(Q->down);
     for (PipeSlot &sl : Q->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        for (hipEvent_t e : {sl.up, sl.dec, sl.down})
+            if (e) (void)hipEventDestroy(e);
         tmd_free(sl.plan);
         if (sl.ws) (void)hipFree(sl.ws);
         if (sl.din) (void)hipFree(sl.din);
         if (sl.dout) (void)hipFree(sl.dout);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
+    if (Q->up) (void)hipStreamDestroy(Q->up);
+    if (Q->down) (void)hipStreamDestroy(Q->down);
     if (cur != Q->device) (void)hipSetDevice(cur);
     delete Q;
 }
@@ -2197,6 +2207,9 @@ int tmd_pipe_create(const tmd_frame_shape *capacity, uint32_t depth, const tmd_p
     const tmd_params pp = {p->bz_tesla, 0u};  // eager launches: the slots' streams overlap
     int rc = TMD_OK;
     if (hipGetDevice(&Q->device) != hipSuccess) rc = TMD_E_HIP;
+    if (rc == TMD_OK && (hipStreamCreateWithFlags(&Q->up, hipStreamNonBlocking) != hipSuccess ||
+                         hipStreamCreateWithFlags(&Q->down, hipStreamNonBlocking) != hipSuccess))
+        rc = TMD_E_HIP;
     Q->slots.resize(rc == TMD_OK ? depth : 0);
     for (PipeSlot &sl : Q->slots) {
         size_t wsb = 0;
@@ -2226,6 +2239,12 @@ int tmd_pipe_create(const tmd_frame_shape *capacity, uint32_t depth, const tmd_p
         sl.out.qmax = (uint16_t *)b;
         sl.out.capacity = n;
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if (hipEventCreateWithFlags(&sl.up, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.dec, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.down, hipEventDisableTiming) != hipSuccess) {
+            rc = TMD_E_HIP;
+            break;
+        }
     }
     if (rc != TMD_OK) {
         tmd_pipe_free(Q);
@@ -2265,10 +2284,10 @@ int tmd_pipe_run(tmd_pipe_t *Q, uint32_t n_frames, const tmd_frame_shape *shapes
     HIP_TRY(hipGetDevice(&cur));
     if (cur != Q->device) HIP_TRY(hipSetDevice(Q->device));
     uint32_t any = 0;
-    // wait for a slot's frame and collect its flags
+    // wait for a slot's frame to be back and collect its flags
     auto finish = [&](PipeSlot &sl) -> int {
         if (sl.frame < 0) return TMD_OK;
-        if (hipStreamSynchronize(sl.stream) != hipSuccess) return TMD_E_HIP;
+        if (hipEventSynchronize(sl.down) != hipSuccess) return TMD_E_HIP;
         uint32_t f = 0;
         const int r = tmd_status(sl.plan, 0, &f);
         if (r == TMD_E_ARG || r == TMD_E_HIP) return r;
@@ -2283,18 +2302,27 @@ int tmd_pipe_run(tmd_pipe_t *Q, uint32_t n_frames, const tmd_frame_shape *shapes
         PipeSlot &sl = Q->slots[i % depth];
         if ((rc = finish(sl)) != TMD_OK) break;
         const tmd_frame_shape &S = shapes[i];
+        // upload (after the slot's previous decode has read its inputs)
+        if (sl.used && hipStreamWaitEvent(Q->up, sl.dec, 0) != hipSuccess) { rc = TMD_E_HIP; break; }
         for (const ArrSpec &a : kPipeIn) {
             const size_t cnt = pipe_count(a.kind, S);
             if (!cnt) continue;
             if (hipMemcpyAsync((void *)in_ptr(sl.in, a.off), in_ptr(in[i], a.off), cnt * a.elem,
-                               hipMemcpyHostToDevice, sl.stream) != hipSuccess) {
+                               hipMemcpyHostToDevice, Q->up) != hipSuccess) {
                 rc = TMD_E_HIP;
                 break;
             }
         }
         if (rc != TMD_OK) break;
+        if (hipEventRecord(sl.up, Q->up) != hipSuccess) { rc = TMD_E_HIP; break; }
+        // decode (after the upload, and after the slot's previous download
+        // has read its outputs)
+        if (hipStreamWaitEvent(sl.stream, sl.up, 0) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if (sl.used && hipStreamWaitEvent(sl.stream, sl.down, 0) != hipSuccess) { rc = TMD_E_HIP; break; }
         tmd_frame_out dev = sl.out;
         if ((rc = tmd_decode_shapes(sl.plan, &S, &sl.in, &dev, sl.ws, sl.stream)) != TMD_OK) break;
+        if (hipEventRecord(sl.dec, sl.stream) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if (hipStreamWaitEvent(Q->down, sl.dec, 0) != hipSuccess) { rc = TMD_E_HIP; break; }
         const size_t nn = (size_t)S.n_attached + S.n_unattached;
         const tmd_frame_out &O = out[i];
         struct {
@@ -2309,18 +2337,25 @@ int tmd_pipe_run(tmd_pipe_t *Q, uint32_t n_frames, const tmd_frame_shape *shapes
                    {O.qmax, sl.out.qmax, 2 * nn}};
         for (auto &d : dl) {
             if (!d.bytes) continue;
-            if (hipMemcpyAsync(d.dst, d.src, d.bytes, hipMemcpyDeviceToHost, sl.stream) != hipSuccess) {
+            if (hipMemcpyAsync(d.dst, d.src, d.bytes, hipMemcpyDeviceToHost, Q->down) != hipSuccess) {
                 rc = TMD_E_HIP;
                 break;
             }
         }
+        if (rc != TMD_OK) break;
+        if (hipEventRecord(sl.down, Q->down) != hipSuccess) { rc = TMD_E_HIP; break; }
+        sl.used = true;
         sl.frame = i;
     }
-    // drain every slot (also after an error, so that no copy is left running)
+    // drain (also after an error, so that no copy is left running)
+    int r = TMD_OK;
+    if (hipStreamSynchronize(Q->up) != hipSuccess) r = TMD_E_HIP;
+    for (PipeSlot &sl : Q->slots)
+        if (hipStreamSynchronize(sl.stream) != hipSuccess) r = TMD_E_HIP;
+    if (hipStreamSynchronize(Q->down) != hipSuccess) r = TMD_E_HIP;
+    if (rc == TMD_OK) rc = r;
     for (PipeSlot &sl : Q->slots) {
-        int r = hipStreamSynchronize(sl.stream) == hipSuccess ? TMD_OK : TMD_E_HIP;
-        if (r == TMD_OK) r = finish(sl);
-        if (rc == TMD_OK) rc = r;
+        if (rc == TMD_OK) rc = finish(sl);
         sl.frame = -1;
     }
     if (cur != Q->device) (void)hipSetDevice(cur);
