@@ -770,9 +770,10 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(const FrameDesc *__rest
 }
 
 // ---------------------------------------------------------------------------
-// K5: unattached clusters; one wave per (bin, frame), 256 clusters per pass
+// K5: unattached clusters; one wave per (bin, frame), 1024 clusters per pass
+// (a pass's loads are all in flight together)
 // ---------------------------------------------------------------------------
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 16;  // a bin is a serial chain of passes: few, wide ones
 
 __global__ __launch_bounds__(kWave) void k_unattached(const FrameDesc *__restrict__ fd)
 {
