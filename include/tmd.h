@@ -215,7 +215,9 @@ int tmd_pipe_create(const tmd_frame_shape *capacity, uint32_t depth, const tmd_p
  * during another slot's kernels; pageable memory gives the same results
  * without that overlap.  Returns when every frame is back; flags[i] receives
  * frame i's status bits (as tmd_status).  The caller owns all host buffers;
- * they must stay valid and unchanged until the call returns.
+ * they must stay valid and unchanged until the call returns.  Calls on one
+ * pipeline must not overlap (one host thread at a time); separate pipelines
+ * are independent.
  * Returns TMD_OK if no frame has a flag, TMD_E_INPUT if any has TMD_F_COUNT,
  * TMD_E_STREAM if any has another flag; errors: TMD_E_ARG (null pipeline,
  * null or misaligned pointer, a shape above the capacity; checked before
