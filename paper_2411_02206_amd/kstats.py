@@ -31,7 +31,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--out", default=None)
-    ap.add_argument("--work", default=os.path.join(ROOT, "gpurun_out", "kstats"))
+    ap.add_argument("--work", default=os.path.join(ROOT, "rocprof_out", "kstats"),
+                    help="folder for rocprofv3's raw output")
     ap.add_argument("--rocprof", default="rocprofv3")
     ap.add_argument("--timeout", type=float, default=300.0)
     args = ap.parse_args()

@@ -91,7 +91,8 @@ def main():
     ap.add_argument("--copy", type=int, default=0, help="run the copy program of MIB MiB and exit")
     ap.add_argument("--workload", default="frame")
     ap.add_argument("--out", default=None)
-    ap.add_argument("--work", default=os.path.join(ROOT, "gpurun_out", "traffic"))
+    ap.add_argument("--work", default=os.path.join(ROOT, "rocprof_out", "traffic"),
+                    help="folder for rocprofv3's raw output")
     ap.add_argument("--rocprof", default="rocprofv3")
     ap.add_argument("--timeout", type=float, default=240.0)
     args = ap.parse_args()
