@@ -84,7 +84,7 @@ def main():
                          "initialises the GPU before the program starts)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build decodes on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: libtmd decodes on one GPU; --gpus {args.gpus} is not supported "
               "(frames are independent: several GPUs would each decode their own frames)",
               file=sys.stderr)
         sys.exit(2)
