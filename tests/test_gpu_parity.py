@@ -135,6 +135,43 @@ def test_long_tracks_and_full_bins(tmd):
     assert_same(tmd, build_frame(tr), label="full bins")
 
 
+def test_max_track_count(tmd):
+    """TMD_MAX_TRACKS (2^24) tracks of one or two clusters: 65 536 tiles, the
+    column scan's longest columns and the largest decode grid."""
+    import paper_2411_02206_amd._lib as L
+    nt = L.MAX_TRACKS
+    rng = np.random.default_rng(24)
+    ncls = np.where(rng.random(nt) < 0.1, 2, 1).astype(np.uint8)
+    na = int(ncls.sum())
+    first = np.zeros(na, bool)
+    first[np.concatenate([[0], np.cumsum(ncls, dtype=np.int64)[:-1]])] = True
+    nu_per_bin = rng.integers(0, 4, NBIN).astype(np.uint32)
+    nu = int(nu_per_bin.sum())
+    fr = {
+        "trk_ncls": ncls,
+        "trk_sec0": rng.integers(0, 36, nt).astype(np.uint8),
+        "trk_row0": rng.integers(0, 151, nt).astype(np.uint8),
+        "trk_pad0": rng.integers(0, 60000, nt).astype(np.uint16),
+        "trk_time0": rng.integers(0, 2**24 - 2**20, nt).astype(np.uint32),
+        "trk_qpt": rng.integers(-2000, 2000, nt).astype(np.int16),
+        "trk_snp": rng.integers(-20000, 20000, nt).astype(np.int16),
+        "trk_tgl": rng.integers(-4000, 4000, nt).astype(np.int16),
+        "cls_row_diff": np.where(first, 0, 1).astype(np.int8),
+        "cls_sec_diff": np.zeros(na, np.uint8),
+        "cls_pad_res": rng.integers(-100, 100, na).astype(np.int16),
+        "cls_time_res": rng.integers(-100, 100, na).astype(np.int16),
+        "cls_qtot": rng.integers(0, 65536, na).astype(np.uint16),
+        "cls_qmax": rng.integers(0, 65536, na).astype(np.uint16),
+        "un_count": nu_per_bin,
+        "un_time_diff": rng.integers(0, 2**32, nu, dtype=np.uint64).astype(np.uint32),
+        "un_pad_diff": rng.integers(0, 65536, nu).astype(np.uint16),
+        "un_qtot": rng.integers(0, 65536, nu).astype(np.uint16),
+        "un_qmax": rng.integers(0, 65536, nu).astype(np.uint16),
+    }
+    print(f"max track count: {nt} tracks, {na} attached, {nu} unattached", flush=True)
+    assert_same(tmd, fr, label="max tracks")
+
+
 def _garbage(seed, nt=700, na=60000, nu=30000):
     rng = np.random.default_rng(seed)
     fr = {
