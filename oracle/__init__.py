@@ -82,6 +82,10 @@ def lib():
         L.oracle_tables.restype = C.c_int
         L.oracle_npads.argtypes = [C.POINTER(C.c_int)]
         L.oracle_npads.restype = C.c_int
+        L.oracle_sat.argtypes = [C.c_float]
+        L.oracle_sat.restype = C.c_int32
+        L.oracle_clamp_snp.argtypes = [C.c_float, C.POINTER(C.c_uint32)]
+        L.oracle_clamp_snp.restype = C.c_float
         L.oracle_fp_canary.argtypes = [C.c_float, C.c_float, C.c_float]
         L.oracle_fp_canary.restype = C.c_float
         _LIB = L
@@ -204,6 +208,18 @@ def npads():
     buf = (C.c_int * NROW)()
     lib().oracle_npads(buf)
     return np.array(buf[:], np.int32)
+
+
+def sat(v):
+    """The decoder's float -> int32 conversion of an already rounded value."""
+    return int(lib().oracle_sat(C.c_float(v)))
+
+
+def clamp_snp(v):
+    """The decoder's sin(phi) limiter: (value, flag bits it raises)."""
+    fl = C.c_uint32(0)
+    r = lib().oracle_clamp_snp(C.c_float(v), C.byref(fl))
+    return np.float32(r), int(fl.value)
 
 
 def fp_canary(a, b, c):

@@ -583,6 +583,18 @@ int oracle_npads(int *dst)
     return O_NROW;
 }
 
+/* The two edge-case helpers, exposed so that tests can check them against
+ * their definitions directly (through a decode, the conversion's NaN and
+ * saturation branches need a runaway garbage track to be reached). */
+int32_t oracle_sat(float v) { return o_sat(v); }
+
+float oracle_clamp_snp(float v, uint32_t *flags)
+{
+    otab t;
+    o_tables(0.0f, &t);
+    return o_clamp_snp(&t, v, flags);
+}
+
 /* a*b+c evaluated as written (two roundings); the canary test checks that the
  * build did not fuse it. */
 float oracle_fp_canary(float a, float b, float c) { return a * b + c; }

@@ -299,3 +299,43 @@ def test_repeat_is_deterministic(tmd):
     a, b = tmd.to_numpy(outs[0]), tmd.to_numpy(outs[1])
     for k in a:
         assert np.array_equal(a[k], b[k])
+
+
+def clamp_pin_frames():
+    """The hand-built tracks of the oracle's clamp-and-flag pins (header
+    sin(phi) beyond the limit, NaN and infinite curvature, updates past the
+    limit, backward rotations, pad and time clamps, a runaway state that
+    saturates and turns NaN), several per frame, by field value."""
+    center = lambda r: int(synth.frames.ROW_NPADS[r] // 2 * 32)
+    def trk(sec0, row0, pad0, time0, qpt, snp, tgl, steps, res=None):
+        res = res or {}
+        cl = [(0, 0, 0, 0, 11, 12)] + [(rd, sd, *res.get(j, (0, 0)), 13 + j, 14)
+                                       for j, (rd, sd) in enumerate(steps, start=1)]
+        return dict(sec0=sec0, row0=row0, pad0=pad0, time0=time0, qpt=qpt, snp=snp, tgl=tgl, cl=cl)
+    line = [(1, 0)] * 79
+    t0 = [trk(4, 20, center(20), 40000, 0, 32767, 100, line), trk(4, 20, center(20), 40000, 0, -32768, 100, line),
+          trk(0, 10, center(10) - 640, 30000, 0, 31130, 0, [(1, 0)] * 6, {1: (100, 0)}),
+          trk(7, 40, 96, 70000, 0, 0, 0, [(1, 0)] * 3, {1: (-200, 0)}),
+          trk(7, 40, 65471, 70000, 0, 0, 0, [(1, 0)] * 3, {1: (200, 0)}),
+          trk(18, 0, center(0), 20, 0, 0, -4096, [(1, 0)] * 5),
+          trk(18, 0, center(0), (1 << 24) - 101, 0, 0, 0, [(1, 0)] * 3, {1: (0, 200)}),
+          trk(2, 30, center(30), 1000000, 0, 0, 400, [(0, 5)] * 119, {j: (908, 100) for j in range(1, 120)})]
+    for d, phi in ((17, 80.0), (9, 0.0), (1, -75.0)):
+        t0.append(trk(3, 50, center(50), 60000, 0, int(round(np.sin(np.radians(phi)) * 32768)), 0,
+                      [(1, d)] + [(1, 0)] * 5))
+    for time0 in ((1 << 24), (1 << 24) + 5, 0xFFFFFFFF):
+        for tgl in (-2000, 2000, 0):
+            t0.append(trk(11, 60, center(60), time0, 0, 0, tgl, [(1, 0)] * 4, {2: (0, 3)} if tgl == 0 else None))
+    t_inf = [trk(9, 30, center(30) + 333, 90000, 0, 0, -700, [(1, 0)] * 40),
+             trk(20, 70, center(70), 50000, 5000, 0, 0, [(1, 0)] * 6),
+             trk(20, 70, center(70), 50000, -5000, 0, 0, [(1, 0)] * 6)]
+    t_half = [trk(30, 100, center(100) - 640, 50000, 16384, 32440, 0, [(1, 0)] * 4)]
+    return [(0.0, build_frame(t0)), (float("inf"), build_frame(t_inf)), (0.5, build_frame(t_half)),
+            (0.5, build_frame(t0 + t_half))]
+
+
+def test_clamp_pin_tracks(tmd):
+    """The clamp-and-flag pin tracks: GPU == oracle, every byte and flag."""
+    for i, (bz, fr) in enumerate(clamp_pin_frames()):
+        exp, st = assert_same(tmd, fr, bz=bz, label=f"clamp pins {i} (bz {bz})")
+        assert st != 0

@@ -147,6 +147,7 @@ def test_garbage_is_deterministic_and_flagged():
     assert sa == sb
     for k in a:
         assert np.array_equal(a[k], b[k])
-    for f in (oracle.F_HDR, oracle.F_SEC, oracle.F_ROW, oracle.F_PAD, oracle.F_TIME, oracle.F_COUNT):
+    for f in (oracle.F_HDR, oracle.F_SEC, oracle.F_ROW, oracle.F_ROT, oracle.F_SNP, oracle.F_PAD,
+              oracle.F_TIME, oracle.F_COUNT):
         assert sa & f, f
     assert a["row_offset"][-1] <= na + nu
