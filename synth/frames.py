@@ -1,19 +1,26 @@
 """Synthetic compressed time frames shaped like Pb-Pb running.
 
 The generator writes the compressed streams directly: track headers, per-cluster
-row/sector steps, Gaussian residuals, charges, and per-(sector,row) delta
-streams of unattached clusters.  It does not run the decoder's track model.
-To make the streams look physical it uses its own, double-precision picture of
-the detector: charged tracks are circles through the origin in a uniform
-field, and each cluster sits where a circle crosses a pad row.  This geometry
-decides
+row/sector steps, residuals, charges, and per-(sector,row) delta streams of
+unattached clusters.  It uses its own double-precision picture of the detector:
+charged tracks are circles through the origin in a uniform field, and each
+cluster sits where a circle crosses a pad row.  This geometry decides
   - which rows and sectors each track visits, including sector crossings and
-    the legs of low-pT loopers, and
-  - the header values (pad, sin(phi)) at a track's first cluster.
-The residuals are then drawn at random (sigma 0.05 cm in pad and time).  The
-decoded track therefore follows the drawn track up to a random walk.  Any
-stream the generator writes is a valid decoder input whatever the geometry:
-out-of-range values are clamped and flagged, identically on every decoder.
+    the legs of low-pT loopers,
+  - the header values (pad, sin(phi), q/pT, tan(lambda)) at a track's first
+    cluster, and
+  - the true position of every cluster (local y; z from the arc length times
+    tan(lambda)), which is then smeared by Gaussian noise (sigma 0.05 cm in y
+    and in z) and quantised to 1/32 pad and 1/32 time bin.
+Residuals are measured code minus predicted code.  The prediction comes from a
+float64 geometric shadow of the documented track model (helix step, rotation
+at sector edges, fixed-gain update), started from the quantised header, so the
+shadow follows the measured clusters and the float32 decoder reproduces them
+(up to one code where the two roundings fall on either side of a tie).  Tracks
+whose shadow comes near a limit of the model (|sin phi| > 0.98, a rotation
+leaving cos phi < 0.05) are redrawn, pads are kept one code inside the pad
+plane and header times are raised so that no time code falls below 32: the
+streams of every workload decode with no status flag.
 
 Frame layout: see the key list in FIELDS below.  Stream order: tracks in
 collision order; each track's clusters are contiguous; unattached clusters are
@@ -38,6 +45,10 @@ _REG = np.repeat(np.arange(4), np.diff(_RSTART))
 ROW_X = np.array([_RX0[g] + (r - _RSTART[g] + 0.5) * _PITCH[g] for r, g in enumerate(_REG)])
 ROW_PW = np.array([_PADW[g] for g in _REG])
 ROW_NPADS = (2 * np.floor(ROW_X * _TAN10 / ROW_PW)).astype(np.int64)
+ROW_GAIN = np.array([0.0625 / _PITCH[g] for g in _REG])   # update gain per cm of innovation
+SIGMA_CM = 0.05          # cluster position noise in y and in z
+S_LIMIT = 0.98           # the shadow's |sin phi| must stay below this
+ROT_COS_MIN = 0.05       # ... and cos phi above this after a rotation
 
 FIELDS = {
     "trk_ncls": np.uint8, "trk_sec0": np.uint8, "trk_row0": np.uint8, "trk_pad0": np.uint16,
@@ -120,6 +131,116 @@ def _local_track(u, k, X):
     return s, y
 
 
+def _arc_from_origin(r, k, inward=False):
+    """Arc length from the origin along a circle through it (curvature k) to a
+    point at distance r from the origin; inward: on the returning half."""
+    ak = np.abs(k)
+    safe = np.where(ak > 1e-12, ak, 1.0)
+    half = np.arcsin(np.clip(ak * r / 2.0, 0.0, 1.0))
+    if inward:
+        return np.where(ak > 1e-12, (2.0 * math.pi - 2.0 * half) / safe, r)
+    return np.where(ak > 1e-12, 2.0 * half / safe, r)
+
+
+def _pad_code(y, rows):
+    """Measured pad code (1/32 pad) of local y on each row, kept one code
+    inside the pad plane."""
+    q = np.rint((y / ROW_PW[rows] + ROW_NPADS[rows] / 2) * 32.0)
+    return np.clip(q, 1, ROW_NPADS[rows] * 32 - 2).astype(np.int64)
+
+
+def _shadow_residuals(rows, secst, pad_meas, tq_meas, ncls, pad0, snpq, tglq, qptq, bz):
+    """Residuals of measured codes against a float64 geometric shadow of the
+    track model, for m tracks at once.
+
+    rows, secst: (m, L) row and sector step (0 or d in 1..17) of cluster j;
+    pad_meas: (m, L) measured pad codes; tq_meas: (m, L) measured time codes
+    relative to cluster 0; ncls: (m,) cluster counts; header: pad0 (code),
+    quantised sin(phi), tan(lambda), q/pT.  Returns (pad residuals, time
+    residuals, ok): ok is False for tracks whose shadow came near a limit of
+    the model or needed a residual beyond int16."""
+    m, L = rows.shape
+    # longest tracks first: the tracks still running at step j are a prefix
+    perm = np.argsort(-ncls, kind="stable")
+    nc = ncls[perm]
+    rows_p, sst_p = rows[perm], secst[perm]
+    pad_p, tq_p = pad_meas[perm], tq_meas[perm]
+    r0 = rows_p[:, 0]
+    x = ROW_X[r0].copy()
+    y = (pad0[perm] / 32.0 - ROW_NPADS[r0] / 2) * ROW_PW[r0]
+    z = np.zeros(m)
+    s = snpq[perm] / 32768.0
+    tgl = tglq[perm] / 4096.0
+    k = qptq[perm] / 1024.0 * (bz * 0.00299792458)
+    ok = np.abs(s) < S_LIMIT
+    pres = np.zeros((m, L), np.int64)
+    tres = np.zeros((m, L), np.int64)
+    # number of tracks with more than j clusters, for every j
+    alive = np.searchsorted(-nc, -np.arange(L), side="left")
+    for j in range(1, L):
+        n = int(alive[j])
+        if n == 0:
+            break
+        xs, ys, ss, ks = x[:n], y[:n], s[:n], k[:n]
+        d = sst_p[:n, j]
+        if d.any():
+            rot = d != 0
+            ang = np.radians(20.0 * d[rot])
+            ca, sa = np.cos(ang), np.sin(ang)
+            xr, yr, sr = xs[rot], ys[rot], ss[rot]
+            cs = np.sqrt(np.maximum(1.0 - sr * sr, 0.0))
+            sn = sr * ca - cs * sa
+            cn = cs * ca + sr * sa
+            okr = ok[:n]
+            okr[rot] &= (cn > ROT_COS_MIN) & (np.abs(sn) < S_LIMIT)
+            xs[rot] = xr * ca + yr * sa
+            ys[rot] = yr * ca - xr * sa
+            ss[rot] = sn
+        rj = rows_p[:n, j]
+        X = ROW_X[rj]
+        dx = X - xs
+        s1 = ss + ks * dx
+        ok[:n] &= np.abs(s1) < S_LIMIT
+        s1 = np.clip(s1, -S_LIMIT, S_LIMIT)
+        sc = np.clip(ss, -S_LIMIT, S_LIMIT)
+        dydx = (sc + s1) / (np.sqrt(1.0 - sc * sc) + np.sqrt(1.0 - s1 * s1))
+        yp = ys + dx * dydx
+        zp = z[:n] + tgl[:n] * (dx * np.sqrt(1.0 + dydx * dydx))
+        pw = ROW_PW[rj]
+        pr = pad_p[:n, j] - np.rint((yp / pw + ROW_NPADS[rj] / 2) * 32.0)
+        tr = tq_p[:n, j] - np.rint(zp * (32.0 / _VDRIFT))
+        pres[:n, j] = pr
+        tres[:n, j] = tr
+        nuy = pr * pw / 32.0
+        nuz = tr * (_VDRIFT / 32.0)
+        s2 = s1 + nuy * ROW_GAIN[rj]
+        ok[:n] &= np.abs(s2) < S_LIMIT
+        x[:n] = X
+        y[:n] = yp + nuy
+        z[:n] = zp + nuz
+        s[:n] = s2
+        tgl[:n] += nuz * ROW_GAIN[rj]
+    ok &= (np.abs(pres) < 30000).all(axis=1) & (np.abs(tres) < 30000).all(axis=1)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(m)
+    return pres[inv], tres[inv], ok[inv]
+
+
+def _measure(rng, rows, y_true, z_true, ncls):
+    """Measured pad codes and time codes (relative to cluster 0) of clusters
+    at true local y and z (cm, z relative to cluster 0's true z), each smeared
+    by Gaussian noise."""
+    m, L = rows.shape
+    y = y_true + rng.normal(0.0, SIGMA_CM, (m, L))
+    z = z_true + rng.normal(0.0, SIGMA_CM, (m, L))
+    pad = _pad_code(y, rows)
+    tq = np.rint(z * (32.0 / _VDRIFT)).astype(np.int64)
+    tq = tq - tq[:, :1]           # cluster 0 defines the header time
+    live = np.arange(L)[None, :] < ncls[:, None]
+    tq[~live] = 0
+    return pad, tq
+
+
 def _draw_rows(rng, n, p_gap=0.05):
     """Row steps: +1, or +2 with probability p_gap."""
     return 1 + (rng.random(n) < p_gap).astype(np.int64)
@@ -138,33 +259,40 @@ def _sample_start_rows(rng, span, skew):
 
 
 def _normal_tracks(rng, spec, n):
-    """Outward tracks: per-track dict of header values and per-step arrays."""
+    """Outward tracks: cluster counts, header values (quantised), row and
+    sector steps, and the residuals of each cluster against the shadow model
+    (pres/tres, (n, NROW)); tq_lo/tq_hi: range of the time codes relative to
+    cluster 0."""
     ncls = rng.integers(spec.ncls_min, spec.ncls_max + 1, n)
-    out = {k: np.zeros(n, np.int64) for k in ("sec0", "row0")}
-    fl = {k: np.zeros(n) for k in ("y0", "s0", "qpt", "tgl")}
+    out = {k: np.zeros(n, np.int64) for k in ("sec0", "row0", "pad0", "snp", "qpt", "tgl", "tq_lo", "tq_hi")}
     crosser = rng.random(n) < spec.crosser_frac
     steps = np.zeros((n, NROW), np.int64)      # row step before cluster j (j >= 1)
     secstep = np.zeros((n, NROW), np.int64)    # sector step before cluster j
+    pres = np.zeros((n, NROW), np.int16)
+    tres = np.zeros((n, NROW), np.int16)
     todo = np.arange(n)
     sectors = np.asarray(spec.sectors)
+    jj = np.arange(NROW)[None, :]
     for attempt in range(60):
         if todo.size == 0:
             break
         if attempt in (20, 40):
             # persistent rejects: redraw their lengths as well
             ncls[todo] = rng.integers(spec.ncls_min, spec.ncls_max + 1, todo.size)
+        # longest first: the tracks still running at row step j are a prefix
+        todo = todo[np.argsort(-ncls[todo], kind="stable")]
         m = todo.size
         nc = ncls[todo]
+        alive = np.searchsorted(-nc, -np.arange(NROW), side="left")
         st = np.zeros((m, NROW), np.int64)
         st[:, 1:] = _draw_rows(rng, m * (NROW - 1)).reshape(m, NROW - 1)
-        jj = np.arange(NROW)[None, :]
         st[jj >= nc[:, None]] = 0
         span = st.sum(axis=1)
         bad_span = span > NROW - 1
         span = np.minimum(span, NROW - 1)
         row0 = _sample_start_rows(rng, span, spec.row_skew)
-        rows = row0[:, None] + np.cumsum(st, axis=1)
-        X = ROW_X[np.minimum(rows, NROW - 1)]
+        rows = np.minimum(row0[:, None] + np.cumsum(st, axis=1), NROW - 1)
+        X = ROW_X[rows]
         pt = np.exp(rng.uniform(math.log(spec.pt_min), math.log(spec.pt_max), m))
         q = np.where(rng.random(m) < 0.5, 1.0, -1.0)
         k = q / pt * spec.bz * 0.00299792458
@@ -181,65 +309,87 @@ def _normal_tracks(rng, spec, n):
         # follow the track through the rows; switch frames at sector edges
         du = np.zeros(m)                    # accumulated frame rotation
         sst = np.zeros((m, NROW), np.int64)
-        ys = np.zeros(m)
-        ss = np.zeros(m)
+        ym = np.zeros((m, NROW))            # true local y of cluster j
         ncross = np.zeros(m, np.int64)
-        y0 = np.zeros(m)
         s0 = np.zeros(m)
         for j in range(NROW):
-            act = j < nc
-            if not act.any():
+            n = int(alive[j])
+            if n == 0:
                 break
-            s, y = _local_track(u - du, k, X[:, j])
-            edge = X[:, j] * _TAN10
-            out_pos = act & (y > edge)
-            out_neg = act & (y < -edge)
-            # crossing into the neighbouring sector (+20 deg or -20 deg)
-            du = du + np.radians(20.0) * out_pos - np.radians(20.0) * out_neg
-            sst[:, j] = np.where(out_pos, 1, np.where(out_neg, 17, 0))
-            ncross += (out_pos | out_neg)
-            s2, y2 = _local_track(u - du, k, X[:, j])
-            s = np.where(out_pos | out_neg, s2, s)
-            y = np.where(out_pos | out_neg, y2, y)
-            ok &= ~act | ((np.abs(s) < 0.95) & (np.abs(y) <= X[:, j] * _TAN10 * 1.0001))
+            Xj = X[:n, j]
+            s, y = _local_track(u[:n] - du[:n], k[:n], Xj)
+            edge = Xj * _TAN10
+            out_pos = y > edge
+            out_neg = y < -edge
+            cross = out_pos | out_neg
+            if cross.any():
+                # crossing into the neighbouring sector (+20 deg or -20 deg)
+                du[:n] += np.radians(20.0) * out_pos - np.radians(20.0) * out_neg
+                sst[:n, j] = np.where(out_pos, 1, np.where(out_neg, 17, 0))
+                ncross[:n] += cross
+                s2, y2 = _local_track(u[:n][cross] - du[:n][cross], k[:n][cross], Xj[cross])
+                s[cross] = s2
+                y[cross] = y2
+            ok[:n] &= (np.abs(s) < 0.95) & (np.abs(y) <= edge * 1.0001)
+            ym[:n, j] = y
             if j == 0:
-                y0, s0 = y.copy(), s.copy()
+                s0 = s.copy()
                 ok &= (sst[:, 0] == 0)
-            ys, ss = y, s
-        del ys, ss
         ok &= np.where(crosser[todo], ncross >= 1, ncross == 0)
+        # measured clusters and their residuals against the shadow model
+        tgl = rng.uniform(-1.0, 1.0, m)
+        arc = _arc_from_origin(np.hypot(X, ym), k[:, None])
+        z_true = tgl[:, None] * (arc - arc[:, :1])
+        del arc
+        pad_m, tq_m = _measure(rng, rows, ym, z_true, nc)
+        del z_true, ym
+        hpad = pad_m[:, 0]
+        hsnp = np.clip(np.rint(s0 * 32768.0), -32767, 32767)
+        hqpt = np.clip(np.rint(q / pt * 1024.0), -32768, 32767)
+        htgl = np.clip(np.rint(tgl * 4096.0), -32768, 32767)
+        pr, tr, sh_ok = _shadow_residuals(rows, sst, pad_m, tq_m, nc, hpad, hsnp, htgl, hqpt, spec.bz)
+        ok &= sh_ok
+        live = jj < nc[:, None]
         good = todo[ok]
         sec = rng.choice(sectors, m)
         out["sec0"][good] = sec[ok]
         out["row0"][good] = row0[ok]
-        fl["y0"][good] = y0[ok]
-        fl["s0"][good] = s0[ok]
-        fl["qpt"][good] = (q / pt)[ok]
-        fl["tgl"][good] = rng.uniform(-1.0, 1.0, m)[ok]
+        out["pad0"][good] = hpad[ok]
+        out["snp"][good] = hsnp[ok]
+        out["qpt"][good] = hqpt[ok]
+        out["tgl"][good] = htgl[ok]
+        out["tq_lo"][good] = np.where(live, tq_m, 0).min(axis=1)[ok]
+        out["tq_hi"][good] = np.where(live, tq_m, 0).max(axis=1)[ok]
         steps[good] = st[ok]
         secstep[good] = sst[ok]
+        pres[good] = pr[ok]
+        tres[good] = tr[ok]
+        del pad_m, tq_m, pr, tr, live
         todo = todo[~ok]
     if todo.size:
-        # rare leftovers: short straight tracks in the middle of a sector
+        # rare leftovers: short straight tracks through the middle of a sector
+        # at constant z, measured without noise (zero residuals)
         ncls[todo] = spec.ncls_min
         out["sec0"][todo] = rng.choice(sectors, todo.size)
         out["row0"][todo] = 60
+        out["pad0"][todo] = _pad_code(np.zeros(1), np.array([60]))[0]
+        for key in ("snp", "qpt", "tgl", "tq_lo", "tq_hi"):
+            out[key][todo] = 0
+        steps[todo] = 0
         steps[todo, 1:spec.ncls_min] = 1
         secstep[todo] = 0
-        fl["y0"][todo] = 0.0
-        fl["s0"][todo] = 0.0
-        fl["qpt"][todo] = 0.1
-        fl["tgl"][todo] = 0.0
-    return ncls, out, fl, steps, secstep
+        pres[todo] = 0
+        tres[todo] = 0
+    return ncls, out, steps, secstep, pres, tres
 
 
-def _looper_legs(rng, spec, n):
-    """Legs of low-pT loopers: each turn is an outward and an inward leg over
-    the same circle; each leg is written as its own track."""
+def _looper_geometry(rng, spec, n, looper_id):
+    """Geometry of low-pT looper legs (at least n, unless the draws keep
+    failing): each turn is an outward and an inward leg over the same circle;
+    each leg is written as its own track."""
     legs = []
     made = 0
     tries = 0
-    looper_id = 0
     while made < n and tries < 50 * n + 100:
         tries += 1
         pt = math.exp(rng.uniform(math.log(spec.looper_pt[0]), math.log(spec.looper_pt[1])))
@@ -309,17 +459,61 @@ def _looper_legs(rng, spec, n):
                                                    (in_rows, in_secs, in_s, in_y, -1.0)):
                 if len(rows) < 5:
                     continue
-                rows = rows[:255]
-                legs.append({"rows": np.array(rows), "secs": side * 18 + np.array(secs[:len(rows)]),
-                             "s0": svals[0], "y0": yvals[0], "qpt": sign * q / pt,
-                             "tgl": sign * tgl, "turn": t, "looper": looper_id})
+                legs.append({"rows": np.array(rows), "secs": side * 18 + np.array(secs),
+                             "y": np.array(yvals), "s0": svals[0], "qpt": sign * q / pt,
+                             "tgl": sign * tgl, "tgl_phys": tgl, "k": k, "inward": sign < 0,
+                             "turn": t, "looper": looper_id})
                 made += 1
         looper_id += 1
+    return legs, looper_id
+
+
+def _looper_legs(rng, spec, n):
+    """Looper legs with quantised headers and residuals against the shadow
+    model; legs whose shadow comes near a limit of the model are dropped and
+    more loopers are drawn."""
+    legs = []
+    looper_id = 0
+    for _ in range(20):
+        if len(legs) >= n:
+            break
+        cand, looper_id = _looper_geometry(rng, spec, n - len(legs), looper_id)
+        if not cand:
+            break
+        m = len(cand)
+        nc = np.array([len(lg["rows"]) for lg in cand])
+        L = int(nc.max())
+        rows = np.zeros((m, L), np.int64)
+        sst = np.zeros((m, L), np.int64)
+        ym = np.zeros((m, L))
+        zt = np.zeros((m, L))
+        for i, lg in enumerate(cand):
+            c = nc[i]
+            rows[i, :c] = lg["rows"]
+            rows[i, c:] = lg["rows"][-1]
+            sc = lg["secs"] % 18
+            sst[i, 1:c] = (np.diff(sc) + 18) % 18
+            ym[i, :c] = lg["y"]
+            arc = _arc_from_origin(np.hypot(ROW_X[lg["rows"]], lg["y"]), lg["k"], inward=lg["inward"])
+            zt[i, :c] = lg["tgl_phys"] * (arc - arc[0])
+        pad_m, tq_m = _measure(rng, rows, ym, zt, nc)
+        hpad = pad_m[:, 0]
+        hsnp = np.clip(np.rint(np.array([lg["s0"] for lg in cand]) * 32768.0), -32767, 32767)
+        hqpt = np.clip(np.rint(np.array([lg["qpt"] for lg in cand]) * 1024.0), -32768, 32767)
+        htgl = np.clip(np.rint(np.array([lg["tgl"] for lg in cand]) * 4096.0), -32768, 32767)
+        pr, tr, ok = _shadow_residuals(rows, sst, pad_m, tq_m, nc, hpad, hsnp, htgl, hqpt, spec.bz)
+        live = np.arange(L)[None, :] < nc[:, None]
+        lo = np.where(live, tq_m, 0).min(axis=1)
+        hi = np.where(live, tq_m, 0).max(axis=1)
+        for i, lg in enumerate(cand):
+            if not ok[i]:
+                continue
+            c = nc[i]
+            lg.update(pad0=int(hpad[i]), snp=int(hsnp[i]), qptq=int(hqpt[i]), tglq=int(htgl[i]),
+                      pres=pr[i, :c].astype(np.int16), tres=tr[i, :c].astype(np.int16),
+                      tq_lo=int(lo[i]), tq_hi=int(hi[i]))
+            legs.append(lg)
     return legs
-
-
-def _quant_header_s(s):
-    return np.clip(np.rint(np.asarray(s) * 32768.0), -32767, 32767).astype(np.int16)
 
 
 CHUNK_COLLISIONS = 25  # collisions per generation chunk (each chunk has its own random stream)
@@ -343,8 +537,7 @@ def _attached_chunk(args):
     rng = np.random.default_rng([spec.seed, spec.frame_index, chunk_id, 104729])
     n_loop = int(round(nt_total * spec.looper_frac))
     n_norm = nt_total - n_loop
-    ncls, hdr, fl, steps, secstep = _normal_tracks(rng, spec, n_norm)
-    rows_rel = np.cumsum(steps, axis=1)
+    ncls, hdr, steps, secstep, pres, tres = _normal_tracks(rng, spec, n_norm)
     jj = np.arange(NROW)[None, :]
     mask = jj < ncls[:, None]
 
@@ -356,7 +549,7 @@ def _attached_chunk(args):
 
     # --- assemble tracks in collision order; a looper's legs stay together ---
     n_legs = len(legs)
-    n_loopers = (legs[-1]["looper"] + 1) if legs else 0
+    n_loopers = (max(lg["looper"] for lg in legs) + 1) if legs else 0
     loop_coll = rng.integers(0, ncoll, n_loopers)
     loop_key = rng.random(n_loopers)
     leg_owner = np.array([lg["looper"] for lg in legs], np.int64)
@@ -371,6 +564,8 @@ def _attached_chunk(args):
     hd = {k: np.zeros(nt, FIELDS[k]) for k in ("trk_ncls", "trk_sec0", "trk_row0", "trk_pad0",
                                                 "trk_time0", "trk_qpt", "trk_snp", "trk_tgl")}
     t_first = coll_t[tr_coll[order]] + 300.0 + rng.uniform(0.0, 485.0, nt)
+    tq_lo = np.zeros(nt, np.int64)   # time codes of a track relative to its cluster 0
+    tq_hi = np.zeros(nt, np.int64)
     # vectorised part for normal tracks
     ord_kind = kind[order]
     ord_idx = idx[order]
@@ -379,29 +574,32 @@ def _attached_chunk(args):
     hd["trk_ncls"][is_norm] = ncls[ni]
     hd["trk_sec0"][is_norm] = hdr["sec0"][ni]
     hd["trk_row0"][is_norm] = hdr["row0"][ni]
-    pw0 = ROW_PW[hdr["row0"][ni]]
-    pad0 = fl["y0"][ni] / pw0 + ROW_NPADS[hdr["row0"][ni]] / 2
-    hd["trk_pad0"][is_norm] = np.clip(np.rint(pad0 * 32), 0, 65535).astype(np.uint16)
-    hd["trk_snp"][is_norm] = _quant_header_s(fl["s0"][ni])
-    hd["trk_qpt"][is_norm] = np.clip(np.rint(fl["qpt"][ni] * 1024), -32768, 32767).astype(np.int16)
-    hd["trk_tgl"][is_norm] = np.clip(np.rint(fl["tgl"][ni] * 4096), -32768, 32767).astype(np.int16)
+    hd["trk_pad0"][is_norm] = hdr["pad0"][ni]
+    hd["trk_snp"][is_norm] = hdr["snp"][ni]
+    hd["trk_qpt"][is_norm] = hdr["qpt"][ni]
+    hd["trk_tgl"][is_norm] = hdr["tgl"][ni]
+    tq_lo[is_norm] = hdr["tq_lo"][ni]
+    tq_hi[is_norm] = hdr["tq_hi"][ni]
     # loopers
     li = np.nonzero(~is_norm)[0]
     for p in li:
         leg = legs[ord_idx[p]]
-        r0 = int(leg["rows"][0])
         hd["trk_ncls"][p] = len(leg["rows"])
         hd["trk_sec0"][p] = int(leg["secs"][0])
-        hd["trk_row0"][p] = r0
-        pad = leg["y0"] / ROW_PW[r0] + ROW_NPADS[r0] / 2
-        hd["trk_pad0"][p] = int(np.clip(np.rint(pad * 32), 0, 65535))
-        hd["trk_snp"][p] = _quant_header_s(leg["s0"])
-        hd["trk_qpt"][p] = int(np.clip(np.rint(leg["qpt"] * 1024), -32768, 32767))
-        hd["trk_tgl"][p] = int(np.clip(np.rint(leg["tgl"] * 4096), -32768, 32767))
+        hd["trk_row0"][p] = int(leg["rows"][0])
+        hd["trk_pad0"][p] = leg["pad0"]
+        hd["trk_snp"][p] = leg["snp"]
+        hd["trk_qpt"][p] = leg["qptq"]
+        hd["trk_tgl"][p] = leg["tglq"]
+        tq_lo[p] = leg["tq_lo"]
+        tq_hi[p] = leg["tq_hi"]
         # later turns drift further: shift their time by the turn's z advance
-        t_first[p] += leg["turn"] * 2.0 * math.pi / abs(leg["qpt"] * spec.bz * 0.00299792458) \
-            * abs(leg["tgl"]) / _VDRIFT
-    hd["trk_time0"][:] = np.clip(np.rint(t_first * 32), 0, 2**24 - 1).astype(np.uint32)
+        t_first[p] += leg["turn"] * 2.0 * math.pi / abs(leg["k"]) * abs(leg["tgl"]) / _VDRIFT
+    # header times: every time code of the track at least 32 and below 2^24 - 32
+    t0q = np.rint(t_first * 32).astype(np.int64)
+    t0q = np.maximum(t0q, 32 - tq_lo)
+    t0q = np.minimum(t0q, 2**24 - 32 - tq_hi)
+    hd["trk_time0"][:] = np.clip(t0q, 0, 2**24 - 1).astype(np.uint32)
 
     # --- per-cluster streams ---
     ncl_t = hd["trk_ncls"].astype(np.int64)
@@ -409,24 +607,22 @@ def _attached_chunk(args):
     starts = np.concatenate([[0], np.cumsum(ncl_t)])
     row_diff = np.zeros(nA, np.int8)
     sec_diff = np.zeros(nA, np.uint8)
-    cl_row = np.zeros(nA, np.int64)
+    pad_res = np.zeros(nA, np.int16)
+    time_res = np.zeros(nA, np.int16)
     # normal tracks: scatter the per-step matrices
-    ncl_n = ncls[ni]
-    st_n = steps[ni]
-    ss_n = secstep[ni]
     m_n = mask[ni]
     dst = starts[:-1][is_norm]
     flat = (dst[:, None] + jj)[m_n]
-    row_diff[flat] = st_n[m_n].astype(np.int8)
-    sec_diff[flat] = ss_n[m_n].astype(np.uint8)
-    cl_row[flat] = (hdr["row0"][ni][:, None] + rows_rel[ni])[m_n]
-    del st_n, ss_n, m_n, flat
+    row_diff[flat] = steps[ni][m_n].astype(np.int8)
+    sec_diff[flat] = secstep[ni][m_n].astype(np.uint8)
+    pad_res[flat] = pres[ni][m_n]
+    time_res[flat] = tres[ni][m_n]
+    del m_n, flat
     for p in li:
         leg = legs[ord_idx[p]]
         a = starts[p]
         rws = leg["rows"].astype(np.int64)
         n = len(rws)
-        cl_row[a:a + n] = rws
         rd = np.zeros(n, np.int64)
         rd[1:] = np.diff(rws)
         row_diff[a:a + n] = rd.astype(np.int8)
@@ -434,22 +630,19 @@ def _attached_chunk(args):
         sd = np.zeros(n, np.int64)
         sd[1:] = (np.diff(sc) + 18) % 18
         sec_diff[a:a + n] = sd.astype(np.uint8)
+        pad_res[a:a + n] = leg["pres"]
+        time_res[a:a + n] = leg["tres"]
     is_first = np.zeros(nA, bool)
     is_first[starts[:-1][ncl_t > 0]] = True
     row_diff[is_first] = 0
     sec_diff[is_first] = 0
-    pwq = ROW_PW[cl_row] / 32.0
-    pad_res = np.rint(rng.normal(0.0, 0.05, nA) / pwq)
-    time_res = np.rint(rng.normal(0.0, 0.05, nA) / (_VDRIFT / 32.0))
     pad_res[is_first] = 0
     time_res[is_first] = 0
-    del pwq, cl_row
     fr = {k: v for k, v in hd.items()}
     fr["cls_row_diff"] = row_diff
     fr["cls_sec_diff"] = sec_diff
-    fr["cls_pad_res"] = np.clip(pad_res, -32768, 32767).astype(np.int16)
-    fr["cls_time_res"] = np.clip(time_res, -32768, 32767).astype(np.int16)
-    del pad_res, time_res
+    fr["cls_pad_res"] = pad_res
+    fr["cls_time_res"] = time_res
     fr["cls_qmax"], fr["cls_qtot"] = _charges(rng, nA)
     return fr
 

@@ -44,3 +44,18 @@ def test_config4_loopers_and_skew():
     rows = np.arange(NBIN) % 152
     cnt = np.bincount(rows, weights=fr["un_count"], minlength=152)
     assert cnt[:20].sum() > 5 * cnt[-20:].sum()          # exponential in row
+
+
+def test_streams_decode_without_flags():
+    """Every workload's streams are valid decoder input: the oracle decodes
+    them with no status flag (no clamp, no count mismatch), and the residuals
+    have the spread of the cluster noise (sigma 0.05 cm, measured minus
+    predicted: about sqrt(2) sigma over the quantum)."""
+    import oracle
+    for name, over in (("tiny", {}), ("frame", {"collisions": 3}), ("stress", {"collisions": 2})):
+        fr = synth.make_frame(synth.spec_for(name, **over))
+        _, status = oracle.decode(fr, bz=0.5)
+        assert status == 0, (name, status)
+        tq = 0.516 / 32
+        sd = fr["cls_time_res"].astype(np.float64).std()
+        assert 0.8 * 2 ** 0.5 * 0.05 / tq < sd < 1.3 * 2 ** 0.5 * 0.05 / tq, (name, sd)
