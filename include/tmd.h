@@ -46,6 +46,7 @@ extern "C" {
 #define TMD_E_INPUT (-3)    /* (tmd_status) counts in the stream disagree with the shape */
 #define TMD_E_STREAM (-4)   /* (tmd_status) the track model had to clamp values */
 #define TMD_E_HIP (-5)      /* HIP runtime error (no device, out of memory, launch failure) */
+#define TMD_E_SCRATCH (-6)  /* (tmd_decode_static) the plan's workspace exceeds TMD_STATIC_SCRATCH_BYTES */
 
 /* status flag bits reported by tmd_status */
 #define TMD_F_HDR 1u    /* track header out of range: n_clusters 0, sector >= 36 (wrapped), row >= 152 (clamped) */
@@ -183,6 +184,25 @@ int tmd_status(tmd_plan_t *plan, uint32_t frame, uint32_t *flags);
 
 /* Release the plan and its device memory (waits for its work). NULL is a no-op. */
 void tmd_free(tmd_plan_t *plan);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * tmd_decode_shapes, with the workspace taken from a scratch array of
+ * TMD_STATIC_SCRATCH_BYTES that the library holds in device memory (one per
+ * GPU, from the library's load until the process ends) instead of a caller
+ * buffer.  shapes may be NULL (the planned shapes).  The call allocates no
+ * device memory; the plan (made once by tmd_plan) and the caller's input and
+ * output buffers are as for tmd_decode.  Every call on one GPU uses that GPU's
+ * scratch array, and the decode needs nothing in it to be initialised; calls
+ * that overlap on one GPU (other streams, other plans, or tmd_decode_static
+ * beside itself) race on it and must be ordered by the caller.
+ * Errors: those of tmd_decode_shapes, and TMD_E_SCRATCH if the plan's
+ * workspace (the *workspace_bytes of tmd_plan) exceeds TMD_STATIC_SCRATCH_BYTES.
+ */
+#define TMD_STATIC_SCRATCH_BYTES (512ull << 20)
+int tmd_decode_static(tmd_plan_t *plan, const tmd_frame_shape *shapes, const tmd_frame_in *in,
+                      tmd_frame_out *out, void *stream);
 
 /*
  * Host-resident frames (paper section 4, Fig. 2: per-stream transfers to the

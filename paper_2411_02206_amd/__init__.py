@@ -14,9 +14,9 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (E_ARG, E_CAPACITY, E_HIP, E_INPUT, E_STREAM, F_COUNT, F_HDR, F_PAD, F_ROT,  # noqa: F401
-                   F_ROW, F_SEC, F_SNP, F_TIME, IN_FIELDS, NBIN, NROW, NSEC, OK, OUT_FIELDS, PLAN_GRAPH,
-                   TmdError)
+from ._lib import (E_ARG, E_CAPACITY, E_HIP, E_INPUT, E_SCRATCH, E_STREAM, F_COUNT, F_HDR, F_PAD,  # noqa: F401
+                   F_ROT, F_ROW, F_SEC, F_SNP, F_TIME, IN_FIELDS, NBIN, NROW, NSEC, OK, OUT_FIELDS, PLAN_GRAPH,
+                   STATIC_SCRATCH_BYTES, TmdError)
 
 __all__ = ["Plan", "Pipeline", "decode", "to_device", "to_host", "alloc_out", "alloc_host_out", "to_numpy",
            "version", "tables"]
@@ -164,6 +164,29 @@ class Plan:
             arr = (_lib.FrameShape * n)(*[_lib.FrameShape(*(int(v) for v in sh)) for sh in shapes])
             _lib.check(_lib.lib().tmd_decode_shapes(self._h, arr, fin, fout, _ptr(workspace), sp),
                        "tmd_decode_shapes")
+
+    def decode_static(self, ins, outs, stream=None, shapes=None):
+        """As decode, with the library's static scratch as the workspace
+        (tmd_decode_static: no device memory is allocated by the call)."""
+        torch = _torch()
+        n = len(self.shapes)
+        if len(ins) != n or len(outs) != n or (shapes is not None and len(shapes) != n):
+            raise ValueError(f"plan has {n} frames")
+        fin = (_lib.FrameIn * n)()
+        fout = (_lib.FrameOut * n)()
+        for i in range(n):
+            for k in IN_FIELDS:
+                setattr(fin[i], k, _ptr(ins[i][k]))
+            for k in OUT_FIELDS:
+                setattr(fout[i], k, _ptr(outs[i][k]))
+            fout[i].capacity = int(outs[i]["capacity"])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        arr = None
+        if shapes is not None:
+            arr = (_lib.FrameShape * n)(*[_lib.FrameShape(*(int(v) for v in sh)) for sh in shapes])
+        _lib.check(_lib.lib().tmd_decode_static(self._h, arr, fin, fout, C.c_void_p(stream.cuda_stream)),
+                   "tmd_decode_static")
 
     def status(self, frame=0):
         """Flag bits of `frame` from the last decode (waits for it)."""

@@ -13,7 +13,8 @@ NSEC, NROW = 36, 152
 NBIN = NSEC * NROW
 MAX_TRACKS = 1 << 24
 
-OK, E_ARG, E_CAPACITY, E_INPUT, E_STREAM, E_HIP = 0, -1, -2, -3, -4, -5
+OK, E_ARG, E_CAPACITY, E_INPUT, E_STREAM, E_HIP, E_SCRATCH = 0, -1, -2, -3, -4, -5, -6
+STATIC_SCRATCH_BYTES = 512 << 20
 F_HDR, F_SEC, F_ROW, F_ROT, F_SNP, F_PAD, F_TIME, F_COUNT = 1, 2, 4, 8, 16, 32, 64, 128
 PLAN_GRAPH = 1
 PIPE_MAX_DEPTH = 8
@@ -60,6 +61,8 @@ def lib():
         L.tmd_decode.restype = C.c_int
         L.tmd_decode_shapes.argtypes = [P, C.POINTER(FrameShape), C.POINTER(FrameIn), C.POINTER(FrameOut), P, P]
         L.tmd_decode_shapes.restype = C.c_int
+        L.tmd_decode_static.argtypes = [P, C.POINTER(FrameShape), C.POINTER(FrameIn), C.POINTER(FrameOut), P]
+        L.tmd_decode_static.restype = C.c_int
         L.tmd_status.argtypes = [P, C.c_uint32, C.POINTER(C.c_uint32)]
         L.tmd_status.restype = C.c_int
         L.tmd_free.argtypes = [P]

@@ -1607,6 +1607,13 @@ __global__ void k_selftest_fp(const float *a, const float *b, float *out, uint32
 }
 
 // ---------------------------------------------------------------------------
+// workspace of tmd_decode_static: device memory of the library itself, one
+// array per GPU (the kernels never see its host-side name, only the address
+// hipGetSymbolAddress gives for the current device)
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[TMD_STATIC_SCRATCH_BYTES];
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 constexpr int kStages = 7;
@@ -1661,6 +1668,25 @@ int hip_fail(hipError_t e)
         hipError_t e_ = (x);                       \
         if (e_ != hipSuccess) return hip_fail(e_); \
     } while (0)
+
+// Device address of `scratch` on each device, looked up once per device
+// (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(int device, void **ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return TMD_E_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TMD_E_HIP;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return TMD_OK;
+}
 
 template <class T>
 bool aligned(const T *p)
@@ -1750,6 +1776,7 @@ const char *tmd_strerror(int code)
     case TMD_E_INPUT: return "stream counts disagree with the frame shape (streams were cut)";
     case TMD_E_STREAM: return "the track model clamped values of the stream";
     case TMD_E_HIP: return "HIP runtime error";
+    case TMD_E_SCRATCH: return "the plan's workspace exceeds the library's static scratch (TMD_STATIC_SCRATCH_BYTES)";
     default: return "unknown error";
     }
 }
@@ -1842,6 +1869,10 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
     int rc = TMD_OK;
     do {
         if (hipGetDevice(&P->device) != hipSuccess) { rc = TMD_E_HIP; break; }
+        {
+            void *sp = nullptr;  // set-up of tmd_decode_static's scratch on this device
+            if ((rc = static_scratch(P->device, &sp)) != TMD_OK) break;
+        }
         {
             int cus = 0;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess) {
@@ -2037,6 +2068,21 @@ int tmd_status(tmd_plan_t *P, uint32_t frame, uint32_t *flags)
     if (f & TMD_F_COUNT) return TMD_E_INPUT;
     if (f) return TMD_E_STREAM;
     return TMD_OK;
+}
+
+int tmd_decode_static(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
+                      void *stream)
+{
+    if (!P) return TMD_E_ARG;
+    if (P->ws_bytes > (size_t)TMD_STATIC_SCRATCH_BYTES) return TMD_E_SCRATCH;
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != P->device) HIP_TRY(hipSetDevice(P->device));
+    void *ws = nullptr;
+    int rc = static_scratch(P->device, &ws);
+    if (cur != P->device) (void)hipSetDevice(cur);
+    if (rc != TMD_OK) return rc;
+    return tmd_decode_shapes(P, shapes ? shapes : P->shapes.data(), in, out, ws, stream);
 }
 
 int tmd_set_profiling(tmd_plan_t *P, uint32_t stage_mask)
