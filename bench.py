@@ -1,17 +1,26 @@
 """Benchmark: decoded TPC clusters/s on one MI355X, bit-exact.
 
-Default workload: one full synthetic Pb-Pb-like time frame (100 collisions x
-2000 tracks, about 1.5e7 attached + 1.0e7 unattached clusters), decoded by the
-plain single-frame launch sequence with inputs resident in HBM.  A step is one
-complete tmd_decode (all kernels: track offsets, bin counts, offsets, ranks,
-attached decode, unattached decode, status).
+Default workload (`batched`): 64 synthetic time frames of log-uniform 10..200
+Pb-Pb-like collisions (about 8e6 tracks and 1.1e9 clusters in all), decoded by
+one plan over all 64 frames whose launch sequence is captured once as a HIP
+graph and replayed.  A step is one replay: the whole decode of the 64 frames
+(track offsets, bin counts, offsets, ranks, attached decode, unattached
+decode, status) with inputs resident in HBM.  The same frames decoded by 64
+plain single-frame plans are timed beside it.
+
+Other workloads: `frame` (one frame of 100 collisions, plain single launch),
+`stress` (500 collisions with loopers, plain launch), `stress-batched` (the
+stress frame through a graph plan), `tiny`, `served` (Poisson arrivals,
+continuous batching, p50/p99 at several offered loads) and `pipeline` (frames
+in host memory, PCIe-inclusive).
 
 Prints one JSON line.  `roofline` reports the dominant kernel's algorithmic
 HBM bytes per launch (attached kernel: 10 B in + 10 B out per attached
 cluster, 15 B per track header; unattached kernel: 10 B in + 10 B out per
-cluster) over its average duration from HIP events recorded on the decode
-stream during the timed steps.  `cpu_baseline` is the plain C oracle on one
-host core over a bounded sample of the same frame.
+cluster) over its average duration from HIP events recorded around it on the
+decode stream during the timed steps (in graph mode: event-record nodes of
+the replayed graph).  `cpu_baseline` is the plain C oracle over the same
+frames: on one host core, and on all host cores with one frame per thread.
 """
 import argparse
 import json
@@ -29,15 +38,20 @@ CLUSTER_IN_BYTES = 10   # attached: row/sector step (1+1), residuals (2+2), char
 UNATT_IN_BYTES = 10     # time diff (4), pad diff (2), charges (2+2)
 CLUSTER_OUT_BYTES = 10  # time (4), pad (2), charges (2+2)
 BIN_BYTES = 4 + 4 + 4   # un_count in, row_offset and row_nattached out
+METRIC = "decoded TPC clusters/s on 1 MI355X (bit-exact) + p50/p99 time-frame latency"
 
 WORKLOADS = {
+    "batched": "64 time frames of log-uniform 10..200 collisions x 2000 tracks (36 sectors, 152 rows, "
+               "track lengths U{5..152}, 10% sector crossers, 40% unattached) decoded by one plan whose "
+               "launch sequence is one captured HIP graph, replayed per step; compared with 64 plain "
+               "per-frame decodes",
     "frame": "one Pb-Pb-like time frame: 100 collisions x 2000 tracks, 36 sectors, 152 rows, "
              "track lengths U{5..152}, 10% sector crossers, 40% unattached; plain single launch",
     "stress": "high-occupancy stress frame: 500 collisions x 2000 tracks, 15% low-pT loopers, "
               "rows skewed exp(-row/40); plain single launch",
+    "stress-batched": "the stress frame (500 collisions, 15% loopers, skewed rows) decoded by a plan "
+                      "captured as a HIP graph and replayed per step",
     "tiny": "tiny plain decode: 1 sector, 1000 tracks of 20..152 clusters, 20000 unattached",
-    "batched": "64 time frames of log-uniform 10..200 collisions x 2000 tracks decoded by one plan "
-               "(one HIP-graph launch), compared with 64 plain per-frame decodes",
     "served": "Poisson arrivals of frames from the batched mix at 25/50/75/100% of the batched peak; "
               "continuous batching under a 200 GB HBM budget; p50/p99 latency",
     "pipeline": "the frame workload held in page-locked host memory, decoded through the native pipeline "
@@ -52,32 +66,151 @@ def algorithmic_bytes(nT, nA, nU):
     return att, una, att + una + 5472 * BIN_BYTES
 
 
-def cpu_baseline(frame, bz, budget_s, n_clusters):
+def kernel_bytes(shapes):
+    """Algorithmic bytes per launch of each kernel over frames of `shapes`:
+    the attached decode 10 B in + 10 B out per attached cluster and 15 B per
+    header; the unattached decode 10 + 10 B per cluster; count and rank read
+    the 2 B of row/sector steps per attached cluster (rank also the 8 B of
+    residuals and charges it packs for the decode)."""
+    nT = sum(s[0] for s in shapes)
+    nA = sum(s[1] for s in shapes)
+    nU = sum(s[2] for s in shapes)
+    att, una, _ = algorithmic_bytes(nT, nA, nU)
+    return {"attached": att, "unattached": una, "count": 2 * nA + nT, "rank": 10 * nA + nT}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Threads for the all-core oracle leg: the CPUs this process may use,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def oracle_single(frames, bz, budget_s):
+    """The plain C oracle on one core over the frames in order, until the
+    budget is spent (at least one frame)."""
     import oracle
     t0 = time.perf_counter()
-    reps = 0
-    res = None
-    while True:
-        res = oracle.decode(frame, bz=bz)
-        reps += 1
+    done = clusters = 0
+    for fr in frames:
+        oracle.decode(fr, bz=bz)
+        done += 1
+        clusters += int(fr["cls_qtot"].shape[0] + fr["un_qtot"].shape[0])
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": n_clusters * reps / dt, "unit": "clusters/s", "cores": 1, "kind": "oracle",
-            "sample": f"the same frame decoded {reps}x by the single-threaded C oracle "
-                      f"({n_clusters} clusters each, {dt:.1f} s)"}, res
+    return clusters / dt, done, clusters, dt
+
+
+def oracle_all(frames, bz, threads):
+    """The same oracle on `threads` host threads, one frame per thread at a
+    time (the C decoder releases the interpreter lock).  Returns the results
+    in frame order and the rate."""
+    import concurrent.futures as cf
+
+    import oracle
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(lambda fr: oracle.decode(fr, bz=bz), frames))
+    dt = time.perf_counter() - t0
+    clusters = sum(int(fr["cls_qtot"].shape[0] + fr["un_qtot"].shape[0]) for fr in frames)
+    return res, clusters / dt, dt
+
+
+def cpu_baseline_entry(single, all_core, n_frames_total, sample_desc):
+    rate1, done, clusters, dt = single
+    line = {"value": rate1, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of {n_frames_total} {sample_desc} decoded one after another by the "
+                      f"single-threaded C oracle ({clusters} clusters, {dt:.1f} s)",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    if all_core is not None:
+        rate, threads, dt_all, n = all_core
+        line["all_core"] = {"value": rate, "unit": "clusters/s", "cores": threads, "kind": "oracle",
+                            "sample": f"all {n} {sample_desc}, one frame per thread ({dt_all:.1f} s)"}
+    return line
+
+
+# ---------------------------------------------------------------------------
+# synthetic frames: generated in forked workers before the GPU is used, or
+# loaded from a cache folder written by an earlier run
+# ---------------------------------------------------------------------------
+def make_frames(specs, workers=16):
+    import synth
+    return synth.make_frames(specs, workers=workers)
+
+
+def frames_for(workload, args):
+    import numpy as np
+
+    import synth
+    if workload in ("batched", "served"):
+        specs = synth.batch_specs(workload, n_frames=args.frames)
+    else:
+        specs = [synth.spec_for("stress" if workload == "stress-batched" else workload)]
+    cache = None
+    if args.frames_cache:
+        cache = os.path.join(args.frames_cache, workload if workload != "stress-batched" else "stress")
+        if os.path.exists(os.path.join(cache, "done")):
+            frames = []
+            for i in range(len(specs)):
+                d = os.path.join(cache, f"{i:03d}")
+                frames.append({k: np.load(os.path.join(d, k + ".npy")) for k in synth.frames.FIELDS})
+            return frames, 0.0, True
+    t = time.perf_counter()
+    frames = make_frames(specs, workers=args.gen_workers)
+    gen_s = time.perf_counter() - t
+    if cache:
+        for i, fr in enumerate(frames):
+            d = os.path.join(cache, f"{i:03d}")
+            os.makedirs(d, exist_ok=True)
+            for k, v in fr.items():
+                np.save(os.path.join(d, k + ".npy"), v)
+        open(os.path.join(cache, "done"), "w").close()
+    return frames, gen_s, False
+
+
+def roofline(kernel, nbytes, avg_ms, workload):
+    if nbytes is None or not avg_ms or avg_ms <= 0:
+        return None
+    from paper_2411_02206_amd import traffic as _traffic
+    ach = nbytes / (avg_ms * 1e-3) / 1e9
+    summ = _traffic.load_summary(workload)
+    kt = summ["kernels"].get(f"k_{kernel}") if summ else None
+    return {"bound": "hbm", "kernel": f"k_{kernel}", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": kt["traffic_bytes"] if kt else None, "bytes_per_launch": nbytes,
+            "avg_ms": round(avg_ms, 4)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="frame", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="batched", choices=sorted(WORKLOADS))
     ap.add_argument("--bz", type=float, default=0.5)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget of the single-core oracle leg (whole frames, at least one)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and check")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched workloads: skip the plain per-frame comparison (profiling runs)")
     ap.add_argument("--frames", type=int, default=64, help="frames of the batched/served workloads")
+    ap.add_argument("--frames-cache", default=None,
+                    help="folder of generated frames: loaded if present, else written after generation")
     ap.add_argument("--seconds-per-load", type=float, default=2.0, help="served: arrival window per load")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="forked processes generating the synthetic frames (1 under a profiler that "
@@ -88,48 +221,50 @@ def main():
               "(frames are independent: several GPUs would each decode their own frames)",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "pipeline":
+        return run_pipeline(args)
+    if args.workload in ("batched", "served", "stress-batched"):
+        return run_batched(args)
+    return run_plain(args)
 
+
+def run_plain(args):
+    """One frame, plain single-frame plan (eager launches)."""
+    frames, gen_s, cached = frames_for(args.workload, args)   # before any GPU use
+    frame = frames[0]
     import numpy as np
     import torch
 
     import paper_2411_02206_amd as tmd
-    import synth
 
-    if args.workload in ("batched", "served"):
-        return run_batched(args)
-    if args.workload == "pipeline":
-        return run_pipeline(args)
-
-    spec = synth.spec_for(args.workload)
-    t = time.perf_counter()
-    frame = synth.make_frame(spec, workers=args.gen_workers)  # forked workers, before any GPU use
-    gen_s = time.perf_counter() - t
     nT, nA, nU = tmd.frame_shape(frame)
     n_clusters = nA + nU
     print(f"[bench] {args.workload}: {nT} tracks, {nA} attached, {nU} unattached "
-          f"(generated in {gen_s:.1f} s)", file=sys.stderr, flush=True)
+          f"({'from cache' if cached else f'generated in {gen_s:.1f} s'})", file=sys.stderr, flush=True)
+    single = None
+    if not args.no_cpu:
+        single = oracle_single([frame], args.bz, args.cpu_seconds)
 
     dev = tmd.to_device(frame)
     plan = tmd.Plan([(nT, nA, nU)], bz=args.bz)
     out = tmd.alloc_out((nT, nA, nU))
     ws = plan.alloc_workspace()
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        plan.decode([dev], [out], ws, stream)
-    torch.cuda.synchronize()
-    status = plan.status(0)
-
-    # per-stage breakdown (events around every stage), then the timed steps
-    # with events around the dominant kernel only
+    # per-stage breakdown (events around every stage), outside the timed steps
     plan.set_profiling(True)
-    for _ in range(args.steps):
+    for _ in range(max(3, args.warmup)):
         plan.decode([dev], [out], ws, stream)
     torch.cuda.synchronize()
     stages, calls = plan.stage_times()
     avg = {k: v / max(calls, 1) for k, v in stages.items()}
     dominant = max(avg, key=avg.get)
+    # warmup, then the timed steps with events around the dominant kernel
     plan.set_profiling(stages=[dominant])
+    for _ in range(args.warmup):
+        plan.decode([dev], [out], ws, stream)
     torch.cuda.synchronize()
+    plan.stage_times()  # drop the warmup's records
+    status = plan.status(0)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plan.decode([dev], [out], ws, stream)
@@ -152,42 +287,23 @@ def main():
         lat.append((e0, e1))
     torch.cuda.synchronize()
     lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
-
-    att_b, una_b, all_b = algorithmic_bytes(nT, nA, nU)
-    # algorithmic bytes per launch of each kernel (what its step of the method
-    # must move): attached decode 10 B in + 10 B out per attached cluster and
-    # 15 B per header; unattached 10 + 10 B per cluster; count and rank read
-    # the 2 B of row/sector steps per attached cluster (the rank kernel also
-    # the 8 B of residuals and charges it packs for the decode)
-    kernel_bytes = {"attached": att_b, "unattached": una_b, "count": 2 * nA + nT,
-                    "rank": 10 * nA + nT}
-    dom_bytes = kernel_bytes.get(dominant)
-    roof = None
-    if dom_bytes is not None and dom_ms > 0:
-        ach = dom_bytes / (dom_ms * 1e-3) / 1e9
-        # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
-        # copy-calibrated), only if taken with the current kernel source
-        from paper_2411_02206_amd import traffic as _traffic
-        summ = _traffic.load_summary(args.workload)
-        kt = summ["kernels"].get(f"k_{dominant}") if summ else None
-        roof = {"bound": "hbm", "kernel": f"k_{dominant}", "achieved": round(ach, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": kt["traffic_bytes"] if kt else None, "bytes_per_launch": dom_bytes,
-                "avg_ms": round(dom_ms, 4)}
+    kb = kernel_bytes([(nT, nA, nU)])
+    roof = roofline(dominant, kb.get(dominant), dom_ms, args.workload)
+    _, _, all_b = algorithmic_bytes(nT, nA, nU)
     step_gbs = all_b / (ms_per_step * 1e-3) / 1e9
 
     cpu = None
     bitexact = None
     if not args.no_cpu:
-        cpu, (exp, est) = cpu_baseline(frame, args.bz, args.cpu_seconds, n_clusters)
+        (exp, est), = oracle_all([frame], args.bz, 1)[0]
         got = tmd.to_numpy(out)
         bitexact = bool(all(np.array_equal(exp[k], got[k]) for k in exp) and est == status)
+        cpu = cpu_baseline_entry(single, None, 1, f"{args.workload} frame")
 
     line = {
-        "metric": "decoded TPC clusters/s on 1 MI355X (bit-exact) + p50/p99 time-frame latency",
-        "value": value, "unit": "clusters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "metric": METRIC, "value": value, "unit": "clusters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "n_tracks": nT,
                    "n_attached": nA, "n_unattached": nU, "bz_tesla": args.bz},
         "roofline": roof,
@@ -203,17 +319,216 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def run_pipeline(args):
-    """Host-resident frames: the same page-locked frame decoded `steps` times
-    through tmd_pipe_run, with 3 slots and with 1; each slot writes its own
-    page-locked output buffers."""
+def run_batched(args):
+    """Frames decoded by one graph plan (a step = one replay), against plain
+    per-frame decodes of the same frames; with --workload served, also the
+    serving loop at several offered loads."""
+    frames, gen_s, cached = frames_for(args.workload, args)   # before any GPU use
     import numpy as np
     import torch
 
     import paper_2411_02206_amd as tmd
-    import synth
+    from paper_2411_02206_amd import serve
 
-    frame = synth.make_frame(synth.spec_for("frame"), workers=args.gen_workers)
+    shapes = [tmd.frame_shape(f) for f in frames]
+    n_clusters = sum(a + u for _, a, u in shapes)
+    nT_all = sum(s[0] for s in shapes)
+    nA_all = sum(s[1] for s in shapes)
+    nU_all = sum(s[2] for s in shapes)
+    print(f"[bench] {args.workload}: {len(frames)} frames, {nT_all} tracks, {n_clusters} clusters "
+          f"({'from cache' if cached else f'generated in {gen_s:.1f} s'})", file=sys.stderr, flush=True)
+    single = None
+    if not args.no_cpu:
+        single = oracle_single(frames, args.bz, args.cpu_seconds)
+        print(f"[bench] oracle, one core: {single[0]:.3e} clusters/s over {single[1]} frames",
+              file=sys.stderr, flush=True)
+
+    ins = [tmd.to_device(f) for f in frames]
+    stream = torch.cuda.current_stream()
+    steps, warmup = args.steps, args.warmup
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    # plain: one plan and one launch sequence per frame
+    plain = None
+    if len(frames) > 1 and not args.no_plain:
+        plans = [tmd.Plan([s], bz=args.bz) for s in shapes]
+        ws = torch.empty(max(p.workspace_bytes for p in plans), dtype=torch.uint8, device="cuda")
+        outs_plain = [tmd.alloc_out(s) for s in shapes]
+
+        def plain_step():
+            for p, i, o in zip(plans, ins, outs_plain):
+                p.decode([i], [o], ws, stream)
+        t_plain = timed(plain_step)
+        plain = {"ms_per_pass": 1e3 * t_plain, "clusters_per_s": n_clusters / t_plain}
+        print(f"[bench] plain: {1e3 * t_plain:.3f} ms per pass over {len(frames)} frames",
+              file=sys.stderr, flush=True)
+
+    # batched: one plan over all frames, its launch sequence one captured graph
+    bplan = tmd.Plan(shapes, bz=args.bz, flags=tmd.PLAN_GRAPH)
+    bws = bplan.alloc_workspace()
+    outs_b = [tmd.alloc_out(s) for s in shapes]
+
+    def batched_step():
+        bplan.decode(ins, outs_b, bws, stream)
+
+    # per-stage breakdown (a graph with event nodes around every stage),
+    # outside the timed steps
+    bplan.set_profiling(True)
+    for _ in range(3):
+        batched_step()
+    torch.cuda.synchronize()
+    stages, calls = bplan.stage_times()
+    avg = {k: v / max(calls, 1) for k, v in stages.items()}
+    dominant = max(avg, key=avg.get)
+    # timed replays: event nodes around the dominant kernel only
+    bplan.set_profiling(stages=[dominant])
+    for _ in range(warmup):
+        batched_step()
+    torch.cuda.synchronize()
+    bplan.stage_times()  # drop the warmup's records
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        batched_step()
+        e1.record(stream)
+        lat.append((e0, e1))
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    dom_stages, dom_calls = bplan.stage_times()
+    dom_ms = dom_stages[dominant] / max(dom_calls, 1)
+    bplan.set_profiling(False)
+    lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
+    flags = [bplan.status(i) for i in range(len(frames))]
+    print(f"[bench] batched: {1e3 * t_batch:.3f} ms per step, {n_clusters / t_batch:.3e} clusters/s; "
+          f"{dominant} {dom_ms:.3f} ms", file=sys.stderr, flush=True)
+
+    def dev_equal(a, b):
+        n = int(a["row_offset"][-1].item())
+        if n != int(b["row_offset"][-1].item()):
+            return False
+        if not (torch.equal(a["row_offset"], b["row_offset"]) and
+                torch.equal(a["row_nattached"], b["row_nattached"])):
+            return False
+        return all(torch.equal(a[k][:n], b[k][:n]) for k in ("time", "pad", "qtot", "qmax"))
+
+    same_plain = None
+    if plain is not None:
+        same_plain = bool(all(dev_equal(a, b) for a, b in zip(outs_plain, outs_b)) and
+                          all(p.status(0) == f for p, f in zip(plans, flags)))
+        del outs_plain, plans, ws
+
+    cpu = None
+    oracle_ok = None
+    if not args.no_cpu:
+        threads = host_threads()
+        res, rate_all, dt_all = oracle_all(frames, args.bz, threads)
+        print(f"[bench] oracle, {threads} threads: {rate_all:.3e} clusters/s", file=sys.stderr, flush=True)
+        oracle_ok = True
+        for i, (exp, est) in enumerate(res):
+            got = tmd.to_numpy(outs_b[i])
+            oracle_ok &= bool(all(np.array_equal(exp[k], got[k]) for k in exp) and est == flags[i])
+            res[i] = None
+        cpu = cpu_baseline_entry(single, (rate_all, threads, dt_all, len(frames)), len(frames),
+                                 "frames of the workload")
+
+    kb = kernel_bytes(shapes)
+    roof = roofline(dominant, kb.get(dominant), dom_ms, args.workload)
+    _, _, all_b = algorithmic_bytes(nT_all, nA_all, nU_all)
+    all_b += (len(frames) - 1) * 5472 * BIN_BYTES
+    step_gbs = all_b / t_batch / 1e9
+    status = 0
+    for f in flags:
+        status |= f
+    line = {
+        "metric": METRIC, "value": n_clusters / t_batch, "unit": "clusters/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": 1e3 * t_batch, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "frames": len(frames),
+                   "n_tracks": nT_all, "n_attached": nA_all, "n_unattached": nU_all, "bz_tesla": args.bz},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "bitexact_vs_oracle": oracle_ok,
+        "bitexact_batched_vs_plain": same_plain,
+        "status_flags": status,
+        "step_algorithmic_GBs": round(step_gbs, 1),
+        "step_hbm_frac": round(step_gbs / HBM_PEAK_GBS, 4),
+        "stage_avg_ms": {k: round(v, 4) for k, v in avg.items()},
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 4)},
+        "plain_per_frame": plain,
+        "batched_vs_plain_speedup": (plain["ms_per_pass"] / (1e3 * t_batch)) if plain else None,
+    }
+
+    if args.workload == "served":
+        line["served"] = run_served(args, ins, shapes, len(frames) / t_batch)
+        line["latency_ms"] = {"p50": line["served"]["100%"]["p50_ms"], "p99": line["served"]["100%"]["p99_ms"]}
+    print(json.dumps(line), flush=True)
+
+
+def run_served(args, ins, shapes, peak_fps):
+    """The serving loop at 25/50/75/100% of the batched peak (frames per
+    second): Poisson arrivals of frames drawn from the mix."""
+    import numpy as np
+
+    from paper_2411_02206_amd import serve
+    loads = {}
+    srv = serve.Server(bz=args.bz, hbm_budget=200e9, slots=4, max_batch=8, graph=True)
+    rng = np.random.default_rng(3)
+    for frac in (0.25, 0.5, 0.75, 1.0):
+        rate = frac * peak_fps
+        n_req = max(50, int(rate * args.seconds_per_load))
+        gaps = rng.exponential(1.0 / rate, n_req)
+        picks = rng.integers(0, len(ins), n_req)
+        srv.done = []
+        t0 = time.perf_counter()
+        arrivals = t0 + np.cumsum(gaps)
+        k = 0
+        nd = 0
+        while len(srv.done) < n_req:
+            now = time.perf_counter()
+            while k < n_req and arrivals[k] <= now:
+                srv.submit(ins[picks[k]], arrival=float(arrivals[k]))
+                k += 1
+            srv.step()
+            # the client takes each result as it completes: its buffers go
+            for r in srv.done[nd:]:
+                r.out = None
+            nd = len(srv.done)
+        t1 = time.perf_counter()
+        lat = [1e3 * r.latency for r in srv.done]
+        served_clusters = sum(shapes[p][1] + shapes[p][2] for p in picks)
+        key = f"{int(frac * 100)}%"
+        loads[key] = {"offered_frames_per_s": rate, "requests": n_req,
+                      "p50_ms": serve.percentile(lat, 50), "p99_ms": serve.percentile(lat, 99),
+                      "clusters_per_s": served_clusters / (t1 - t0)}
+        print(f"[bench] load {frac:.2f}: p50 {loads[key]['p50_ms']:.3f} ms, p99 {loads[key]['p99_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+    srv.close()
+    return loads
+
+
+def run_pipeline(args):
+    """Host-resident frames: the same page-locked frame decoded `steps` times
+    through tmd_pipe_run, with 3 slots and with 1; each slot writes its own
+    page-locked output buffers."""
+    frames, _, _ = frames_for("frame", args)
+    frame = frames[0]
+    import numpy as np
+    import torch
+
+    import paper_2411_02206_amd as tmd
+
     shape = tmd.frame_shape(frame)
     nT, nA, nU = shape
     n_clusters = nA + nU
@@ -256,152 +571,6 @@ def run_pipeline(args):
         "pcie_GBs_each_way": round(in_bytes / (best["ms_per_frame"] * 1e-3) / 1e9, 1),
         "bitexact_vs_device_decode": bool(bitexact),
     }
-    print(json.dumps(line), flush=True)
-
-
-def _gen(spec):
-    import synth
-    return synth.make_frame(spec)
-
-
-def make_frames(specs, workers=16):
-    """Generate frames in parallel worker processes (forked before any GPU use)."""
-    import multiprocessing as mp
-    n = max(1, min(workers, len(specs), os.cpu_count() or 1))
-    if n == 1:
-        return [_gen(s) for s in specs]
-    with mp.get_context("fork").Pool(n) as pool:
-        return pool.map(_gen, specs, chunksize=1)
-
-
-def run_batched(args):
-    """Batched workload (one plan over all frames, HIP graph) against plain
-    per-frame decodes of the same frames; with --workload served, also the
-    serving loop at several offered loads."""
-    import synth
-    specs = synth.batch_specs(args.workload, n_frames=args.frames)
-    t = time.perf_counter()
-    frames = make_frames(specs, workers=args.gen_workers)
-    gen_s = time.perf_counter() - t
-
-    import numpy as np
-    import torch
-
-    import paper_2411_02206_amd as tmd
-    from paper_2411_02206_amd import serve
-
-    shapes = [tmd.frame_shape(f) for f in frames]
-    n_clusters = sum(a + u for _, a, u in shapes)
-    print(f"[bench] {args.workload}: {len(frames)} frames, {sum(s[0] for s in shapes)} tracks, {n_clusters} "
-          f"clusters (generated in {gen_s:.1f} s)", file=sys.stderr, flush=True)
-    ins = [tmd.to_device(f) for f in frames]
-    stream = torch.cuda.current_stream()
-
-    # plain: one plan and one launch sequence per frame
-    plans = [tmd.Plan([s], bz=args.bz) for s in shapes]
-    ws_bytes = max(p.workspace_bytes for p in plans)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    outs_plain = [tmd.alloc_out(s) for s in shapes]
-
-    def plain_step():
-        for p, i, o in zip(plans, ins, outs_plain):
-            p.decode([i], [o], ws, stream)
-
-    # batched: one plan over all frames, captured once as a HIP graph
-    bplan = tmd.Plan(shapes, bz=args.bz, flags=tmd.PLAN_GRAPH)
-    bws = bplan.alloc_workspace()
-    outs_b = [tmd.alloc_out(s) for s in shapes]
-
-    def batched_step():
-        bplan.decode(ins, outs_b, bws, stream)
-
-    def timed(fn, steps, warmup):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
-
-    steps = max(1, args.steps // 10)
-    t_plain = timed(plain_step, steps, 1)
-    t_batch = timed(batched_step, steps, 1)
-    print(f"[bench] plain {1e3 * t_plain:.3f} ms, batched {1e3 * t_batch:.3f} ms per pass over "
-          f"{len(frames)} frames", file=sys.stderr, flush=True)
-    # every frame bit-identical between the two forms
-    def dev_equal(a, b):
-        n = int(a["row_offset"][-1].item())
-        if n != int(b["row_offset"][-1].item()):
-            return False
-        if not (torch.equal(a["row_offset"], b["row_offset"]) and
-                torch.equal(a["row_nattached"], b["row_nattached"])):
-            return False
-        return all(torch.equal(a[k][:n], b[k][:n]) for k in ("time", "pad", "qtot", "qmax"))
-
-    same = all(dev_equal(a, b) for a, b in zip(outs_plain, outs_b))
-    flags_same = all(p.status(0) == bplan.status(i) for i, p in enumerate(plans))
-    oracle_ok = None
-    if not args.no_cpu:
-        import oracle
-        oracle_ok = True
-        for i in (0, len(frames) // 2):
-            exp, est = oracle.decode(frames[i], bz=args.bz)
-            got = tmd.to_numpy(outs_b[i])
-            oracle_ok &= bool(all(np.array_equal(exp[k], got[k]) for k in exp) and est == bplan.status(i))
-
-    line = {
-        "metric": "decoded TPC clusters/s on 1 MI355X (bit-exact) + p50/p99 time-frame latency",
-        "value": n_clusters / t_batch, "unit": "clusters/s", "n_gpus": 1, "steps": steps, "warmup": 1,
-        "ms_per_step": 1e3 * t_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "frames": len(frames),
-                   "n_clusters": n_clusters, "bz_tesla": args.bz},
-        "plain_per_frame": {"ms_per_pass": 1e3 * t_plain, "clusters_per_s": n_clusters / t_plain},
-        "batched_vs_plain_speedup": t_plain / t_batch,
-        "bitexact_batched_vs_plain": bool(same and flags_same),
-        "bitexact_vs_oracle_sampled_frames": oracle_ok,
-    }
-    del outs_plain, plans, ws
-
-    if args.workload == "served":
-        peak_fps = len(frames) / t_batch
-        loads = {}
-        srv = serve.Server(bz=args.bz, hbm_budget=200e9, slots=4, max_batch=8, graph=True)
-        rng = np.random.default_rng(3)
-        for frac in (0.25, 0.5, 0.75, 1.0):
-            rate = frac * peak_fps
-            n_req = max(50, int(rate * args.seconds_per_load))
-            gaps = rng.exponential(1.0 / rate, n_req)
-            picks = rng.integers(0, len(frames), n_req)
-            srv.done = []
-            t0 = time.perf_counter()
-            arrivals = t0 + np.cumsum(gaps)
-            k = 0
-            nd = 0
-            while len(srv.done) < n_req:
-                now = time.perf_counter()
-                while k < n_req and arrivals[k] <= now:
-                    srv.submit(ins[picks[k]], arrival=float(arrivals[k]))
-                    k += 1
-                srv.step()
-                # the client takes each result as it completes: its buffers go
-                for r in srv.done[nd:]:
-                    r.out = None
-                nd = len(srv.done)
-            t1 = time.perf_counter()
-            lat = [1e3 * r.latency for r in srv.done]
-            served_clusters = sum(shapes[p][1] + shapes[p][2] for p in picks)
-            loads[f"{int(frac * 100)}%"] = {
-                "offered_frames_per_s": rate, "requests": n_req,
-                "p50_ms": serve.percentile(lat, 50), "p99_ms": serve.percentile(lat, 99),
-                "clusters_per_s": served_clusters / (t1 - t0)}
-            print(f"[bench] load {frac:.2f}: p50 {loads[f'{int(frac * 100)}%']['p50_ms']:.3f} ms, "
-                  f"p99 {loads[f'{int(frac * 100)}%']['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
-        srv.close()
-        line["served"] = loads
-        line["latency_ms"] = {"p50": loads["100%"]["p50_ms"], "p99": loads["100%"]["p99_ms"]}
     print(json.dumps(line), flush=True)
 
 

@@ -128,6 +128,13 @@ typedef struct {
 } tmd_params;
 
 /*
+ * Defines: the set-up of the decode of the paper's section 4 (its first kernel
+ * propagates each track through the TPC with the stored residuals; the track
+ * model itself is deferred by the paper to its reference on global tracking,
+ * so the float32 tables built here are those of this project's model, see the
+ * implementation).  Frames of one plan are decoded together (the batched form;
+ * section 4 runs several instances concurrently on streams instead).
+ *
  * Prepare decoding of n_frames frames of the given shapes in one call of
  * tmd_decode (n_frames = 1: a plain single-frame decode; more: the batched
  * form, one launch sequence over all frames).  Builds the float32 constant
@@ -146,6 +153,13 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
              tmd_plan_t **plan, size_t *workspace_bytes);
 
 /*
+ * Defines: the decoding of section 4 -- attached clusters rebuilt by
+ * propagating each track and adding its residuals (the first kernel: one lane
+ * per track), unattached clusters rebuilt by summing the differences within
+ * each region (the second kernel: here a region is one (sector,row) bin), with
+ * the indices into the structure-of-arrays input that section 4 precomputes on
+ * the CPU computed here on the GPU.
+ *
  * Enqueue the decode of n_frames frames (in[i], out[i] for frame i, shaped as
  * planned) on `stream` (a hipStream_t; NULL = the default stream) and return.
  * The kernels: track start offsets (scan of trk_ncls), per-cluster (sector,row)
@@ -161,6 +175,10 @@ int tmd_decode(tmd_plan_t *plan, const tmd_frame_in *in, tmd_frame_out *out, voi
                void *stream);
 
 /*
+ * Defines: the decode of tmd_decode (section 4) over frames of changing sizes,
+ * for a serving loop (the paper processes time frames of varying size one
+ * after another; it prints no interface for this).
+ *
  * As tmd_decode, for frames whose shapes (shapes[i], n_frames entries) are no
  * larger than the planned ones in every count: the plan's shapes are then
  * capacities, and one plan (and its workspace, and in TMD_PLAN_GRAPH mode its
@@ -175,6 +193,11 @@ int tmd_decode_shapes(tmd_plan_t *plan, const tmd_frame_shape *shapes, const tmd
                       tmd_frame_out *out, void *workspace, void *stream);
 
 /*
+ * Defines: the status of a decode.  The paper's decoding restores the stored
+ * values exactly (section 4) and says nothing of invalid input; the flags are
+ * this project's clamp-and-flag reading, under which every output byte of an
+ * invalid stream is still defined.
+ *
  * Flags of frame `frame` from the last tmd_decode on this plan; waits for that
  * decode to finish.  Returns TMD_OK if no flag is set, TMD_E_INPUT if
  * TMD_F_COUNT is set, TMD_E_STREAM if another flag is set, TMD_E_ARG for a bad
@@ -182,7 +205,8 @@ int tmd_decode_shapes(tmd_plan_t *plan, const tmd_frame_shape *shapes, const tmd
  */
 int tmd_status(tmd_plan_t *plan, uint32_t frame, uint32_t *flags);
 
-/* Release the plan and its device memory (waits for its work). NULL is a no-op. */
+/* Release the plan and its device memory (waits for its work). NULL is a no-op.
+ * (Resource management of this library; no passage of the paper defines it.) */
 void tmd_free(tmd_plan_t *plan);
 
 /*
@@ -265,9 +289,11 @@ int tmd_tables(float bz, float *dst, int cap);
 
 /*
  * Stage timing.  tmd_set_profiling selects stages by bit (bit i = stage i as
- * named by tmd_stage_name; 0 = off, ~0u = all); tmd_decode (not in
- * TMD_PLAN_GRAPH mode) then records a pair of HIP events around each selected
- * stage on its stream.  tmd_stage_times waits for the recorded calls, writes
+ * named by tmd_stage_name; 0 = off, ~0u = all); tmd_decode then records a
+ * pair of HIP events around each selected stage on its stream.  In
+ * TMD_PLAN_GRAPH mode the plan captures a second graph (once per stage mask)
+ * with an event-record node before and after each selected stage, and every
+ * replay points those nodes at fresh events, so each call is timed on its own.  tmd_stage_times waits for the recorded calls, writes
  * the summed milliseconds of each stage to ms[0 .. n-1] (0 for unselected
  * stages), the number of recorded calls to *calls, and clears the record.
  * Returns the number of stages.

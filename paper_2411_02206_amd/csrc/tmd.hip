@@ -770,10 +770,31 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(const FrameDesc *__rest
 }
 
 // ---------------------------------------------------------------------------
-// K5: unattached clusters; one wave per (bin, frame), 1024 clusters per pass
-// (a pass's loads are all in flight together)
+// K5: unattached clusters; one wave per (bin, frame).  A lane takes 4
+// consecutive clusters of a group of 256 and moves them with one wide access
+// per array (16 bytes of time, 8 of each 16-bit field: the address unit
+// handles a wave's access at a cost that grows with the instructions more
+// than with their width).  Bins start anywhere, so the accesses are not
+// aligned to their width (the hardware allows that for global memory).  The
+// one lane whose group is cut by the bin's end uses element accesses, so
+// nothing outside the bin is read or written.  4 groups (1024 clusters) per
+// pass, all their loads in flight together.
 // ---------------------------------------------------------------------------
-constexpr int kUnroll = 16;  // a bin is a serial chain of passes: few, wide ones
+constexpr int kUGroups = 4;
+
+template <class V, class T>
+__device__ __forceinline__ V load_wide(const GLB T *p)
+{
+    V v;
+    __builtin_memcpy(&v, (const GLB char *)p, sizeof(V));
+    return v;
+}
+
+template <class V, class T>
+__device__ __forceinline__ void store_wide(GLB T *p, const V &v)
+{
+    __builtin_memcpy((GLB char *)p, &v, sizeof(V));
+}
 
 __global__ __launch_bounds__(kWave) void k_unattached(const FrameDesc *__restrict__ fd)
 {
@@ -784,32 +805,74 @@ __global__ __launch_bounds__(kWave) void k_unattached(const FrameDesc *__restric
     const uint32_t src = F.uin[k];
     const uint32_t dst = F.roff[k] + F.rna[k];
     const uint32_t lane = lane_id();
+    // the whole bin lies inside the output (a store past the capacity is never
+    // issued; the offsets kernel keeps dst + cnt <= n_attached + n_unattached
+    // for consistent streams, and capacity >= that sum)
+    const uint32_t room = dst < F.cap ? (uint32_t)min((uint64_t)cnt, F.cap - dst) : 0u;
     uint32_t ct = 0, cp = 0;
-    for (uint32_t i = 0; i < cnt; i += kWave * kUnroll) {
-        uint32_t td[kUnroll], pd[kUnroll];
-        uint16_t qt[kUnroll], qm[kUnroll];
+    for (uint32_t i = 0; i < cnt; i += kUGroups * 4 * kWave) {
+        uint32_t td[kUGroups][4], pd[kUGroups][4], qt[kUGroups][4], qm[kUGroups][4];
 #pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
-            const uint32_t idx = i + u * kWave + lane;
-            const bool act = idx < cnt;
-            td[u] = act ? F.utdiff[src + idx] : 0u;
-            pd[u] = act ? (uint32_t)F.updiff[src + idx] : 0u;
-            qt[u] = act ? F.uqtot[src + idx] : (uint16_t)0;
-            qm[u] = act ? F.uqmax[src + idx] : (uint16_t)0;
+        for (int u = 0; u < kUGroups; u++) {
+            const uint32_t e = i + (uint32_t)u * 4 * kWave + 4 * lane;  // first element of this lane
+            if (e + 4 <= cnt) {
+                const uint4 t4 = load_wide<uint4>(F.utdiff + src + e);
+                const uint2 p4 = load_wide<uint2>(F.updiff + src + e);
+                const uint2 a4 = load_wide<uint2>(F.uqtot + src + e);
+                const uint2 b4 = load_wide<uint2>(F.uqmax + src + e);
+                td[u][0] = t4.x; td[u][1] = t4.y; td[u][2] = t4.z; td[u][3] = t4.w;
+                pd[u][0] = p4.x & 0xFFFFu; pd[u][1] = p4.x >> 16; pd[u][2] = p4.y & 0xFFFFu; pd[u][3] = p4.y >> 16;
+                qt[u][0] = a4.x & 0xFFFFu; qt[u][1] = a4.x >> 16; qt[u][2] = a4.y & 0xFFFFu; qt[u][3] = a4.y >> 16;
+                qm[u][0] = b4.x & 0xFFFFu; qm[u][1] = b4.x >> 16; qm[u][2] = b4.y & 0xFFFFu; qm[u][3] = b4.y >> 16;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const bool act = e + q < cnt;
+                    td[u][q] = act ? F.utdiff[src + e + q] : 0u;
+                    pd[u][q] = act ? (uint32_t)F.updiff[src + e + q] : 0u;
+                    qt[u][q] = act ? (uint32_t)F.uqtot[src + e + q] : 0u;
+                    qm[u][q] = act ? (uint32_t)F.uqmax[src + e + q] : 0u;
+                }
+            }
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
-            const uint32_t idx = i + u * kWave + lane;
-            const uint32_t st = ct + wave_incl_add(td[u]);
-            const uint32_t sp = cp + wave_incl_add(pd[u]);
-            if (idx < cnt && dst + idx < F.cap) {
-                F.otime[dst + idx] = st;
-                F.opad[dst + idx] = (uint16_t)sp;
-                F.oqtot[dst + idx] = qt[u];
-                F.oqmax[dst + idx] = qm[u];
+        for (int u = 0; u < kUGroups; u++) {
+            const uint32_t e = i + (uint32_t)u * 4 * kWave + 4 * lane;
+            // running sums: the lane's own four, then the lanes before it
+            uint32_t st[4], sp[4];
+            st[0] = td[u][0];
+            sp[0] = pd[u][0];
+#pragma unroll
+            for (int q = 1; q < 4; q++) {
+                st[q] = st[q - 1] + td[u][q];
+                sp[q] = sp[q - 1] + pd[u][q];
             }
-            ct = readlane(st, kWave - 1);
-            cp = readlane(sp, kWave - 1);
+            const uint32_t it = wave_incl_add(st[3]), ip = wave_incl_add(sp[3]);
+            const uint32_t bt = ct + it - st[3], bp = cp + ip - sp[3];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                st[q] += bt;
+                sp[q] += bp;
+            }
+            if (e + 4 <= room) {
+                store_wide(F.otime + dst + e, make_uint4(st[0], st[1], st[2], st[3]));
+                store_wide(F.opad + dst + e, make_uint2((sp[0] & 0xFFFFu) | (sp[1] << 16),
+                                                        (sp[2] & 0xFFFFu) | (sp[3] << 16)));
+                store_wide(F.oqtot + dst + e, make_uint2(qt[u][0] | (qt[u][1] << 16), qt[u][2] | (qt[u][3] << 16)));
+                store_wide(F.oqmax + dst + e, make_uint2(qm[u][0] | (qm[u][1] << 16), qm[u][2] | (qm[u][3] << 16)));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    if (e + q < room) {
+                        F.otime[dst + e + q] = st[q];
+                        F.opad[dst + e + q] = (uint16_t)sp[q];
+                        F.oqtot[dst + e + q] = (uint16_t)qt[u][q];
+                        F.oqmax[dst + e + q] = (uint16_t)qm[u][q];
+                    }
+                }
+            }
+            ct = readlane(it, kWave - 1) + ct;
+            cp = readlane(ip, kWave - 1) + cp;
         }
     }
 }
@@ -1043,7 +1106,10 @@ __device__ __forceinline__ int32_t sat_rint(float v)
 
 // IEEE square root of a positive normal float.  v_sqrt_f32 is within one ulp;
 // of its result and the two neighbours, the residuals x - r' * r (one fused
-// multiply-add each) pick the correctly rounded one.  Every square root in the
+// multiply-add each) pick the correctly rounded one.  This is the correction
+// LLVM's AMDGPU back end itself emits for a correctly rounded f32 square root
+// (the remainder of each neighbouring float, exact under a fused
+// multiply-add, tells on which side of the true root it lies).  Every square root in the
 // decode loop has its argument in [2^-9, 2^9]: (1 - s)(1 + s) with |s| <=
 // 0.999, and 1 + (dy/dx)^2 with |dy/dx| <= 1.998 / (2 sqrt(0.001999)).
 __device__ __forceinline__ float sqrt_pos(float x)
@@ -1653,6 +1719,14 @@ struct tmd_plan {
     std::vector<hipEvent_t> event_pool;                // events ready for reuse
     hipGraphExec_t graph = nullptr;   // TMD_PLAN_GRAPH: the captured launch sequence
     hipStream_t capture = nullptr;    // stream the graph is captured on
+    // TMD_PLAN_GRAPH with profiling: a second graph with an event-record node
+    // before and after each selected stage; each replay points those nodes
+    // at fresh events from the pool
+    hipGraph_t prof_src = nullptr;     // the captured graph (its nodes address the exec's)
+    hipGraphExec_t prof_graph = nullptr;
+    uint32_t prof_mask = 0;            // stages the profiling graph brackets
+    std::vector<hipEvent_t> prof_marks;      // capture-time events, 2 per stage (null: unselected)
+    std::vector<hipGraphNode_t> prof_nodes;  // their record nodes
 };
 
 namespace {
@@ -1706,28 +1780,30 @@ uint32_t attached_waves(uint32_t nT, bool single, uint32_t simds)
     return (uint64_t)nT <= (uint64_t)(kWave + 2) * w ? w : w0;
 }
 
-// Enqueue the pipeline on stream s, one kernel after the other.  Each stage
-// in the profiling mask is bracketed by its own pair of events (from the
-// plan's pool).
-int launch_all(tmd_plan_t *P, hipStream_t s, uint32_t mask)
+// Events for the stages selected in `mask` (2 per stage, null for the
+// others), taken from the plan's pool.  Timing only: no system-scope fence
+// (no cache write-back and invalidation around the timed kernels).
+int take_events(tmd_plan_t *P, uint32_t mask, std::vector<hipEvent_t> &ev)
 {
-    std::vector<hipEvent_t> ev;
-    if (mask) {
-        ev.assign(2 * kStages, nullptr);
-        for (int st = 0; st < kStages; st++) {
-            if (!((mask >> st) & 1u)) continue;
-            for (int e = 0; e < 2; e++) {
-                if (!P->event_pool.empty()) {
-                    ev[2 * st + e] = P->event_pool.back();
-                    P->event_pool.pop_back();
-                } else {
-                    // timing only: no system-scope fence (no cache write-back
-                    // and invalidation around the timed kernels)
-                    HIP_TRY(hipEventCreateWithFlags(&ev[2 * st + e], hipEventDisableSystemFence));
-                }
+    ev.assign(2 * kStages, nullptr);
+    for (int st = 0; st < kStages; st++) {
+        if (!((mask >> st) & 1u)) continue;
+        for (int e = 0; e < 2; e++) {
+            if (!P->event_pool.empty()) {
+                ev[2 * st + e] = P->event_pool.back();
+                P->event_pool.pop_back();
+            } else {
+                HIP_TRY(hipEventCreateWithFlags(&ev[2 * st + e], hipEventDisableSystemFence));
             }
         }
     }
+    return TMD_OK;
+}
+
+// Enqueue the pipeline on stream s, one kernel after the other.  Each stage
+// with events in `ev` (2 per stage, or empty) is bracketed by them.
+int launch_all(tmd_plan_t *P, hipStream_t s, const std::vector<hipEvent_t> &ev)
+{
     auto begin = [&](int st, hipStream_t q) -> int {
         return (ev.size() && ev[2 * st] && hipEventRecord(ev[2 * st], q) != hipSuccess) ? TMD_E_HIP : TMD_OK;
     };
@@ -1759,7 +1835,129 @@ int launch_all(tmd_plan_t *P, hipStream_t s, uint32_t mask)
     hipLaunchKernelGGL(k_unattached, dim3(NBIN, P->n_frames), dim3(kWave), 0, s, P->d_desc);
     if (end(6, s)) return TMD_E_HIP;
     HIP_TRY(hipGetLastError());
-    if (mask) P->prof_events.push_back(ev);
+    return TMD_OK;
+}
+
+// Capture the launch sequence on the plan's capture stream and instantiate it.
+int capture_graph(tmd_plan_t *P, hipGraph_t *src, hipGraphExec_t *exec)
+{
+    hipGraph_t g = nullptr;
+    *src = nullptr;
+    *exec = nullptr;
+    if (hipStreamBeginCapture(P->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return TMD_E_HIP;
+    const int rc = launch_all(P, P->capture, {});
+    const hipError_t ec = hipStreamEndCapture(P->capture, &g);
+    if (rc != TMD_OK || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return TMD_E_HIP;
+    }
+    if (hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        *exec = nullptr;
+        (void)hipGraphDestroy(g);
+        return TMD_E_HIP;
+    }
+    *src = g;
+    return TMD_OK;
+}
+
+void drop_prof_graph(tmd_plan_t *P)
+{
+    if (P->prof_graph) (void)hipGraphExecDestroy(P->prof_graph);
+    if (P->prof_src) (void)hipGraphDestroy(P->prof_src);
+    for (hipEvent_t e : P->prof_marks)
+        if (e) (void)hipEventDestroy(e);
+    P->prof_graph = nullptr;
+    P->prof_src = nullptr;
+    P->prof_marks.clear();
+    P->prof_nodes.clear();
+    P->prof_mask = 0;
+}
+
+// The kernel each stage launches (graph nodes are matched to stages by it).
+const void *stage_kernel(int st)
+{
+    switch (st) {
+    case 0: return (const void *)k_tilesum;
+    case 1: return (const void *)k_count;
+    case 2: return (const void *)k_colscan;
+    case 3: return (const void *)k_offsets;
+    case 4: return (const void *)k_rank;
+    case 5: return (const void *)k_attached;
+    default: return (const void *)k_unattached;
+    }
+}
+
+// The profiling graph for P->profiling, made once per stage mask: the launch
+// sequence is captured (stream capture leaves event records out of a graph),
+// then an event-record node is inserted before and after the kernel node of
+// each selected stage (between it and its neighbours in the chain).  The
+// nodes record placeholder events; each replay points them at fresh ones.
+int prof_graph_ready(tmd_plan_t *P)
+{
+    if (P->prof_graph && P->prof_mask == P->profiling) return TMD_OK;
+    drop_prof_graph(P);
+    hipGraph_t g = nullptr;
+    hipGraphExec_t unused = nullptr;
+    int rc = capture_graph(P, &g, &unused);
+    if (unused) (void)hipGraphExecDestroy(unused);
+    if (rc != TMD_OK) return rc;
+    P->prof_src = g;
+    P->prof_marks.assign(2 * kStages, nullptr);
+    P->prof_nodes.assign(2 * kStages, nullptr);
+    size_t nn = 0;
+    if (hipGraphGetNodes(g, nullptr, &nn) != hipSuccess) rc = TMD_E_HIP;
+    std::vector<hipGraphNode_t> nodes(nn);
+    if (rc == TMD_OK && nn && hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) rc = TMD_E_HIP;
+    for (size_t i = 0; rc == TMD_OK && i < nn; i++) {
+        hipGraphNodeType t;
+        if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if (t != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp;
+        if (hipGraphKernelNodeGetParams(nodes[i], &kp) != hipSuccess) { rc = TMD_E_HIP; break; }
+        int st = -1;
+        for (int k = 0; k < kStages; k++)
+            if (kp.func == stage_kernel(k)) st = k;
+        if (st < 0 || !((P->profiling >> st) & 1u)) continue;
+        hipGraphNode_t K = nodes[i];
+        size_t np = 0, ns = 0;
+        if (hipGraphNodeGetDependencies(K, nullptr, &np) != hipSuccess ||
+            hipGraphNodeGetDependentNodes(K, nullptr, &ns) != hipSuccess) {
+            rc = TMD_E_HIP;
+            break;
+        }
+        std::vector<hipGraphNode_t> pre(np), suc(ns);
+        if ((np && hipGraphNodeGetDependencies(K, pre.data(), &np) != hipSuccess) ||
+            (ns && hipGraphNodeGetDependentNodes(K, suc.data(), &ns) != hipSuccess)) {
+            rc = TMD_E_HIP;
+            break;
+        }
+        hipEvent_t &m0 = P->prof_marks[2 * st], &m1 = P->prof_marks[2 * st + 1];
+        hipGraphNode_t &E0 = P->prof_nodes[2 * st], &E1 = P->prof_nodes[2 * st + 1];
+        if (hipEventCreateWithFlags(&m0, hipEventDisableSystemFence) != hipSuccess ||
+            hipEventCreateWithFlags(&m1, hipEventDisableSystemFence) != hipSuccess) {
+            rc = TMD_E_HIP;
+            break;
+        }
+        // pre -> E0 -> K -> E1 -> suc
+        if (hipGraphAddEventRecordNode(&E0, g, pre.data(), np, m0) != hipSuccess) { rc = TMD_E_HIP; break; }
+        for (size_t q = 0; q < np && rc == TMD_OK; q++)
+            if (hipGraphRemoveDependencies(g, &pre[q], &K, 1) != hipSuccess) rc = TMD_E_HIP;
+        if (rc == TMD_OK && hipGraphAddDependencies(g, &E0, &K, 1) != hipSuccess) rc = TMD_E_HIP;
+        if (rc == TMD_OK && hipGraphAddEventRecordNode(&E1, g, &K, 1, m1) != hipSuccess) rc = TMD_E_HIP;
+        for (size_t q = 0; q < ns && rc == TMD_OK; q++)
+            if (hipGraphRemoveDependencies(g, &K, &suc[q], 1) != hipSuccess ||
+                hipGraphAddDependencies(g, &E1, &suc[q], 1) != hipSuccess)
+                rc = TMD_E_HIP;
+    }
+    if (rc == TMD_OK && hipGraphInstantiate(&P->prof_graph, g, nullptr, nullptr, 0) != hipSuccess) {
+        P->prof_graph = nullptr;
+        rc = TMD_E_HIP;
+    }
+    if (rc != TMD_OK) {
+        drop_prof_graph(P);
+        return rc;
+    }
+    P->prof_mask = P->profiling;
     return TMD_OK;
 }
 
@@ -1817,6 +2015,7 @@ void tmd_free(tmd_plan_t *P)
             if (e) (void)hipEventDestroy(e);
     for (auto e : P->event_pool) (void)hipEventDestroy(e);
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
+    drop_prof_graph(P);
     if (P->capture) (void)hipStreamDestroy(P->capture);
     if (P->desc_done) (void)hipEventDestroy(P->desc_done);
     if (P->done) (void)hipEventDestroy(P->done);
@@ -2021,31 +2220,44 @@ int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_fr
         if (P->params.flags & TMD_PLAN_GRAPH) {
             // the kernels read only plan-owned buffers (descriptor table,
             // tables, tile map), so one captured graph serves every call
-            if (!P->graph) {
-                hipGraph_t g = nullptr;
-                if (hipStreamBeginCapture(P->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-                    rc = TMD_E_HIP;
+            if (P->profiling) {
+                // the profiling graph, its record nodes pointed at fresh events
+                if ((rc = prof_graph_ready(P)) != TMD_OK) break;
+                // fresh events for the stages whose kernels are in the graph
+                uint32_t have = 0;
+                for (int st = 0; st < kStages; st++)
+                    if (P->prof_nodes[2 * st]) have |= 1u << st;
+                std::vector<hipEvent_t> ev;
+                if ((rc = take_events(P, have, ev)) != TMD_OK) break;
+                for (int k = 0; k < 2 * kStages && rc == TMD_OK; k++)
+                    if (ev[k] && hipGraphExecEventRecordNodeSetEvent(P->prof_graph, P->prof_nodes[k], ev[k]) !=
+                                     hipSuccess)
+                        rc = TMD_E_HIP;
+                if (rc == TMD_OK && hipGraphLaunch(P->prof_graph, s) != hipSuccess) rc = TMD_E_HIP;
+                if (rc != TMD_OK) {
+                    for (hipEvent_t e : ev)
+                        if (e) P->event_pool.push_back(e);
                     break;
                 }
-                rc = launch_all(P, P->capture, 0u);
-                hipError_t ec = hipStreamEndCapture(P->capture, &g);
-                if (rc != TMD_OK || ec != hipSuccess) {
-                    if (g) (void)hipGraphDestroy(g);
-                    rc = TMD_E_HIP;
-                    break;
+                P->prof_events.push_back(ev);
+            } else {
+                if (!P->graph) {
+                    hipGraph_t g = nullptr;
+                    if ((rc = capture_graph(P, &g, &P->graph)) != TMD_OK) break;
+                    (void)hipGraphDestroy(g);
                 }
-                hipError_t ei = hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                if (ei != hipSuccess) {
-                    P->graph = nullptr;
-                    rc = TMD_E_HIP;
-                    break;
-                }
+                if (hipGraphLaunch(P->graph, s) != hipSuccess) { rc = TMD_E_HIP; break; }
             }
-            if (hipGraphLaunch(P->graph, s) != hipSuccess) { rc = TMD_E_HIP; break; }
         } else {
-            rc = launch_all(P, s, P->profiling);
-            if (rc != TMD_OK) break;
+            std::vector<hipEvent_t> ev;
+            if (P->profiling && (rc = take_events(P, P->profiling, ev)) != TMD_OK) break;
+            rc = launch_all(P, s, ev);
+            if (rc != TMD_OK) {
+                for (hipEvent_t e : ev)
+                    if (e) P->event_pool.push_back(e);
+                break;
+            }
+            if (P->profiling) P->prof_events.push_back(ev);
         }
         if (hipMemcpyAsync(P->h_status, P->d_status, sizeof(uint32_t) * P->n_frames, hipMemcpyDeviceToHost,
                            s) != hipSuccess) {

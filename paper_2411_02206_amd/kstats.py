@@ -27,7 +27,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="frame")
+    ap.add_argument("--workload", default="batched")
+    ap.add_argument("--bench-args", default="", help="more bench.py arguments, e.g. '--frames-cache DIR'")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--out", default=None)
@@ -39,7 +40,7 @@ def main():
     if os.path.isdir(args.work):
         shutil.rmtree(args.work)
     prog = [sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--workload", args.workload, "--steps",
-            str(args.steps), "--warmup", str(args.warmup), "--no-cpu", "--gen-workers", "1"]
+            str(args.steps), "--warmup", str(args.warmup), "--no-cpu", "--no-plain", "--gen-workers", "1"] + args.bench_args.split()
     cmd = [args.rocprof, "--kernel-trace", "--stats", "--output-format", "csv", "-d", args.work, "-o", "run",
            "--"] + prog
     print("[kstats] " + " ".join(cmd), flush=True)

@@ -89,7 +89,8 @@ def run_pass(rocprof, counter, outdir, prog, timeout):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--copy", type=int, default=0, help="run the copy program of MIB MiB and exit")
-    ap.add_argument("--workload", default="frame")
+    ap.add_argument("--workload", default="batched")
+    ap.add_argument("--bench-args", default="", help="more bench.py arguments, e.g. '--frames-cache DIR'")
     ap.add_argument("--out", default=None)
     ap.add_argument("--work", default=os.path.join(ROOT, "rocprof_out", "traffic"),
                     help="folder for rocprofv3's raw output")
@@ -101,7 +102,7 @@ def main():
         return
     py = sys.executable
     bench = [py, "-u", os.path.join(ROOT, "bench.py"), "--workload", args.workload, "--steps", "3",
-             "--warmup", "1", "--no-cpu", "--gen-workers", "1"]
+             "--warmup", "1", "--no-cpu", "--no-plain", "--gen-workers", "1"] + args.bench_args.split()
     copyp = [py, "-u", "-m", "paper_2411_02206_amd.traffic", "--copy", str(COPY_MIB)]
     res = {}
     for tag, prog in (("bench", bench), ("copy", copyp)):

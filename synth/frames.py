@@ -336,34 +336,39 @@ def _normal_tracks(rng, spec, n):
                 s0 = s.copy()
                 ok &= (sst[:, 0] == 0)
         ok &= np.where(crosser[todo], ncross >= 1, ncross == 0)
-        # measured clusters and their residuals against the shadow model
+        # measured clusters and their residuals against the shadow model, for
+        # the tracks the geometry accepted
         tgl = rng.uniform(-1.0, 1.0, m)
-        arc = _arc_from_origin(np.hypot(X, ym), k[:, None])
-        z_true = tgl[:, None] * (arc - arc[:, :1])
+        sec = rng.choice(sectors, m)
+        gi = np.nonzero(ok)[0]
+        rows_g, nc_g, k_g = rows[gi], nc[gi], k[gi]
+        arc = _arc_from_origin(np.hypot(X[gi], ym[gi]), k_g[:, None])
+        z_true = tgl[gi, None] * (arc - arc[:, :1])
         del arc
-        pad_m, tq_m = _measure(rng, rows, ym, z_true, nc)
+        pad_m, tq_m = _measure(rng, rows_g, ym[gi], z_true, nc_g)
         del z_true, ym
         hpad = pad_m[:, 0]
-        hsnp = np.clip(np.rint(s0 * 32768.0), -32767, 32767)
-        hqpt = np.clip(np.rint(q / pt * 1024.0), -32768, 32767)
-        htgl = np.clip(np.rint(tgl * 4096.0), -32768, 32767)
-        pr, tr, sh_ok = _shadow_residuals(rows, sst, pad_m, tq_m, nc, hpad, hsnp, htgl, hqpt, spec.bz)
-        ok &= sh_ok
-        live = jj < nc[:, None]
-        good = todo[ok]
-        sec = rng.choice(sectors, m)
-        out["sec0"][good] = sec[ok]
-        out["row0"][good] = row0[ok]
-        out["pad0"][good] = hpad[ok]
-        out["snp"][good] = hsnp[ok]
-        out["qpt"][good] = hqpt[ok]
-        out["tgl"][good] = htgl[ok]
-        out["tq_lo"][good] = np.where(live, tq_m, 0).min(axis=1)[ok]
-        out["tq_hi"][good] = np.where(live, tq_m, 0).max(axis=1)[ok]
-        steps[good] = st[ok]
-        secstep[good] = sst[ok]
-        pres[good] = pr[ok]
-        tres[good] = tr[ok]
+        hsnp = np.clip(np.rint(s0[gi] * 32768.0), -32767, 32767)
+        hqpt = np.clip(np.rint((q / pt)[gi] * 1024.0), -32768, 32767)
+        htgl = np.clip(np.rint(tgl[gi] * 4096.0), -32768, 32767)
+        pr, tr, sh_ok = _shadow_residuals(rows_g, sst[gi], pad_m, tq_m, nc_g, hpad, hsnp, htgl, hqpt, spec.bz)
+        live = jj < nc_g[:, None]
+        sel = gi[sh_ok]          # candidates accepted by both
+        ok[:] = False
+        ok[sel] = True
+        good = todo[sel]
+        out["sec0"][good] = sec[sel]
+        out["row0"][good] = row0[sel]
+        out["pad0"][good] = hpad[sh_ok]
+        out["snp"][good] = hsnp[sh_ok]
+        out["qpt"][good] = hqpt[sh_ok]
+        out["tgl"][good] = htgl[sh_ok]
+        out["tq_lo"][good] = np.where(live, tq_m, 0).min(axis=1)[sh_ok]
+        out["tq_hi"][good] = np.where(live, tq_m, 0).max(axis=1)[sh_ok]
+        steps[good] = st[sel]
+        secstep[good] = sst[sel]
+        pres[good] = pr[sh_ok]
+        tres[good] = tr[sh_ok]
         del pad_m, tq_m, pr, tr, live
         todo = todo[~ok]
     if todo.size:
@@ -647,24 +652,11 @@ def _attached_chunk(args):
     return fr
 
 
-def make_frame(spec: FrameSpec, workers: int = 1) -> dict:
-    """Draw one compressed frame (dict of numpy arrays, see FIELDS).  With
-    workers > 1 the chunks of collisions are generated in forked worker
-    processes (call this before the process uses a GPU)."""
-    chunks = [(spec, c, n, t) for c, n, t in _chunks(spec)]
-    if workers > 1 and len(chunks) > 1:
-        import multiprocessing as mp
-        with mp.get_context("fork").Pool(min(workers, len(chunks))) as pool:
-            parts = pool.map(_attached_chunk, chunks, chunksize=1)
-    else:
-        parts = [_attached_chunk(c) for c in chunks]
-    fr = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
-    del parts
-    nA = int(fr["cls_qtot"].shape[0])
+def _unattached(args):
+    """Unattached-cluster streams of a frame with nA attached clusters."""
+    spec, nA = args
     rng = np.random.default_rng([spec.seed, spec.frame_index, 1 << 20, 104729])
     span_bins = 100.0 * max(spec.collisions, 1)
-
-    # --- unattached clusters ---
     nU = spec.n_unattached if spec.n_unattached >= 0 else int(round(nA * spec.unattached_ratio))
     sectors = np.asarray(spec.sectors)
     u_sec = rng.choice(sectors, nU)
@@ -680,7 +672,7 @@ def make_frame(spec: FrameSpec, workers: int = 1) -> dict:
     # time: a sorted uniform sample over the frame's span has exponential gaps
     t_span = (span_bins + 785.0) * 32.0
     gap_mean = t_span / np.maximum(count[u_bin], 1)
-    fr["un_count"] = count
+    fr = {"un_count": count}
     fr["un_time_diff"] = np.minimum(np.floor(rng.exponential(1.0, nU) * gap_mean),
                                     2**32 - 1).astype(np.uint32)
     # pad: independent uniform positions along the row, stored as differences
@@ -692,6 +684,47 @@ def make_frame(spec: FrameSpec, workers: int = 1) -> dict:
     fr["un_pad_diff"] = ((pads - prev) & 0xFFFF).astype(np.uint16)
     fr["un_qmax"], fr["un_qtot"] = _charges(rng, nU)
     return fr
+
+
+def make_frames(specs, workers: int = 1) -> list:
+    """Draw several frames (see make_frame).  With workers > 1 every chunk of
+    collisions of every frame, then every frame's unattached clusters, is a
+    task for a pool of forked worker processes (call this before the process
+    uses a GPU).  The result does not depend on `workers`."""
+    tasks = [(i, (spec, c, n, t)) for i, spec in enumerate(specs) for c, n, t in _chunks(spec)]
+    pool = None
+    if workers > 1 and len(tasks) > 1:
+        import multiprocessing as mp
+        pool = mp.get_context("fork").Pool(min(workers, len(tasks)))
+    try:
+        # largest chunks first, so that the pool's last tasks are short ones
+        order = sorted(range(len(tasks)), key=lambda q: -tasks[q][1][3])
+        args = [tasks[q][1] for q in order]
+        res = pool.map(_attached_chunk, args, chunksize=1) if pool else [_attached_chunk(a) for a in args]
+        parts = [[] for _ in specs]
+        for q, r in sorted(zip(order, res), key=lambda z: z[0]):
+            parts[tasks[q][0]].append(r)
+        del res
+        frames = []
+        for p in parts:
+            frames.append({k: np.concatenate([c[k] for c in p]) for k in p[0]})
+            p.clear()
+        uargs = [(spec, int(fr["cls_qtot"].shape[0])) for spec, fr in zip(specs, frames)]
+        un = pool.map(_unattached, uargs, chunksize=1) if pool else [_unattached(a) for a in uargs]
+    finally:
+        if pool:
+            pool.close()
+            pool.join()
+    for fr, u in zip(frames, un):
+        fr.update(u)
+    return frames
+
+
+def make_frame(spec: FrameSpec, workers: int = 1) -> dict:
+    """Draw one compressed frame (dict of numpy arrays, see FIELDS).  With
+    workers > 1 the chunks of collisions are generated in forked worker
+    processes (call this before the process uses a GPU)."""
+    return make_frames([spec], workers)[0]
 
 
 def _charges(rng, n):
