@@ -273,6 +273,84 @@ int tmd_pipe_run(tmd_pipe_t *pipe, uint32_t n_frames, const tmd_frame_shape *sha
 /* Release a pipeline (waits for its streams). NULL is a no-op. */
 void tmd_pipe_free(tmd_pipe_t *pipe);
 
+/*
+ * Defines: the compression that section 4's decode inverts: attached clusters
+ * stored as residuals to their track's extrapolation, unattached clusters
+ * sorted by position within their region and stored as differences to the
+ * previous one.  The paper describes it only in words; this is this project's
+ * encoder for its track model, the inverse of tmd_decode.
+ *
+ * Physical clusters (DEVICE pointers, read only): n_tracks tracks, track t
+ * owning clusters [trk_first[t], trk_first[t + 1]) (trk_first[0] = 0,
+ * trk_first[n_tracks] = n_clusters, non-decreasing), in the order they were
+ * measured; trk_qpt = q/pT (c/GeV) and trk_tgl = tan(lambda) per track;
+ * per cluster: sector (0..35), row (0..151), pad (in pads, 0 at the -y edge)
+ * and time (in time bins) as doubles, the local sin(phi) of the track there
+ * (used where a header is written), and the two charges.  Unattached
+ * clusters: sector, row, pad, time, charges.
+ */
+typedef struct {
+    uint32_t n_tracks, n_clusters, n_unattached;
+    const uint32_t *trk_first;
+    const double *trk_qpt, *trk_tgl;
+    const uint8_t *cl_sec, *cl_row;
+    const double *cl_pad, *cl_time, *cl_snp;
+    const uint16_t *cl_qtot, *cl_qmax;
+    const uint8_t *un_sec, *un_row;
+    const double *un_pad, *un_time;
+    const uint16_t *un_qtot, *un_qmax;
+} tmd_enc_in;
+
+/*
+ * The compressed frame (DEVICE pointers, written), laid out as tmd_frame_in:
+ * header arrays need n_clusters entries (a track splits into several headers
+ * where the model cannot follow it), cluster arrays n_clusters (cluster i of
+ * the input is cluster i of the output), unattached arrays n_unattached (in
+ * bin order, sorted inside a bin by time, pad, qTot, qMax), un_count
+ * TMD_NBIN.  counts: 3 device words written by the call: [0] headers
+ * written (the frame's n_tracks), [1] headers opened inside a track, [2]
+ * nonzero if an input was outside the codable range (pad beyond [0, 65535] or
+ * time beyond [0, 2^24) in 1/32 units for attached clusters, [0, 2^32) for
+ * unattached ones, a bin outside the detector, or a bad trk_first); the frame
+ * is then not defined.
+ */
+typedef struct {
+    uint8_t *trk_ncls, *trk_sec0, *trk_row0;
+    uint16_t *trk_pad0;
+    uint32_t *trk_time0;
+    int16_t *trk_qpt, *trk_snp, *trk_tgl;
+    int8_t *cls_row_diff;
+    uint8_t *cls_sec_diff;
+    int16_t *cls_pad_res, *cls_time_res;
+    uint16_t *cls_qtot, *cls_qmax;
+    uint32_t *un_count;
+    uint32_t *un_time_diff;
+    uint16_t *un_pad_diff, *un_qtot, *un_qmax;
+    uint32_t *counts;
+} tmd_enc_out;
+
+/*
+ * Bytes of device workspace tmd_encode needs for these sizes (256-byte
+ * aligned, caller-allocated, contents need not be initialised).
+ * Errors: TMD_E_ARG (null pointer).
+ */
+int tmd_encode_workspace(uint32_t n_tracks, uint32_t n_clusters, uint32_t n_unattached, size_t *bytes);
+
+/*
+ * Enqueue the encode on `stream`, with the float32 track model of the plan's
+ * field (the plan's frame shapes do not matter).  Per track, every cluster is
+ * quantised (rint of 32 x pad and 32 x time), the model predicts it from the
+ * previous one and the residuals are stored; a new header is opened at the
+ * first cluster, and wherever the row step leaves int8, the side changes, a
+ * header already has 255 clusters, the prediction clamps or flags anything,
+ * the cluster is not where the model puts it, or a residual leaves int16.
+ * tmd_decode of the result restores the quantised clusters exactly.
+ * Errors: TMD_E_ARG (null or misaligned pointer), TMD_E_CAPACITY (workspace
+ * too small), TMD_E_HIP; data problems are reported in out->counts[2].
+ */
+int tmd_encode(tmd_plan_t *plan, const tmd_enc_in *in, tmd_enc_out *out, void *workspace, size_t workspace_bytes,
+               void *stream);
+
 /* Static message for a return code. */
 const char *tmd_strerror(int code);
 
@@ -286,6 +364,24 @@ const char *tmd_version(void);
  * -(count needed) if cap is too small.
  */
 int tmd_tables(float bz, float *dst, int cap);
+
+/*
+ * Defines: the work split of the first kernel of section 4 (one thread per
+ * track), which the paper does not tune further; these are this library's
+ * scheduling knobs, picked per device and frame mix by the autotuner
+ * (paper_2411_02206_amd/autotune.py).  Results never depend on them.
+ *
+ * Scheduling of the attached decode for later calls on the plan.
+ * tracks_per_wave (64..128; 0 = 64): tracks a wave takes; above 64, the
+ * tracks that start last are each decoded after a track that ends earlier, in
+ * the same lane (length bucketing of tracks across the lanes).
+ * persist_waves_per_simd (0..64; 0 = off): instead of one workgroup per wave
+ * of work, launch a persistent grid of that many waves per SIMD which pull the
+ * waves of work from per-XCD counters.  Waits for the plan's last call; a
+ * TMD_PLAN_GRAPH plan captures its graph again at the next call.
+ * Errors: TMD_E_ARG (null plan, a value out of range), TMD_E_HIP.
+ */
+int tmd_set_schedule(tmd_plan_t *plan, uint32_t tracks_per_wave, uint32_t persist_waves_per_simd);
 
 /*
  * Stage timing.  tmd_set_profiling selects stages by bit (bit i = stage i as

@@ -18,7 +18,7 @@ from ._lib import (E_ARG, E_CAPACITY, E_HIP, E_INPUT, E_SCRATCH, E_STREAM, F_COU
                    F_ROT, F_ROW, F_SEC, F_SNP, F_TIME, IN_FIELDS, NBIN, NROW, NSEC, OK, OUT_FIELDS, PLAN_GRAPH,
                    STATIC_SCRATCH_BYTES, TmdError)
 
-__all__ = ["Plan", "Pipeline", "decode", "to_device", "to_host", "alloc_out", "alloc_host_out", "to_numpy",
+__all__ = ["Plan", "Pipeline", "decode", "encode", "to_device", "to_host", "alloc_out", "alloc_host_out", "to_numpy",
            "version", "tables"]
 
 # element types of the frame arrays; unsigned 16/32-bit data travel in signed
@@ -196,6 +196,13 @@ class Plan:
             _lib.check(rc, "tmd_status")
         return int(f.value)
 
+    def set_schedule(self, tracks_per_wave=64, persist=0):
+        """Scheduling knobs of the attached decode (tmd_set_schedule): tracks
+        per wave (64..128) and persistent waves per SIMD (0: off).  Results
+        do not depend on them."""
+        _lib.check(_lib.lib().tmd_set_schedule(self._h, int(tracks_per_wave), int(persist)), "tmd_set_schedule")
+        self.schedule = (int(tracks_per_wave), int(persist))
+
     def set_profiling(self, on=True, stages=None):
         """Record events around every stage (on=True), none (False), or the
         named stages only (stages: iterable of stage names)."""
@@ -217,6 +224,73 @@ class Plan:
         if n < 0:
             _lib.check(n, "tmd_stage_times")
         return {L.tmd_stage_name(i).decode(): buf[i] for i in range(n)}, int(calls.value)
+
+
+ENC_DTYPES = {"trk_first": np.uint32, "trk_qpt": np.float64, "trk_tgl": np.float64, "cl_sec": np.uint8,
+              "cl_row": np.uint8, "cl_pad": np.float64, "cl_time": np.float64, "cl_snp": np.float64,
+              "cl_qtot": np.uint16, "cl_qmax": np.uint16, "un_sec": np.uint8, "un_row": np.uint8,
+              "un_pad": np.float64, "un_time": np.float64, "un_qtot": np.uint16, "un_qmax": np.uint16}
+
+
+def encode(phys, bz=0.5, device="cuda", stream=None, plan=None):
+    """Encode physical clusters (dict of arrays, keys as ENC_DTYPES: tracks
+    by trk_first ranges, pads and times as doubles) on the GPU into a
+    compressed frame (tmd_encode).  Returns (frame dict of numpy arrays, number
+    of headers opened inside a track).  Raises TmdError on an input outside
+    the codable range."""
+    torch = _torch()
+    L = _lib.lib()
+    dev = {}
+    for k, dt in ENC_DTYPES.items():
+        a = np.ascontiguousarray(phys[k], dtype=dt)
+        if a.dtype == np.float64:
+            dev[k] = torch.from_numpy(a).to(device)
+        else:
+            dev[k] = torch.from_numpy(a.view(_SIGNED[a.dtype])).to(device)
+    nt = int(dev["trk_qpt"].numel())
+    n = int(dev["cl_pad"].numel())
+    nu = int(dev["un_pad"].numel())
+    ein = _lib.EncIn(nt, n, nu)
+    for k in _lib.ENC_IN_TRACK + _lib.ENC_IN_CLUSTER + _lib.ENC_IN_UNATT:
+        setattr(ein, k, _ptr(dev[k]))
+    sizes = {"trk": max(n, 1), "cls": max(n, 1), "un": max(nu, 1)}
+    out = {}
+    for k in IN_FIELDS:
+        dt = _SIGNED[np.dtype(IN_DTYPES[k])]
+        cnt = NBIN if k == "un_count" else sizes[k.split("_")[0]]
+        out[k] = torch.empty(cnt, dtype=getattr(torch, np.dtype(dt).name), device=device)
+    counts = torch.zeros(4, dtype=torch.int32, device=device)
+    eout = _lib.EncOut()
+    for k in IN_FIELDS:
+        setattr(eout, k, _ptr(out[k]))
+    eout.counts = _ptr(counts)
+    wsb = C.c_size_t()
+    _lib.check(L.tmd_encode_workspace(nt, n, nu, C.byref(wsb)), "tmd_encode_workspace")
+    ws = torch.empty(max(int(wsb.value), 256), dtype=torch.uint8, device=device)
+    own = plan is None
+    if own:
+        plan = Plan([(1, 1, 1)], bz=bz)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _lib.check(L.tmd_encode(plan._h, C.byref(ein), C.byref(eout), _ptr(ws), int(wsb.value),
+                            C.c_void_p(stream.cuda_stream)), "tmd_encode")
+    stream.synchronize()
+    c = counts.cpu().numpy().view(np.uint32)
+    if c[2]:
+        raise TmdError(E_INPUT, "tmd_encode: input outside the codable range")
+    res = {}
+    for k in IN_FIELDS:
+        a = out[k].cpu().numpy().view(IN_DTYPES[k])
+        if k.startswith("trk_"):
+            a = a[:int(c[0])]
+        elif k.startswith("cls_"):
+            a = a[:n]
+        elif k != "un_count":
+            a = a[:nu]
+        res[k] = a.copy()
+    if own:
+        plan.free()
+    return res, int(c[1])
 
 
 def to_host(frame, pin=True):

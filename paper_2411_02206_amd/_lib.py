@@ -39,6 +39,20 @@ class FrameOut(C.Structure):
     _fields_ = [(n, P) for n in OUT_FIELDS] + [("capacity", C.c_uint64)]
 
 
+ENC_IN_TRACK = ["trk_first", "trk_qpt", "trk_tgl"]
+ENC_IN_CLUSTER = ["cl_sec", "cl_row", "cl_pad", "cl_time", "cl_snp", "cl_qtot", "cl_qmax"]
+ENC_IN_UNATT = ["un_sec", "un_row", "un_pad", "un_time", "un_qtot", "un_qmax"]
+
+
+class EncIn(C.Structure):
+    _fields_ = [("n_tracks", C.c_uint32), ("n_clusters", C.c_uint32), ("n_unattached", C.c_uint32)] + \
+        [(n, P) for n in ENC_IN_TRACK + ENC_IN_CLUSTER + ENC_IN_UNATT]
+
+
+class EncOut(C.Structure):
+    _fields_ = [(n, P) for n in IN_FIELDS] + [("counts", P)]
+
+
 class Params(C.Structure):
     _fields_ = [("bz_tesla", C.c_float), ("flags", C.c_uint32)]
 
@@ -73,6 +87,8 @@ def lib():
         L.tmd_version.restype = C.c_char_p
         L.tmd_tables.argtypes = [C.c_float, C.POINTER(C.c_float), C.c_int]
         L.tmd_tables.restype = C.c_int
+        L.tmd_set_schedule.argtypes = [P, C.c_uint32, C.c_uint32]
+        L.tmd_set_schedule.restype = C.c_int
         L.tmd_set_profiling.argtypes = [P, C.c_uint32]
         L.tmd_set_profiling.restype = C.c_int
         L.tmd_stage_times.argtypes = [P, C.POINTER(C.c_double), C.c_uint32, C.POINTER(C.c_uint32)]
@@ -85,6 +101,10 @@ def lib():
         L.tmd_selftest_math.restype = C.c_int
         L.tmd_selftest_sqrt.argtypes = [C.c_uint32, C.c_uint32, P, P]
         L.tmd_selftest_sqrt.restype = C.c_int
+        L.tmd_encode_workspace.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_size_t)]
+        L.tmd_encode_workspace.restype = C.c_int
+        L.tmd_encode.argtypes = [P, C.POINTER(EncIn), C.POINTER(EncOut), P, C.c_size_t, P]
+        L.tmd_encode.restype = C.c_int
         L.tmd_pipe_create.argtypes = [C.POINTER(FrameShape), C.c_uint32, C.POINTER(Params), C.POINTER(P)]
         L.tmd_pipe_create.restype = C.c_int
         L.tmd_pipe_run.argtypes = [P, C.c_uint32, C.POINTER(FrameShape), C.POINTER(FrameIn), C.POINTER(FrameOut),

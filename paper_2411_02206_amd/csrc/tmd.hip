@@ -316,10 +316,13 @@ __device__ __forceinline__ void step_pos(int &sec, int &row, int rd, uint32_t sd
 // word of each frame)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTile) void k_tilesum(const FrameDesc *__restrict__ fd,
-                                                   const uint32_t *__restrict__ tile_frame, uint32_t ntiles)
+                                                   const uint32_t *__restrict__ tile_frame, uint32_t ntiles,
+                                                   uint32_t *__restrict__ work)
 {
     if (blockIdx.x >= ntiles) {  // one extra block per frame: clear its status word
         if (threadIdx.x == 0) *fd[blockIdx.x - ntiles].status = 0u;
+        // (and the first one the attached decode's work counters, if used)
+        if (work && blockIdx.x == ntiles && threadIdx.x < kXcds) work[threadIdx.x] = 0u;
         return;
     }
     const uint32_t tile = blockIdx.x;
@@ -1477,134 +1480,128 @@ __device__ __forceinline__ void track_init(const FrameDesc &F, const Geo *__rest
     I.k = ((float)F.qpt[t] * 0x1p-10f) * geo->kb;
 }
 
-// lane `src`'s TrackInit, in every lane
-__device__ __forceinline__ TrackInit track_init_from(const TrackInit &I, uint32_t src)
+// The TrackInit of window item `src` (0..127), held by lane src in A (items
+// 0..63) or by lane src - 64 in B (items 64..127); src may differ per lane.
+__device__ __forceinline__ TrackInit track_init_pull(const TrackInit &A, const TrackInit &B, uint32_t src)
 {
+    const uint32_t l = src & 63u;
+    const bool hi = src >= (uint32_t)kWave;
+    auto pick = [&](uint32_t a, uint32_t b) -> uint32_t {
+        const uint32_t va = bperm(a, l), vb = bperm(b, l);
+        return hi ? vb : va;
+    };
+    auto pickf = [&](float a, float b) -> float { return __uint_as_float(pick(__float_as_uint(a), __float_as_uint(b))); };
     TrackInit R;
-    R.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(I.x), (int)src));
-    R.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(I.y), (int)src));
-    R.s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(I.s), (int)src));
-    R.tgl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(I.tgl), (int)src));
-    R.k = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(I.k), (int)src));
-    R.t0 = __builtin_amdgcn_readlane(I.t0, (int)src);
-    R.pad0 = readlane(I.pad0, (int)src);
-    R.fl = readlane(I.fl, (int)src);
-    R.n = readlane(I.n, (int)src);
-    R.c0 = readlane(I.c0, (int)src);
-    R.cls = readlane(I.cls, (int)src);
-    R.row = readlane(I.row, (int)src);
+    R.x = pickf(A.x, B.x);
+    R.y = pickf(A.y, B.y);
+    R.s = pickf(A.s, B.s);
+    R.tgl = pickf(A.tgl, B.tgl);
+    R.k = pickf(A.k, B.k);
+    R.t0 = (int32_t)pick((uint32_t)A.t0, (uint32_t)B.t0);
+    R.pad0 = pick(A.pad0, B.pad0);
+    R.fl = pick(A.fl, B.fl);
+    R.n = pick(A.n, B.n);
+    R.c0 = pick(A.c0, B.c0);
+    R.cls = pick(A.cls, B.cls);
+    R.row = pick(A.row, B.row);
     return R;
 }
 
-// Waves: a frame's decode uses F.awaves waves; wave fw takes the tracks at
-// schedule positions [fw nT / awaves, (fw + 1) nT / awaves).  Normally that is
-// at most 64 (awaves = ceil(nT / 64)).  When ceil(nT / 64) is just above a
-// multiple of the number of SIMDs, the host picks that multiple instead (every
-// SIMD then runs the same number of decode waves, where a few would run one
-// more): a wave then has up to 66 tracks, and one or two of them are decoded
-// each after another track of the wave.  Those are the tracks that start last
-// (in the wave's row order; the shortest ones if its rows are mixed), and each
-// follows the track that ends first, so that the lane's rows stay in step with
-// the wave's.  A single-frame call uses the first awaves workgroups, dealt
-// evenly to the XCDs.
-__global__ __launch_bounds__(kAttWaves * kWave) void k_attached(const FrameDesc *__restrict__ fd,
-                                                               const uint32_t *__restrict__ tile_frame,
-                                                               const Geo *__restrict__ geo, uint32_t single)
+// Tracks per attached-decode wave: up to two per lane.
+constexpr uint32_t kMaxWaveTracks = 2 * kWave;
+
+// Lane assignment of one wave.  The wave takes the tracks at schedule
+// positions [b0, b1) of its frame (at most 128).  With more than 64 of them,
+// the nx = (b1 - b0) - 64 tracks that start last (in the wave's row order)
+// are each decoded after another track of the wave, in the same lane: the
+// k-th earliest-starting of them follows the track with the k-th earliest
+// end.  Matched this way, a lane's second track starts after its first one
+// ends whenever any assignment allows it, so the lane's rows stay in step
+// with the wave's (the decode stays correct in any case: a lane's clusters
+// are always decoded in order).  Packing tracks of different lengths and
+// start rows into the lanes this way raises the lanes' use per wave step.
+// `S` is LDS scratch of 320 words.
+__device__ __forceinline__ void wave_lanes(const FrameDesc &F, const Geo *__restrict__ geo, uint32_t b0,
+                                           uint32_t b1, uint32_t *S, int &mode, LaneTrack &T)
 {
-    static_assert(kAttWaves == 1, "one wave per workgroup: the wave index is the workgroup index");
-    // LDS holds only the record rings and staging (10 KB per wave); the
-    // tables stay in global memory.  One-wave workgroups: the grid's waves
-    // are all resident at once, and small workgroups let the dispatcher spread
-    // them evenly over the CUs.
-    __shared__ uint2 ra[kRing][kWave];  // record rings: (output slot, charges)
-    __shared__ uint2 rb[kRing][kWave];  // (residuals, row | rotation << 8)
-    __shared__ uint2 stg[kBlk][kWave];  // per step of the block: the decoded (time, pad)
-    const uint32_t W1 = single ? fd[0].awaves : 0u;
-    if (single && blockIdx.x >= W1) return;
-    const uint32_t gw = single ? xcd_tile(blockIdx.x, W1) : xcd_tile(blockIdx.x, gridDim.x);
-    const FrameDesc F = fd[single ? 0u : tile_frame[gw / kTileWaves]];
-    const uint32_t fw = gw - F.tile0 * kTileWaves;  // wave of the frame
-    if (fw >= F.awaves) return;  // beyond this call's frame (capacity plans)
     const uint32_t lane = lane_id();
-    const uint32_t b0 = (uint32_t)((uint64_t)fw * F.nT / F.awaves);
-    const uint32_t b1 = (uint32_t)((uint64_t)(fw + 1) * F.nT / F.awaves);
-    TrackInit I = {};
-    const bool own = b0 + lane < b1;
-    if (own) track_init(F, geo, F.order[b0 + lane], I);
-    // tracks beyond the 64th (at most two; wave-uniform)
-    const uint32_t nx = b1 - b0 > (uint32_t)kWave ? min(b1 - b0 - (uint32_t)kWave, 2u) : 0u;
-    TrackInit X[2] = {};
-    bool live_x = false, x0 = true, x1 = true;
-#pragma unroll
-    for (uint32_t e = 0; e < 2; e++) {
-        if (e >= nx) break;
-        track_init(F, geo, F.order[b0 + kWave + e], X[e]);
-        if (X[e].n > 0) {
-            live_x = true;
-            x0 = x0 && X[e].cls == 0;
-            x1 = x1 && X[e].cls == 1;
-        }
-    }
+    const uint32_t nt = b1 - b0;
+    TrackInit I = {}, J = {};
+    if (lane < nt) track_init(F, geo, F.order[b0 + lane], I);
+    if (kWave + lane < nt) track_init(F, geo, F.order[b0 + kWave + lane], J);
     // wave mode: 0 rows ascending, 1 rows descending, 2 one cluster per step
-    const uint64_t any_live = __ballot(I.n > 0);
-    const uint64_t asc = __ballot(I.n > 0 && I.cls == 0);
-    const uint64_t dsc = __ballot(I.n > 0 && I.cls == 1);
-    const int mode = (asc == any_live && (!live_x || x0)) ? 0 : ((dsc == any_live && (!live_x || x1)) ? 1 : 2);
-    LaneTrack T = {};
-    if (nx > 0) {
-        // the tracks decoded second: those that start last (largest start key)
-        auto start_key = [&](const TrackInit &J) -> uint32_t {
-            if (J.n == 0) return 0u;
-            return mode == 0 ? J.row + 1u : (mode == 1 ? 256u - J.row : 256u - J.n);
+    {
+        const bool not_asc = (I.n > 0 && I.cls != 0) || (J.n > 0 && J.cls != 0);
+        const bool not_dsc = (I.n > 0 && I.cls != 1) || (J.n > 0 && J.cls != 1);
+        mode = __ballot(not_asc) == 0 ? 0 : (__ballot(not_dsc) == 0 ? 1 : 2);
+    }
+    if (nt > (uint32_t)kWave) {
+        const uint32_t nx = nt - (uint32_t)kWave;
+        // start keys (larger: later in the wave's order), made distinct by the
+        // item index; rank 0 = the latest start
+        auto start_key = [&](const TrackInit &X) -> uint32_t {
+            if (X.n == 0) return 0u;
+            return mode == 0 ? X.row + 1u : (mode == 1 ? 256u - X.row : 256u - min(X.n, 255u));
         };
-#pragma unroll
-        for (uint32_t e = 0; e < 2; e++) {
-            if (e >= nx) break;
-            const uint32_t best = wave_max_u32(own ? (start_key(I) << 6) | lane : 0u);
-            const uint32_t src = best & 63u;
-            if ((best >> 6) > start_key(X[e])) {  // swap with lane src's track
-                const TrackInit Y = track_init_from(I, src);
-                if (lane == src) I = X[e];
-                X[e] = Y;
-            }
+        const uint32_t kI = (start_key(I) << 8) | lane, kJ = (start_key(J) << 8) | (kWave + lane);
+        uint32_t *key = S, *ek = S + kMaxWaveTracks, *base_src = ek + kWave, *extra_src = base_src + kWave;
+        key[lane] = kI;
+        key[kWave + lane] = kJ;
+        __syncthreads();
+        uint32_t rI = 0, rJ = 0;
+        for (uint32_t q = 0; q < nt; q++) {
+            const uint32_t v = key[q];
+            rI += v > kI ? 1u : 0u;
+            rJ += v > kJ ? 1u : 0u;
         }
-        // each follows the track that ends first (smallest end key; lanes
-        // without records first)
+        // base tracks (rank >= nx) go to lanes 0..63 in rank order; extras
+        // (rank < nx) are listed by ascending start (nx - 1 - rank)
+        if (lane < nt) {
+            if (rI >= nx) base_src[rI - nx] = lane;
+            else extra_src[nx - 1 - rI] = lane;
+        }
+        if (kWave + lane < nt) {
+            if (rJ >= nx) base_src[rJ - nx] = kWave + lane;
+            else extra_src[nx - 1 - rJ] = kWave + lane;
+        }
+        __syncthreads();
+        const TrackInit B = track_init_pull(I, J, base_src[lane]);
+        // end keys of the base tracks; lanes ranked by (end, lane)
         uint32_t end_key = 0;
-        if (I.n > 0) {
+        if (B.n > 0) {
             if (mode == 2) {
-                end_key = I.n;
+                end_key = B.n;
             } else {
-                const uint32_t lr = F.recs[I.c0 + I.n - 1].w & 0xFFu;  // row of the last cluster
+                const uint32_t lr = F.recs[B.c0 + B.n - 1].w & 0xFFu;  // row of the last cluster
                 end_key = mode == 0 ? lr + 1u : 256u - lr;
             }
         }
-        bool taken = false;
-#pragma unroll
-        for (uint32_t e = 0; e < 2; e++) {
-            if (e >= nx) break;
-            const uint32_t pick = wave_min(taken ? 0xFFFFFFFFu : ((end_key << 6) | lane)) & 63u;
-            if (lane == pick) {
-                taken = true;
-                const TrackInit &J = X[e];
-                if (I.n == 0) {  // a lane without records: the track becomes its own
-                    const uint32_t fl0 = I.fl;
-                    I = J;
-                    I.fl |= fl0;
-                } else {
-                    T.fl |= J.fl;
-                    if (J.n > 0) {
-                        T.nA = I.n;
-                        T.c0B = J.c0;
-                        T.n = J.n;  // (added below)
-                        T.xB = J.x;
-                        T.yB = J.y;
-                        T.sB = J.s;
-                        T.tglB = J.tgl;
-                        T.kB = J.k;
-                        T.t0B = J.t0;
-                        T.pad0B = J.pad0;
-                    }
+        const uint32_t eI = (end_key << 8) | lane;
+        ek[lane] = eI;
+        __syncthreads();
+        uint32_t er = 0;
+        for (uint32_t q = 0; q < (uint32_t)kWave; q++) er += ek[q] < eI ? 1u : 0u;
+        const TrackInit X = track_init_pull(I, J, er < nx ? extra_src[er] : 0u);
+        __syncthreads();  // the scratch is reused by the decode loop
+        I = B;
+        if (er < nx) {
+            if (I.n == 0) {  // a lane without records: the track becomes its own
+                const uint32_t fl0 = I.fl;
+                I = X;
+                I.fl |= fl0;
+            } else {
+                T.fl |= X.fl;
+                if (X.n > 0) {
+                    T.nA = I.n;
+                    T.c0B = X.c0;
+                    T.n = X.n;  // (added below)
+                    T.xB = X.x;
+                    T.yB = X.y;
+                    T.sB = X.s;
+                    T.tglB = X.tgl;
+                    T.kB = X.k;
+                    T.t0B = X.t0;
+                    T.pad0B = X.pad0;
                 }
             }
         }
@@ -1624,11 +1621,67 @@ __global__ __launch_bounds__(kAttWaves * kWave) void k_attached(const FrameDesc 
         T.n = I.n;
         T.nA = I.n;
     }
-    if (mode == 0) attached_loop<0>(F, geo, ra, rb, stg, T);
-    else if (mode == 1) attached_loop<1>(F, geo, ra, rb, stg, T);
-    else attached_loop<2>(F, geo, ra, rb, stg, T);
-    const uint32_t fl = wave_or(T.fl);
-    if (lane == 0 && fl) atomicOr(F.status, fl);
+}
+
+// Waves: a frame's decode uses F.awaves waves; wave fw takes the tracks at
+// schedule positions [fw nT / awaves, (fw + 1) nT / awaves), at most 128 (see
+// wave_lanes).  The plan chooses awaves from its tracks-per-wave setting and,
+// for a single frame, balances the count over the device's SIMDs.  The grid
+// has 4 wave slots per 256-track tile of each frame's planned capacity; slot
+// fw of frame f is fw = gw - 4 tile0(f), and slots at or beyond the call's
+// awaves return at once.  Slots are dealt to the XCDs in contiguous ranges.
+// Persistent mode (work != null): the grid is smaller than the slot count and
+// each workgroup takes slot after slot of its XCD's range from that XCD's
+// counter in `work` (cleared by the tile-sum kernel of the same call) until
+// the range is used up.
+__global__ __launch_bounds__(kAttWaves * kWave) void k_attached(const FrameDesc *__restrict__ fd,
+                                                               const uint32_t *__restrict__ tile_frame,
+                                                               const Geo *__restrict__ geo, uint32_t single,
+                                                               uint32_t *__restrict__ work, uint32_t slots)
+{
+    static_assert(kAttWaves == 1, "one wave per workgroup: the wave index is the workgroup index");
+    // LDS holds only the record rings and staging (10 KB per wave); the
+    // tables stay in global memory.  One-wave workgroups: the grid's waves
+    // are all resident at once, and small workgroups let the dispatcher spread
+    // them evenly over the CUs.
+    __shared__ uint2 ra[kRing][kWave];  // record rings: (output slot, charges)
+    __shared__ uint2 rb[kRing][kWave];  // (residuals, row | rotation << 8)
+    __shared__ uint2 stg[kBlk][kWave];  // per step of the block: the decoded (time, pad)
+    static_assert(sizeof(stg) >= 320 * sizeof(uint32_t), "lane-assignment scratch lives in the staging area");
+    const uint32_t lane = lane_id();
+    const uint32_t S = single ? fd[0].awaves : slots;  // wave slots in use
+    const uint32_t x = blockIdx.x % kXcds;
+    const uint32_t per = S / kXcds, extra = S % kXcds;
+    const uint32_t first = x * per + (x < extra ? x : extra), count = per + (x < extra ? 1u : 0u);
+    for (uint32_t it = blockIdx.x / kXcds;; ) {
+        uint32_t gw;
+        if (work) {  // persistent: the next slot of this XCD's range
+            uint32_t i = 0;
+            if (lane == 0) i = atomicAdd(&work[x], 1u);
+            i = __builtin_amdgcn_readfirstlane(i);
+            if (i >= count) break;
+            gw = first + i;
+        } else {  // one slot per workgroup
+            if (it >= count) break;
+            gw = first + it;
+        }
+        const FrameDesc F = fd[single ? 0u : tile_frame[gw / kTileWaves]];
+        const uint32_t fw = gw - F.tile0 * kTileWaves;  // wave of the frame
+        if (fw < F.awaves) {  // (slots beyond this call's frame: nothing to do)
+            const uint32_t b0 = (uint32_t)((uint64_t)fw * F.nT / F.awaves);
+            const uint32_t b1 = (uint32_t)((uint64_t)(fw + 1) * F.nT / F.awaves);
+            int mode = 0;
+            LaneTrack T = {};
+            wave_lanes(F, geo, b0, b1, reinterpret_cast<uint32_t *>(&stg[0][0]), mode, T);
+            if (mode == 0) attached_loop<0>(F, geo, ra, rb, stg, T);
+            else if (mode == 1) attached_loop<1>(F, geo, ra, rb, stg, T);
+            else attached_loop<2>(F, geo, ra, rb, stg, T);
+            const uint32_t fl = wave_or(T.fl);
+            if (lane == 0 && fl) atomicOr(F.status, fl);
+        }
+        if (!work) break;
+        __syncthreads();  // the LDS of this item is done before the next one's
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1673,6 +1726,432 @@ __global__ void k_selftest_fp(const float *a, const float *b, float *out, uint32
 }
 
 // ---------------------------------------------------------------------------
+// Encoder: the inverse of the decode (section 4: attached clusters are stored
+// as residuals to their track's extrapolation, unattached clusters sorted by
+// position within their region and stored as differences to the previous
+// one).  Input: clusters in physical units (pad and time as doubles, grouped
+// by track) and track parameters; output: a compressed frame for tmd_decode.
+//
+//   E1 k_enc_tracks   one lane per track: quantise, run the same float32 model
+//                     as the decode, store residuals; open a new header where
+//                     the model cannot follow (row step beyond int8, side
+//                     change, 255 clusters, a clamp, a residual beyond int16)
+//   E2 k_enc_scan_*   header clusters -> header indices (block sums, prefix)
+//   E3 k_enc_headers  header arrays and cluster counts
+//   U1 k_enc_un_keys  unattached: quantise, bin counts, sort keys
+//   U2 k_rad_*        stable LSD radix sort of (bin, time, pad) then (qTot,
+//                     qMax) as the lower digits: 12 passes of 8 bits
+//   U3 k_enc_un_delta differences to the predecessor within the bin
+// ---------------------------------------------------------------------------
+struct EncDesc {
+    // input
+    uint32_t nT, n, nU;
+    const GLB uint32_t *first;  // [nT + 1]
+    const GLB double *qpt, *tgl;
+    const GLB uint8_t *sec, *row;
+    const GLB double *pad, *time, *snp;
+    const GLB uint16_t *qtot, *qmax;
+    const GLB uint8_t *usec, *urow;
+    const GLB double *upad, *utime;
+    const GLB uint16_t *uqtot, *uqmax;
+    // output
+    GLB uint8_t *ncls, *sec0, *row0;
+    GLB uint16_t *pad0;
+    GLB uint32_t *time0;
+    GLB int16_t *oqpt, *osnp, *otgl;
+    GLB int8_t *rdiff;
+    GLB uint8_t *sdiff;
+    GLB int16_t *pres, *tres;
+    GLB uint16_t *cqtot, *cqmax;
+    GLB uint32_t *ucount, *utdiff;
+    GLB uint16_t *updiff, *uoqtot, *uoqmax;
+    GLB uint32_t *counts;  // [0] headers, [1] splits, [2] input errors
+    // workspace
+    GLB uint8_t *hn;     // [n] clusters of the header opened at cluster c, else 0
+    GLB uint32_t *htrk;  // [n] track of the header opened at cluster c
+    GLB uint32_t *bsum;  // [ceil(n / 1024) + 1] headers per block of clusters, then their prefix
+    GLB unsigned long long *k0, *k1;  // [nU] sort keys (ping-pong)
+    GLB uint32_t *v0, *v1;            // [nU] sort payloads (qTot << 16 | qMax)
+    GLB uint32_t *rhist;              // [256 * rblocks] radix histograms, then offsets
+    uint32_t rblocks;
+};
+
+constexpr uint32_t kEncErrInput = 1u;  // counts[2]: a cluster outside the codable range
+constexpr int kRadTile = 4096;         // radix sort: elements per block (4 waves x 16 chunks of 64)
+
+__device__ __forceinline__ int16_t enc_q16(double v, double scale)
+{
+    double q = __builtin_rint(v * scale);
+    q = q > 32767.0 ? 32767.0 : q;
+    q = q < -32767.0 ? -32767.0 : q;
+    return (int16_t)q;
+}
+
+struct EncState {
+    float x, y, z, s, tgl, k;
+    int sec, row;
+    int32_t t0;
+};
+
+__device__ void enc_init(const Geo *__restrict__ g, EncState &st, int sec0, int row0, uint32_t pad0, uint32_t time0,
+                         int16_t qptq, int16_t snpq, int16_t tglq, uint32_t &fl)
+{
+    if (sec0 >= NSEC) { fl |= TMD_F_HDR; sec0 = sec0 % NSEC; }
+    if (row0 >= NROW) { fl |= TMD_F_HDR; row0 = NROW - 1; }
+    uint32_t t0 = time0;
+    if (t0 >= kTimeLim) { fl |= TMD_F_TIME; t0 = kTimeLim - 1; }
+    const RowGeo &R = g->row[row0];
+    st.sec = sec0;
+    st.row = row0;
+    st.t0 = (int32_t)t0;
+    st.x = R.x;
+    st.y = ((float)pad0 * 0x1p-5f - R.padoff) * R.pw;
+    st.z = 0.0f;
+    st.s = clamp_snp((float)snpq * 0x1p-15f, g->snp_max, fl);
+    st.tgl = (float)tglq * 0x1p-12f;
+    st.k = ((float)qptq * 0x1p-10f) * g->kb;
+}
+
+// the decode's step (rotation, row step, helix propagation, predicted codes)
+__device__ void enc_predict(const Geo *__restrict__ g, EncState &st, uint32_t sd, int rd, int32_t &P, int32_t &T,
+                            uint32_t &fl)
+{
+    uint32_t d = sd;
+    if (d >= 18) { fl |= TMD_F_SEC; d %= 18; }
+    if (d != 0) {
+        const float ca = g->cosb[d], sa = g->sinb[d];
+        const float cs = sqrtf((1.0f - st.s) * (1.0f + st.s));
+        const float xn = (st.x * ca) + (st.y * sa);
+        const float yn = (st.y * ca) - (st.x * sa);
+        const float sn = (st.s * ca) - (cs * sa);
+        const float cn = (cs * ca) + (st.s * sa);
+        if (!(cn > 0.0f)) fl |= TMD_F_ROT;
+        st.x = xn;
+        st.y = yn;
+        st.s = clamp_snp(sn, g->snp_max, fl);
+        st.sec = (st.sec / 18) * 18 + (st.sec % 18 + (int)d) % 18;
+    }
+    int row = st.row + rd;
+    if (row < 0) { fl |= TMD_F_ROW; row = 0; }
+    if (row >= NROW) { fl |= TMD_F_ROW; row = NROW - 1; }
+    st.row = row;
+    const RowGeo &R = g->row[row];
+    const float dx = R.x - st.x;
+    const float s1 = clamp_snp(st.s + (st.k * dx), g->snp_max, fl);
+    const float a0 = sqrtf((1.0f - st.s) * (1.0f + st.s));
+    const float a1 = sqrtf((1.0f - s1) * (1.0f + s1));
+    const float dydx = (st.s + s1) / (a0 + a1);
+    st.y = st.y + (dx * dydx);
+    st.z = st.z + (st.tgl * (dx * sqrtf(1.0f + (dydx * dydx))));
+    st.s = s1;
+    st.x = R.x;
+    P = sat_rint(((st.y * R.inv_pw) + R.padoff) * 32.0f);
+    T = sat_rint(st.z * g->inv_vd32);
+}
+
+__device__ void enc_update(const Geo *__restrict__ g, EncState &st, int32_t pres, int32_t tres, uint32_t &fl)
+{
+    const RowGeo &R = g->row[st.row];
+    const float nuy = (float)pres * R.pwq;
+    const float nuz = (float)tres * g->vdq;
+    st.y = st.y + nuy;
+    st.z = st.z + nuz;
+    st.s = clamp_snp(st.s + (nuy * R.ks), g->snp_max, fl);
+    st.tgl = st.tgl + (nuz * R.kt);
+}
+
+// E1: one lane per track
+__global__ __launch_bounds__(256) void k_enc_tracks(const EncDesc E, const Geo *__restrict__ g)
+{
+    const uint32_t it = blockIdx.x * 256 + threadIdx.x;
+    if (it == 0 && (E.first[0] != 0 || E.first[E.nT] != E.n)) atomicOr(&E.counts[2], kEncErrInput);
+    if (it >= E.nT) return;
+    const uint32_t a = E.first[it], e = E.first[it + 1];
+    if (a > e || e > E.n) {
+        atomicOr(&E.counts[2], kEncErrInput);
+        return;
+    }
+    const int16_t qptq = enc_q16(E.qpt[it], 1024.0), tglq = enc_q16(E.tgl[it], 4096.0);
+    uint32_t hdr = a, hcount = 0, splits = 0, err = 0;
+    EncState st = {};
+    for (uint32_t c = a; c < e; c++) {
+        const double pq = __builtin_rint(E.pad[c] * 32.0), tq = __builtin_rint(E.time[c] * 32.0);
+        if (!(pq >= 0.0 && pq <= 65535.0 && tq >= 0.0 && tq < (double)kTimeLim)) {
+            err = 1;
+            break;
+        }
+        const int32_t padq = (int32_t)pq, timeq = (int32_t)tq;
+        bool open_new = c == a;
+        int32_t rd = 0, sd = 0, pr = 0, tr = 0;
+        if (!open_new) {
+            const int drow = (int)E.row[c] - (int)E.row[c - 1];
+            const bool same_side = (E.sec[c] / 18) == (E.sec[c - 1] / 18);
+            if (drow < -128 || drow > 127 || !same_side || hcount == 255) {
+                open_new = true;
+            } else {
+                rd = drow;
+                sd = ((int)(E.sec[c] % 18) - (int)(E.sec[c - 1] % 18) + 18) % 18;
+                EncState trial = st;
+                uint32_t fl = 0;
+                int32_t P, T;
+                enc_predict(g, trial, (uint32_t)sd, rd, P, T, fl);
+                const int64_t p64 = (int64_t)padq - P;
+                const int64_t t64 = (int64_t)timeq - trial.t0 - T;
+                if (fl || p64 < -32768 || p64 > 32767 || t64 < -32768 || t64 > 32767 || trial.sec != (int)E.sec[c] ||
+                    trial.row != (int)E.row[c]) {
+                    open_new = true;
+                } else {
+                    pr = (int32_t)p64;
+                    tr = (int32_t)t64;
+                    enc_update(g, trial, pr, tr, fl);
+                    if (fl) open_new = true;
+                    else st = trial;
+                }
+            }
+        }
+        if (open_new) {
+            if (c != a) {
+                splits++;
+                E.hn[hdr] = (uint8_t)hcount;
+            }
+            hdr = c;
+            hcount = 1;
+            E.htrk[c] = it;
+            uint32_t fl = 0;
+            enc_init(g, st, E.sec[c], E.row[c], (uint32_t)padq, (uint32_t)timeq, qptq, enc_q16(E.snp[c], 32768.0),
+                     tglq, fl);
+            rd = sd = pr = tr = 0;
+        } else {
+            hcount++;
+            E.hn[c] = 0;
+        }
+        E.rdiff[c] = (int8_t)rd;
+        E.sdiff[c] = (uint8_t)sd;
+        E.pres[c] = (int16_t)pr;
+        E.tres[c] = (int16_t)tr;
+        E.cqtot[c] = E.qtot[c];
+        E.cqmax[c] = E.qmax[c];
+    }
+    if (err) {
+        atomicOr(&E.counts[2], kEncErrInput);
+        return;
+    }
+    if (e > a) E.hn[hdr] = (uint8_t)hcount;
+    if (splits) atomicAdd(&E.counts[1], splits);
+}
+
+// E2: headers per block of 1024 clusters
+__global__ __launch_bounds__(256) void k_enc_scan_blocks(const EncDesc E)
+{
+    const uint32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
+    uint32_t h = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) h += (c0 + q < E.n && E.hn[c0 + q] != 0) ? 1u : 0u;
+    uint32_t tot;
+    block_excl_add(h, &tot);
+    if (threadIdx.x == 0) E.bsum[blockIdx.x] = tot;
+}
+
+// E2: exclusive prefix of the block counts (one block); the total -> counts[0]
+__global__ __launch_bounds__(1024) void k_enc_scan_prefix(const EncDesc E, uint32_t nb)
+{
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < nb; b0 += 1024) {
+        const uint32_t b = b0 + threadIdx.x;
+        const uint32_t v = b < nb ? E.bsum[b] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_add<16>(v, &tot);
+        const uint32_t base = carry;
+        if (b < nb) E.bsum[b] = base + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = base + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) E.counts[0] = carry;
+}
+
+// E3: header arrays at their indices
+__global__ __launch_bounds__(256) void k_enc_headers(const EncDesc E)
+{
+    const uint32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
+    uint32_t h[4], cnt = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        h[q] = (c0 + q < E.n) ? E.hn[c0 + q] : 0u;
+        cnt += h[q] ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t idx = E.bsum[blockIdx.x] + block_excl_add(cnt, &tot);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        if (!h[q]) continue;
+        const uint32_t c = c0 + q, t = E.htrk[c];
+        E.ncls[idx] = (uint8_t)h[q];
+        E.sec0[idx] = E.sec[c];
+        E.row0[idx] = E.row[c];
+        E.pad0[idx] = (uint16_t)__builtin_rint(E.pad[c] * 32.0);
+        E.time0[idx] = (uint32_t)__builtin_rint(E.time[c] * 32.0);
+        E.oqpt[idx] = enc_q16(E.qpt[t], 1024.0);
+        E.osnp[idx] = enc_q16(E.snp[c], 32768.0);
+        E.otgl[idx] = enc_q16(E.tgl[t], 4096.0);
+        idx++;
+    }
+}
+
+// U1: quantise unattached clusters, count them per bin, build sort keys
+// (bin << 48 | time << 16 | pad) and payloads (qTot << 16 | qMax)
+__global__ __launch_bounds__(256) void k_enc_un_keys(const EncDesc E)
+{
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= E.nU) return;
+    const double pq = __builtin_rint(E.upad[i] * 32.0), tq = __builtin_rint(E.utime[i] * 32.0);
+    const uint32_t sec = E.usec[i], row = E.urow[i];
+    if (!(pq >= 0.0 && pq <= 65535.0 && tq >= 0.0 && tq <= 4294967295.0) || sec >= NSEC || row >= NROW) {
+        atomicOr(&E.counts[2], kEncErrInput);
+        E.k0[i] = 0;
+        E.v0[i] = 0;
+        return;
+    }
+    const uint64_t bin = sec * NROW + row;
+    E.k0[i] = (bin << 48) | ((uint64_t)(uint32_t)tq << 16) | (uint64_t)(uint32_t)pq;
+    E.v0[i] = ((uint32_t)E.uqtot[i] << 16) | E.uqmax[i];
+    atomicAdd(&E.ucount[bin], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_enc_clear(const EncDesc E)
+{
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < NBIN) E.ucount[i] = 0;
+    if (i < 3) E.counts[i] = 0;
+}
+
+// U2: one pass of a stable LSD radix sort on 8-bit digit `shift` of the key
+// (key_pass) or of the payload.  Blocks own tiles of kRadTile elements in
+// order; within a tile, wave w owns elements [1024 w, 1024 w + 1024).
+__device__ __forceinline__ uint32_t rad_digit(bool key_pass, unsigned long long k, uint32_t v, uint32_t shift)
+{
+    return key_pass ? (uint32_t)(k >> shift) & 0xFFu : (v >> shift) & 0xFFu;
+}
+
+// (kernel parameters are plain pointers, cast to the global address space
+// inside: a qualified parameter type would give the kernel a different symbol
+// in the device and host compilations)
+__global__ __launch_bounds__(256) void k_rad_hist(const EncDesc E, const unsigned long long *kin_,
+                                                  const uint32_t *vin_, uint32_t key_pass, uint32_t shift)
+{
+    const GLB unsigned long long *kin = (const GLB unsigned long long *)kin_;
+    const GLB uint32_t *vin = (const GLB uint32_t *)vin_;
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kRadTile;
+    for (uint32_t q = threadIdx.x; q < (uint32_t)kRadTile; q += 256) {
+        const uint32_t i = base + q;
+        if (i < E.nU) atomicAdd(&cnt[rad_digit(key_pass, kin[i], vin[i], shift)], 1u);
+    }
+    __syncthreads();
+    E.rhist[(size_t)blockIdx.x * 256 + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// histograms -> offsets: rhist[b][d] = sum of all digits < d + digit d in blocks < b
+__global__ __launch_bounds__(256) void k_rad_offsets(const EncDesc E)
+{
+    const uint32_t d = threadIdx.x;
+    uint32_t run = 0;
+    for (uint32_t b = 0; b < E.rblocks; b++) {
+        const uint32_t v = E.rhist[(size_t)b * 256 + d];
+        E.rhist[(size_t)b * 256 + d] = run;
+        run += v;
+    }
+    uint32_t all;
+    const uint32_t before = block_excl_add(run, &all);
+    for (uint32_t b = 0; b < E.rblocks; b++) E.rhist[(size_t)b * 256 + d] += before;
+}
+
+__global__ __launch_bounds__(256) void k_rad_scatter(const EncDesc E, const unsigned long long *kin_,
+                                                     const uint32_t *vin_, unsigned long long *kout_,
+                                                     uint32_t *vout_, uint32_t key_pass, uint32_t shift)
+{
+    const GLB unsigned long long *kin = (const GLB unsigned long long *)kin_;
+    const GLB uint32_t *vin = (const GLB uint32_t *)vin_;
+    GLB unsigned long long *kout = (GLB unsigned long long *)kout_;
+    GLB uint32_t *vout = (GLB uint32_t *)vout_;
+    __shared__ uint32_t wcnt[4][256];  // per wave: digit counts, then running positions
+    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+    for (uint32_t q = threadIdx.x; q < 4 * 256; q += 256) (&wcnt[0][0])[q] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kRadTile + w * 1024;
+    for (uint32_t ch = 0; ch < 16; ch++) {
+        const uint32_t i = base + ch * kWave + lane;
+        if (i < E.nU) atomicAdd(&wcnt[w][rad_digit(key_pass, kin[i], vin[i], shift)], 1u);
+    }
+    __syncthreads();
+    {
+        const uint32_t d = threadIdx.x;
+        uint32_t run = E.rhist[(size_t)blockIdx.x * 256 + d];
+        for (int ww = 0; ww < 4; ww++) {
+            const uint32_t c = wcnt[ww][d];
+            wcnt[ww][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (uint32_t ch = 0; ch < 16; ch++) {
+        const uint32_t i = base + ch * kWave + lane;
+        const bool act = i < E.nU;
+        unsigned long long k = 0;
+        uint32_t v = 0, dg = 0;
+        if (act) {
+            k = kin[i];
+            v = vin[i];
+            dg = rad_digit(key_pass, k, v, shift);
+        }
+        uint64_t same = __ballot(act);
+#pragma unroll
+        for (int bit = 0; bit < 8; bit++) {
+            const uint64_t m = __ballot(act && ((dg >> bit) & 1u));
+            same &= ((dg >> bit) & 1u) ? m : ~m;
+        }
+        if (act) {
+            const uint32_t pos = wcnt[w][dg] + (uint32_t)__popcll(same & below);
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // the last lane of each digit group moves that digit's position on
+        if (act && (same & ~below & ~(1ull << lane)) == 0) wcnt[w][dg] += (uint32_t)__popcll(same);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// U3: differences to the predecessor in the same bin (the first against zero)
+__global__ __launch_bounds__(256) void k_enc_un_delta(const EncDesc E, const unsigned long long *ks_,
+                                                      const uint32_t *vs_)
+{
+    const GLB unsigned long long *ks = (const GLB unsigned long long *)ks_;
+    const GLB uint32_t *vs = (const GLB uint32_t *)vs_;
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= E.nU) return;
+    const unsigned long long k = ks[i];
+    uint32_t pt = 0, pp = 0;
+    if (i > 0) {
+        const unsigned long long kp = ks[i - 1];
+        if ((kp >> 48) == (k >> 48)) {
+            pt = (uint32_t)(kp >> 16);
+            pp = (uint32_t)kp & 0xFFFFu;
+        }
+    }
+    const uint32_t v = vs[i];
+    E.utdiff[i] = (uint32_t)(k >> 16) - pt;
+    E.updiff[i] = (uint16_t)(((uint32_t)k & 0xFFFFu) - pp);
+    E.uoqtot[i] = (uint16_t)(v >> 16);
+    E.uoqmax[i] = (uint16_t)(v & 0xFFFFu);
+}
+
+// ---------------------------------------------------------------------------
 // workspace of tmd_decode_static: device memory of the library itself, one
 // array per GPU (the kernels never see its host-side name, only the address
 // hipGetSymbolAddress gives for the current device)
@@ -1697,6 +2176,9 @@ struct FrameLayout {
 struct tmd_plan {
     int device = 0;
     uint32_t simds = 1024;  // SIMDs of the device (CUs x 4): the attached decode balances its waves over them
+    uint32_t tracks_per_wave = kWave;  // attached decode: tracks per wave (64..128; tmd_set_schedule)
+    uint32_t persist = 0;              // attached decode: persistent grid of persist waves per SIMD (0: off)
+    uint32_t *d_work = nullptr;        // its per-XCD work counters
     uint32_t n_frames = 0;
     uint32_t total_tiles = 0;
     tmd_params params{};
@@ -1768,16 +2250,17 @@ bool aligned(const T *p)
     return ((uintptr_t)p % alignof(T)) == 0;
 }
 
-// Waves of the attached decode for a frame of nT tracks: ceil(nT / 64), or,
-// for a single-frame call whose count is just above a multiple of the SIMD
-// count, that multiple (tracks per wave up to 66: at most two decoded after
-// another track of the wave; see k_attached).
-uint32_t attached_waves(uint32_t nT, bool single, uint32_t simds)
+// Waves of the attached decode for a frame of nT tracks: ceil(nT / tpw) (tpw:
+// the plan's tracks per wave, 64..128), or, for a single-frame call whose count
+// is just above a multiple of the SIMD count, that multiple (tracks per wave
+// up to tpw + 2, at most 128; see wave_lanes).
+uint32_t attached_waves(uint32_t nT, bool single, uint32_t simds, uint32_t tpw)
 {
-    const uint32_t w0 = (uint32_t)(((uint64_t)nT + kWave - 1) / kWave);
+    const uint32_t w0 = (uint32_t)(((uint64_t)nT + tpw - 1) / tpw);
     if (!single || simds == 0 || w0 <= simds || w0 % simds == 0) return w0;
     const uint32_t w = w0 / simds * simds;
-    return (uint64_t)nT <= (uint64_t)(kWave + 2) * w ? w : w0;
+    const uint64_t cap = std::min<uint64_t>((uint64_t)tpw + 2, kMaxWaveTracks);
+    return (uint64_t)nT <= cap * w ? w : w0;
 }
 
 // Events for the stages selected in `mask` (2 per stage, null for the
@@ -1813,7 +2296,8 @@ int launch_all(tmd_plan_t *P, hipStream_t s, const std::vector<hipEvent_t> &ev)
     };
     const uint32_t T = P->total_tiles;
     if (begin(0, s)) return TMD_E_HIP;
-    hipLaunchKernelGGL(k_tilesum, dim3(T + P->n_frames), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame, T);
+    uint32_t *work = P->persist ? P->d_work : nullptr;
+    hipLaunchKernelGGL(k_tilesum, dim3(T + P->n_frames), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame, T, work);
     if (end(0, s) || begin(1, s)) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_count, dim3(T), dim3(kCountThreads), 0, s, P->d_desc, P->d_tile_frame);
     if (end(1, s) || begin(2, s)) return TMD_E_HIP;
@@ -1828,9 +2312,15 @@ int launch_all(tmd_plan_t *P, hipStream_t s, const std::vector<hipEvent_t> &ev)
     // streams they take as long in all: the unattached waves slow the attached
     // decode by about what they take alone.)
     if (begin(5, s)) return TMD_E_HIP;
-    if (T)
-        hipLaunchKernelGGL(k_attached, dim3(T * (kTileWaves / kAttWaves)), dim3(kAttWaves * kWave), 0, s, P->d_desc,
-                           P->d_tile_frame, P->d_geo, P->n_frames == 1 ? 1u : 0u);
+    if (T) {
+        // wave slots: 4 per tile of the planned capacity; persistent: a grid
+        // of persist waves per SIMD (a multiple of the XCD count) takes them
+        const uint32_t slots = T * (kTileWaves / kAttWaves);
+        uint32_t grid = slots;
+        if (work) grid = std::max<uint32_t>(kXcds, std::min<uint32_t>(slots, P->simds * P->persist) / kXcds * kXcds);
+        hipLaunchKernelGGL(k_attached, dim3(grid), dim3(kAttWaves * kWave), 0, s, P->d_desc, P->d_tile_frame, P->d_geo,
+                           P->n_frames == 1 ? 1u : 0u, work, slots);
+    }
     if (end(5, s) || begin(6, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_unattached, dim3(NBIN, P->n_frames), dim3(kWave), 0, s, P->d_desc);
     if (end(6, s)) return TMD_E_HIP;
@@ -2023,6 +2513,7 @@ void tmd_free(tmd_plan_t *P)
     if (P->d_tile_frame) (void)hipFree(P->d_tile_frame);
     if (P->d_desc) (void)hipFree(P->d_desc);
     if (P->d_status) (void)hipFree(P->d_status);
+    if (P->d_work) (void)hipFree(P->d_work);
     if (P->h_status) (void)hipHostFree(P->h_status);
     if (P->h_desc) (void)hipHostFree(P->h_desc);
     if (cur != P->device) (void)hipSetDevice(cur);
@@ -2098,6 +2589,7 @@ int tmd_plan(const tmd_frame_shape *shapes, uint32_t n_frames, const tmd_params 
         }
         if (hipMalloc(&P->d_desc, sizeof(FrameDesc) * n_frames) != hipSuccess) { rc = TMD_E_HIP; break; }
         if (hipMalloc(&P->d_status, sizeof(uint32_t) * n_frames) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if (hipMalloc(&P->d_work, sizeof(uint32_t) * kXcds) != hipSuccess) { rc = TMD_E_HIP; break; }
         if (hipMemset(P->d_status, 0, sizeof(uint32_t) * n_frames) != hipSuccess) { rc = TMD_E_HIP; break; }
         if (hipHostMalloc((void **)&P->h_status, sizeof(uint32_t) * n_frames, 0) != hipSuccess) {
             rc = TMD_E_HIP;
@@ -2194,7 +2686,7 @@ int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_fr
         D.nT = S.n_tracks; D.nA = S.n_attached; D.nU = S.n_unattached;
         D.ntile = (S.n_tracks + kTile - 1) / kTile;  // <= the planned L.ntile
         D.tile0 = L.tile0;
-        D.awaves = attached_waves(S.n_tracks, P->n_frames == 1, P->simds);
+        D.awaves = attached_waves(S.n_tracks, P->n_frames == 1, P->simds, P->tracks_per_wave);
     }
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
@@ -2297,6 +2789,26 @@ int tmd_decode_static(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_fr
     return tmd_decode_shapes(P, shapes ? shapes : P->shapes.data(), in, out, ws, stream);
 }
 
+int tmd_set_schedule(tmd_plan_t *P, uint32_t tracks_per_wave, uint32_t persist_waves_per_simd)
+{
+    if (!P) return TMD_E_ARG;
+    if (tracks_per_wave == 0) tracks_per_wave = kWave;
+    if (tracks_per_wave < (uint32_t)kWave || tracks_per_wave > kMaxWaveTracks || persist_waves_per_simd > 64)
+        return TMD_E_ARG;
+    if (P->tracks_per_wave == tracks_per_wave && P->persist == persist_waves_per_simd) return TMD_OK;
+    // the next call waits for the last one (it still uses the old settings)
+    if (P->called) HIP_TRY(hipEventSynchronize(P->done));
+    P->tracks_per_wave = tracks_per_wave;
+    P->persist = persist_waves_per_simd;
+    P->desc_valid = false;  // wave counts change: upload the descriptors again
+    if (P->graph) {         // launch shapes change: capture again
+        (void)hipGraphExecDestroy(P->graph);
+        P->graph = nullptr;
+    }
+    drop_prof_graph(P);
+    return TMD_OK;
+}
+
 int tmd_set_profiling(tmd_plan_t *P, uint32_t stage_mask)
 {
     if (!P) return TMD_E_ARG;
@@ -2356,6 +2868,140 @@ int tmd_selftest_fp(const float *a, const float *b, float *out, uint32_t n, void
     hipLaunchKernelGGL(k_selftest_fp, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, a, b, out, n);
     HIP_TRY(hipGetLastError());
     return TMD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Encoder host side
+// ---------------------------------------------------------------------------
+namespace {
+
+struct EncLayout {
+    size_t hn, htrk, bsum, k0, k1, v0, v1, rhist, total;
+    uint32_t nb, rblocks;
+};
+
+EncLayout enc_layout(uint32_t n, uint32_t nU)
+{
+    EncLayout L;
+    L.nb = (n + 1023) / 1024;
+    L.rblocks = (nU + kRadTile - 1) / kRadTile;
+    size_t off = 0;
+    L.hn = off;    off += align256(std::max<size_t>(n, 1));
+    L.htrk = off;  off += align256(4 * std::max<size_t>(n, 1));
+    L.bsum = off;  off += align256(4 * ((size_t)L.nb + 1));
+    L.k0 = off;    off += align256(8 * std::max<size_t>(nU, 1));
+    L.k1 = off;    off += align256(8 * std::max<size_t>(nU, 1));
+    L.v0 = off;    off += align256(4 * std::max<size_t>(nU, 1));
+    L.v1 = off;    off += align256(4 * std::max<size_t>(nU, 1));
+    L.rhist = off; off += align256(4 * 256 * std::max<size_t>(L.rblocks, 1));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tmd_encode_workspace(uint32_t n_tracks, uint32_t n_clusters, uint32_t n_unattached, size_t *bytes)
+{
+    (void)n_tracks;
+    if (!bytes) return TMD_E_ARG;
+    *bytes = enc_layout(n_clusters, n_unattached).total;
+    return TMD_OK;
+}
+
+int tmd_encode(tmd_plan_t *P, const tmd_enc_in *in, tmd_enc_out *out, void *workspace, size_t workspace_bytes,
+               void *stream)
+{
+    if (!P || !in || !out || !workspace || !out->counts) return TMD_E_ARG;
+    if ((uintptr_t)workspace % 256) return TMD_E_ARG;
+    const uint32_t nT = in->n_tracks, n = in->n_clusters, nU = in->n_unattached;
+    const EncLayout L = enc_layout(n, nU);
+    if (workspace_bytes < L.total) return TMD_E_CAPACITY;
+    if (!in->trk_first || !out->un_count) return TMD_E_ARG;
+    if (nT && (!in->trk_qpt || !in->trk_tgl)) return TMD_E_ARG;
+    if (n && (!in->cl_sec || !in->cl_row || !in->cl_pad || !in->cl_time || !in->cl_snp || !in->cl_qtot ||
+              !in->cl_qmax || !out->trk_ncls || !out->trk_sec0 || !out->trk_row0 || !out->trk_pad0 ||
+              !out->trk_time0 || !out->trk_qpt || !out->trk_snp || !out->trk_tgl || !out->cls_row_diff ||
+              !out->cls_sec_diff || !out->cls_pad_res || !out->cls_time_res || !out->cls_qtot || !out->cls_qmax))
+        return TMD_E_ARG;
+    if (nU && (!in->un_sec || !in->un_row || !in->un_pad || !in->un_time || !in->un_qtot || !in->un_qmax ||
+               !out->un_time_diff || !out->un_pad_diff || !out->un_qtot || !out->un_qmax))
+        return TMD_E_ARG;
+    if (!aligned(in->trk_first) || !aligned(in->trk_qpt) || !aligned(in->trk_tgl) || !aligned(in->cl_pad) ||
+        !aligned(in->cl_time) || !aligned(in->cl_snp) || !aligned(in->cl_qtot) || !aligned(in->cl_qmax) ||
+        !aligned(in->un_pad) || !aligned(in->un_time) || !aligned(in->un_qtot) || !aligned(in->un_qmax) ||
+        !aligned(out->trk_pad0) || !aligned(out->trk_time0) || !aligned(out->trk_qpt) || !aligned(out->trk_snp) ||
+        !aligned(out->trk_tgl) || !aligned(out->cls_pad_res) || !aligned(out->cls_time_res) ||
+        !aligned(out->cls_qtot) || !aligned(out->cls_qmax) || !aligned(out->un_count) ||
+        !aligned(out->un_time_diff) || !aligned(out->un_pad_diff) || !aligned(out->un_qtot) ||
+        !aligned(out->un_qmax) || !aligned(out->counts))
+        return TMD_E_ARG;
+    EncDesc E;
+    memset(&E, 0, sizeof(E));
+    E.nT = nT; E.n = n; E.nU = nU;
+    E.first = (const GLB uint32_t *)in->trk_first;
+    E.qpt = (const GLB double *)in->trk_qpt; E.tgl = (const GLB double *)in->trk_tgl;
+    E.sec = (const GLB uint8_t *)in->cl_sec; E.row = (const GLB uint8_t *)in->cl_row;
+    E.pad = (const GLB double *)in->cl_pad; E.time = (const GLB double *)in->cl_time;
+    E.snp = (const GLB double *)in->cl_snp;
+    E.qtot = (const GLB uint16_t *)in->cl_qtot; E.qmax = (const GLB uint16_t *)in->cl_qmax;
+    E.usec = (const GLB uint8_t *)in->un_sec; E.urow = (const GLB uint8_t *)in->un_row;
+    E.upad = (const GLB double *)in->un_pad; E.utime = (const GLB double *)in->un_time;
+    E.uqtot = (const GLB uint16_t *)in->un_qtot; E.uqmax = (const GLB uint16_t *)in->un_qmax;
+    E.ncls = (GLB uint8_t *)out->trk_ncls; E.sec0 = (GLB uint8_t *)out->trk_sec0;
+    E.row0 = (GLB uint8_t *)out->trk_row0; E.pad0 = (GLB uint16_t *)out->trk_pad0;
+    E.time0 = (GLB uint32_t *)out->trk_time0; E.oqpt = (GLB int16_t *)out->trk_qpt;
+    E.osnp = (GLB int16_t *)out->trk_snp; E.otgl = (GLB int16_t *)out->trk_tgl;
+    E.rdiff = (GLB int8_t *)out->cls_row_diff; E.sdiff = (GLB uint8_t *)out->cls_sec_diff;
+    E.pres = (GLB int16_t *)out->cls_pad_res; E.tres = (GLB int16_t *)out->cls_time_res;
+    E.cqtot = (GLB uint16_t *)out->cls_qtot; E.cqmax = (GLB uint16_t *)out->cls_qmax;
+    E.ucount = (GLB uint32_t *)out->un_count; E.utdiff = (GLB uint32_t *)out->un_time_diff;
+    E.updiff = (GLB uint16_t *)out->un_pad_diff; E.uoqtot = (GLB uint16_t *)out->un_qtot;
+    E.uoqmax = (GLB uint16_t *)out->un_qmax; E.counts = (GLB uint32_t *)out->counts;
+    char *ws = (char *)workspace;
+    E.hn = (GLB uint8_t *)(ws + L.hn); E.htrk = (GLB uint32_t *)(ws + L.htrk);
+    E.bsum = (GLB uint32_t *)(ws + L.bsum);
+    E.k0 = (GLB unsigned long long *)(ws + L.k0); E.k1 = (GLB unsigned long long *)(ws + L.k1);
+    E.v0 = (GLB uint32_t *)(ws + L.v0); E.v1 = (GLB uint32_t *)(ws + L.v1);
+    E.rhist = (GLB uint32_t *)(ws + L.rhist);
+    E.rblocks = L.rblocks;
+    hipStream_t s = (hipStream_t)stream;
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != P->device) HIP_TRY(hipSetDevice(P->device));
+    // calls on one plan are ordered on the device (they share its tables only,
+    // but keep the plan's ordering rule)
+    if (P->called) (void)hipStreamWaitEvent(s, P->done, 0);
+    hipLaunchKernelGGL(k_enc_clear, dim3((NBIN + 255) / 256), dim3(256), 0, s, E);
+    if (nT) hipLaunchKernelGGL(k_enc_tracks, dim3((nT + 255) / 256), dim3(256), 0, s, E, P->d_geo);
+    if (n) {
+        hipLaunchKernelGGL(k_enc_scan_blocks, dim3(L.nb), dim3(256), 0, s, E);
+        hipLaunchKernelGGL(k_enc_scan_prefix, dim3(1), dim3(1024), 0, s, E, L.nb);
+        hipLaunchKernelGGL(k_enc_headers, dim3(L.nb), dim3(256), 0, s, E);
+    }
+    if (nU) {
+        hipLaunchKernelGGL(k_enc_un_keys, dim3((nU + 255) / 256), dim3(256), 0, s, E);
+        // the payload's digits first (the lower-order part of the order),
+        // then the key's; 12 passes, so the result ends in (k0, v0)
+        unsigned long long *ka = (unsigned long long *)E.k0, *kb = (unsigned long long *)E.k1;
+        uint32_t *va = (uint32_t *)E.v0, *vb = (uint32_t *)E.v1;
+        for (int pass = 0; pass < 12; pass++) {
+            const uint32_t key_pass = pass >= 4 ? 1u : 0u;
+            const uint32_t shift = key_pass ? 8u * (uint32_t)(pass - 4) : 8u * (uint32_t)pass;
+            hipLaunchKernelGGL(k_rad_hist, dim3(L.rblocks), dim3(256), 0, s, E, ka, va, key_pass, shift);
+            hipLaunchKernelGGL(k_rad_offsets, dim3(1), dim3(256), 0, s, E);
+            hipLaunchKernelGGL(k_rad_scatter, dim3(L.rblocks), dim3(256), 0, s, E, ka, va, kb, vb, key_pass, shift);
+            std::swap(ka, kb);
+            std::swap(va, vb);
+        }
+        hipLaunchKernelGGL(k_enc_un_delta, dim3((nU + 255) / 256), dim3(256), 0, s, E, ka, va);
+    }
+    hipError_t e = hipGetLastError();
+    if (cur != P->device) (void)hipSetDevice(cur);
+    return e == hipSuccess ? TMD_OK : TMD_E_HIP;
 }
 
 }  // extern "C"

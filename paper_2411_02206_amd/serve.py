@@ -6,21 +6,29 @@ The scheduler keeps up to `slots` batches in flight, each on its own stream
 requests whose buffers fit the HBM budget -- up to `max_batch` of them -- and
 decodes them together with one launch sequence; batches admitted while
 others are still running overlap with them on the device.  A request's
-latency runs from its arrival to the completion event of its batch.
+latency runs from its arrival to the moment its batch's completion event was
+reached on the device (read from the event's timestamp, not from when the
+scheduler next looked).
 
-Each slot owns one plan whose frame shapes are capacities (tmd_decode_shapes):
-max_batch entries of the server's per-frame capacity.  A batch fills the
-first entries and leaves the rest idle, so the plan, its workspace and (with
-graph=True) its captured HIP graph are made once and reused for every batch.
-The capacity starts at the first frame's shape times 1.25 (or is given) and
-grows by the same factor when a larger frame arrives; a slot rebuilds its plan
-when it is next idle.  All decoding is done by libtmd; this module schedules.
+Each slot owns plans whose frame shapes are capacities (tmd_decode_shapes):
+one per batch size 1, 2, 4, ... up to max_batch, each with that many entries
+of the server's per-frame capacity.  A batch of b frames uses the smallest
+plan with at least b entries and leaves its remaining entries idle, so few
+idle entries are launched, and the plans, the slot's one workspace (sized for
+its largest plan) and (with graph=True) their captured HIP graphs are made
+once and reused.  The capacity starts at the first frame's shape times 1.25
+(or is given) and grows by the same factor when a larger frame arrives; a
+slot rebuilds its plans when it is next used.  The HBM budget covers the
+requests' buffers and the slots' workspaces: a slot whose plans must be
+rebuilt admits a batch only if the new workspace fits as well.  `warm()`
+builds every slot's plans and graphs ahead of the traffic.  All decoding is
+done by libtmd; this module schedules.
 """
 import collections
 import threading
 import time
 
-from . import IN_FIELDS, NBIN, Plan, alloc_out, frame_shape, to_device
+from . import IN_FIELDS, NBIN, PLAN_GRAPH, Plan, alloc_out, frame_shape, to_device
 
 # bytes of the device buffers of one request: inputs (when copied in) and outputs
 IN_BYTES_TRACK = 15
@@ -40,6 +48,16 @@ def frame_bytes(shape, inputs=True):
 
 def _grow(cap, shape):
     return tuple(max(c, int(s * GROWTH) + 1) if s > c else c for c, s in zip(cap, shape))
+
+
+def batch_sizes(max_batch):
+    """Entries of a slot's plans: 1, 2, 4, ... and max_batch."""
+    sizes, b = [], 1
+    while b < max_batch:
+        sizes.append(b)
+        b *= 2
+    sizes.append(max_batch)
+    return sizes
 
 
 class Request:
@@ -62,16 +80,18 @@ class Request:
 
 
 class _Slot:
-    """A stream with its capacity plan, workspace and idle-entry buffers."""
+    """A stream with its capacity plans, workspace and idle-entry buffers."""
 
     def __init__(self, stream):
         self.stream = stream
-        self.plan = None
+        self.plans = {}    # entries -> Plan
         self.ws = None
+        self.ws_bytes = 0  # reserved in the server's budget
         self.cap = None
         self.idle_in = None
         self.idle_out = None
         self.reqs = None   # the batch in flight, if any
+        self.plan = None   # its plan
         self.event = None
         self.keep = None   # its input buffers
 
@@ -81,15 +101,18 @@ class Server:
     the scheduling runs in step()/run_until() on the calling thread (or
     start() for a background thread).  capacity: per-frame (n_tracks,
     n_attached, n_unattached) of the slot plans, or None to size them from
-    the frames that arrive."""
+    the frames that arrive.  schedule: (tracks per wave, persistent waves per
+    SIMD) for the plans' attached decode (see Plan.set_schedule)."""
 
     def __init__(self, bz=0.5, hbm_budget=200e9, slots=4, max_batch=8, graph=False, device="cuda",
-                 capacity=None, executor=None):
+                 capacity=None, executor=None, schedule=None):
         self.bz = bz
         self.budget = float(hbm_budget)
         self.max_batch = max_batch
+        self.sizes = batch_sizes(max_batch)
         self.graph = graph
         self.device = device
+        self.schedule = schedule
         self.capacity = tuple(capacity) if capacity is not None else None
         self.peak_in_use = 0.0
         self.in_use = 0.0
@@ -101,6 +124,12 @@ class Server:
             import torch
             self._torch = torch
             self._slots = [_Slot(torch.cuda.Stream(device=device)) for _ in range(slots)]
+            # device clock reference: completion times are this host time
+            # plus the device time elapsed since the reference event
+            self._ref = torch.cuda.Event(enable_timing=True)
+            self._ref.record(self._slots[0].stream)
+            self._ref.synchronize()
+            self._ref_host = time.perf_counter()
         else:
             self._torch = None
             self._slots = [_Slot(None) for _ in range(slots)]
@@ -119,41 +148,72 @@ class Server:
         return r
 
     # -- scheduler -----------------------------------------------------------
-    def _slot_ready(self, S):
-        """Make slot S's plan match the current capacity (S is idle)."""
-        if S.plan is not None and S.cap == self.capacity:
-            return
+    def _build(self, S, cap):
+        """Plans of slot S for capacity `cap`; returns their workspace bytes
+        (the workspace itself is allocated by _commit)."""
+        for p in S.plans.values():
+            p.free()
+        S.plans = {}
+        flags = PLAN_GRAPH if self.graph else 0
+        for b in self.sizes:
+            p = Plan([cap] * b, bz=self.bz, flags=flags)
+            if self.schedule is not None:
+                p.set_schedule(*self.schedule)
+            S.plans[b] = p
+        return max(p.workspace_bytes for p in S.plans.values())
+
+    def _commit(self, S, cap, ws_bytes):
         torch = self._torch
-        from . import PLAN_GRAPH
-        if S.plan is not None:
-            self.in_use -= S.ws.numel()
-            S.plan.free()
-        S.cap = self.capacity
-        S.plan = Plan([S.cap] * self.max_batch, bz=self.bz, flags=PLAN_GRAPH if self.graph else 0)
+        if S.ws is not None:
+            self.in_use -= S.ws_bytes
+            S.ws = None
+        S.cap = cap
+        S.ws_bytes = ws_bytes
         with torch.cuda.stream(S.stream):
-            S.ws = S.plan.alloc_workspace(self.device)
+            S.ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=self.device)
             if S.idle_in is None:
                 S.idle_in = {k: None for k in IN_FIELDS}
                 S.idle_in["un_count"] = torch.zeros(NBIN, dtype=torch.int32, device=self.device)
                 o = alloc_out((0, 0, 0), self.device)
                 S.idle_out = {k: (o[k] if k in ("row_offset", "row_nattached") else None) for k in o}
                 S.idle_out["capacity"] = 0
-        self.in_use += S.ws.numel()
+        self.in_use += ws_bytes
         self.peak_in_use = max(self.peak_in_use, self.in_use)
+
+    def warm(self, capacity=None):
+        """Build every slot's plans for `capacity` (default: the server's) and
+        replay each plan once on idle entries, so that plan creation and graph
+        capture happen before the traffic."""
+        if capacity is not None:
+            self.capacity = tuple(capacity)
+        if self._executor is not None or self.capacity is None:
+            return
+        for S in self._slots:
+            if S.cap != self.capacity:
+                ws = self._build(S, self.capacity)
+                self._commit(S, self.capacity, ws)
+            for b, p in S.plans.items():
+                p.decode([S.idle_in] * b, [S.idle_out] * b, S.ws, S.stream, shapes=[(0, 0, 0)] * b)
+        self._torch.cuda.synchronize()
+
+    def _done_time(self, S):
+        if self._executor is not None or S.event is None:
+            return time.perf_counter()
+        return self._ref_host + self._ref.elapsed_time(S.event) * 1e-3
 
     def _retire(self):
         still = []
         for si in self._busy:
             S = self._slots[si]
             if S.event is None or S.event.query():
-                now = time.perf_counter()
+                t = self._done_time(S)
                 for i, r in enumerate(S.reqs):
-                    r.done_time = now
+                    r.done_time = t
                     if S.plan is not None and self._executor is None:
                         r.flags = S.plan.status(i)
                     self.in_use -= r.nbytes
                     self.done.append(r)
-                S.reqs, S.event, S.keep = None, None, None
+                S.reqs, S.event, S.keep, S.plan = None, None, None, None
                 self._free.append(si)
             else:
                 still.append(si)
@@ -162,25 +222,34 @@ class Server:
     def _admit(self):
         if not self._free:
             return False
+        si = self._free[-1]
+        S = self._slots[si]
         batch = []
+        cap = self.capacity
+        rebuild_ws = None  # workspace bytes of the slot's plans for `cap`, if they must be rebuilt
         with self.lock:
             while self.waiting and len(batch) < self.max_batch:
                 r = self.waiting[0]
-                if self.in_use + r.nbytes > self.budget:
+                new_cap = _grow((0, 0, 0), r.shape) if cap is None else (
+                    _grow(cap, r.shape) if any(s > c for s, c in zip(r.shape, cap)) else cap)
+                extra = 0.0
+                if self._executor is None and new_cap != S.cap:
+                    if new_cap != cap or rebuild_ws is None:
+                        rebuild_ws = self._build(S, new_cap)
+                    extra = rebuild_ws - S.ws_bytes
+                if self.in_use + r.nbytes + extra > self.budget:
                     break
                 self.waiting.popleft()
                 self.in_use += r.nbytes
-                self.peak_in_use = max(self.peak_in_use, self.in_use)
+                self.peak_in_use = max(self.peak_in_use, self.in_use + extra)
                 batch.append(r)
+                cap = new_cap
         if not batch:
+            if S.plans and S.cap is not None and self._executor is None and rebuild_ws is not None:
+                self._build(S, S.cap)  # the trial plans did not fit: back to the slot's own
             return False
-        for r in batch:
-            if self.capacity is None:
-                self.capacity = _grow((0, 0, 0), r.shape)
-            elif any(s > c for s, c in zip(r.shape, self.capacity)):
-                self.capacity = _grow(self.capacity, r.shape)
-        si = self._free.pop()
-        S = self._slots[si]
+        self.capacity = cap
+        self._free.pop()
         now = time.perf_counter()
         for r in batch:
             r.admitted = now
@@ -189,15 +258,20 @@ class Server:
         if self._executor is not None:
             self._executor(batch)
             return True
-        self._slot_ready(S)
+        if S.cap != cap:
+            if rebuild_ws is None:
+                rebuild_ws = self._build(S, cap)
+            self._commit(S, cap, rebuild_ws)
         torch = self._torch
-        idle = self.max_batch - len(batch)
+        entries = next(b for b in self.sizes if b >= len(batch))
+        S.plan = S.plans[entries]
+        idle = entries - len(batch)
         with torch.cuda.stream(S.stream):
             ins = [r.frame if r.on_device else to_device(r.frame, self.device) for r in batch]
             outs = [alloc_out(r.shape, self.device) for r in batch]
             S.plan.decode(ins + [S.idle_in] * idle, outs + [S.idle_out] * idle, S.ws, S.stream,
                           shapes=[r.shape for r in batch] + [(0, 0, 0)] * idle)
-            S.event = torch.cuda.Event()
+            S.event = torch.cuda.Event(enable_timing=True)
             S.event.record(S.stream)
         for r, o in zip(batch, outs):
             r.out = o
@@ -242,9 +316,10 @@ class Server:
         if self._torch is not None:
             self._torch.cuda.synchronize()
         for S in self._slots:
-            if S.plan is not None:
-                S.plan.free()
-                S.plan = None
+            for p in S.plans.values():
+                p.free()
+            S.plans = {}
+            S.plan = None
             S.ws = None
 
 

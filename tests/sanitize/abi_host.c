@@ -52,6 +52,15 @@ int main(void)
     EXPECT(tmd_pipe_create(&sh, TMD_PIPE_MAX_DEPTH + 1u, &p, &pipe) == TMD_E_ARG);
     EXPECT(tmd_pipe_run(NULL, 1, &sh, &in, &out, &fl) == TMD_E_ARG);
     tmd_pipe_free(NULL);
+    size_t eb = 0;
+    EXPECT(tmd_encode_workspace(10, 100, 50, &eb) == TMD_OK && eb > 0);
+    EXPECT(tmd_encode_workspace(10, 100, 50, NULL) == TMD_E_ARG);
+    tmd_enc_in ein;
+    tmd_enc_out eout;
+    memset(&ein, 0, sizeof(ein));
+    memset(&eout, 0, sizeof(eout));
+    EXPECT(tmd_encode(NULL, &ein, &eout, NULL, 0, NULL) == TMD_E_ARG);
+    EXPECT(tmd_set_schedule(NULL, 64, 0) == TMD_E_ARG);
     EXPECT(tmd_set_profiling(NULL, 1u) == TMD_E_ARG);
     EXPECT(tmd_stage_times(NULL, NULL, 0, NULL) == TMD_E_ARG);
     EXPECT(strcmp(tmd_stage_name(0), "tilesum") == 0 && strcmp(tmd_stage_name(99), "") == 0);

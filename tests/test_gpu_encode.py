@@ -1,0 +1,77 @@
+"""The GPU encoder (tmd_encode) against the oracle's encoder, bit for bit:
+header arrays, per-cluster steps and residuals, unattached bin counts and
+differences, and the number of mid-track headers; then the GPU decode of the
+GPU encoding restores the quantised clusters exactly (the round trip
+decode(encode(x)) == quantize(x)).  Inputs: exact helices with Gaussian
+noise (several fields, including 0), tracks the model has to split (side
+change, more than 255 clusters, residuals beyond int16), unattached clusters
+with equal positions (ordered by their charges), and sizes that take many
+blocks of the sort and of the header scan."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import physgen as pg
+from test_oracle_roundtrip import _manual_phys
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tmd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2411_02206_amd as m
+    return m
+
+
+def check_encode(tmd, phys, bz, label):
+    exp, exp_split = oracle.encode(phys, bz=bz)
+    got, got_split = tmd.encode(phys, bz=bz)
+    for k in exp:
+        assert got[k].dtype == exp[k].dtype, (label, k)
+        assert np.array_equal(exp[k], got[k]), (label, k, exp[k].shape, got[k].shape)
+    assert got_split == exp_split, (label, got_split, exp_split)
+    # the GPU decode of the GPU encoding: quantize(x), in the canonical layout
+    out, flags = tmd.decode(tmd.to_device(got), bz=bz)
+    res = tmd.to_numpy(out)
+    want = pg.expected_clusters(phys)
+    for k in want:
+        assert np.array_equal(want[k], res[k]), (label, "roundtrip", k)
+    assert flags == 0, (label, flags)
+    return exp_split
+
+
+@pytest.mark.parametrize("seed,bz", [(0, 0.5), (1, 0.5), (2, 0.0), (3, 2.0), (4, -0.5)])
+def test_encode_physical(tmd, seed, bz):
+    phys = pg.generate(seed=seed, n_tracks=300, n_un=5000, bz=bz)
+    check_encode(tmd, phys, bz, f"seed {seed} bz {bz}")
+
+
+def test_encode_splits(tmd):
+    rng = np.random.default_rng(3)
+    side_change = [(i % 18 if i < 5 else 18 + i % 18, 40 + i, 20.0 + 0.3 * i, 900.0 + i, 0.1) for i in range(10)]
+    zigzag = [(3, 10 + (i % 2), 30.0 + rng.normal(0, 0.02), 1000.0 + 0.1 * i, 0.0) for i in range(300)]
+    jumpy = [(5, 20 + i, 40.0 + (1500.0 if i == 6 else 0.0), 800.0 + i, 0.0) for i in range(12)]
+    un = [(1, 2, 3.25, 4.0, 5, 6), (1, 2, 3.25, 4.0, 5, 5), (1, 2, 3.25, 4.0, 4, 9), (0, 0, 0.0, 0.0, 0, 0)]
+    phys = _manual_phys([(0.5, 0.2, side_change), (1.0, 0.0, zigzag), (0.2, 0.0, jumpy)], un=un)
+    assert check_encode(tmd, phys, 0.5, "splits") >= 3
+
+
+def test_encode_many_blocks(tmd):
+    """Enough clusters for hundreds of header-scan blocks and unattached
+    clusters for dozens of sort tiles (with many equal times in a bin)."""
+    phys = pg.generate(seed=9, n_tracks=6000, n_un=150000, bz=0.5)
+    rng = np.random.default_rng(9)
+    phys["un_time"] = np.floor(rng.uniform(0, 50, phys["un_time"].shape[0]))  # many ties
+    check_encode(tmd, phys, 0.5, "many blocks")
+
+
+def test_encode_empty_and_bad_input(tmd):
+    phys = pg.generate(seed=1, n_tracks=5, n_un=0, bz=0.5)
+    check_encode(tmd, phys, 0.5, "no unattached")
+    bad = pg.generate(seed=1, n_tracks=5, n_un=10, bz=0.5)
+    bad["un_pad"] = bad["un_pad"].copy()
+    bad["un_pad"][3] = 5000.0   # 160000 in 1/32 pad: beyond 16 bits
+    with pytest.raises(tmd.TmdError):
+        tmd.encode(bad, bz=0.5)

@@ -86,3 +86,18 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_LIB", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_kernel_symbols_agree_between_host_and_device():
+    """Every kernel is registered by the host code under the symbol its
+    device code object defines (a parameter type that differs between the two
+    compilations, such as an address-space-qualified pointer, would leave the
+    launch without a kernel)."""
+    data = open(_lib.LIB_PATH, "rb").read()
+    names = {}
+    for m in re.finditer(rb"_ZN12_GLOBAL__N_1(\d+)(k_[A-Za-z0-9_]+?)E[A-Za-z0-9_]*", data):
+        full = m.group(0).split(b".")[0]
+        names.setdefault(m.group(2), set()).add(full)
+    assert len(names) >= 15
+    bad = {k: v for k, v in names.items() if len(v) != 1}
+    assert not bad, bad
