@@ -58,6 +58,9 @@ extern "C" {
 #define TMD_F_TIME 64u  /* decoded or header time outside [0, 2^24 - 1] (clamped) */
 #define TMD_F_COUNT 128u /* sum of track lengths != n_attached, or sum of un_count != n_unattached:
                             streams are cut at the declared sizes */
+#define TMD_F_CODED 256u /* (tmd_decode_rans) the entropy-coded input is not a well-formed coded frame of
+                            its shape: the arrays decoded from it are undefined (the decode of them is
+                            still safe) */
 
 /* plan flags */
 #define TMD_PLAN_GRAPH 1u   /* capture the launch sequence in a HIP graph and replay it */
@@ -200,7 +203,7 @@ int tmd_decode_shapes(tmd_plan_t *plan, const tmd_frame_shape *shapes, const tmd
  *
  * Flags of frame `frame` from the last tmd_decode on this plan; waits for that
  * decode to finish.  Returns TMD_OK if no flag is set, TMD_E_INPUT if
- * TMD_F_COUNT is set, TMD_E_STREAM if another flag is set, TMD_E_ARG for a bad
+ * TMD_F_COUNT or TMD_F_CODED is set, TMD_E_STREAM if another flag is set, TMD_E_ARG for a bad
  * frame index; *flags receives the bits.
  */
 int tmd_status(tmd_plan_t *plan, uint32_t frame, uint32_t *flags);
@@ -350,6 +353,39 @@ int tmd_encode_workspace(uint32_t n_tracks, uint32_t n_clusters, uint32_t n_unat
  */
 int tmd_encode(tmd_plan_t *plan, const tmd_enc_in *in, tmd_enc_out *out, void *workspace, size_t workspace_bytes,
                void *stream);
+
+/*
+ * Defines: the entropy decoding that comes right before the track-model
+ * decoding (section 4; the paper's compressed time frames are ANS-coded, in a
+ * format of its reference that this project does not have).  The coded format
+ * here is this project's:
+ *   - the 19 arrays of tmd_frame_in, in that order, as 39 byte planes (plane
+ *     p of an array of w-byte little-endian elements holds byte p of each);
+ *   - per plane a static model: frequencies f[0..255] summing to 2^12;
+ *   - the plane's symbols in chunks of 32768, symbol i of a chunk in
+ *     interleaved stream i mod 64; each stream is rANS with a 32-bit state in
+ *     [2^23, 2^31), byte-wise renormalisation, its final state first (4 bytes,
+ *     little endian), then its renormalisation bytes in reading order.
+ * Bytes (little endian): a 64-byte header ("TMDR", version 1, n_tracks,
+ * n_attached, n_unattached, 0), the u64 offset of each of the 39 planes, then
+ * the planes, each on an 8-byte boundary: f[256] as u16, for each chunk the
+ * u32 offsets of its 64 streams and the end of the last (from the start of
+ * the plane's data), then the data.
+ *
+ * tmd_rans_workspace: bytes of the area where tmd_decode_rans puts the
+ * decoded arrays of n_frames frames of these shapes.
+ * tmd_decode_rans: decode the coded frames (coded[i], coded_bytes[i]: DEVICE
+ * buffers) into rans_workspace, then decode them as tmd_decode_shapes does
+ * (shapes[i] no larger than the plan's; workspace as for tmd_decode), all on
+ * `stream`.  A frame whose coded data is malformed gets TMD_F_CODED in its
+ * status (tmd_status).
+ * Errors: TMD_E_ARG (null or misaligned pointer, a shape above the plan's),
+ * and those of tmd_decode_shapes.
+ */
+int tmd_rans_workspace(const tmd_frame_shape *shapes, uint32_t n_frames, size_t *bytes);
+int tmd_decode_rans(tmd_plan_t *plan, const tmd_frame_shape *shapes, const uint8_t *const *coded,
+                    const uint64_t *coded_bytes, tmd_frame_out *out, void *workspace, void *rans_workspace,
+                    void *stream);
 
 /* Static message for a return code. */
 const char *tmd_strerror(int code);

@@ -87,6 +87,12 @@ def lib():
         L.oracle_sat.restype = C.c_int32
         L.oracle_clamp_snp.argtypes = [C.c_float, C.POINTER(C.c_uint32)]
         L.oracle_clamp_snp.restype = C.c_float
+        L.oracle_rans_bound.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
+        L.oracle_rans_bound.restype = C.c_uint64
+        L.oracle_rans_encode.argtypes = [C.POINTER(P), C.c_uint32, C.c_uint32, C.c_uint32, P, C.c_uint64]
+        L.oracle_rans_encode.restype = C.c_uint64
+        L.oracle_rans_decode.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(P)]
+        L.oracle_rans_decode.restype = C.c_int
         L.oracle_fp_canary.argtypes = [C.c_float, C.c_float, C.c_float]
         L.oracle_fp_canary.restype = C.c_float
         _LIB = L
@@ -225,3 +231,37 @@ def clamp_snp(v):
 
 def fp_canary(a, b, c):
     return np.float32(lib().oracle_fp_canary(C.c_float(a), C.c_float(b), C.c_float(c)))
+
+
+# the 19 arrays of a frame in coded order (rans_oracle.c), with their types
+RANS_ARRAYS = TRACK_FIELDS + CLUSTER_FIELDS + [("un_count", np.uint32)] + UNATT_FIELDS
+
+
+def rans_encode(frame):
+    """Entropy-code the 19 arrays of a frame (rans_oracle.c's format).
+    Returns the coded bytes (numpy uint8)."""
+    nt, na, nu = frame_sizes(frame)
+    arrs = [np.ascontiguousarray(frame[k], dt) for k, dt in RANS_ARRAYS]
+    ptrs = (P * len(arrs))(*[a.ctypes.data_as(P) for a in arrs])
+    cap = int(lib().oracle_rans_bound(nt, na, nu))
+    dst = np.zeros(cap, np.uint8)
+    n = int(lib().oracle_rans_encode(ptrs, nt, na, nu, dst.ctypes.data_as(P), cap))
+    if n == 0:
+        raise RuntimeError("oracle_rans_encode: buffer too small")
+    return dst[:n].copy()
+
+
+def rans_decode(blob, shape):
+    """Decode coded bytes of a frame of shape (n_tracks, n_attached,
+    n_unattached) back into its 19 arrays."""
+    nt, na, nu = shape
+    cnt = {"trk": nt, "cls": na, "un": nu}
+    out = {}
+    for k, dt in RANS_ARRAYS:
+        out[k] = np.zeros(NBIN if k == "un_count" else cnt[k.split("_")[0]], dt)
+    ptrs = (P * len(RANS_ARRAYS))(*[out[k].ctypes.data_as(P) for k, _ in RANS_ARRAYS])
+    blob = np.ascontiguousarray(blob, np.uint8)
+    rc = lib().oracle_rans_decode(blob.ctypes.data_as(P), blob.size, nt, na, nu, ptrs)
+    if rc != 0:
+        raise ValueError("oracle_rans_decode: not a coded frame of this shape")
+    return out

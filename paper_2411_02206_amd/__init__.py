@@ -14,11 +14,11 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (E_ARG, E_CAPACITY, E_HIP, E_INPUT, E_SCRATCH, E_STREAM, F_COUNT, F_HDR, F_PAD,  # noqa: F401
+from ._lib import (E_ARG, E_CAPACITY, E_HIP, E_INPUT, E_SCRATCH, E_STREAM, F_CODED, F_COUNT, F_HDR, F_PAD,  # noqa: F401
                    F_ROT, F_ROW, F_SEC, F_SNP, F_TIME, IN_FIELDS, NBIN, NROW, NSEC, OK, OUT_FIELDS, PLAN_GRAPH,
                    STATIC_SCRATCH_BYTES, TmdError)
 
-__all__ = ["Plan", "Pipeline", "decode", "encode", "to_device", "to_host", "alloc_out", "alloc_host_out", "to_numpy",
+__all__ = ["Plan", "Pipeline", "decode", "decode_rans", "encode", "to_device", "to_host", "alloc_out", "alloc_host_out", "to_numpy",
            "version", "tables"]
 
 # element types of the frame arrays; unsigned 16/32-bit data travel in signed
@@ -188,6 +188,35 @@ class Plan:
         _lib.check(_lib.lib().tmd_decode_static(self._h, arr, fin, fout, C.c_void_p(stream.cuda_stream)),
                    "tmd_decode_static")
 
+    def rans_workspace_bytes(self, shapes=None):
+        shapes = shapes or self.shapes
+        arr = (_lib.FrameShape * len(shapes))(*[_lib.FrameShape(*(int(v) for v in sh)) for sh in shapes])
+        b = C.c_size_t()
+        _lib.check(_lib.lib().tmd_rans_workspace(arr, len(shapes), C.byref(b)), "tmd_rans_workspace")
+        return int(b.value)
+
+    def decode_rans(self, coded, outs, workspace, rans_workspace, stream=None, shapes=None):
+        """Entropy-decode the coded frames (device uint8 tensors in the format
+        of include/tmd.h) into rans_workspace and decode them
+        (tmd_decode_rans)."""
+        torch = _torch()
+        n = len(self.shapes)
+        shapes = shapes or self.shapes
+        if len(coded) != n or len(outs) != n or len(shapes) != n:
+            raise ValueError(f"plan has {n} frames")
+        arr = (_lib.FrameShape * n)(*[_lib.FrameShape(*(int(v) for v in sh)) for sh in shapes])
+        ptrs = (C.c_void_p * n)(*[c.data_ptr() for c in coded])
+        sizes = (C.c_uint64 * n)(*[c.numel() for c in coded])
+        fout = (_lib.FrameOut * n)()
+        for i in range(n):
+            for k in OUT_FIELDS:
+                setattr(fout[i], k, _ptr(outs[i][k]))
+            fout[i].capacity = int(outs[i]["capacity"])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _lib.check(_lib.lib().tmd_decode_rans(self._h, arr, ptrs, sizes, fout, _ptr(workspace), _ptr(rans_workspace),
+                                              C.c_void_p(stream.cuda_stream)), "tmd_decode_rans")
+
     def status(self, frame=0):
         """Flag bits of `frame` from the last decode (waits for it)."""
         f = C.c_uint32()
@@ -291,6 +320,23 @@ def encode(phys, bz=0.5, device="cuda", stream=None, plan=None):
     if own:
         plan.free()
     return res, int(c[1])
+
+
+def decode_rans(coded, shape, bz=0.5, device="cuda"):
+    """Decode one entropy-coded frame (bytes in the format of include/tmd.h,
+    numpy or a device tensor) of the given shape.  Returns (outputs, flags)."""
+    torch = _torch()
+    if not hasattr(coded, "is_cuda"):
+        coded = torch.from_numpy(np.ascontiguousarray(coded, np.uint8)).to(device)
+    shape = tuple(int(v) for v in shape)
+    plan = Plan([shape], bz=bz)
+    out = alloc_out(shape, device)
+    ws = plan.alloc_workspace(device)
+    rws = torch.empty(max(plan.rans_workspace_bytes(), 256), dtype=torch.uint8, device=device)
+    plan.decode_rans([coded], [out], ws, rws)
+    flags = plan.status(0)
+    plan.free()
+    return out, flags
 
 
 def to_host(frame, pin=True):

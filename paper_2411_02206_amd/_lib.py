@@ -15,7 +15,7 @@ MAX_TRACKS = 1 << 24
 
 OK, E_ARG, E_CAPACITY, E_INPUT, E_STREAM, E_HIP, E_SCRATCH = 0, -1, -2, -3, -4, -5, -6
 STATIC_SCRATCH_BYTES = 512 << 20
-F_HDR, F_SEC, F_ROW, F_ROT, F_SNP, F_PAD, F_TIME, F_COUNT = 1, 2, 4, 8, 16, 32, 64, 128
+F_HDR, F_SEC, F_ROW, F_ROT, F_SNP, F_PAD, F_TIME, F_COUNT, F_CODED = 1, 2, 4, 8, 16, 32, 64, 128, 256
 PLAN_GRAPH = 1
 PIPE_MAX_DEPTH = 8
 
@@ -105,6 +105,11 @@ def lib():
         L.tmd_encode_workspace.restype = C.c_int
         L.tmd_encode.argtypes = [P, C.POINTER(EncIn), C.POINTER(EncOut), P, C.c_size_t, P]
         L.tmd_encode.restype = C.c_int
+        L.tmd_rans_workspace.argtypes = [C.POINTER(FrameShape), C.c_uint32, C.POINTER(C.c_size_t)]
+        L.tmd_rans_workspace.restype = C.c_int
+        L.tmd_decode_rans.argtypes = [P, C.POINTER(FrameShape), C.POINTER(P), C.POINTER(C.c_uint64),
+                                      C.POINTER(FrameOut), P, P, P]
+        L.tmd_decode_rans.restype = C.c_int
         L.tmd_pipe_create.argtypes = [C.POINTER(FrameShape), C.c_uint32, C.POINTER(Params), C.POINTER(P)]
         L.tmd_pipe_create.restype = C.c_int
         L.tmd_pipe_run.argtypes = [P, C.c_uint32, C.POINTER(FrameShape), C.POINTER(FrameIn), C.POINTER(FrameOut),

@@ -170,6 +170,7 @@ constexpr int kHRow = NBIN + kNKey;  // per-tile histogram row: bins, then keys
     Q uint16_t *tkey;    /* [nT] scheduling key of each track */                              \
     Q uint32_t *order;   /* [nT] tracks sorted by (key, index): the decode's schedule */      \
     Q uint32_t *status;                                                                       \
+    const Q uint32_t *pre_status; /* flags the frame starts with (entropy decoding), or null */ \
     uint64_t cap; /* entries of the output cluster arrays; every store is checked */          \
     uint32_t nT, nA, nU, ntile, tile0;                                                        \
     uint32_t awaves; /* waves of the attached decode */                                       \
@@ -320,7 +321,10 @@ __global__ __launch_bounds__(kTile) void k_tilesum(const FrameDesc *__restrict__
                                                    uint32_t *__restrict__ work)
 {
     if (blockIdx.x >= ntiles) {  // one extra block per frame: clear its status word
-        if (threadIdx.x == 0) *fd[blockIdx.x - ntiles].status = 0u;
+        if (threadIdx.x == 0) {
+            const FrameDesc &G = fd[blockIdx.x - ntiles];
+            *G.status = G.pre_status ? *G.pre_status : 0u;
+        }
         // (and the first one the attached decode's work counters, if used)
         if (work && blockIdx.x == ntiles && threadIdx.x < kXcds) work[threadIdx.x] = 0u;
         return;
@@ -2152,6 +2156,149 @@ __global__ __launch_bounds__(256) void k_enc_un_delta(const EncDesc E, const uns
 }
 
 // ---------------------------------------------------------------------------
+// Entropy-coded frames (the step before the track-model decode; section 4 and
+// the paper's introduction: the compressed time frame is ANS-coded).  The
+// coded format is this project's, laid out in include/tmd.h: the 19 arrays of
+// a frame in 39 byte planes, each plane a static 12-bit model and chunks of
+// 64 interleaved rANS streams of up to 512 symbols.  One wave decodes one
+// chunk: lane l runs stream l and writes symbols l, l + 64, ... of the chunk
+// into byte p of the elements of its array (the arrays live in the caller's
+// workspace and go straight to the decode).
+// ---------------------------------------------------------------------------
+constexpr int kRansPlanes = 39, kRansArrays = 19, kRansLanes = 64, kRansPerLane = 512;
+constexpr uint32_t kRansChunk = kRansLanes * kRansPerLane;
+constexpr uint32_t kRansLow = 1u << 23;
+constexpr uint32_t kRansHdr = 64;
+constexpr uint32_t kRansBad = TMD_F_CODED;
+
+struct RansDesc {
+    const GLB uint8_t *src;
+    uint64_t size;
+    GLB uint8_t *dst[kRansArrays];
+    uint32_t n[kRansArrays];      // elements of each array
+    uint32_t item0[kRansPlanes + 1];  // first chunk (work item) of each plane
+    GLB uint32_t *err;            // TMD_F_CODED if the data is not a well-formed coded frame
+    uint32_t nT, nA, nU;
+};
+
+__device__ __constant__ const uint8_t kRansWidth[kRansArrays] = {1, 1, 1, 2, 4, 2, 2, 2, 1, 1, 2, 2, 2, 2, 4, 4, 2, 2, 2};
+
+__global__ void k_fill32(uint32_t *p, uint32_t n, uint32_t v)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
+}
+
+__global__ __launch_bounds__(kRansLanes) void k_rans(const RansDesc R)
+{
+    __shared__ uint32_t f[256], c[256];
+    __shared__ uint8_t sym[1 << 12];
+    const uint32_t lane = lane_id();
+    const uint32_t item = blockIdx.x;
+    if (item == 0 && lane == 0) {  // header: "TMDR", version 1, the frame's shape
+        bool ok = R.size >= kRansHdr + 8 * kRansPlanes;
+        if (ok) {
+            uint32_t h[5];
+            for (int q = 0; q < 5; q++) {
+                h[q] = 0;
+                for (int k = 3; k >= 0; k--) h[q] = (h[q] << 8) | R.src[4 + 4 * q + k];
+            }
+            ok = R.src[0] == 'T' && R.src[1] == 'M' && R.src[2] == 'D' && R.src[3] == 'R' && h[0] == 1u &&
+                 h[1] == R.nT && h[2] == R.nA && h[3] == R.nU;
+        }
+        if (!ok) atomicOr(R.err, kRansBad);
+    }
+    uint32_t p = 0;
+    while (p + 1 < (uint32_t)kRansPlanes && R.item0[p + 1] <= item) p++;
+    // plane p -> array a, byte b of its elements
+    uint32_t a = 0, b = p;
+    while (a + 1 < (uint32_t)kRansArrays && b >= kRansWidth[a]) {
+        b -= kRansWidth[a];
+        a++;
+    }
+    const uint32_t w = kRansWidth[a], n = R.n[a];
+    const uint32_t ch = item - R.item0[p];
+    const uint32_t nch = (n + kRansChunk - 1) / kRansChunk;
+    bool bad = false;
+    uint64_t pos = 0;
+    if (kRansHdr + 8 * (p + 1) <= R.size) {
+        for (int q = 7; q >= 0; q--) pos = (pos << 8) | R.src[kRansHdr + 8 * p + q];
+    } else {
+        bad = true;
+    }
+    const uint64_t meta = 512 + 4ull * 65 * nch;  // the plane's model and chunk offsets
+    if (bad || pos > R.size || R.size - pos < meta) {
+        if (lane == 0) atomicOr(R.err, kRansBad);
+        return;
+    }
+    const uint64_t data0 = pos + meta;
+    // the model: frequencies, their prefix, and the symbol of every slot
+    uint32_t fl[4], tot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const uint64_t o = pos + 2 * (4 * lane + q);
+        fl[q] = (uint32_t)R.src[o] | ((uint32_t)R.src[o + 1] << 8);
+        tot += fl[q];
+    }
+    const uint32_t incl = wave_incl_add(tot);
+    uint32_t run = incl - tot;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        f[4 * lane + q] = fl[q];
+        c[4 * lane + q] = run;
+        run += fl[q];
+    }
+    if (readlane(incl, kWave - 1) != (1u << 12)) {
+        if (lane == 0) atomicOr(R.err, kRansBad);
+        return;
+    }
+    __syncthreads();
+    for (uint32_t slot = lane; slot < (1u << 12); slot += kRansLanes) {
+        // the last symbol whose range starts at or below the slot (symbols
+        // of frequency 0 start where the next one does)
+        uint32_t lo = 0, hi = 255;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (c[mid] <= slot) lo = mid;
+            else hi = mid - 1;
+        }
+        sym[slot] = (uint8_t)lo;
+    }
+    __syncthreads();
+    // this lane's stream
+    const uint64_t offs = pos + 512 + 4ull * 65 * ch;
+    auto rd32 = [&](uint64_t o) -> uint32_t {
+        return (uint32_t)R.src[o] | ((uint32_t)R.src[o + 1] << 8) | ((uint32_t)R.src[o + 2] << 16) |
+               ((uint32_t)R.src[o + 3] << 24);
+    };
+    const uint32_t o0 = rd32(offs + 4 * lane), o1 = rd32(offs + 4 * lane + 4);
+    uint64_t ptr = data0 + o0;
+    const uint64_t end = data0 + o1;
+    const uint32_t c0 = ch * kRansChunk;
+    const uint32_t len = n - c0 < kRansChunk ? n - c0 : kRansChunk;
+    uint32_t err = 0;
+    if (o1 < o0 || o1 - o0 < 4 || end > R.size) {
+        err = kRansBad;
+    } else {
+        uint32_t x = rd32(ptr);
+        ptr += 4;
+        GLB uint8_t *dst = R.dst[a];
+        for (uint32_t i = lane; i < len; i += kRansLanes) {
+            const uint32_t slot = x & 0xFFFu;
+            const uint32_t s = sym[slot];
+            x = f[s] * (x >> 12) + slot - c[s];
+            for (int q = 0; q < 4 && x < kRansLow; q++) {  // at most 4 bytes bring x back above 2^23
+                uint32_t byte = 0;
+                if (ptr < end) byte = R.src[ptr++];
+                else err = kRansBad;
+                x = (x << 8) | byte;
+            }
+            dst[(uint64_t)(c0 + i) * w + b] = (uint8_t)s;
+        }
+    }
+    if (__ballot(err != 0) && lane == 0) atomicOr(R.err, kRansBad);
+}
+
+// ---------------------------------------------------------------------------
 // workspace of tmd_decode_static: device memory of the library itself, one
 // array per GPU (the kernels never see its host-side name, only the address
 // hipGetSymbolAddress gives for the current device)
@@ -2623,8 +2770,29 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
     return tmd_decode_shapes(P, P->shapes.data(), in, out, workspace, stream);
 }
 
+}  // extern "C"
+
+namespace {
+int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
+                void *workspace, void *stream, const uint32_t *const *pre_status);
+}  // namespace
+
+extern "C" {
+
 int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
                       void *workspace, void *stream)
+{
+    return decode_impl(P, shapes, in, out, workspace, stream, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+// tmd_decode_shapes, with an optional device word per frame that the frame's
+// status starts from (flags of a step before the decode)
+int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
+                void *workspace, void *stream, const uint32_t *const *pre_status)
 {
     if (!P || !shapes || !in || !out || !workspace) return TMD_E_ARG;
     if ((uintptr_t)workspace % 256) return TMD_E_ARG;
@@ -2682,6 +2850,7 @@ int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_fr
         D.tkey = (uint16_t *)(ws + L.tkey);
         D.order = (uint32_t *)(ws + L.order);
         D.status = P->d_status + f;
+        D.pre_status = pre_status ? pre_status[f] : nullptr;
         D.cap = O.capacity;
         D.nT = S.n_tracks; D.nA = S.n_attached; D.nU = S.n_unattached;
         D.ntile = (S.n_tracks + kTile - 1) / kTile;  // <= the planned L.ntile
@@ -2763,13 +2932,17 @@ int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_fr
     return rc;
 }
 
+}  // namespace
+
+extern "C" {
+
 int tmd_status(tmd_plan_t *P, uint32_t frame, uint32_t *flags)
 {
     if (!P || !flags || frame >= P->n_frames) return TMD_E_ARG;
     HIP_TRY(hipEventSynchronize(P->done));
     uint32_t f = P->h_status[frame];
     *flags = f;
-    if (f & TMD_F_COUNT) return TMD_E_INPUT;
+    if (f & (TMD_F_COUNT | TMD_F_CODED)) return TMD_E_INPUT;
     if (f) return TMD_E_STREAM;
     return TMD_OK;
 }
@@ -3002,6 +3175,120 @@ int tmd_encode(tmd_plan_t *P, const tmd_enc_in *in, tmd_enc_out *out, void *work
     hipError_t e = hipGetLastError();
     if (cur != P->device) (void)hipSetDevice(cur);
     return e == hipSuccess ? TMD_OK : TMD_E_HIP;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Entropy-coded frames: host side
+// ---------------------------------------------------------------------------
+namespace {
+
+// element counts of the 19 arrays of a frame, in tmd_frame_in order
+void rans_counts(const tmd_frame_shape &S, uint32_t *n)
+{
+    for (int i = 0; i < 8; i++) n[i] = S.n_tracks;
+    for (int i = 8; i < 14; i++) n[i] = S.n_attached;
+    n[14] = NBIN;
+    for (int i = 15; i < 19; i++) n[i] = S.n_unattached;
+}
+
+constexpr uint8_t kRansWidthHost[kRansArrays] = {1, 1, 1, 2, 4, 2, 2, 2, 1, 1, 2, 2, 2, 2, 4, 4, 2, 2, 2};
+constexpr int rans_width_sum(int a) { return a == kRansArrays ? 0 : kRansWidthHost[a] + rans_width_sum(a + 1); }
+static_assert(rans_width_sum(0) == kRansPlanes, "one plane per byte of the element widths");
+
+// bytes of one frame's decoded arrays (each 256-byte aligned) and its error word
+size_t rans_frame_bytes(const tmd_frame_shape &S)
+{
+    uint32_t n[kRansArrays];
+    rans_counts(S, n);
+    size_t b = 256;
+    for (int a = 0; a < kRansArrays; a++) b += align256((size_t)kRansWidthHost[a] * std::max<uint32_t>(n[a], 1));
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tmd_rans_workspace(const tmd_frame_shape *shapes, uint32_t n_frames, size_t *bytes)
+{
+    if (!shapes || !bytes || n_frames == 0) return TMD_E_ARG;
+    size_t b = 0;
+    for (uint32_t f = 0; f < n_frames; f++) b += rans_frame_bytes(shapes[f]);
+    *bytes = b;
+    return TMD_OK;
+}
+
+int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t *const *coded,
+                    const uint64_t *coded_bytes, tmd_frame_out *out, void *workspace, void *rans_workspace,
+                    void *stream)
+{
+    if (!P || !shapes || !coded || !coded_bytes || !out || !workspace || !rans_workspace) return TMD_E_ARG;
+    if ((uintptr_t)rans_workspace % 256) return TMD_E_ARG;
+    const uint32_t nf = P->n_frames;
+    for (uint32_t f = 0; f < nf; f++) {
+        const tmd_frame_shape &C = P->shapes[f], &S = shapes[f];
+        if (!coded[f] || S.n_tracks > C.n_tracks || S.n_attached > C.n_attached || S.n_unattached > C.n_unattached)
+            return TMD_E_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != P->device) HIP_TRY(hipSetDevice(P->device));
+    std::vector<tmd_frame_in> in(nf);
+    std::vector<const uint32_t *> pre(nf);
+    char *ws = (char *)rans_workspace;
+    int rc = TMD_OK;
+    // (the previous call on this plan may still read these arrays)
+    if (P->called && hipStreamWaitEvent(s, P->done, 0) != hipSuccess) rc = TMD_E_HIP;
+    for (uint32_t f = 0; f < nf && rc == TMD_OK; f++) {
+        const tmd_frame_shape &S = shapes[f];
+        RansDesc R;
+        memset(&R, 0, sizeof(R));
+        R.src = (const GLB uint8_t *)coded[f];
+        R.size = coded_bytes[f];
+        R.nT = S.n_tracks;
+        R.nA = S.n_attached;
+        R.nU = S.n_unattached;
+        rans_counts(S, R.n);
+        uint32_t *err = (uint32_t *)ws;
+        R.err = (GLB uint32_t *)err;
+        size_t off = 256;
+        void *arr[kRansArrays];
+        for (int a = 0; a < kRansArrays; a++) {
+            arr[a] = ws + off;
+            R.dst[a] = (GLB uint8_t *)arr[a];
+            off += align256((size_t)kRansWidthHost[a] * std::max<uint32_t>(R.n[a], 1));
+        }
+        uint32_t items = 0, plane = 0;
+        for (int a = 0; a < kRansArrays; a++)
+            for (int b = 0; b < kRansWidthHost[a]; b++) {
+                R.item0[plane++] = items;
+                items += (R.n[a] + kRansChunk - 1) / kRansChunk;
+            }
+        R.item0[kRansPlanes] = items;
+        tmd_frame_in &I = in[f];
+        I.trk_ncls = (const uint8_t *)arr[0]; I.trk_sec0 = (const uint8_t *)arr[1]; I.trk_row0 = (const uint8_t *)arr[2];
+        I.trk_pad0 = (const uint16_t *)arr[3]; I.trk_time0 = (const uint32_t *)arr[4];
+        I.trk_qpt = (const int16_t *)arr[5]; I.trk_snp = (const int16_t *)arr[6]; I.trk_tgl = (const int16_t *)arr[7];
+        I.cls_row_diff = (const int8_t *)arr[8]; I.cls_sec_diff = (const uint8_t *)arr[9];
+        I.cls_pad_res = (const int16_t *)arr[10]; I.cls_time_res = (const int16_t *)arr[11];
+        I.cls_qtot = (const uint16_t *)arr[12]; I.cls_qmax = (const uint16_t *)arr[13];
+        I.un_count = (const uint32_t *)arr[14]; I.un_time_diff = (const uint32_t *)arr[15];
+        I.un_pad_diff = (const uint16_t *)arr[16]; I.un_qtot = (const uint16_t *)arr[17];
+        I.un_qmax = (const uint16_t *)arr[18];
+        pre[f] = err;
+        // the error word starts at 0 (a fill kernel, not a memset node, so the
+        // sequence can be captured in a graph)
+        hipLaunchKernelGGL(k_fill32, dim3(1), dim3(64), 0, s, err, 1u, 0u);
+        if (items) hipLaunchKernelGGL(k_rans, dim3(items), dim3(kRansLanes), 0, s, R);
+        if (hipGetLastError() != hipSuccess) rc = TMD_E_HIP;
+        ws += rans_frame_bytes(S);
+    }
+    if (cur != P->device) (void)hipSetDevice(cur);
+    if (rc != TMD_OK) return rc;
+    return decode_impl(P, shapes, in.data(), out, workspace, stream, pre.data());
 }
 
 }  // extern "C"

@@ -63,6 +63,17 @@ def main():
     phys = pg.generate(seed=7, n_tracks=60, n_un=500, bz=0.5)
     enc, nsplit = oracle.encode(phys, bz=0.5)
     print(f"encode phys {digest(enc, nsplit)}", flush=True)
+    for name, fr, _ in cases[:3]:
+        blob = oracle.rans_encode(fr)
+        back = oracle.rans_decode(blob, oracle.frame_sizes(fr))
+        same = all(np.array_equal(fr[k], back[k]) for k, _ in oracle.RANS_ARRAYS)
+        bad = 0
+        for cut in (0, 16, blob.size // 3, blob.size - 1):
+            try:
+                oracle.rans_decode(blob[:cut], oracle.frame_sizes(fr))
+            except ValueError:
+                bad += 1
+        print(f"rans {name} {blob.size} {same} {bad}", flush=True)
 
 
 if __name__ == "__main__":

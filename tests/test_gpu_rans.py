@@ -1,0 +1,86 @@
+"""Entropy-coded frames on the GPU (tmd_decode_rans): frames coded by the
+oracle's rANS coder are decoded by the library's rANS kernel into its
+workspace and then by the track-model decode in the same call; the result
+must equal the oracle's decode of the uncoded frame, bit for bit.  Also: a
+batched graph plan over several coded frames, and malformed coded data
+(wrong magic, wrong shape, truncated, corrupted streams), which must be
+flagged or at least decoded safely."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from test_gpu_parity import _garbage
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tmd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2411_02206_amd as m
+    return m
+
+
+def check(tmd, exp, est, out, flags, label):
+    got = tmd.to_numpy(out)
+    for k in exp:
+        assert np.array_equal(exp[k], got[k]), (label, k)
+    assert flags == est, (label, flags, est)
+
+
+@pytest.mark.parametrize("case", ["tiny", "frame", "stress", "garbage", "empty"])
+def test_coded_frame_decodes_like_the_plain_one(tmd, case):
+    if case == "tiny":
+        fr = synth.make_frame(synth.spec_for("tiny"))
+    elif case == "frame":
+        fr = synth.make_frame(synth.spec_for("frame", collisions=3))
+    elif case == "stress":
+        fr = synth.make_frame(synth.spec_for("stress", collisions=1))
+    elif case == "garbage":
+        fr = _garbage(21)
+    else:
+        fr = {k: np.zeros(0 if k != "un_count" else tmd.NBIN, dt) for k, dt in oracle.RANS_ARRAYS}
+    bz = 5.0 if case == "garbage" else 0.5
+    blob = oracle.rans_encode(fr)
+    exp, est = oracle.decode(fr, bz=bz)
+    out, flags = tmd.decode_rans(blob, oracle.frame_sizes(fr), bz=bz)
+    check(tmd, exp, est, out, flags, case)
+
+
+def test_coded_frames_batched_graph(tmd):
+    import torch
+    frames = synth.make_frames(synth.batch_specs("batched", n_frames=4, coll_range=(1, 4)))
+    shapes = [tmd.frame_shape(f) for f in frames]
+    coded = [torch.from_numpy(oracle.rans_encode(f)).cuda() for f in frames]
+    plan = tmd.Plan(shapes, flags=tmd.PLAN_GRAPH)
+    ws = plan.alloc_workspace()
+    rws = torch.empty(plan.rans_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    outs = [tmd.alloc_out(s) for s in shapes]
+    for rep in range(2):
+        plan.decode_rans(coded, outs, ws, rws)
+        torch.cuda.synchronize()
+        for i, f in enumerate(frames):
+            check(tmd, *oracle.decode(f), outs[i], plan.status(i), (rep, i))
+    plan.free()
+
+
+def test_malformed_coded_data_is_flagged(tmd):
+    fr = synth.make_frame(synth.spec_for("tiny"))
+    shape = oracle.frame_sizes(fr)
+    blob = oracle.rans_encode(fr)
+    bad_magic = blob.copy()
+    bad_magic[1] = ord("X")
+    for label, b, sh in (("magic", bad_magic, shape), ("truncated", blob[:blob.size // 2], shape),
+                         ("header only", blob[:200], shape), ("shape", blob, (shape[0], shape[1] - 1, shape[2]))):
+        out, flags = tmd.decode_rans(b, sh)
+        assert flags & tmd.F_CODED, label
+    # corrupted stream bytes: decoded safely (whatever the values), flagged or not
+    rng = np.random.default_rng(0)
+    noisy = blob.copy()
+    idx = rng.integers(400, noisy.size, 2000)
+    noisy[idx] ^= 0x5A
+    out, flags = tmd.decode_rans(noisy, shape)
+    got = tmd.to_numpy(out)
+    assert got["row_offset"].size == tmd.NBIN + 1

@@ -1,5 +1,6 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only,
-no GPU): the oracle (valid, garbage and encoded frames) and the host side of
+no GPU): the oracle (valid, garbage and encoded frames, rANS coding
+of frames and rejection of malformed coded data) and the host side of
 libtmd (tables, messages, argument checks, plan creation without a GPU).
 Any report aborts the child process.  The oracle's sanitized results must
 equal those of its normal build."""
@@ -23,7 +24,8 @@ def test_oracle_under_sanitizers(tmp_path):
     so = str(tmp_path / "liboracle_san.so")
     subprocess.run(["gcc", "-O1", "-g", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-shared", "-fPIC",
                     "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
-                    "-o", so, os.path.join(ROOT, "oracle", "tmd_oracle.c"), "-lm"], check=True)
+                    "-o", so, os.path.join(ROOT, "oracle", "tmd_oracle.c"),
+                    os.path.join(ROOT, "oracle", "rans_oracle.c"), "-lm"], check=True)
     script = os.path.join(HERE, "run_oracle.py")
     env = dict(os.environ, TMD_ORACLE_LIB=so, LD_PRELOAD=_gcc_lib("libasan.so"), **SAN_ENV)
     san = subprocess.run([sys.executable, script], env=env, capture_output=True, text=True, timeout=600)
@@ -32,7 +34,7 @@ def test_oracle_under_sanitizers(tmp_path):
     ref = subprocess.run([sys.executable, script], env=env, capture_output=True, text=True, timeout=600)
     assert ref.returncode == 0, ref.stderr[-4000:]
     assert san.stdout.splitlines() == ref.stdout.splitlines()
-    assert len(san.stdout.splitlines()) == 6
+    assert len(san.stdout.splitlines()) == 9
 
 
 def test_library_host_code_under_sanitizers(tmp_path):
