@@ -8,7 +8,9 @@ graph and replayed.  A step is one replay: the whole decode of the 64 frames
 decode, status) with inputs resident in HBM.  The same frames decoded by 64
 plain single-frame plans are timed beside it.
 
-Other workloads: `frame` (one frame of 100 collisions, plain single launch),
+Other workloads: `coded` (the batched frames entropy-coded on the GPU by
+tmd_encode_rans; a step decodes the coded bytes and then the frames, one
+tmd_decode_rans call), `frame` (one frame of 100 collisions, plain single launch),
 `stress` (500 collisions with loopers, plain launch), `stress-batched` (the
 stress frame through a graph plan), `tiny`, `served` (Poisson arrivals,
 continuous batching, p50/p99 at several offered loads) and `pipeline` (frames
@@ -45,6 +47,10 @@ WORKLOADS = {
                "track lengths U{5..152}, 10% sector crossers, 40% unattached) decoded by one plan whose "
                "launch sequence is one captured HIP graph, replayed per step; compared with 64 plain "
                "per-frame decodes",
+    "coded": "the 64 batched frames entropy-coded (39 byte planes per frame, static 12-bit models, 64 "
+             "interleaved rANS streams per 32768-symbol chunk; coded on the GPU before the timed steps); a "
+             "step is one tmd_decode_rans call: the entropy decoding of every frame, then the graph plan's "
+             "decode of all frames; compared with the same plan decoding the uncoded frames",
     "frame": "one Pb-Pb-like time frame: 100 collisions x 2000 tracks, 36 sectors, 152 rows, "
              "track lengths U{5..152}, 10% sector crossers, 40% unattached; plain single launch",
     "stress": "high-occupancy stress frame: 500 collisions x 2000 tracks, 15% low-pT loopers, "
@@ -100,19 +106,29 @@ def host_threads():
     return max(1, min(n, 16))
 
 
-def oracle_single(frames, bz, budget_s):
+def oracle_single(frames, bz, budget_s, coded=False):
     """The plain C oracle on one core over the frames in order, until the
-    budget is spent (at least one frame)."""
+    budget is spent (at least one frame).  coded: each frame is first coded
+    by the oracle's rANS coder (not timed), then its entropy decoding and
+    track-model decoding are timed."""
     import oracle
-    t0 = time.perf_counter()
+    t_start = time.perf_counter()
+    dt = 0.0
     done = clusters = 0
     for fr in frames:
-        oracle.decode(fr, bz=bz)
+        if coded:
+            shape = oracle.frame_sizes(fr)
+            blob = oracle.rans_encode(fr)
+            t0 = time.perf_counter()
+            oracle.decode(oracle.rans_decode(blob, shape), bz=bz)
+        else:
+            t0 = time.perf_counter()
+            oracle.decode(fr, bz=bz)
+        dt += time.perf_counter() - t0
         done += 1
         clusters += int(fr["cls_qtot"].shape[0] + fr["un_qtot"].shape[0])
-        if time.perf_counter() - t0 >= budget_s:
+        if time.perf_counter() - t_start >= budget_s:
             break
-    dt = time.perf_counter() - t0
     return clusters / dt, done, clusters, dt
 
 
@@ -131,10 +147,10 @@ def oracle_all(frames, bz, threads):
     return res, clusters / dt, dt
 
 
-def cpu_baseline_entry(single, all_core, n_frames_total, sample_desc):
+def cpu_baseline_entry(single, all_core, n_frames_total, sample_desc, what="decoded"):
     rate1, done, clusters, dt = single
     line = {"value": rate1, "unit": "clusters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of {n_frames_total} {sample_desc} decoded one after another by the "
+            "sample": f"{done} of {n_frames_total} {sample_desc} {what} one after another by the "
                       f"single-threaded C oracle ({clusters} clusters, {dt:.1f} s)",
             "cpu_model": cpu_model(), "nproc": os.cpu_count()}
     if all_core is not None:
@@ -157,6 +173,8 @@ def frames_for(workload, args):
     import numpy as np
 
     import synth
+    if workload == "coded":
+        workload = "batched"
     if workload in ("batched", "served"):
         specs = synth.batch_specs(workload, n_frames=args.frames)
     else:
@@ -223,7 +241,7 @@ def main():
         sys.exit(2)
     if args.workload == "pipeline":
         return run_pipeline(args)
-    if args.workload in ("batched", "served", "stress-batched"):
+    if args.workload in ("batched", "served", "stress-batched", "coded"):
         return run_batched(args)
     return run_plain(args)
 
@@ -342,9 +360,10 @@ def run_batched(args):
     nU_all = sum(s[2] for s in shapes)
     print(f"[bench] {args.workload}: {len(frames)} frames, {nT_all} tracks, {n_clusters} clusters "
           f"({'from cache' if cached else f'generated in {gen_s:.1f} s'})", file=sys.stderr, flush=True)
+    coded_run = args.workload == "coded"
     single = None
     if not args.no_cpu:
-        single = oracle_single(frames, args.bz, args.cpu_seconds)
+        single = oracle_single(frames, args.bz, args.cpu_seconds, coded=coded_run)
         print(f"[bench] oracle, one core: {single[0]:.3e} clusters/s over {single[1]} frames",
               file=sys.stderr, flush=True)
 
@@ -364,7 +383,7 @@ def run_batched(args):
 
     # plain: one plan and one launch sequence per frame
     plain = None
-    if len(frames) > 1 and not args.no_plain:
+    if len(frames) > 1 and not args.no_plain and not coded_run:
         plans = [tmd.Plan([s], bz=args.bz) for s in shapes]
         ws = torch.empty(max(p.workspace_bytes for p in plans), dtype=torch.uint8, device="cuda")
         outs_plain = [tmd.alloc_out(s) for s in shapes]
@@ -392,6 +411,33 @@ def run_batched(args):
     schedule, tune_info = autotune.tuned(bplan, ins, outs_b, bws, stream)
     print(f"[bench] schedule {schedule} ({tune_info['cache']})", file=sys.stderr, flush=True)
 
+    coded_info = None
+    if coded_run:
+        # the uncoded frames through the same plan, for comparison
+        t_uncoded = timed(batched_step)
+        # code every frame on the GPU (before the timed steps), then drop
+        # the uncoded inputs: a step reads only the coded bytes
+        enc_ws = torch.empty(max(tmd.rans_encode_sizes(s)[0] for s in shapes), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        coded = [tmd.encode_rans(i, workspace=enc_ws).clone() for i in ins]
+        torch.cuda.synchronize()
+        t_enc = time.perf_counter() - t0
+        del enc_ws
+        ins = None
+        coded_bytes = sum(int(c.numel()) for c in coded)
+        raw_bytes = sum(HDR_BYTES * t + CLUSTER_IN_BYTES * a + UNATT_IN_BYTES * u + 4 * 5472 for t, a, u in shapes)
+        rws = torch.empty(max(bplan.rans_workspace_bytes(), 256), dtype=torch.uint8, device="cuda")
+        print(f"[bench] coded {raw_bytes} B of arrays into {coded_bytes} B in {t_enc:.2f} s "
+              f"(uncoded step {1e3 * t_uncoded:.3f} ms)", file=sys.stderr, flush=True)
+        coded_info = {"array_bytes": raw_bytes, "coded_bytes": coded_bytes,
+                      "coded_fraction": round(coded_bytes / raw_bytes, 4),
+                      "uncoded_ms_per_step": round(1e3 * t_uncoded, 4),
+                      "encode_s_all_frames": round(t_enc, 3)}
+
+        def batched_step():
+            bplan.decode_rans(coded, outs_b, bws, rws, stream)
+
     # per-stage breakdown (a graph with event nodes around every stage),
     # outside the timed steps
     bplan.set_profiling(True)
@@ -401,8 +447,9 @@ def run_batched(args):
     stages, calls = bplan.stage_times()
     avg = {k: v / max(calls, 1) for k, v in stages.items()}
     dominant = max(avg, key=avg.get)
-    # timed replays: event nodes around the dominant kernel only
-    bplan.set_profiling(stages=[dominant])
+    # timed replays: event nodes around the dominant kernel only (and the
+    # entropy decoding, in the coded workload)
+    bplan.set_profiling(stages=[dominant] + (["rans"] if coded_run and dominant != "rans" else []))
     for _ in range(warmup):
         batched_step()
     torch.cuda.synchronize()
@@ -419,6 +466,8 @@ def run_batched(args):
     t_batch = (time.perf_counter() - t0) / steps
     dom_stages, dom_calls = bplan.stage_times()
     dom_ms = dom_stages[dominant] / max(dom_calls, 1)
+    if coded_run:
+        coded_info["rans_ms"] = round(dom_stages["rans"] / max(dom_calls, 1), 4)
     bplan.set_profiling(False)
     lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
     flags = [bplan.status(i) for i in range(len(frames))]
@@ -451,10 +500,18 @@ def run_batched(args):
             got = tmd.to_numpy(outs_b[i])
             oracle_ok &= bool(all(np.array_equal(exp[k], got[k]) for k in exp) and est == flags[i])
             res[i] = None
-        cpu = cpu_baseline_entry(single, (rate_all, threads, dt_all, len(frames)), len(frames),
-                                 "frames of the workload")
+        if coded_run:
+            cpu = cpu_baseline_entry(single, None, len(frames), "frames of the workload (coded by the oracle's "
+                                     "rANS coder, untimed)", what="entropy-decoded and decoded")
+        else:
+            cpu = cpu_baseline_entry(single, (rate_all, threads, dt_all, len(frames)), len(frames),
+                                     "frames of the workload")
 
     kb = kernel_bytes(shapes)
+    if coded_run:
+        # the entropy decoding reads the coded bytes and writes the arrays
+        kb["rans"] = coded_info["coded_bytes"] + coded_info["array_bytes"]
+        coded_info["rans_roofline"] = roofline("rans", kb["rans"], coded_info["rans_ms"], args.workload)
     roof = roofline(dominant, kb.get(dominant), dom_ms, args.workload)
     _, _, all_b = algorithmic_bytes(nT_all, nA_all, nU_all)
     all_b += (len(frames) - 1) * 5472 * BIN_BYTES
@@ -484,6 +541,8 @@ def run_batched(args):
                      "autotune": tune_info},
     }
 
+    if coded_info is not None:
+        line["coded"] = coded_info
     if args.workload == "served":
         line["served"] = run_served(args, ins, shapes, len(frames) / t_batch, schedule)
         line["latency_ms"] = {"p50": line["served"]["100%"]["p50_ms"], "p99": line["served"]["100%"]["p99_ms"]}

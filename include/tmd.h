@@ -387,6 +387,28 @@ int tmd_decode_rans(tmd_plan_t *plan, const tmd_frame_shape *shapes, const uint8
                     const uint64_t *coded_bytes, tmd_frame_out *out, void *workspace, void *rans_workspace,
                     void *stream);
 
+/*
+ * Defines: the coding side of the format above (the paper's frames are
+ * entropy-coded after the track-model encoding, section 4), on the device.
+ * tmd_rans_encode_workspace: for a frame of `shape`, the workspace bytes of
+ * tmd_encode_rans and the coded size it may reach (the capacity it needs).
+ * tmd_encode_rans: code the frame `in` (DEVICE arrays of `shape`, as for
+ * tmd_decode) into `coded` (DEVICE, `capacity` bytes, at least the bound),
+ * and write the coded size to *coded_bytes (a DEVICE u64, 8-byte aligned),
+ * all on `stream` of the current device.  `workspace`: DEVICE, 256-byte
+ * aligned.  The model of each plane: every symbol that occurs gets
+ * max(1, floor(count 2^12 / n)); while their sum is below 2^12 the symbol
+ * with the smallest f n - count 2^12 gets one more, while it is above the
+ * symbol with f > 1 and the largest f n - count 2^12 one less (ties: the
+ * lowest symbol); a plane without symbols has f[0] = 2^12.  The bytes are
+ * those of the format above, alignment gaps zero.
+ * Errors: TMD_E_ARG (null or misaligned pointer, an array of more than 2^30
+ * elements), TMD_E_CAPACITY (capacity below the bound), TMD_E_HIP.
+ */
+int tmd_rans_encode_workspace(const tmd_frame_shape *shape, size_t *workspace_bytes, uint64_t *coded_bound);
+int tmd_encode_rans(const tmd_frame_shape *shape, const tmd_frame_in *in, uint8_t *coded, uint64_t capacity,
+                    uint64_t *coded_bytes, void *workspace, void *stream);
+
 /* Static message for a return code. */
 const char *tmd_strerror(int code);
 
@@ -425,10 +447,12 @@ int tmd_set_schedule(tmd_plan_t *plan, uint32_t tracks_per_wave, uint32_t persis
  * pair of HIP events around each selected stage on its stream.  In
  * TMD_PLAN_GRAPH mode the plan captures a second graph (once per stage mask)
  * with an event-record node before and after each selected stage, and every
- * replay points those nodes at fresh events, so each call is timed on its own.  tmd_stage_times waits for the recorded calls, writes
- * the summed milliseconds of each stage to ms[0 .. n-1] (0 for unselected
- * stages), the number of recorded calls to *calls, and clears the record.
- * Returns the number of stages.
+ * replay points those nodes at fresh events, so each call is timed on its
+ * own.  The last stage ("rans") is the entropy decoding of tmd_decode_rans,
+ * all its frames between one pair of events.  tmd_stage_times waits for the
+ * recorded calls, writes the summed milliseconds of each stage to
+ * ms[0 .. n-1] (0 for unselected stages), the number of recorded calls to
+ * *calls, and clears the record.  Returns the number of stages.
  */
 int tmd_set_profiling(tmd_plan_t *plan, uint32_t stage_mask);
 int tmd_stage_times(tmd_plan_t *plan, double *ms, uint32_t n, uint32_t *calls);

@@ -339,6 +339,38 @@ def decode_rans(coded, shape, bz=0.5, device="cuda"):
     return out, flags
 
 
+def rans_encode_sizes(shape):
+    """(workspace bytes, largest coded size) of tmd_encode_rans for a frame of `shape`."""
+    ws, bound = C.c_size_t(), C.c_uint64()
+    sh = _lib.FrameShape(*(int(v) for v in shape))
+    _lib.check(_lib.lib().tmd_rans_encode_workspace(C.byref(sh), C.byref(ws), C.byref(bound)),
+               "tmd_rans_encode_workspace")
+    return int(ws.value), int(bound.value)
+
+
+def encode_rans(frame, stream=None, workspace=None):
+    """Entropy-code a frame held in device tensors (see to_device) with
+    tmd_encode_rans.  Returns the coded bytes as a device uint8 tensor."""
+    torch = _torch()
+    shape = frame_shape(frame)
+    dev = frame["trk_ncls"].device
+    ws_bytes, bound = rans_encode_sizes(shape)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+    coded = torch.empty(bound, dtype=torch.uint8, device=dev)
+    size = torch.zeros(1, dtype=torch.int64, device=dev)
+    fin = _lib.FrameIn()
+    for k in IN_FIELDS:
+        setattr(fin, k, _ptr(frame[k]))
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    sh = _lib.FrameShape(*shape)
+    _lib.check(_lib.lib().tmd_encode_rans(C.byref(sh), C.byref(fin), _ptr(coded), bound, _ptr(size),
+                                          _ptr(workspace), C.c_void_p(stream.cuda_stream)), "tmd_encode_rans")
+    stream.synchronize()
+    return coded[:int(size.item())]
+
+
 def to_host(frame, pin=True):
     """Copy a numpy frame dict to torch CPU tensors, page-locked if `pin`
     (what lets a Pipeline's transfers overlap its kernels)."""

@@ -110,6 +110,11 @@ def lib():
         L.tmd_decode_rans.argtypes = [P, C.POINTER(FrameShape), C.POINTER(P), C.POINTER(C.c_uint64),
                                       C.POINTER(FrameOut), P, P, P]
         L.tmd_decode_rans.restype = C.c_int
+        L.tmd_rans_encode_workspace.argtypes = [C.POINTER(FrameShape), C.POINTER(C.c_size_t),
+                                                C.POINTER(C.c_uint64)]
+        L.tmd_rans_encode_workspace.restype = C.c_int
+        L.tmd_encode_rans.argtypes = [C.POINTER(FrameShape), C.POINTER(FrameIn), P, C.c_uint64, P, P, P]
+        L.tmd_encode_rans.restype = C.c_int
         L.tmd_pipe_create.argtypes = [C.POINTER(FrameShape), C.c_uint32, C.POINTER(Params), C.POINTER(P)]
         L.tmd_pipe_create.restype = C.c_int
         L.tmd_pipe_run.argtypes = [P, C.c_uint32, C.POINTER(FrameShape), C.POINTER(FrameIn), C.POINTER(FrameOut),

@@ -2299,6 +2299,275 @@ __global__ __launch_bounds__(kRansLanes) void k_rans(const RansDesc R)
 }
 
 // ---------------------------------------------------------------------------
+// Entropy coding of a frame on the device (the inverse of k_rans, same
+// format): per-plane histograms, the 12-bit models, one wave per chunk coding
+// its 64 streams backwards into a per-lane area, then a single block placing
+// the planes and a wave per chunk packing its streams into place.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRansLaneCap = 1032;  // 4 state bytes + at most 2 bytes per symbol, rounded to 8
+constexpr uint32_t kRansMeta0 = 64 + 8 * kRansPlanes;  // the header and the plane offsets
+
+struct RansEncDesc {
+    const GLB uint8_t *src[kRansArrays];
+    uint32_t n[kRansArrays];
+    uint32_t item0[kRansPlanes + 1];
+    GLB uint32_t *hist;    // [plane][256] symbol counts
+    GLB uint16_t *freq;    // [plane][256] the model
+    GLB uint8_t *lanes;    // [item][64][kRansLaneCap]: each stream, ending at the end of its area
+    GLB uint32_t *lens;    // [item][64]: bytes of each stream
+    GLB uint32_t *ctot;    // [item]: bytes of each chunk's streams
+    GLB uint64_t *cstart;  // [item]: offset of each chunk's streams from its plane's data
+    GLB uint64_t *ppos;    // [plane]: position of each plane; [kRansPlanes]: the coded size
+    GLB uint8_t *dst;
+    GLB uint64_t *size;    // the coded size (the caller's word)
+    uint32_t nT, nA, nU;
+};
+
+// plane p of an item, and the array and byte of that plane
+__device__ __forceinline__ void rans_item_plane(const uint32_t *item0, uint32_t item, uint32_t &p, uint32_t &a,
+                                                uint32_t &b)
+{
+    p = 0;
+    while (p + 1 < (uint32_t)kRansPlanes && item0[p + 1] <= item) p++;
+    a = 0;
+    b = p;
+    while (a + 1 < (uint32_t)kRansArrays && b >= kRansWidth[a]) {
+        b -= kRansWidth[a];
+        a++;
+    }
+}
+
+// symbol counts of one chunk of one plane
+__global__ __launch_bounds__(256) void k_renc_hist(const RansEncDesc E)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t p, a, b;
+    rans_item_plane(E.item0, blockIdx.x, p, a, b);
+    const uint32_t w = kRansWidth[a], n = E.n[a];
+    const uint32_t c0 = (blockIdx.x - E.item0[p]) * kRansChunk;
+    const uint32_t len = n - c0 < kRansChunk ? n - c0 : kRansChunk;
+    const GLB uint8_t *src = E.src[a];
+    for (uint32_t i = threadIdx.x; i < len; i += 256) atomicAdd(&h[src[(uint64_t)(c0 + i) * w + b]], 1u);
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&E.hist[256 * p + threadIdx.x], h[threadIdx.x]);
+}
+
+// The model of each plane (one wave per plane): frequencies summing to 2^12,
+// every symbol that occurs at least 1: first max(1, floor(count 2^12 / n));
+// while the sum is short, one more unit to the symbol whose f n - count 2^12
+// is smallest; while it is over, one unit less for the symbol with f > 1
+// whose f n - count 2^12 is largest (ties: the lowest symbol).  A plane
+// without symbols gets f[0] = 2^12.
+__global__ __launch_bounds__(64) void k_renc_model(const RansEncDesc E)
+{
+    const uint32_t p = blockIdx.x, lane = threadIdx.x;
+    uint32_t a = 0, b = p;
+    while (a + 1 < (uint32_t)kRansArrays && b >= kRansWidth[a]) {
+        b -= kRansWidth[a];
+        a++;
+    }
+    const uint64_t n = E.n[a];
+    uint64_t cnt[4];
+    int64_t f[4];
+    int64_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        cnt[q] = E.hist[256 * p + 4 * lane + q];
+        f[q] = 0;
+        if (n && cnt[q]) {
+            const uint64_t v = (cnt[q] << 12) / n;
+            f[q] = v ? (int64_t)v : 1;
+        }
+        sum += f[q];
+    }
+    for (int off = 1; off < kWave; off <<= 1) sum += __shfl_xor(sum, off);
+    if (n == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) f[q] = (lane == 0 && q == 0) ? 4096 : 0;
+        sum = 4096;
+    }
+    while (sum != 4096) {
+        const bool up = sum < 4096;
+        // this lane's best candidate (its lowest symbol on ties), then the wave's
+        int64_t bx = 0;
+        int bs = -1;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if (!cnt[q] || (!up && f[q] <= 1)) continue;
+            const int64_t ex = f[q] * (int64_t)n - (int64_t)(cnt[q] << 12);
+            if (bs < 0 || (up ? ex < bx : ex > bx)) {
+                bs = 4 * (int)lane + q;
+                bx = ex;
+            }
+        }
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int64_t ox = __shfl_xor(bx, off);
+            const int os = __shfl_xor(bs, off);
+            const bool take = os >= 0 && (bs < 0 || (up ? ox < bx : ox > bx) || (ox == bx && os < bs));
+            if (take) {
+                bx = ox;
+                bs = os;
+            }
+        }
+        if (bs >> 2 == (int)lane) {
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if ((bs & 3) == q) f[q] += up ? 1 : -1;
+        }
+        sum += up ? 1 : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) E.freq[256 * p + 4 * lane + q] = (uint16_t)f[q];
+}
+
+// one wave per chunk: lane l codes stream l (symbols l, l + 64, ... of the
+// chunk) from its last symbol to its first, writing bytes downwards from the
+// end of its area, and finally its state in front of them
+__global__ __launch_bounds__(kRansLanes) void k_renc_code(const RansEncDesc E)
+{
+    __shared__ uint32_t f[256], c[256];
+    const uint32_t lane = lane_id(), item = blockIdx.x;
+    uint32_t p, a, b;
+    rans_item_plane(E.item0, item, p, a, b);
+    uint32_t run = 0;
+    uint32_t fl[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        fl[q] = E.freq[256 * p + 4 * lane + q];
+        run += fl[q];
+    }
+    const uint32_t incl = wave_incl_add(run);
+    run = incl - run;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        f[4 * lane + q] = fl[q];
+        c[4 * lane + q] = run;
+        run += fl[q];
+    }
+    __syncthreads();
+    const uint32_t w = kRansWidth[a], n = E.n[a];
+    const uint32_t c0 = (item - E.item0[p]) * kRansChunk;
+    const uint32_t len = n - c0 < kRansChunk ? n - c0 : kRansChunk;
+    const uint32_t k = lane < len ? (len - lane + kRansLanes - 1) / kRansLanes : 0;
+    const GLB uint8_t *src = E.src[a];
+    GLB uint8_t *area = E.lanes + ((uint64_t)item * kRansLanes + lane) * kRansLaneCap;
+    uint32_t pos = kRansLaneCap;
+    uint32_t x = kRansLow;
+    for (uint32_t j = k; j-- > 0;) {
+        const uint32_t s = src[(uint64_t)(c0 + lane + kRansLanes * j) * w + b];
+        const uint32_t fs = f[s];
+        const uint32_t x_max = (kRansLow >> 4) * fs;  // 2^19 f: x / f must stay below 2^19
+        while (x >= x_max) {
+            area[--pos] = (uint8_t)x;
+            x >>= 8;
+        }
+        x = ((x / fs) << 12) + x % fs + c[s];
+    }
+    area[--pos] = (uint8_t)(x >> 24);
+    area[--pos] = (uint8_t)(x >> 16);
+    area[--pos] = (uint8_t)(x >> 8);
+    area[--pos] = (uint8_t)x;
+    const uint32_t bytes = kRansLaneCap - pos;
+    E.lens[(uint64_t)item * kRansLanes + lane] = bytes;
+    const uint32_t tot = wave_incl_add(bytes);
+    if (lane == kWave - 1) E.ctot[item] = tot;
+}
+
+// single block: plane positions, chunk starts, the header, offsets and models
+__global__ __launch_bounds__(256) void k_renc_place(const RansEncDesc E)
+{
+    __shared__ uint64_t part[256];
+    const uint32_t t = threadIdx.x;
+    uint64_t pos = kRansMeta0;  // already a multiple of 8
+    for (uint32_t p = 0; p < (uint32_t)kRansPlanes; p++) {
+        const uint32_t i0 = E.item0[p], i1 = E.item0[p + 1], nch = i1 - i0;
+        const uint64_t data0 = pos + 512 + 4ull * 65 * nch;
+        // the plane's model
+        for (uint32_t q = t; q < 256; q += 256) {
+            const uint16_t v = E.freq[256 * p + q];
+            E.dst[pos + 2 * q] = (uint8_t)v;
+            E.dst[pos + 2 * q + 1] = (uint8_t)(v >> 8);
+        }
+        if (t == 0) {
+            E.ppos[p] = pos;
+            for (int q = 0; q < 8; q++) E.dst[64 + 8 * p + q] = (uint8_t)(pos >> (8 * q));
+        }
+        // chunk starts: exclusive prefix of the chunk totals, 256 at a time
+        uint64_t base = 0;
+        for (uint32_t i = i0; i < i1; i += 256) {
+            const uint64_t v = i + t < i1 ? E.ctot[i + t] : 0;
+            part[t] = v;
+            __syncthreads();
+            for (uint32_t off = 1; off < 256; off <<= 1) {
+                const uint64_t o = t >= off ? part[t - off] : 0;
+                __syncthreads();
+                part[t] += o;
+                __syncthreads();
+            }
+            if (i + t < i1) E.cstart[i + t] = base + part[t] - v;
+            base += part[255];
+            __syncthreads();
+        }
+        const uint64_t end = data0 + base;
+        const uint64_t next = p + 1 < (uint32_t)kRansPlanes ? (end + 7) & ~7ull : end;
+        for (uint64_t q = end + t; q < next; q += 256) E.dst[q] = 0;  // padding to the next plane
+        pos = next;
+    }
+    if (t < 64) {  // the header: "TMDR", version 1, the shape, zeros
+        uint8_t v = 0;
+        if (t < 4) v = (uint8_t)"TMDR"[t];
+        else if (t < 24) {
+            const uint32_t h[5] = {1u, E.nT, E.nA, E.nU, 0u};
+            v = (uint8_t)(h[(t - 4) / 4] >> (8 * ((t - 4) % 4)));
+        }
+        E.dst[t] = v;
+    }
+    if (t == 0) {
+        E.ppos[kRansPlanes] = pos;
+        *E.size = pos;
+    }
+}
+
+// one wave per chunk: its offset table and its streams, back to back
+__global__ __launch_bounds__(kRansLanes) void k_renc_pack(const RansEncDesc E)
+{
+    __shared__ uint32_t pre[kRansLanes + 1];
+    const uint32_t lane = lane_id(), item = blockIdx.x;
+    uint32_t p, a, b;
+    rans_item_plane(E.item0, item, p, a, b);
+    const uint32_t ch = item - E.item0[p], nch = E.item0[p + 1] - E.item0[p];
+    const uint64_t pos = E.ppos[p];
+    const uint64_t data0 = pos + 512 + 4ull * 65 * nch;
+    const uint64_t cs = E.cstart[item];
+    const uint32_t len = E.lens[(uint64_t)item * kRansLanes + lane];
+    const uint32_t incl = wave_incl_add(len);
+    pre[lane + 1] = incl;
+    if (lane == 0) pre[0] = 0;
+    __syncthreads();
+    GLB uint8_t *offs = E.dst + pos + 512 + 4ull * 65 * ch;
+    for (uint32_t q = lane; q < 4 * (kRansLanes + 1); q += kRansLanes) {
+        const uint32_t v = (uint32_t)(cs + pre[q / 4]);
+        offs[q] = (uint8_t)(v >> (8 * (q % 4)));
+    }
+    const uint32_t total = pre[kRansLanes];
+    GLB uint8_t *out = E.dst + data0 + cs;
+    const GLB uint8_t *areas = E.lanes + (uint64_t)item * kRansLanes * kRansLaneCap;
+    for (uint32_t t = lane; t < total; t += kRansLanes) {
+        // the stream that holds byte t of the chunk
+        uint32_t lo = 0, hi = kRansLanes - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t sl = pre[lo + 1] - pre[lo];
+        out[t] = areas[(uint64_t)lo * kRansLaneCap + (kRansLaneCap - sl) + (t - pre[lo])];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // workspace of tmd_decode_static: device memory of the library itself, one
 // array per GPU (the kernels never see its host-side name, only the address
 // hipGetSymbolAddress gives for the current device)
@@ -2308,8 +2577,11 @@ static __device__ __align__(256) uint8_t scratch[TMD_STATIC_SCRATCH_BYTES];
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-constexpr int kStages = 7;
-const char *kStageNames[kStages] = {"tilesum", "count", "colscan", "offsets", "rank", "attached", "unattached"};
+constexpr int kStages = 7;  // the decode's stages
+// (stage kStages, "rans": the entropy decoding of tmd_decode_rans)
+constexpr int kAllStages = kStages + 1;
+const char *kStageNames[kAllStages] = {"tilesum",  "count",      "colscan", "offsets",
+                                       "rank",     "attached",   "unattached", "rans"};
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -2344,6 +2616,8 @@ struct tmd_plan {
     hipEvent_t done = nullptr;
     bool called = false;  // `done` has been recorded at least once
     uint32_t profiling = 0;                            // stage mask
+    bool prof_rans = false;                            // events around tmd_decode_rans's entropy decoding
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> rans_events;
     std::vector<std::vector<hipEvent_t>> prof_events;  // per recorded call: 2 per stage (unrecorded: null)
     std::vector<hipEvent_t> event_pool;                // events ready for reuse
     hipGraphExec_t graph = nullptr;   // TMD_PLAN_GRAPH: the captured launch sequence
@@ -2650,6 +2924,10 @@ void tmd_free(tmd_plan_t *P)
     for (auto &v : P->prof_events)
         for (auto e : v)
             if (e) (void)hipEventDestroy(e);
+    for (auto &v : P->rans_events) {
+        (void)hipEventDestroy(v.first);
+        (void)hipEventDestroy(v.second);
+    }
     for (auto e : P->event_pool) (void)hipEventDestroy(e);
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
     drop_prof_graph(P);
@@ -2986,6 +3264,7 @@ int tmd_set_profiling(tmd_plan_t *P, uint32_t stage_mask)
 {
     if (!P) return TMD_E_ARG;
     P->profiling = stage_mask & ((1u << kStages) - 1u);
+    P->prof_rans = (stage_mask >> kStages) & 1u;
     return TMD_OK;
 }
 
@@ -3002,16 +3281,29 @@ int tmd_stage_times(tmd_plan_t *P, double *ms, uint32_t n, uint32_t *calls)
             acc[i] += t;
         }
     }
-    if (calls) *calls = (uint32_t)P->prof_events.size();
+    double rans = 0.0;
+    for (auto &v : P->rans_events) {
+        HIP_TRY(hipEventSynchronize(v.second));
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, v.first, v.second));
+        rans += t;
+    }
+    if (calls) *calls = (uint32_t)std::max(P->prof_events.size(), P->rans_events.size());
     for (auto &ev : P->prof_events)
         for (auto e : ev)
             if (e) P->event_pool.push_back(e);
     P->prof_events.clear();
-    for (uint32_t i = 0; i < n && i < (uint32_t)kStages; i++) ms[i] = acc[i];
-    return kStages;
+    for (auto &v : P->rans_events) {
+        P->event_pool.push_back(v.first);
+        P->event_pool.push_back(v.second);
+    }
+    P->rans_events.clear();
+    acc.push_back(rans);
+    for (uint32_t i = 0; i < n && i < (uint32_t)kAllStages; i++) ms[i] = acc[i];
+    return kAllStages;
 }
 
-const char *tmd_stage_name(uint32_t stage) { return stage < (uint32_t)kStages ? kStageNames[stage] : ""; }
+const char *tmd_stage_name(uint32_t stage) { return stage < (uint32_t)kAllStages ? kStageNames[stage] : ""; }
 
 int tmd_selftest_math(const float *a, uint32_t *out, uint32_t n, void *stream)
 {
@@ -3242,6 +3534,14 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
     int rc = TMD_OK;
     // (the previous call on this plan may still read these arrays)
     if (P->called && hipStreamWaitEvent(s, P->done, 0) != hipSuccess) rc = TMD_E_HIP;
+    std::pair<hipEvent_t, hipEvent_t> ev(nullptr, nullptr);
+    if (rc == TMD_OK && P->prof_rans) {
+        std::vector<hipEvent_t> two;
+        if ((rc = take_events(P, 1u, two)) == TMD_OK) {
+            ev = {two[0], two[1]};
+            if (hipEventRecord(ev.first, s) != hipSuccess) rc = TMD_E_HIP;
+        }
+    }
     for (uint32_t f = 0; f < nf && rc == TMD_OK; f++) {
         const tmd_frame_shape &S = shapes[f];
         RansDesc R;
@@ -3286,9 +3586,124 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
         if (hipGetLastError() != hipSuccess) rc = TMD_E_HIP;
         ws += rans_frame_bytes(S);
     }
+    if (ev.second) {
+        if (rc == TMD_OK && hipEventRecord(ev.second, s) == hipSuccess) {
+            P->rans_events.push_back(ev);
+        } else {
+            P->event_pool.push_back(ev.first);
+            P->event_pool.push_back(ev.second);
+        }
+    }
     if (cur != P->device) (void)hipSetDevice(cur);
     if (rc != TMD_OK) return rc;
     return decode_impl(P, shapes, in.data(), out, workspace, stream, pre.data());
+}
+
+}  // extern "C"
+
+namespace {
+
+// bytes of a coded frame of this shape at most, and the encoder's workspace
+struct RansEncLayout {
+    uint32_t items = 0;
+    uint32_t item0[kRansPlanes + 1];
+    uint64_t bound = 0;
+    size_t hist, freq, lens, ctot, cstart, ppos, lanes, total;
+};
+
+int rans_enc_layout(const tmd_frame_shape &S, RansEncLayout &L)
+{
+    uint32_t n[kRansArrays];
+    rans_counts(S, n);
+    uint64_t bound = kRansMeta0;
+    uint32_t plane = 0, items = 0;
+    for (int a = 0; a < kRansArrays; a++) {
+        if (n[a] > (1u << 30)) return TMD_E_ARG;  // a plane's offsets are 32-bit
+        const uint32_t nch = (n[a] + kRansChunk - 1) / kRansChunk;
+        for (int b = 0; b < kRansWidthHost[a]; b++) {
+            L.item0[plane++] = items;
+            items += nch;
+            bound += 8 + 512 + (4ull * 65 + 4ull * kRansLanes) * nch + 2ull * n[a];
+        }
+    }
+    L.item0[kRansPlanes] = items;
+    L.items = items;
+    L.bound = bound;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(std::max<size_t>(bytes, 1));
+        return o;
+    };
+    L.hist = take(4ull * 256 * kRansPlanes);
+    L.freq = take(2ull * 256 * kRansPlanes);
+    L.lens = take(4ull * kRansLanes * items);
+    L.ctot = take(4ull * items);
+    L.cstart = take(8ull * items);
+    L.ppos = take(8ull * (kRansPlanes + 1));
+    L.lanes = take((size_t)kRansLaneCap * kRansLanes * items);
+    L.total = off;
+    return TMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tmd_rans_encode_workspace(const tmd_frame_shape *shape, size_t *workspace_bytes, uint64_t *coded_bound)
+{
+    if (!shape || !workspace_bytes || !coded_bound) return TMD_E_ARG;
+    RansEncLayout L;
+    const int rc = rans_enc_layout(*shape, L);
+    if (rc != TMD_OK) return rc;
+    *workspace_bytes = L.total;
+    *coded_bound = L.bound;
+    return TMD_OK;
+}
+
+int tmd_encode_rans(const tmd_frame_shape *shape, const tmd_frame_in *in, uint8_t *coded, uint64_t capacity,
+                    uint64_t *coded_bytes, void *workspace, void *stream)
+{
+    if (!shape || !in || !coded || !coded_bytes || !workspace) return TMD_E_ARG;
+    if ((uintptr_t)workspace % 256 || (uintptr_t)coded_bytes % 8) return TMD_E_ARG;
+    RansEncLayout L;
+    int rc = rans_enc_layout(*shape, L);
+    if (rc != TMD_OK) return rc;
+    if (capacity < L.bound) return TMD_E_CAPACITY;
+    const void *arr[kRansArrays] = {in->trk_ncls, in->trk_sec0, in->trk_row0, in->trk_pad0, in->trk_time0,
+                                    in->trk_qpt, in->trk_snp, in->trk_tgl, in->cls_row_diff, in->cls_sec_diff,
+                                    in->cls_pad_res, in->cls_time_res, in->cls_qtot, in->cls_qmax, in->un_count,
+                                    in->un_time_diff, in->un_pad_diff, in->un_qtot, in->un_qmax};
+    RansEncDesc E;
+    memset(&E, 0, sizeof(E));
+    rans_counts(*shape, E.n);
+    for (int a = 0; a < kRansArrays; a++) {
+        if (E.n[a] && !arr[a]) return TMD_E_ARG;
+        E.src[a] = (const GLB uint8_t *)arr[a];
+    }
+    memcpy(E.item0, L.item0, sizeof(E.item0));
+    char *ws = (char *)workspace;
+    E.hist = (GLB uint32_t *)(ws + L.hist);
+    E.freq = (GLB uint16_t *)(ws + L.freq);
+    E.lens = (GLB uint32_t *)(ws + L.lens);
+    E.ctot = (GLB uint32_t *)(ws + L.ctot);
+    E.cstart = (GLB uint64_t *)(ws + L.cstart);
+    E.ppos = (GLB uint64_t *)(ws + L.ppos);
+    E.lanes = (GLB uint8_t *)(ws + L.lanes);
+    E.dst = (GLB uint8_t *)coded;
+    E.size = (GLB uint64_t *)coded_bytes;
+    E.nT = shape->n_tracks;
+    E.nA = shape->n_attached;
+    E.nU = shape->n_unattached;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_fill32, dim3(1), dim3(256), 0, s, (uint32_t *)(ws + L.hist), 256u * kRansPlanes, 0u);
+    if (L.items) hipLaunchKernelGGL(k_renc_hist, dim3(L.items), dim3(256), 0, s, E);
+    hipLaunchKernelGGL(k_renc_model, dim3(kRansPlanes), dim3(64), 0, s, E);
+    if (L.items) hipLaunchKernelGGL(k_renc_code, dim3(L.items), dim3(kRansLanes), 0, s, E);
+    hipLaunchKernelGGL(k_renc_place, dim3(1), dim3(256), 0, s, E);
+    if (L.items) hipLaunchKernelGGL(k_renc_pack, dim3(L.items), dim3(kRansLanes), 0, s, E);
+    if (hipGetLastError() != hipSuccess) return TMD_E_HIP;
+    return TMD_OK;
 }
 
 }  // extern "C"

@@ -60,6 +60,20 @@ int main(void)
     memset(&ein, 0, sizeof(ein));
     memset(&eout, 0, sizeof(eout));
     EXPECT(tmd_encode(NULL, &ein, &eout, NULL, 0, NULL) == TMD_E_ARG);
+    size_t rb = 0;
+    EXPECT(tmd_rans_workspace(&sh, 1, &rb) == TMD_OK && rb > 0);
+    EXPECT(tmd_rans_workspace(NULL, 1, &rb) == TMD_E_ARG);
+    EXPECT(tmd_rans_workspace(&sh, 0, &rb) == TMD_E_ARG);
+    EXPECT(tmd_decode_rans(NULL, &sh, NULL, NULL, &out, NULL, NULL, NULL) == TMD_E_ARG);
+    uint64_t bound = 0;
+    EXPECT(tmd_rans_encode_workspace(&sh, &rb, &bound) == TMD_OK && rb > 0 && bound > 376);
+    EXPECT(tmd_rans_encode_workspace(&sh, NULL, &bound) == TMD_E_ARG);
+    tmd_frame_shape huge = {10, (1u << 30) + 1u, 0};
+    EXPECT(tmd_rans_encode_workspace(&huge, &rb, &bound) == TMD_E_ARG);
+    static uint64_t word;
+    static unsigned char area[512] __attribute__((aligned(256)));
+    EXPECT(tmd_encode_rans(NULL, &in, area, 512, &word, area, NULL) == TMD_E_ARG);
+    EXPECT(tmd_encode_rans(&sh, &in, area, 512, &word, area, NULL) == TMD_E_CAPACITY);
     EXPECT(tmd_set_schedule(NULL, 64, 0) == TMD_E_ARG);
     EXPECT(tmd_set_profiling(NULL, 1u) == TMD_E_ARG);
     EXPECT(tmd_stage_times(NULL, NULL, 0, NULL) == TMD_E_ARG);

@@ -84,3 +84,30 @@ def test_malformed_coded_data_is_flagged(tmd):
     out, flags = tmd.decode_rans(noisy, shape)
     got = tmd.to_numpy(out)
     assert got["row_offset"].size == tmd.NBIN + 1
+
+
+@pytest.mark.parametrize("case", ["tiny", "frame", "stress", "garbage", "empty", "no tracks"])
+def test_gpu_encoder_matches_oracle(tmd, case):
+    """tmd_encode_rans writes the oracle coder's bytes, and they decode back."""
+    if case == "tiny":
+        fr = synth.make_frame(synth.spec_for("tiny"))
+    elif case == "frame":
+        fr = synth.make_frame(synth.spec_for("frame", collisions=3))
+    elif case == "stress":
+        fr = synth.make_frame(synth.spec_for("stress", collisions=1))
+    elif case == "garbage":
+        fr = _garbage(22)
+    else:
+        fr = {k: np.zeros(0 if k != "un_count" else tmd.NBIN, dt) for k, dt in oracle.RANS_ARRAYS}
+        if case == "no tracks":
+            rng = np.random.default_rng(5)
+            cnt = rng.integers(0, 4, tmd.NBIN).astype(np.uint32)
+            nu = int(cnt.sum())
+            fr["un_count"] = cnt
+            for k, dt in oracle.RANS_ARRAYS:
+                if k.startswith("un_") and k != "un_count":
+                    fr[k] = rng.integers(0, np.iinfo(dt).max, nu, dtype=np.int64).astype(dt)
+    want = oracle.rans_encode(fr)
+    got = tmd.encode_rans(tmd.to_device(fr)).cpu().numpy()
+    assert got.size == want.size, (case, got.size, want.size)
+    assert np.array_equal(got, want), (case, int(np.flatnonzero(got != want)[0]))
