@@ -44,6 +44,7 @@
 #include <algorithm>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "tmd.h"
@@ -211,6 +212,11 @@ __device__ __forceinline__ uint32_t wave_incl_add(uint32_t v)
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int l)
 {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v)
+{
+    return (uint64_t)readlane((uint32_t)v, 0) | ((uint64_t)readlane((uint32_t)(v >> 32), 0) << 32);
 }
 
 __device__ __forceinline__ uint32_t wave_or(uint32_t v)
@@ -2160,152 +2166,307 @@ __global__ __launch_bounds__(256) void k_enc_un_delta(const EncDesc E, const uns
 // the paper's introduction: the compressed time frame is ANS-coded).  The
 // coded format is this project's, laid out in include/tmd.h: the 19 arrays of
 // a frame in 39 byte planes, each plane a static 12-bit model and chunks of
-// 64 interleaved rANS streams of up to 512 symbols.  One wave decodes one
-// chunk: lane l runs stream l and writes symbols l, l + 64, ... of the chunk
-// into byte p of the elements of its array (the arrays live in the caller's
-// workspace and go straight to the decode).
+// 64 rANS lanes that share one stream of 16-bit words.
+//   k_rans_prep: one block per plane builds its decode tables (the symbol of
+//     every 12-bit slot; each symbol's frequency and start) and finds where
+//     its chunks' data begins.
+//   k_rans<W>: one wave per chunk of an array of W-byte elements.  Lane l
+//     runs lane l of the W planes side by side (W independent state chains),
+//     so every step yields whole elements.  A step's words are consecutive in
+//     the chunk's stream (lanes in order), so the stream is read ahead, one
+//     block of kRansBlk steps early, with one-dword-per-lane loads into an LDS
+//     ring per plane; the decoded elements of a block are staged in LDS and
+//     written 4 per lane.  Global memory is touched only between blocks.
 // ---------------------------------------------------------------------------
 constexpr int kRansPlanes = 39, kRansArrays = 19, kRansLanes = 64, kRansPerLane = 512;
 constexpr uint32_t kRansChunk = kRansLanes * kRansPerLane;
-constexpr uint32_t kRansLow = 1u << 23;
+constexpr uint32_t kRansLow = 1u << 16;
 constexpr uint32_t kRansHdr = 64;
+constexpr uint32_t kRansVersion = 2;
 constexpr uint32_t kRansBad = TMD_F_CODED;
+constexpr uint32_t kRansBlk = 4;                 // steps per block (256 elements: 4 per lane)
+constexpr uint32_t kRansUnit = 128;              // words per read-ahead load (a dword per lane)
+constexpr uint32_t kRansAhead = 2 * kRansLanes * kRansBlk;  // words kept ahead of the reads
+constexpr uint32_t kRansRing = 1024;             // words of a plane's ring
+constexpr uint32_t kRansTab = 4096 + 4 * 256;    // bytes of a plane's decode tables
+static_assert(kRansBlk * kRansLanes == 4 * kRansLanes, "a block's elements are 4 per lane");
+static_assert(kRansAhead + kRansUnit <= kRansRing, "the ring holds what is read ahead");
 
-struct RansDesc {
-    const GLB uint8_t *src;
+__device__ __constant__ const uint8_t kRansWidth[kRansArrays] = {1, 1, 1, 2, 4, 2, 2, 2, 1, 1, 2, 2, 2, 2, 4, 4, 2, 2, 2};
+// first plane of each array
+__device__ __constant__ const uint8_t kRansPlane0[kRansArrays] = {0,  1,  2,  3,  5,  9,  11, 13, 15, 16,
+                                                                  17, 19, 21, 23, 25, 29, 33, 35, 37};
+
+struct RansDesc {  // (the same layout on the host and the device: 600 bytes)
+    const GLB uint8_t *src;       // the coded frame (16-byte aligned)
     uint64_t size;
     GLB uint8_t *dst[kRansArrays];
     uint32_t n[kRansArrays];      // elements of each array
-    uint32_t item0[kRansPlanes + 1];  // first chunk (work item) of each plane
+    GLB uint8_t *tabs;            // per plane kRansTab bytes: sym[4096], then f | c << 16 for each symbol
+    GLB uint64_t *pinfo;          // per plane: its position, the start of its chunks' data (0: unusable)
     GLB uint32_t *err;            // TMD_F_CODED if the data is not a well-formed coded frame
     uint32_t nT, nA, nU;
+    uint32_t nw[3];               // arrays of width 1, 2 and 4, in order
+    uint32_t warr[3][12];
+    uint32_t witem0[3][13];       // first work item of each, then the total
 };
 
-__device__ __constant__ const uint8_t kRansWidth[kRansArrays] = {1, 1, 1, 2, 4, 2, 2, 2, 1, 1, 2, 2, 2, 2, 4, 4, 2, 2, 2};
+static_assert(sizeof(RansDesc) == 600, "descriptor layout");
 
 __global__ void k_fill32(uint32_t *p, uint32_t n, uint32_t v)
 {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 
-__global__ __launch_bounds__(kRansLanes) void k_rans(const RansDesc R)
+__device__ __forceinline__ uint32_t rans_rd32(const GLB uint8_t *s, uint64_t o)
 {
-    __shared__ uint32_t f[256], c[256];
-    __shared__ uint8_t sym[1 << 12];
-    const uint32_t lane = lane_id();
-    const uint32_t item = blockIdx.x;
-    if (item == 0 && lane == 0) {  // header: "TMDR", version 1, the frame's shape
-        bool ok = R.size >= kRansHdr + 8 * kRansPlanes;
-        if (ok) {
-            uint32_t h[5];
-            for (int q = 0; q < 5; q++) {
-                h[q] = 0;
-                for (int k = 3; k >= 0; k--) h[q] = (h[q] << 8) | R.src[4 + 4 * q + k];
-            }
-            ok = R.src[0] == 'T' && R.src[1] == 'M' && R.src[2] == 'D' && R.src[3] == 'R' && h[0] == 1u &&
-                 h[1] == R.nT && h[2] == R.nA && h[3] == R.nU;
-        }
-        if (!ok) atomicOr(R.err, kRansBad);
+    return (uint32_t)s[o] | ((uint32_t)s[o + 1] << 8) | ((uint32_t)s[o + 2] << 16) | ((uint32_t)s[o + 3] << 24);
+}
+
+// (the descriptors of all frames of a call: device memory, one per frame)
+__global__ __launch_bounds__(256) void k_rans_prep(const RansDesc *descs)
+{
+    __shared__ uint32_t cend[256];  // c_s + f_s
+    __shared__ uint32_t wsum[4];
+    const uint32_t p = blockIdx.x % kRansPlanes, t = threadIdx.x;
+    const GLB RansDesc *R = (const GLB RansDesc *)descs + blockIdx.x / kRansPlanes;
+    uint32_t a = 0;
+    while (a + 1 < (uint32_t)kRansArrays && kRansPlane0[a + 1] <= p) a++;
+    const uint64_t n = R->n[a];
+    const uint64_t nch = (n + kRansChunk - 1) / kRansChunk;
+    bool ok = R->size >= kRansHdr + 8 * kRansPlanes;
+    if (p == 0 && t == 0) {  // the header: "TMDR", version 2, the frame's shape
+        bool hok = ok && R->src[0] == 'T' && R->src[1] == 'M' && R->src[2] == 'D' && R->src[3] == 'R' &&
+                   rans_rd32(R->src, 4) == kRansVersion && rans_rd32(R->src, 8) == R->nT &&
+                   rans_rd32(R->src, 12) == R->nA && rans_rd32(R->src, 16) == R->nU;
+        if (!hok) atomicOr(R->err, kRansBad);
     }
-    uint32_t p = 0;
-    while (p + 1 < (uint32_t)kRansPlanes && R.item0[p + 1] <= item) p++;
-    // plane p -> array a, byte b of its elements
-    uint32_t a = 0, b = p;
-    while (a + 1 < (uint32_t)kRansArrays && b >= kRansWidth[a]) {
-        b -= kRansWidth[a];
-        a++;
-    }
-    const uint32_t w = kRansWidth[a], n = R.n[a];
-    const uint32_t ch = item - R.item0[p];
-    const uint32_t nch = (n + kRansChunk - 1) / kRansChunk;
-    bool bad = false;
     uint64_t pos = 0;
-    if (kRansHdr + 8 * (p + 1) <= R.size) {
-        for (int q = 7; q >= 0; q--) pos = (pos << 8) | R.src[kRansHdr + 8 * p + q];
-    } else {
-        bad = true;
-    }
-    const uint64_t meta = 512 + 4ull * 65 * nch;  // the plane's model and chunk offsets
-    if (bad || pos > R.size || R.size - pos < meta) {
-        if (lane == 0) atomicOr(R.err, kRansBad);
-        return;
-    }
-    const uint64_t data0 = pos + meta;
-    // the model: frequencies, their prefix, and the symbol of every slot
-    uint32_t fl[4], tot = 0;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const uint64_t o = pos + 2 * (4 * lane + q);
-        fl[q] = (uint32_t)R.src[o] | ((uint32_t)R.src[o + 1] << 8);
-        tot += fl[q];
-    }
-    const uint32_t incl = wave_incl_add(tot);
-    uint32_t run = incl - tot;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        f[4 * lane + q] = fl[q];
-        c[4 * lane + q] = run;
-        run += fl[q];
-    }
-    if (readlane(incl, kWave - 1) != (1u << 12)) {
-        if (lane == 0) atomicOr(R.err, kRansBad);
-        return;
-    }
+    if (ok) pos = (uint64_t)rans_rd32(R->src, kRansHdr + 8 * p) | ((uint64_t)rans_rd32(R->src, kRansHdr + 8 * p + 4) << 32);
+    ok = ok && pos <= R->size && R->size - pos >= 512 + 4 * (nch + 1);
+    const uint32_t f = ok ? (uint32_t)R->src[pos + 2 * t] | ((uint32_t)R->src[pos + 2 * t + 1] << 8) : 0u;
+    // exclusive prefix of the frequencies over the block's 4 waves
+    const uint32_t inc = wave_incl_add(f);
+    if (lane_id() == kWave - 1) wsum[t / kWave] = inc;
     __syncthreads();
-    for (uint32_t slot = lane; slot < (1u << 12); slot += kRansLanes) {
-        // the last symbol whose range starts at or below the slot (symbols
-        // of frequency 0 start where the next one does)
-        uint32_t lo = 0, hi = 255;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (c[mid] <= slot) lo = mid;
-            else hi = mid - 1;
+    uint32_t base = 0, tot = 0;
+    for (uint32_t q = 0; q < 4; q++) {
+        base += q < t / kWave ? wsum[q] : 0u;
+        tot += wsum[q];
+    }
+    const uint32_t c = base + inc - f;
+    cend[t] = c + f;
+    if (n && tot != 4096u) ok = false;
+    GLB uint8_t *tab = R->tabs + (uint64_t)p * kRansTab;
+    ((GLB uint32_t *)(tab + 4096))[t] = f | (c << 16);
+    __syncthreads();
+    // the symbol of slots 16t .. 16t + 15: the number of symbols whose range
+    // ends at or below the slot
+    uint32_t slot = 16 * t, lo = 0, hi = 256;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (cend[mid] <= slot) lo = mid + 1;
+        else hi = mid;
+    }
+    uint32_t s = lo, wv[4];
+    for (int q = 0; q < 16; q++, slot++) {
+        while (s < 255 && cend[s] <= slot) s++;
+        if (q % 4 == 0) wv[q / 4] = 0;
+        wv[q / 4] |= s << (8 * (q % 4));
+    }
+    *(GLB uint4 *)(tab + 16 * t) = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+    if (t == 0) {
+        R->pinfo[2 * p] = pos;
+        R->pinfo[2 * p + 1] = ok ? ((pos + 512 + 4 * (nch + 1) + 15) & ~15ull) : 0ull;
+        if (!ok && n) atomicOr(R->err, kRansBad);
+    }
+}
+
+// (witem: for each width class, the first work item of each frame, then the
+// total; a work item is one chunk of one array of the class)
+template <int W>
+__global__ __launch_bounds__(kRansLanes) void k_rans(const RansDesc *descs, const uint32_t *witem, uint32_t nf)
+{
+    constexpr int WI = W == 1 ? 0 : (W == 2 ? 1 : 2);
+    // the frame of this work item: the last one whose first item is at or below it
+    const GLB uint32_t *fi = (const GLB uint32_t *)witem + WI * (nf + 1);
+    uint32_t flo = 0, fhi = nf - 1;
+    while (flo < fhi) {
+        const uint32_t mid = (flo + fhi + 1) >> 1;
+        if (readlane(fi[mid], 0) <= blockIdx.x) flo = mid;
+        else fhi = mid - 1;
+    }
+    const GLB RansDesc *R = (const GLB RansDesc *)descs + flo;
+    using Elem = typename std::conditional<W == 1, uint8_t, typename std::conditional<W == 2, uint16_t, uint32_t>::type>::type;
+    __shared__ uint32_t sym4[W][1024];   // the symbol of every slot, 4 per word
+    __shared__ uint32_t fc[W][256];
+    __shared__ uint32_t ring[W][kRansRing / 2];  // 2 words per entry
+    __shared__ uint32_t stage[kRansBlk * kRansLanes * W / 4];
+    const uint32_t lane = lane_id(), item = blockIdx.x - readlane(fi[flo], 0);
+    // the array and chunk of this item
+    // (the descriptor's fields read once, into wave-uniform registers)
+    uint32_t a = readlane(R->warr[WI][0], 0), i0 = 0;
+    const uint32_t nw = readlane(R->nw[WI], 0);
+#pragma unroll
+    for (int k = 1; k < 12; k++)
+        if ((uint32_t)k < nw && readlane(R->witem0[WI][k], 0) <= item) {
+            a = readlane(R->warr[WI][k], 0);
+            i0 = readlane(R->witem0[WI][k], 0);
         }
-        sym[slot] = (uint8_t)lo;
-    }
-    __syncthreads();
-    // this lane's stream
-    const uint64_t offs = pos + 512 + 4ull * 65 * ch;
-    auto rd32 = [&](uint64_t o) -> uint32_t {
-        return (uint32_t)R.src[o] | ((uint32_t)R.src[o + 1] << 8) | ((uint32_t)R.src[o + 2] << 16) |
-               ((uint32_t)R.src[o + 3] << 24);
-    };
-    const uint32_t o0 = rd32(offs + 4 * lane), o1 = rd32(offs + 4 * lane + 4);
-    uint64_t ptr = data0 + o0;
-    const uint64_t end = data0 + o1;
+    const GLB uint8_t *const src = (const GLB uint8_t *)readlane64((uint64_t)R->src);
+    const uint64_t size = readlane64(R->size);
+    const uint32_t ch = item - i0, n = readlane(R->n[a], 0), p0 = readlane(kRansPlane0[a], 0);
     const uint32_t c0 = ch * kRansChunk;
     const uint32_t len = n - c0 < kRansChunk ? n - c0 : kRansChunk;
-    uint32_t err = 0;
-    if (o1 < o0 || o1 - o0 < 4 || end > R.size) {
-        err = kRansBad;
-    } else {
-        uint32_t x = rd32(ptr);
-        ptr += 4;
-        GLB uint8_t *dst = R.dst[a];
-        for (uint32_t i = lane; i < len; i += kRansLanes) {
-            const uint32_t slot = x & 0xFFFu;
-            const uint32_t s = sym[slot];
-            x = f[s] * (x >> 12) + slot - c[s];
-            for (int q = 0; q < 4 && x < kRansLow; q++) {  // at most 4 bytes bring x back above 2^23
-                uint32_t byte = 0;
-                if (ptr < end) byte = R.src[ptr++];
-                else err = kRansBad;
-                x = (x << 8) | byte;
-            }
-            dst[(uint64_t)(c0 + i) * w + b] = (uint8_t)s;
+    const uint32_t steps = (len + kRansLanes - 1) / kRansLanes;
+    const uint32_t nch = (n + kRansChunk - 1) / kRansChunk;
+    GLB Elem *dst = (GLB Elem *)R->dst[a] + c0;
+    // the W planes' tables (all of a plane's loads in flight together)
+    static_assert(kRansTab / 16 == 5 * kRansLanes, "5 table loads per lane");
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+        const GLB uint4 *tb = (const GLB uint4 *)(R->tabs + (uint64_t)(p0 + q) * kRansTab);
+        uint4 tv[5];
+#pragma unroll
+        for (int k = 0; k < 5; k++) tv[k] = tb[lane + kRansLanes * k];
+#pragma unroll
+        for (int k = 0; k < 5; k++) {
+            const uint32_t i = lane + kRansLanes * k;
+            uint32_t *d = k < 4 ? &sym4[q][4 * i] : &fc[q][4 * (i - 256)];
+            d[0] = tv[k].x; d[1] = tv[k].y; d[2] = tv[k].z; d[3] = tv[k].w;
         }
     }
-    if (__ballot(err != 0) && lane == 0) atomicOr(R.err, kRansBad);
+    // the W planes' chunk data: states, word streams
+    uint32_t x[W];
+    uint64_t wbase[W];
+    uint32_t nwords[W], rd[W], wr[W];
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+        const uint64_t pos = readlane64(R->pinfo[2 * (p0 + q)]), data0 = readlane64(R->pinfo[2 * (p0 + q) + 1]);
+        uint32_t o0 = 0, o1 = 0;
+        if (data0) {
+            o0 = readlane(rans_rd32(src, pos + 512 + 4ull * ch), 0);
+            o1 = readlane(rans_rd32(src, pos + 512 + 4ull * ch + 4), 0);
+        }
+        const bool qok = data0 && ch < nch && o1 >= o0 && o1 - o0 >= 4 * kRansLanes && (o0 % 16) == 0 &&
+                         ((o1 - o0) % 16) == 0 && data0 + o1 <= size;
+        bad |= !qok;
+        const uint64_t d0 = qok ? data0 + o0 : 0;
+        x[q] = qok ? ((const GLB uint32_t *)(src + d0))[lane] : kRansLow;
+        wbase[q] = d0 + 4 * kRansLanes;
+        nwords[q] = qok ? (o1 - o0 - 4 * kRansLanes) / 2 : 0;
+        rd[q] = 0;
+        wr[q] = 0;
+    }
+    // every stored state is in [2^16, 2^32) (this also waits for the states
+    // here, not inside the loop)
+#pragma unroll
+    for (int q = 0; q < W; q++) bad |= __ballot(x[q] < kRansLow) != 0;
+    if (bad) {  // not a well-formed chunk: flagged, its elements 0
+        if (lane == 0) atomicOr(R->err, kRansBad);
+        for (uint32_t e = lane; e < len; e += kRansLanes) dst[e] = 0;
+        return;
+    }
+    // the first kRansAhead words of each stream (a plane's loads in flight together)
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+        constexpr uint32_t U = kRansAhead / kRansUnit;
+        uint32_t v[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            const uint32_t wi = kRansUnit * u + 2 * lane;
+            v[u] = wi < nwords[q] ? ((const GLB uint32_t *)(src + wbase[q]))[wi / 2] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) ring[q][((kRansUnit * u + 2 * lane) % kRansRing) / 2] = v[u];
+        wr[q] = kRansAhead;
+    }
+    __syncthreads();
+    uint32_t over = 0;  // a stream read beyond its words
+    for (uint32_t j0 = 0; j0 < steps; j0 += kRansBlk) {
+        // read ahead what the next block may read: up to 3 units per plane
+        // (the units not needed are not loaded, their registers hold 0)
+        uint32_t pf[W][3], m[W];
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+            m[q] = 0;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const uint32_t u0 = wr[q] + kRansUnit * k;
+                const uint32_t wi = u0 + 2 * lane;
+                const bool take = u0 < rd[q] + kRansAhead && u0 < nwords[q];
+                pf[q][k] = take && wi < nwords[q] ? ((const GLB uint32_t *)(src + wbase[q]))[wi / 2] : 0u;
+                m[q] += take;
+            }
+        }
+        // the block's steps
+        for (uint32_t s = 0; s < kRansBlk; s++) {
+            const uint32_t j = j0 + s;
+            if (j >= steps) break;
+            const bool live = kRansLanes * j + lane < len;
+            uint32_t v = 0;
+#pragma unroll
+            for (int q = 0; q < W; q++) {
+                const uint32_t slot = x[q] & 4095u;
+                const uint32_t sy = (sym4[q][slot >> 2] >> (8 * (slot & 3))) & 0xFFu;
+                const uint32_t e = fc[q][sy];
+                uint32_t xn = (e & 0xFFFFu) * (x[q] >> 12) + slot - (e >> 16);
+                const bool need = live && xn < kRansLow;
+                const uint64_t msk = __ballot(need);
+                if (need) {
+                    const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(msk >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)msk, 0u));
+                    const uint32_t wi = (rd[q] + r) % kRansRing;
+                    xn = (xn << 16) | ((ring[q][wi / 2] >> (16 * (wi & 1))) & 0xFFFFu);
+                }
+                rd[q] += (uint32_t)__popcll(msk);
+                if (live) x[q] = xn;
+                v |= sy << (8 * q);
+            }
+            ((Elem *)stage)[kRansLanes * s + lane] = (Elem)v;
+        }
+        // end of the block: the read-ahead has arrived, the elements go out.
+        // All three units go into the ring: the slots of units not loaded
+        // hold words already read (a unit's slot last held the word kRansRing
+        // earlier, and the reads are at most kRansAhead + 3 kRansUnit behind),
+        // and are written again before they are read.
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) ring[q][((wr[q] + kRansUnit * k + 2 * lane) % kRansRing) / 2] = pf[q][k];
+            wr[q] += kRansUnit * m[q];
+            over |= rd[q] > nwords[q];
+        }
+        __syncthreads();
+        const uint32_t nb = len - kRansLanes * j0 < kRansLanes * kRansBlk ? len - kRansLanes * j0 : kRansLanes * kRansBlk;
+        const Elem *sv = (const Elem *)stage + 4 * lane;
+        GLB Elem *dv = dst + kRansLanes * j0 + 4 * lane;
+        if (4 * lane + 4 <= nb) {
+            if (W == 1) *(GLB uint32_t *)dv = *(const uint32_t *)sv;
+            else if (W == 2) *(GLB uint2 *)dv = *(const uint2 *)sv;
+            else *(GLB uint4 *)dv = *(const uint4 *)sv;
+        } else {
+            for (uint32_t e = 0; e < 4; e++)
+                if (4 * lane + e < nb) dv[e] = sv[e];
+        }
+        __syncthreads();
+    }
+    // a well-formed chunk: every state back at its start, every word read
+    bool fine = !over;
+#pragma unroll
+    for (int q = 0; q < W; q++) fine = fine && x[q] == kRansLow && nwords[q] - rd[q] < 8;
+    if (__ballot(!fine) && lane == 0) atomicOr(R->err, kRansBad);
 }
 
 // ---------------------------------------------------------------------------
 // Entropy coding of a frame on the device (the inverse of k_rans, same
 // format): per-plane histograms, the 12-bit models, one wave per chunk coding
-// its 64 streams backwards into a per-lane area, then a single block placing
-// the planes and a wave per chunk packing its streams into place.
+// its 64 lanes backwards (each step's words go in front of the later steps'
+// ones, lanes in order), then a single block placing the planes and a wave
+// per chunk packing its states and words into place.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kRansLaneCap = 1032;  // 4 state bytes + at most 2 bytes per symbol, rounded to 8
-constexpr uint32_t kRansMeta0 = 64 + 8 * kRansPlanes;  // the header and the plane offsets
+constexpr uint32_t kRansMeta0 = (64 + 8 * kRansPlanes + 15) & ~15u;  // the header and the plane offsets
 
 struct RansEncDesc {
     const GLB uint8_t *src[kRansArrays];
@@ -2313,15 +2474,18 @@ struct RansEncDesc {
     uint32_t item0[kRansPlanes + 1];
     GLB uint32_t *hist;    // [plane][256] symbol counts
     GLB uint16_t *freq;    // [plane][256] the model
-    GLB uint8_t *lanes;    // [item][64][kRansLaneCap]: each stream, ending at the end of its area
-    GLB uint32_t *lens;    // [item][64]: bytes of each stream
-    GLB uint32_t *ctot;    // [item]: bytes of each chunk's streams
-    GLB uint64_t *cstart;  // [item]: offset of each chunk's streams from its plane's data
+    GLB uint16_t *words;   // [item][kRansChunk]: each chunk's words, ending at the end of its area
+    GLB uint32_t *states;  // [item][64]: each chunk's final states
+    GLB uint32_t *nwords;  // [item]: words of each chunk
+    GLB uint64_t *cstart;  // [item]: offset of each chunk's data from its plane's data
     GLB uint64_t *ppos;    // [plane]: position of each plane; [kRansPlanes]: the coded size
     GLB uint8_t *dst;
     GLB uint64_t *size;    // the coded size (the caller's word)
     uint32_t nT, nA, nU;
 };
+
+// bytes of a chunk's data: its states and words, padded to 16
+__device__ __forceinline__ uint64_t rans_chunk_bytes(uint32_t nw) { return (4ull * kRansLanes + 2ull * nw + 15) & ~15ull; }
 
 // plane p of an item, and the array and byte of that plane
 __device__ __forceinline__ void rans_item_plane(const uint32_t *item0, uint32_t item, uint32_t &p, uint32_t &a,
@@ -2330,11 +2494,8 @@ __device__ __forceinline__ void rans_item_plane(const uint32_t *item0, uint32_t 
     p = 0;
     while (p + 1 < (uint32_t)kRansPlanes && item0[p + 1] <= item) p++;
     a = 0;
-    b = p;
-    while (a + 1 < (uint32_t)kRansArrays && b >= kRansWidth[a]) {
-        b -= kRansWidth[a];
-        a++;
-    }
+    while (a + 1 < (uint32_t)kRansArrays && kRansPlane0[a + 1] <= p) a++;
+    b = p - kRansPlane0[a];
 }
 
 // symbol counts of one chunk of one plane
@@ -2363,11 +2524,8 @@ __global__ __launch_bounds__(256) void k_renc_hist(const RansEncDesc E)
 __global__ __launch_bounds__(64) void k_renc_model(const RansEncDesc E)
 {
     const uint32_t p = blockIdx.x, lane = threadIdx.x;
-    uint32_t a = 0, b = p;
-    while (a + 1 < (uint32_t)kRansArrays && b >= kRansWidth[a]) {
-        b -= kRansWidth[a];
-        a++;
-    }
+    uint32_t a = 0;
+    while (a + 1 < (uint32_t)kRansArrays && kRansPlane0[a + 1] <= p) a++;
     const uint64_t n = E.n[a];
     uint64_t cnt[4];
     int64_t f[4];
@@ -2422,9 +2580,9 @@ __global__ __launch_bounds__(64) void k_renc_model(const RansEncDesc E)
     for (int q = 0; q < 4; q++) E.freq[256 * p + 4 * lane + q] = (uint16_t)f[q];
 }
 
-// one wave per chunk: lane l codes stream l (symbols l, l + 64, ... of the
-// chunk) from its last symbol to its first, writing bytes downwards from the
-// end of its area, and finally its state in front of them
+// one wave per chunk: the 64 lanes code their symbols from the last step to
+// the first; a step's words (lanes in order) go in front of the words of the
+// steps after it, so the area ends with the stream in reading order
 __global__ __launch_bounds__(kRansLanes) void k_renc_code(const RansEncDesc E)
 {
     __shared__ uint32_t f[256], c[256];
@@ -2450,29 +2608,29 @@ __global__ __launch_bounds__(kRansLanes) void k_renc_code(const RansEncDesc E)
     const uint32_t w = kRansWidth[a], n = E.n[a];
     const uint32_t c0 = (item - E.item0[p]) * kRansChunk;
     const uint32_t len = n - c0 < kRansChunk ? n - c0 : kRansChunk;
-    const uint32_t k = lane < len ? (len - lane + kRansLanes - 1) / kRansLanes : 0;
+    const uint32_t steps = (len + kRansLanes - 1) / kRansLanes;
     const GLB uint8_t *src = E.src[a];
-    GLB uint8_t *area = E.lanes + ((uint64_t)item * kRansLanes + lane) * kRansLaneCap;
-    uint32_t pos = kRansLaneCap;
+    GLB uint16_t *area = E.words + (uint64_t)item * kRansChunk;
+    uint32_t wp = kRansChunk;  // start of the words written so far
     uint32_t x = kRansLow;
-    for (uint32_t j = k; j-- > 0;) {
-        const uint32_t s = src[(uint64_t)(c0 + lane + kRansLanes * j) * w + b];
+    for (uint32_t j = steps; j-- > 0;) {
+        const uint32_t i = kRansLanes * j + lane;
+        const bool live = i < len;
+        const uint32_t s = live ? src[(uint64_t)(c0 + i) * w + b] : 0u;
         const uint32_t fs = f[s];
-        const uint32_t x_max = (kRansLow >> 4) * fs;  // 2^19 f: x / f must stay below 2^19
-        while (x >= x_max) {
-            area[--pos] = (uint8_t)x;
-            x >>= 8;
+        const bool emit = live && (uint64_t)x >= ((uint64_t)(kRansLow >> 12) << 16) * fs;
+        const uint64_t msk = __ballot(emit);
+        const uint32_t ne = (uint32_t)__popcll(msk);
+        if (emit) {
+            const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(msk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)msk, 0u));
+            area[wp - ne + r] = (uint16_t)x;
+            x >>= 16;
         }
-        x = ((x / fs) << 12) + x % fs + c[s];
+        wp -= ne;
+        if (live) x = ((x / fs) << 12) + x % fs + c[s];
     }
-    area[--pos] = (uint8_t)(x >> 24);
-    area[--pos] = (uint8_t)(x >> 16);
-    area[--pos] = (uint8_t)(x >> 8);
-    area[--pos] = (uint8_t)x;
-    const uint32_t bytes = kRansLaneCap - pos;
-    E.lens[(uint64_t)item * kRansLanes + lane] = bytes;
-    const uint32_t tot = wave_incl_add(bytes);
-    if (lane == kWave - 1) E.ctot[item] = tot;
+    E.states[(uint64_t)item * kRansLanes + lane] = x;
+    if (lane == 0) E.nwords[item] = kRansChunk - wp;
 }
 
 // single block: plane positions, chunk starts, the header, offsets and models
@@ -2480,24 +2638,26 @@ __global__ __launch_bounds__(256) void k_renc_place(const RansEncDesc E)
 {
     __shared__ uint64_t part[256];
     const uint32_t t = threadIdx.x;
-    uint64_t pos = kRansMeta0;  // already a multiple of 8
+    uint64_t pos = kRansMeta0;
+    for (uint32_t i = 64 + 8 * kRansPlanes + t; i < kRansMeta0; i += 256) E.dst[i] = 0;
     for (uint32_t p = 0; p < (uint32_t)kRansPlanes; p++) {
         const uint32_t i0 = E.item0[p], i1 = E.item0[p + 1], nch = i1 - i0;
-        const uint64_t data0 = pos + 512 + 4ull * 65 * nch;
+        const uint64_t data0 = (pos + 512 + 4ull * (nch + 1) + 15) & ~15ull;
         // the plane's model
-        for (uint32_t q = t; q < 256; q += 256) {
-            const uint16_t v = E.freq[256 * p + q];
-            E.dst[pos + 2 * q] = (uint8_t)v;
-            E.dst[pos + 2 * q + 1] = (uint8_t)(v >> 8);
+        {
+            const uint16_t v = E.freq[256 * p + t];
+            E.dst[pos + 2 * t] = (uint8_t)v;
+            E.dst[pos + 2 * t + 1] = (uint8_t)(v >> 8);
         }
+        for (uint64_t q = pos + 512 + 4ull * (nch + 1) + t; q < data0; q += 256) E.dst[q] = 0;
         if (t == 0) {
             E.ppos[p] = pos;
             for (int q = 0; q < 8; q++) E.dst[64 + 8 * p + q] = (uint8_t)(pos >> (8 * q));
         }
-        // chunk starts: exclusive prefix of the chunk totals, 256 at a time
+        // chunk starts: exclusive prefix of the chunk sizes, 256 at a time
         uint64_t base = 0;
         for (uint32_t i = i0; i < i1; i += 256) {
-            const uint64_t v = i + t < i1 ? E.ctot[i + t] : 0;
+            const uint64_t v = i + t < i1 ? rans_chunk_bytes(E.nwords[i + t]) : 0;
             part[t] = v;
             __syncthreads();
             for (uint32_t off = 1; off < 256; off <<= 1) {
@@ -2510,16 +2670,19 @@ __global__ __launch_bounds__(256) void k_renc_place(const RansEncDesc E)
             base += part[255];
             __syncthreads();
         }
+        if (t == 0) {  // the end of the plane's data, after its last chunk's offset
+            const uint32_t v = (uint32_t)base;
+            for (int q = 0; q < 4; q++) E.dst[pos + 512 + 4ull * nch + q] = (uint8_t)(v >> (8 * q));
+        }
         const uint64_t end = data0 + base;
-        const uint64_t next = p + 1 < (uint32_t)kRansPlanes ? (end + 7) & ~7ull : end;
-        for (uint64_t q = end + t; q < next; q += 256) E.dst[q] = 0;  // padding to the next plane
-        pos = next;
+        const uint64_t next = p + 1 < (uint32_t)kRansPlanes ? (end + 15) & ~15ull : end;
+        pos = next;  // (the data ends on a 16-byte boundary: no gap)
     }
-    if (t < 64) {  // the header: "TMDR", version 1, the shape, zeros
+    if (t < 64) {  // the header: "TMDR", version 2, the shape, zeros
         uint8_t v = 0;
         if (t < 4) v = (uint8_t)"TMDR"[t];
         else if (t < 24) {
-            const uint32_t h[5] = {1u, E.nT, E.nA, E.nU, 0u};
+            const uint32_t h[5] = {kRansVersion, E.nT, E.nA, E.nU, 0u};
             v = (uint8_t)(h[(t - 4) / 4] >> (8 * ((t - 4) % 4)));
         }
         E.dst[t] = v;
@@ -2530,40 +2693,27 @@ __global__ __launch_bounds__(256) void k_renc_place(const RansEncDesc E)
     }
 }
 
-// one wave per chunk: its offset table and its streams, back to back
+// one wave per chunk: its offset, states and words, then zero padding
 __global__ __launch_bounds__(kRansLanes) void k_renc_pack(const RansEncDesc E)
 {
-    __shared__ uint32_t pre[kRansLanes + 1];
     const uint32_t lane = lane_id(), item = blockIdx.x;
     uint32_t p, a, b;
     rans_item_plane(E.item0, item, p, a, b);
     const uint32_t ch = item - E.item0[p], nch = E.item0[p + 1] - E.item0[p];
     const uint64_t pos = E.ppos[p];
-    const uint64_t data0 = pos + 512 + 4ull * 65 * nch;
+    const uint64_t data0 = (pos + 512 + 4ull * (nch + 1) + 15) & ~15ull;
     const uint64_t cs = E.cstart[item];
-    const uint32_t len = E.lens[(uint64_t)item * kRansLanes + lane];
-    const uint32_t incl = wave_incl_add(len);
-    pre[lane + 1] = incl;
-    if (lane == 0) pre[0] = 0;
-    __syncthreads();
-    GLB uint8_t *offs = E.dst + pos + 512 + 4ull * 65 * ch;
-    for (uint32_t q = lane; q < 4 * (kRansLanes + 1); q += kRansLanes) {
-        const uint32_t v = (uint32_t)(cs + pre[q / 4]);
-        offs[q] = (uint8_t)(v >> (8 * (q % 4)));
-    }
-    const uint32_t total = pre[kRansLanes];
+    const uint32_t nw = E.nwords[item];
+    if (lane < 4) E.dst[pos + 512 + 4ull * ch + lane] = (uint8_t)((uint32_t)cs >> (8 * lane));
     GLB uint8_t *out = E.dst + data0 + cs;
-    const GLB uint8_t *areas = E.lanes + (uint64_t)item * kRansLanes * kRansLaneCap;
-    for (uint32_t t = lane; t < total; t += kRansLanes) {
-        // the stream that holds byte t of the chunk
-        uint32_t lo = 0, hi = kRansLanes - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (pre[mid] <= t) lo = mid;
-            else hi = mid - 1;
-        }
-        const uint32_t sl = pre[lo + 1] - pre[lo];
-        out[t] = areas[(uint64_t)lo * kRansLaneCap + (kRansLaneCap - sl) + (t - pre[lo])];
+    const uint32_t x = E.states[(uint64_t)item * kRansLanes + lane];
+    for (int q = 0; q < 4; q++) out[4 * lane + q] = (uint8_t)(x >> (8 * q));
+    const GLB uint16_t *wsrc = E.words + (uint64_t)item * kRansChunk + (kRansChunk - nw);
+    GLB uint8_t *wout = out + 4 * kRansLanes;
+    const uint32_t bytes = (uint32_t)rans_chunk_bytes(nw) - 4 * kRansLanes;
+    for (uint32_t t = lane; t < bytes; t += kRansLanes) {
+        const uint32_t k = t / 2;
+        wout[t] = k < nw ? (uint8_t)(wsrc[k] >> (8 * (t & 1))) : (uint8_t)0;
     }
 }
 
@@ -2617,6 +2767,10 @@ struct tmd_plan {
     bool called = false;  // `done` has been recorded at least once
     uint32_t profiling = 0;                            // stage mask
     bool prof_rans = false;                            // events around tmd_decode_rans's entropy decoding
+    void *h_rans = nullptr;                            // pinned staging of its descriptors
+    size_t h_rans_bytes = 0;
+    hipEvent_t rans_copy = nullptr;                    // their last upload
+    bool rans_staged = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> rans_events;
     std::vector<std::vector<hipEvent_t>> prof_events;  // per recorded call: 2 per stage (unrecorded: null)
     std::vector<hipEvent_t> event_pool;                // events ready for reuse
@@ -2941,6 +3095,8 @@ void tmd_free(tmd_plan_t *P)
     if (P->d_work) (void)hipFree(P->d_work);
     if (P->h_status) (void)hipHostFree(P->h_status);
     if (P->h_desc) (void)hipHostFree(P->h_desc);
+    if (P->h_rans) (void)hipHostFree(P->h_rans);
+    if (P->rans_copy) (void)hipEventDestroy(P->rans_copy);
     if (cur != P->device) (void)hipSetDevice(cur);
     delete P;
 }
@@ -3488,13 +3644,41 @@ void rans_counts(const tmd_frame_shape &S, uint32_t *n)
 constexpr uint8_t kRansWidthHost[kRansArrays] = {1, 1, 1, 2, 4, 2, 2, 2, 1, 1, 2, 2, 2, 2, 4, 4, 2, 2, 2};
 constexpr int rans_width_sum(int a) { return a == kRansArrays ? 0 : kRansWidthHost[a] + rans_width_sum(a + 1); }
 static_assert(rans_width_sum(0) == kRansPlanes, "one plane per byte of the element widths");
+constexpr int rans_width_count(int w, int a = 0)
+{
+    return a == kRansArrays ? 0 : (kRansWidthHost[a] == w) + rans_width_count(w, a + 1);
+}
+static_assert(rans_width_count(1) <= 12 && rans_width_count(2) <= 12 && rans_width_count(4) <= 12 &&
+                  rans_width_count(1) + rans_width_count(2) + rans_width_count(4) == kRansArrays,
+              "arrays of 1, 2 or 4 bytes, at most 12 of each");
 
-// bytes of one frame's decoded arrays (each 256-byte aligned) and its error word
+// The entropy decoding's workspace: the error words of all frames, their
+// descriptors and work-item offsets (copied in by each call), then for each
+// frame its planes' decode tables and positions and its decoded arrays (each
+// section 256-byte aligned).
+constexpr size_t kRansTabOff = 0;
+constexpr size_t kRansInfoOff = kRansTabOff + 256 * ((kRansPlanes * (size_t)kRansTab + 255) / 256);
+constexpr size_t kRansArrOff = kRansInfoOff + 256 * ((16 * kRansPlanes + 255) / 256);
+
+struct RansHead {
+    size_t err, desc, witem, frames;
+};
+
+RansHead rans_head(uint32_t nf)
+{
+    RansHead H;
+    H.err = 0;
+    H.desc = align256(4ull * nf);
+    H.witem = H.desc + align256(sizeof(RansDesc) * nf);
+    H.frames = H.witem + align256(4ull * 3 * (nf + 1));
+    return H;
+}
+
 size_t rans_frame_bytes(const tmd_frame_shape &S)
 {
     uint32_t n[kRansArrays];
     rans_counts(S, n);
-    size_t b = 256;
+    size_t b = kRansArrOff;
     for (int a = 0; a < kRansArrays; a++) b += align256((size_t)kRansWidthHost[a] * std::max<uint32_t>(n[a], 1));
     return b;
 }
@@ -3506,7 +3690,7 @@ extern "C" {
 int tmd_rans_workspace(const tmd_frame_shape *shapes, uint32_t n_frames, size_t *bytes)
 {
     if (!shapes || !bytes || n_frames == 0) return TMD_E_ARG;
-    size_t b = 0;
+    size_t b = rans_head(n_frames).frames;
     for (uint32_t f = 0; f < n_frames; f++) b += rans_frame_bytes(shapes[f]);
     *bytes = b;
     return TMD_OK;
@@ -3521,53 +3705,51 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
     const uint32_t nf = P->n_frames;
     for (uint32_t f = 0; f < nf; f++) {
         const tmd_frame_shape &C = P->shapes[f], &S = shapes[f];
-        if (!coded[f] || S.n_tracks > C.n_tracks || S.n_attached > C.n_attached || S.n_unattached > C.n_unattached)
+        if (!coded[f] || (uintptr_t)coded[f] % 16 || S.n_tracks > C.n_tracks || S.n_attached > C.n_attached ||
+            S.n_unattached > C.n_unattached)
             return TMD_E_ARG;
     }
     hipStream_t s = (hipStream_t)stream;
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
     if (cur != P->device) HIP_TRY(hipSetDevice(P->device));
+    const RansHead H = rans_head(nf);
+    char *ws = (char *)rans_workspace;
     std::vector<tmd_frame_in> in(nf);
     std::vector<const uint32_t *> pre(nf);
-    char *ws = (char *)rans_workspace;
-    int rc = TMD_OK;
-    // (the previous call on this plan may still read these arrays)
-    if (P->called && hipStreamWaitEvent(s, P->done, 0) != hipSuccess) rc = TMD_E_HIP;
-    std::pair<hipEvent_t, hipEvent_t> ev(nullptr, nullptr);
-    if (rc == TMD_OK && P->prof_rans) {
-        std::vector<hipEvent_t> two;
-        if ((rc = take_events(P, 1u, two)) == TMD_OK) {
-            ev = {two[0], two[1]};
-            if (hipEventRecord(ev.first, s) != hipSuccess) rc = TMD_E_HIP;
-        }
-    }
-    for (uint32_t f = 0; f < nf && rc == TMD_OK; f++) {
+    // the descriptors and work-item offsets of every frame, staged in pinned memory
+    const size_t hbytes = H.frames - H.desc;
+    std::vector<uint8_t> hbuf(hbytes, 0);
+    RansDesc *desc = (RansDesc *)hbuf.data();
+    uint32_t *witem = (uint32_t *)(hbuf.data() + (H.witem - H.desc));
+    char *fws = ws + H.frames;
+    for (uint32_t f = 0; f < nf; f++) {
         const tmd_frame_shape &S = shapes[f];
-        RansDesc R;
-        memset(&R, 0, sizeof(R));
+        RansDesc &R = desc[f];
         R.src = (const GLB uint8_t *)coded[f];
         R.size = coded_bytes[f];
         R.nT = S.n_tracks;
         R.nA = S.n_attached;
         R.nU = S.n_unattached;
         rans_counts(S, R.n);
-        uint32_t *err = (uint32_t *)ws;
-        R.err = (GLB uint32_t *)err;
-        size_t off = 256;
+        R.err = (GLB uint32_t *)(ws + H.err) + f;
+        R.tabs = (GLB uint8_t *)(fws + kRansTabOff);
+        R.pinfo = (GLB uint64_t *)(fws + kRansInfoOff);
+        size_t off = kRansArrOff;
         void *arr[kRansArrays];
         for (int a = 0; a < kRansArrays; a++) {
-            arr[a] = ws + off;
+            arr[a] = fws + off;
             R.dst[a] = (GLB uint8_t *)arr[a];
             off += align256((size_t)kRansWidthHost[a] * std::max<uint32_t>(R.n[a], 1));
         }
-        uint32_t items = 0, plane = 0;
-        for (int a = 0; a < kRansArrays; a++)
-            for (int b = 0; b < kRansWidthHost[a]; b++) {
-                R.item0[plane++] = items;
-                items += (R.n[a] + kRansChunk - 1) / kRansChunk;
-            }
-        R.item0[kRansPlanes] = items;
+        // work items of each width class: one per chunk of its arrays
+        for (int a = 0; a < kRansArrays; a++) {
+            const int wi = kRansWidthHost[a] == 1 ? 0 : (kRansWidthHost[a] == 2 ? 1 : 2);
+            const uint32_t k = R.nw[wi]++;
+            R.warr[wi][k] = (uint32_t)a;
+            R.witem0[wi][k + 1] = R.witem0[wi][k] + (R.n[a] + kRansChunk - 1) / kRansChunk;
+        }
+        for (int wi = 0; wi < 3; wi++) witem[wi * (nf + 1) + f + 1] = witem[wi * (nf + 1) + f] + R.witem0[wi][R.nw[wi]];
         tmd_frame_in &I = in[f];
         I.trk_ncls = (const uint8_t *)arr[0]; I.trk_sec0 = (const uint8_t *)arr[1]; I.trk_row0 = (const uint8_t *)arr[2];
         I.trk_pad0 = (const uint16_t *)arr[3]; I.trk_time0 = (const uint32_t *)arr[4];
@@ -3578,22 +3760,59 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
         I.un_count = (const uint32_t *)arr[14]; I.un_time_diff = (const uint32_t *)arr[15];
         I.un_pad_diff = (const uint16_t *)arr[16]; I.un_qtot = (const uint16_t *)arr[17];
         I.un_qmax = (const uint16_t *)arr[18];
-        pre[f] = err;
-        // the error word starts at 0 (a fill kernel, not a memset node, so the
-        // sequence can be captured in a graph)
-        hipLaunchKernelGGL(k_fill32, dim3(1), dim3(64), 0, s, err, 1u, 0u);
-        if (items) hipLaunchKernelGGL(k_rans, dim3(items), dim3(kRansLanes), 0, s, R);
-        if (hipGetLastError() != hipSuccess) rc = TMD_E_HIP;
-        ws += rans_frame_bytes(S);
+        pre[f] = (const uint32_t *)(ws + H.err) + f;
+        fws += rans_frame_bytes(S);
     }
-    if (ev.second) {
-        if (rc == TMD_OK && hipEventRecord(ev.second, s) == hipSuccess) {
-            P->rans_events.push_back(ev);
-        } else {
-            P->event_pool.push_back(ev.first);
-            P->event_pool.push_back(ev.second);
+    int rc = TMD_OK;
+    do {
+        // (the previous call on this plan may still read the workspace, and
+        // its upload may still read the staging buffer)
+        if (P->called && hipStreamWaitEvent(s, P->done, 0) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if (P->rans_staged && hipEventSynchronize(P->rans_copy) != hipSuccess) { rc = TMD_E_HIP; break; }
+        if (P->h_rans_bytes < hbytes) {
+            if (P->h_rans) (void)hipHostFree(P->h_rans);
+            P->h_rans = nullptr;
+            P->h_rans_bytes = 0;
+            if (hipHostMalloc(&P->h_rans, hbytes, 0) != hipSuccess) { rc = TMD_E_HIP; break; }
+            P->h_rans_bytes = hbytes;
         }
-    }
+        if (!P->rans_copy && hipEventCreateWithFlags(&P->rans_copy, hipEventDisableTiming) != hipSuccess) {
+            rc = TMD_E_HIP;
+            break;
+        }
+        memcpy(P->h_rans, hbuf.data(), hbytes);
+        if (hipMemcpyAsync(ws + H.desc, P->h_rans, hbytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipEventRecord(P->rans_copy, s) != hipSuccess) {
+            rc = TMD_E_HIP;
+            break;
+        }
+        P->rans_staged = true;
+        std::pair<hipEvent_t, hipEvent_t> ev(nullptr, nullptr);
+        if (P->prof_rans) {
+            std::vector<hipEvent_t> two;
+            if ((rc = take_events(P, 1u, two)) != TMD_OK) break;
+            ev = {two[0], two[1]};
+            if (hipEventRecord(ev.first, s) != hipSuccess) rc = TMD_E_HIP;
+        }
+        // the error words start at 0 (a fill kernel, not a memset node, so the
+        // sequence can be captured in a graph)
+        const RansDesc *dd = (const RansDesc *)(ws + H.desc);
+        const uint32_t *dw = (const uint32_t *)(ws + H.witem);
+        hipLaunchKernelGGL(k_fill32, dim3(1), dim3(256), 0, s, (uint32_t *)(ws + H.err), nf, 0u);
+        hipLaunchKernelGGL(k_rans_prep, dim3(kRansPlanes * nf), dim3(256), 0, s, dd);
+        if (const uint32_t it = witem[0 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<1>, dim3(it), dim3(kRansLanes), 0, s, dd, dw, nf);
+        if (const uint32_t it = witem[1 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<2>, dim3(it), dim3(kRansLanes), 0, s, dd, dw, nf);
+        if (const uint32_t it = witem[2 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<4>, dim3(it), dim3(kRansLanes), 0, s, dd, dw, nf);
+        if (hipGetLastError() != hipSuccess) rc = TMD_E_HIP;
+        if (ev.second) {
+            if (rc == TMD_OK && hipEventRecord(ev.second, s) == hipSuccess) {
+                P->rans_events.push_back(ev);
+            } else {
+                P->event_pool.push_back(ev.first);
+                P->event_pool.push_back(ev.second);
+            }
+        }
+    } while (0);
     if (cur != P->device) (void)hipSetDevice(cur);
     if (rc != TMD_OK) return rc;
     return decode_impl(P, shapes, in.data(), out, workspace, stream, pre.data());
@@ -3608,7 +3827,7 @@ struct RansEncLayout {
     uint32_t items = 0;
     uint32_t item0[kRansPlanes + 1];
     uint64_t bound = 0;
-    size_t hist, freq, lens, ctot, cstart, ppos, lanes, total;
+    size_t hist, freq, words, states, nwords, cstart, ppos, total;
 };
 
 int rans_enc_layout(const tmd_frame_shape &S, RansEncLayout &L)
@@ -3623,7 +3842,9 @@ int rans_enc_layout(const tmd_frame_shape &S, RansEncLayout &L)
         for (int b = 0; b < kRansWidthHost[a]; b++) {
             L.item0[plane++] = items;
             items += nch;
-            bound += 8 + 512 + (4ull * 65 + 4ull * kRansLanes) * nch + 2ull * n[a];
+            // alignment, model, chunk offsets, then per chunk its states, at
+            // most one word per symbol, and padding
+            bound += 16 + 512 + 4ull * (nch + 1) + 16 + (4ull * kRansLanes + 16) * nch + 2ull * n[a];
         }
     }
     L.item0[kRansPlanes] = items;
@@ -3637,11 +3858,11 @@ int rans_enc_layout(const tmd_frame_shape &S, RansEncLayout &L)
     };
     L.hist = take(4ull * 256 * kRansPlanes);
     L.freq = take(2ull * 256 * kRansPlanes);
-    L.lens = take(4ull * kRansLanes * items);
-    L.ctot = take(4ull * items);
+    L.words = take(2ull * kRansChunk * items);
+    L.states = take(4ull * kRansLanes * items);
+    L.nwords = take(4ull * items);
     L.cstart = take(8ull * items);
     L.ppos = take(8ull * (kRansPlanes + 1));
-    L.lanes = take((size_t)kRansLaneCap * kRansLanes * items);
     L.total = off;
     return TMD_OK;
 }
@@ -3685,11 +3906,11 @@ int tmd_encode_rans(const tmd_frame_shape *shape, const tmd_frame_in *in, uint8_
     char *ws = (char *)workspace;
     E.hist = (GLB uint32_t *)(ws + L.hist);
     E.freq = (GLB uint16_t *)(ws + L.freq);
-    E.lens = (GLB uint32_t *)(ws + L.lens);
-    E.ctot = (GLB uint32_t *)(ws + L.ctot);
+    E.words = (GLB uint16_t *)(ws + L.words);
+    E.states = (GLB uint32_t *)(ws + L.states);
+    E.nwords = (GLB uint32_t *)(ws + L.nwords);
     E.cstart = (GLB uint64_t *)(ws + L.cstart);
     E.ppos = (GLB uint64_t *)(ws + L.ppos);
-    E.lanes = (GLB uint8_t *)(ws + L.lanes);
     E.dst = (GLB uint8_t *)coded;
     E.size = (GLB uint64_t *)coded_bytes;
     E.nT = shape->n_tracks;
