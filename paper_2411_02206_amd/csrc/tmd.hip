@@ -2170,13 +2170,16 @@ __global__ __launch_bounds__(256) void k_enc_un_delta(const EncDesc E, const uns
 //   k_rans_prep: one block per plane builds its decode tables (the symbol of
 //     every 12-bit slot; each symbol's frequency and start) and finds where
 //     its chunks' data begins.
-//   k_rans<W>: one wave per chunk of an array of W-byte elements.  Lane l
-//     runs lane l of the W planes side by side (W independent state chains),
-//     so every step yields whole elements.  A step's words are consecutive in
-//     the chunk's stream (lanes in order), so the stream is read ahead, one
-//     block of kRansBlk steps early, with one-dword-per-lane loads into an LDS
-//     ring per plane; the decoded elements of a block are staged in LDS and
-//     written 4 per lane.  Global memory is touched only between blocks.
+//   k_rans<W>: workgroups of kRansWaves waves, one wave per chunk of an
+//     array of W-byte elements; the waves of a workgroup take consecutive
+//     chunks of one array and share its planes' tables.  Lane l runs lane l
+//     of the W planes side by side (W independent state chains), so every
+//     step yields whole elements; planes of a single symbol (f = 2^12) need
+//     no decoding.  A step's words are consecutive in the chunk's stream
+//     (lanes in order), so the stream is read ahead one block of steps early,
+//     with one-dword-per-lane loads into an LDS ring per plane; the decoded
+//     elements of a block are staged in LDS and written out whole.  Global
+//     memory is touched only between blocks.
 // ---------------------------------------------------------------------------
 constexpr int kRansPlanes = 39, kRansArrays = 19, kRansLanes = 64, kRansPerLane = 512;
 constexpr uint32_t kRansChunk = kRansLanes * kRansPerLane;
@@ -2184,13 +2187,19 @@ constexpr uint32_t kRansLow = 1u << 16;
 constexpr uint32_t kRansHdr = 64;
 constexpr uint32_t kRansVersion = 2;
 constexpr uint32_t kRansBad = TMD_F_CODED;
-constexpr uint32_t kRansBlk = 4;                 // steps per block (256 elements: 4 per lane)
 constexpr uint32_t kRansUnit = 128;              // words per read-ahead load (a dword per lane)
-constexpr uint32_t kRansAhead = 2 * kRansLanes * kRansBlk;  // words kept ahead of the reads
-constexpr uint32_t kRansRing = 1024;             // words of a plane's ring
 constexpr uint32_t kRansTab = 4096 + 4 * 256;    // bytes of a plane's decode tables
-static_assert(kRansBlk * kRansLanes == 4 * kRansLanes, "a block's elements are 4 per lane");
-static_assert(kRansAhead + kRansUnit <= kRansRing, "the ring holds what is read ahead");
+constexpr uint32_t kRansWaves = 4;               // waves (chunks) per workgroup of k_rans
+// steps per block (a lane's elements per block), and words of a plane's ring,
+// for W-byte elements (4-byte ones take shorter blocks and rings: less LDS)
+constexpr uint32_t rans_blk(int W) { return W == 4 ? 2 : 4; }
+constexpr uint32_t rans_ring(int W) { return W == 4 ? 512 : 1024; }
+// (a block reads fewer than kRansLanes blk words; the read-ahead keeps
+// 2 kRansLanes blk words ahead and lands whole units)
+static_assert(2 * kRansLanes * rans_blk(1) + kRansUnit <= rans_ring(1) &&
+                  2 * kRansLanes * rans_blk(2) + kRansUnit <= rans_ring(2) &&
+                  2 * kRansLanes * rans_blk(4) + kRansUnit <= rans_ring(4),
+              "the ring holds what is read ahead");
 
 __device__ __constant__ const uint8_t kRansWidth[kRansArrays] = {1, 1, 1, 2, 4, 2, 2, 2, 1, 1, 2, 2, 2, 2, 4, 4, 2, 2, 2};
 // first plane of each array
@@ -2272,7 +2281,7 @@ __global__ __launch_bounds__(256) void k_rans_prep(const RansDesc *descs)
     for (int q = 0; q < 16; q++, slot++) {
         while (s < 255 && cend[s] <= slot) s++;
         if (q % 4 == 0) wv[q / 4] = 0;
-        wv[q / 4] |= s << (8 * (q % 4));
+        wv[q / 4] |= min(s, 255u) << (8 * (q % 4));  // (256 only in a model that does not sum to 2^12)
     }
     *(GLB uint4 *)(tab + 16 * t) = make_uint4(wv[0], wv[1], wv[2], wv[3]);
     if (t == 0) {
@@ -2282,12 +2291,186 @@ __global__ __launch_bounds__(256) void k_rans_prep(const RansDesc *descs)
     }
 }
 
-// (witem: for each width class, the first work item of each frame, then the
-// total; a work item is one chunk of one array of the class)
+// A wave's chunk, for rans_chunk: where its planes' data and tables are,
+// where its elements go, and the bytes of its planes of one symbol.
 template <int W>
-__global__ __launch_bounds__(kRansLanes) void k_rans(const RansDesc *descs, const uint32_t *witem, uint32_t nf)
+struct RansChunk {
+    using Elem = typename std::conditional<W == 1, uint8_t, typename std::conditional<W == 2, uint16_t, uint32_t>::type>::type;
+    const GLB uint8_t *src;
+    const GLB uint64_t *pinfo;  // of the array's first plane
+    uint32_t ch;
+    GLB Elem *dst;              // the chunk's first element
+    uint32_t len, steps, cval;
+    const uint8_t *sym;         // LDS: sym[plane][4096]
+    const uint32_t *fc;         // LDS: fc[plane][256]
+    uint32_t *ring;             // LDS: this wave's rings, ring[chain][rans_ring(W) / 2]
+    Elem *stage;                // LDS: this wave's stage
+    uint32_t *trash;            // LDS: this wave's trash slots
+    uint32_t lane;
+    GLB uint32_t *err;
+};
+
+// Decode one chunk whose planes pl[0 .. K-1] need decoding (K independent
+// state chains per lane).  One step takes one symbol of each chain per lane,
+// the chains side by side (table reads of all chains, then their arithmetic,
+// then their ring reads).  A lane whose state fell below 2^16 takes the word
+// at rd + (the number of such lanes below it); every lane reads the ring and
+// masks the word out where it is not needed (no branch, so the chains' reads
+// can overlap).  Global memory is touched only between blocks.
+template <int W, int K>
+__device__ __forceinline__ void rans_chunk(const RansChunk<W> &C, const uint32_t *pl)
+{
+    using Elem = typename RansChunk<W>::Elem;
+    using Out = typename std::conditional<rans_blk(W) * W == 4, uint32_t, uint2>::type;  // a lane's elements of a block
+    constexpr uint32_t B = rans_blk(W), RING = rans_ring(W), AHEAD = 2 * kRansLanes * B;
+    static_assert(B * W == 4 || B * W == 8, "4 or 8 bytes per lane and block");
+    const uint32_t lane = C.lane, len = C.len, steps = C.steps;
+    // the chains' data: states, word streams
+    uint32_t x[K ? K : 1], nwords[K ? K : 1], rd[K ? K : 1], wr[K ? K : 1];
+    const GLB uint32_t *wsrc[K ? K : 1];
+    const uint8_t *sym[K ? K : 1];
+    const uint32_t *fc[K ? K : 1];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const uint64_t pos = readlane64(C.pinfo[2 * pl[k]]), data0 = readlane64(C.pinfo[2 * pl[k] + 1]);
+        const uint32_t o0 = readlane(rans_rd32(C.src, pos + 512 + 4ull * C.ch), 0);
+        const uint32_t o1 = readlane(rans_rd32(C.src, pos + 512 + 4ull * C.ch + 4), 0);
+        wsrc[k] = (const GLB uint32_t *)(C.src + data0 + o0);
+        x[k] = wsrc[k][lane];
+        wsrc[k] += kRansLanes;
+        nwords[k] = (o1 - o0 - 4 * kRansLanes) / 2;
+        rd[k] = 0;
+        sym[k] = C.sym + 4096 * pl[k];
+        fc[k] = C.fc + 256 * pl[k];
+    }
+    // the first AHEAD words of each stream (a chain's loads in flight together)
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        constexpr uint32_t U = AHEAD / kRansUnit;
+        uint32_t v[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            const uint32_t wi = kRansUnit * u + 2 * lane;
+            v[u] = wi < nwords[k] ? wsrc[k][wi / 2] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) C.ring[k * (RING / 2) + ((kRansUnit * u + 2 * lane) % RING) / 2] = v[u];
+        wr[k] = AHEAD;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    auto step = [&](bool live) -> uint32_t {
+        uint32_t slot[K ? K : 1], sy[K ? K : 1], e[K ? K : 1], xn[K ? K : 1], need[K ? K : 1];
+        uint64_t msk[K ? K : 1];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            slot[k] = x[k] & 4095u;
+            sy[k] = sym[k][slot[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) e[k] = fc[k][sy[k]];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            xn[k] = __umul24(e[k] & 0xFFFFu, x[k] >> 12) + slot[k] - (e[k] >> 16);
+            need[k] = live && xn[k] < kRansLow;
+            msk[k] = __builtin_amdgcn_ballot_w64(need[k]);
+        }
+        uint32_t v = C.cval;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(msk[k] >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)msk[k], 0u));
+            const uint32_t w = ((const uint16_t *)(C.ring + k * (RING / 2)))[(rd[k] + r) & (RING - 1)];
+            xn[k] = (xn[k] << (need[k] << 4)) | (w & (0u - need[k]));
+            rd[k] += (uint32_t)__popcll(msk[k]);
+            if (live) x[k] = xn[k];
+            v |= sy[k] << (8 * pl[k]);
+        }
+        return v;
+    };
+    uint32_t over = 0;  // a stream read beyond its words
+    for (uint32_t j0 = 0; j0 < steps; j0 += B) {
+        // read ahead what the next block may read: up to 3 units per chain
+        // (the units not needed are not loaded, their registers hold 0)
+        uint32_t pf[K ? K : 1][3], m[K ? K : 1];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            m[k] = 0;
+#pragma unroll
+            for (int u = 0; u < 3; u++) {
+                const uint32_t u0 = wr[k] + kRansUnit * u;
+                const uint32_t wi = u0 + 2 * lane;
+                const bool take = u0 < rd[k] + AHEAD && u0 < nwords[k];
+                pf[k][u] = take && wi < nwords[k] ? wsrc[k][wi / 2] : 0u;
+                m[k] += take;
+            }
+        }
+        if (kRansLanes * (j0 + B) <= len) {  // every lane has a symbol at every step
+#pragma unroll
+            for (uint32_t s = 0; s < B; s++) C.stage[kRansLanes * s + lane] = (Elem)step(true);
+        } else {
+            for (uint32_t s = 0; s < B; s++) {
+                const uint32_t j = j0 + s;
+                if (j >= steps) break;
+                C.stage[kRansLanes * s + lane] = (Elem)step(kRansLanes * j + lane < len);
+            }
+        }
+        // end of the block: the read-ahead has arrived, the elements go out.
+        // Every register is written (a write under a condition would make the
+        // compiler wait for all loads at the next block's start): the units
+        // loaded into the ring, the others into the wave's trash slots.
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+#pragma unroll
+            for (int u = 0; u < 3; u++) {
+                uint32_t *d = (uint32_t)u < m[k] ? &C.ring[k * (RING / 2) + ((wr[k] + kRansUnit * u + 2 * lane) % RING) / 2]
+                                                 : &C.trash[lane];
+                *d = pf[k][u];
+            }
+            wr[k] += kRansUnit * m[k];
+            over |= rd[k] > nwords[k];
+        }
+        // (the stage and the rings are this wave's own: in-order LDS, no barrier)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t nb = len - kRansLanes * j0 < kRansLanes * B ? len - kRansLanes * j0 : kRansLanes * B;
+        const Elem *sv = C.stage + B * lane;
+        GLB Elem *dv = C.dst + kRansLanes * j0 + B * lane;
+        if (B * lane + B <= nb) {
+            *(GLB Out *)dv = *(const Out *)sv;
+        } else {
+            for (uint32_t e = 0; e < B; e++)
+                if (B * lane + e < nb) dv[e] = sv[e];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // a well-formed chunk: every state back at its start, every word read
+    bool fine = !over;
+#pragma unroll
+    for (int k = 0; k < K; k++) fine = fine && x[k] == kRansLow && nwords[k] - rd[k] < 8;
+    if (__ballot(!fine) && lane == 0) atomicOr(C.err, kRansBad);
+}
+
+// (witem: for each width class, the first work item of each frame, then the
+// total; a work item is kRansWaves consecutive chunks of one array of the
+// class)
+template <int W>
+__global__ __launch_bounds__(kRansLanes * kRansWaves) void k_rans(const RansDesc *descs, const uint32_t *witem,
+                                                                  uint32_t nf)
 {
     constexpr int WI = W == 1 ? 0 : (W == 2 ? 1 : 2);
+    constexpr uint32_t B = rans_blk(W), RING = rans_ring(W);
+    using Elem = typename RansChunk<W>::Elem;
+    __shared__ __align__(16) uint8_t sym[W][4096];  // the symbol of every slot
+    __shared__ __align__(16) uint32_t fc[W][256];   // f | c << 16 of every symbol
+    __shared__ uint32_t ring[kRansWaves][W][RING / 2];  // 2 words per entry
+    __shared__ __align__(16) Elem stage[kRansWaves][B * kRansLanes];
+    __shared__ uint32_t trash[kRansWaves][kRansLanes];  // where read-ahead units not loaded are written
+    const uint32_t wave = threadIdx.x / kRansLanes, lane = lane_id();
     // the frame of this work item: the last one whose first item is at or below it
     const GLB uint32_t *fi = (const GLB uint32_t *)witem + WI * (nf + 1);
     uint32_t flo = 0, fhi = nf - 1;
@@ -2297,14 +2480,9 @@ __global__ __launch_bounds__(kRansLanes) void k_rans(const RansDesc *descs, cons
         else fhi = mid - 1;
     }
     const GLB RansDesc *R = (const GLB RansDesc *)descs + flo;
-    using Elem = typename std::conditional<W == 1, uint8_t, typename std::conditional<W == 2, uint16_t, uint32_t>::type>::type;
-    __shared__ uint32_t sym4[W][1024];   // the symbol of every slot, 4 per word
-    __shared__ uint32_t fc[W][256];
-    __shared__ uint32_t ring[W][kRansRing / 2];  // 2 words per entry
-    __shared__ uint32_t stage[kRansBlk * kRansLanes * W / 4];
-    const uint32_t lane = lane_id(), item = blockIdx.x - readlane(fi[flo], 0);
-    // the array and chunk of this item
-    // (the descriptor's fields read once, into wave-uniform registers)
+    const uint32_t item = blockIdx.x - readlane(fi[flo], 0);
+    // the array and chunks of this item (the descriptor's fields read once,
+    // into wave-uniform registers)
     uint32_t a = readlane(R->warr[WI][0], 0), i0 = 0;
     const uint32_t nw = readlane(R->nw[WI], 0);
 #pragma unroll
@@ -2315,31 +2493,44 @@ __global__ __launch_bounds__(kRansLanes) void k_rans(const RansDesc *descs, cons
         }
     const GLB uint8_t *const src = (const GLB uint8_t *)readlane64((uint64_t)R->src);
     const uint64_t size = readlane64(R->size);
-    const uint32_t ch = item - i0, n = readlane(R->n[a], 0), p0 = readlane(kRansPlane0[a], 0);
-    const uint32_t c0 = ch * kRansChunk;
-    const uint32_t len = n - c0 < kRansChunk ? n - c0 : kRansChunk;
-    const uint32_t steps = (len + kRansLanes - 1) / kRansLanes;
+    const uint32_t n = readlane(R->n[a], 0), p0 = readlane(kRansPlane0[a], 0);
     const uint32_t nch = (n + kRansChunk - 1) / kRansChunk;
-    GLB Elem *dst = (GLB Elem *)R->dst[a] + c0;
-    // the W planes' tables (all of a plane's loads in flight together)
-    static_assert(kRansTab / 16 == 5 * kRansLanes, "5 table loads per lane");
+    // the planes' tables, shared by the workgroup's waves
+    static_assert(kRansTab / 16 <= 2 * kRansLanes * kRansWaves, "2 table loads per thread");
 #pragma unroll
     for (int q = 0; q < W; q++) {
         const GLB uint4 *tb = (const GLB uint4 *)(R->tabs + (uint64_t)(p0 + q) * kRansTab);
-        uint4 tv[5];
+        uint4 tv[2];
 #pragma unroll
-        for (int k = 0; k < 5; k++) tv[k] = tb[lane + kRansLanes * k];
+        for (int k = 0; k < 2; k++) {
+            const uint32_t i = threadIdx.x + kRansLanes * kRansWaves * k;
+            tv[k] = tb[min(i, kRansTab / 16 - 1)];
+        }
 #pragma unroll
-        for (int k = 0; k < 5; k++) {
-            const uint32_t i = lane + kRansLanes * k;
-            uint32_t *d = k < 4 ? &sym4[q][4 * i] : &fc[q][4 * (i - 256)];
-            d[0] = tv[k].x; d[1] = tv[k].y; d[2] = tv[k].z; d[3] = tv[k].w;
+        for (int k = 0; k < 2; k++) {
+            const uint32_t i = threadIdx.x + kRansLanes * kRansWaves * k;
+            if (i < kRansTab / 16) *(uint4 *)(i < 256 ? (void *)&sym[q][16 * i] : (void *)&fc[q][4 * (i - 256)]) = tv[k];
         }
     }
-    // the W planes' chunk data: states, word streams
+    __syncthreads();
+    // this wave's chunk (no workgroup barrier after this point)
+    const uint32_t ch = kRansWaves * (item - i0) + wave;
+    if (ch >= nch) return;
+    const uint32_t c0 = ch * kRansChunk;
+    const uint32_t len = n - c0 < kRansChunk ? n - c0 : kRansChunk;
+    const uint32_t steps = (len + kRansLanes - 1) / kRansLanes;
+    GLB Elem *dst = (GLB Elem *)readlane64((uint64_t)R->dst[a]) + c0;
+    uint32_t(*rg)[RING / 2] = ring[wave];
+    Elem *stg = stage[wave];
+    // planes of one symbol: its byte, nothing to decode
+    uint32_t cst = 0, csym[W];
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+        csym[q] = readlane(sym[q][0], 0);
+        if ((readlane(fc[q][csym[q]], 0) & 0xFFFFu) == 4096u) cst |= 1u << q;
+    }
+    // the W planes' chunk data must be well formed: offsets, sizes, states
     uint32_t x[W];
-    uint64_t wbase[W];
-    uint32_t nwords[W], rd[W], wr[W];
     bool bad = false;
 #pragma unroll
     for (int q = 0; q < W; q++) {
@@ -2349,15 +2540,11 @@ __global__ __launch_bounds__(kRansLanes) void k_rans(const RansDesc *descs, cons
             o0 = readlane(rans_rd32(src, pos + 512 + 4ull * ch), 0);
             o1 = readlane(rans_rd32(src, pos + 512 + 4ull * ch + 4), 0);
         }
-        const bool qok = data0 && ch < nch && o1 >= o0 && o1 - o0 >= 4 * kRansLanes && (o0 % 16) == 0 &&
+        const bool qok = data0 && o1 >= o0 && o1 - o0 >= 4 * kRansLanes && (o0 % 16) == 0 &&
                          ((o1 - o0) % 16) == 0 && data0 + o1 <= size;
         bad |= !qok;
         const uint64_t d0 = qok ? data0 + o0 : 0;
         x[q] = qok ? ((const GLB uint32_t *)(src + d0))[lane] : kRansLow;
-        wbase[q] = d0 + 4 * kRansLanes;
-        nwords[q] = qok ? (o1 - o0 - 4 * kRansLanes) / 2 : 0;
-        rd[q] = 0;
-        wr[q] = 0;
     }
     // every stored state is in [2^16, 2^32) (this also waits for the states
     // here, not inside the loop)
@@ -2368,95 +2555,30 @@ __global__ __launch_bounds__(kRansLanes) void k_rans(const RansDesc *descs, cons
         for (uint32_t e = lane; e < len; e += kRansLanes) dst[e] = 0;
         return;
     }
-    // the first kRansAhead words of each stream (a plane's loads in flight together)
+    // the planes that need decoding run as K chains; the others only add
+    // their byte to every element
+    uint32_t cval = 0, K = 0, pl[W];
 #pragma unroll
     for (int q = 0; q < W; q++) {
-        constexpr uint32_t U = kRansAhead / kRansUnit;
-        uint32_t v[U];
-#pragma unroll
-        for (uint32_t u = 0; u < U; u++) {
-            const uint32_t wi = kRansUnit * u + 2 * lane;
-            v[u] = wi < nwords[q] ? ((const GLB uint32_t *)(src + wbase[q]))[wi / 2] : 0u;
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < U; u++) ring[q][((kRansUnit * u + 2 * lane) % kRansRing) / 2] = v[u];
-        wr[q] = kRansAhead;
+        pl[q] = 0;
+        if ((cst >> q) & 1u) cval |= csym[q] << (8 * q);
     }
-    __syncthreads();
-    uint32_t over = 0;  // a stream read beyond its words
-    for (uint32_t j0 = 0; j0 < steps; j0 += kRansBlk) {
-        // read ahead what the next block may read: up to 3 units per plane
-        // (the units not needed are not loaded, their registers hold 0)
-        uint32_t pf[W][3], m[W];
 #pragma unroll
-        for (int q = 0; q < W; q++) {
-            m[q] = 0;
+    for (int q = 0; q < W; q++)
+        if (!((cst >> q) & 1u)) {
 #pragma unroll
-            for (int k = 0; k < 3; k++) {
-                const uint32_t u0 = wr[q] + kRansUnit * k;
-                const uint32_t wi = u0 + 2 * lane;
-                const bool take = u0 < rd[q] + kRansAhead && u0 < nwords[q];
-                pf[q][k] = take && wi < nwords[q] ? ((const GLB uint32_t *)(src + wbase[q]))[wi / 2] : 0u;
-                m[q] += take;
-            }
+            for (int k = 0; k < W; k++) pl[k] = (uint32_t)k == K ? (uint32_t)q : pl[k];
+            K++;
         }
-        // the block's steps
-        for (uint32_t s = 0; s < kRansBlk; s++) {
-            const uint32_t j = j0 + s;
-            if (j >= steps) break;
-            const bool live = kRansLanes * j + lane < len;
-            uint32_t v = 0;
-#pragma unroll
-            for (int q = 0; q < W; q++) {
-                const uint32_t slot = x[q] & 4095u;
-                const uint32_t sy = (sym4[q][slot >> 2] >> (8 * (slot & 3))) & 0xFFu;
-                const uint32_t e = fc[q][sy];
-                uint32_t xn = (e & 0xFFFFu) * (x[q] >> 12) + slot - (e >> 16);
-                const bool need = live && xn < kRansLow;
-                const uint64_t msk = __ballot(need);
-                if (need) {
-                    const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(msk >> 32),
-                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)msk, 0u));
-                    const uint32_t wi = (rd[q] + r) % kRansRing;
-                    xn = (xn << 16) | ((ring[q][wi / 2] >> (16 * (wi & 1))) & 0xFFFFu);
-                }
-                rd[q] += (uint32_t)__popcll(msk);
-                if (live) x[q] = xn;
-                v |= sy << (8 * q);
-            }
-            ((Elem *)stage)[kRansLanes * s + lane] = (Elem)v;
-        }
-        // end of the block: the read-ahead has arrived, the elements go out.
-        // All three units go into the ring: the slots of units not loaded
-        // hold words already read (a unit's slot last held the word kRansRing
-        // earlier, and the reads are at most kRansAhead + 3 kRansUnit behind),
-        // and are written again before they are read.
-#pragma unroll
-        for (int q = 0; q < W; q++) {
-#pragma unroll
-            for (int k = 0; k < 3; k++) ring[q][((wr[q] + kRansUnit * k + 2 * lane) % kRansRing) / 2] = pf[q][k];
-            wr[q] += kRansUnit * m[q];
-            over |= rd[q] > nwords[q];
-        }
-        __syncthreads();
-        const uint32_t nb = len - kRansLanes * j0 < kRansLanes * kRansBlk ? len - kRansLanes * j0 : kRansLanes * kRansBlk;
-        const Elem *sv = (const Elem *)stage + 4 * lane;
-        GLB Elem *dv = dst + kRansLanes * j0 + 4 * lane;
-        if (4 * lane + 4 <= nb) {
-            if (W == 1) *(GLB uint32_t *)dv = *(const uint32_t *)sv;
-            else if (W == 2) *(GLB uint2 *)dv = *(const uint2 *)sv;
-            else *(GLB uint4 *)dv = *(const uint4 *)sv;
-        } else {
-            for (uint32_t e = 0; e < 4; e++)
-                if (4 * lane + e < nb) dv[e] = sv[e];
-        }
-        __syncthreads();
+    RansChunk<W> C{src, R->pinfo + 2 * p0, ch, dst, len, steps, cval, &sym[0][0], &fc[0][0], &rg[0][0], stg,
+                   trash[wave], lane, R->err};
+    switch (K) {
+    case 0: rans_chunk<W, 0>(C, pl); break;
+    case 1: rans_chunk<W, 1>(C, pl); break;
+    case 2: if constexpr (W >= 2) rans_chunk<W, 2>(C, pl); break;
+    case 3: if constexpr (W >= 3) rans_chunk<W, 3>(C, pl); break;
+    default: if constexpr (W >= 4) rans_chunk<W, 4>(C, pl); break;
     }
-    // a well-formed chunk: every state back at its start, every word read
-    bool fine = !over;
-#pragma unroll
-    for (int q = 0; q < W; q++) fine = fine && x[q] == kRansLow && nwords[q] - rd[q] < 8;
-    if (__ballot(!fine) && lane == 0) atomicOr(R->err, kRansBad);
 }
 
 // ---------------------------------------------------------------------------
@@ -3747,7 +3869,8 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
             const int wi = kRansWidthHost[a] == 1 ? 0 : (kRansWidthHost[a] == 2 ? 1 : 2);
             const uint32_t k = R.nw[wi]++;
             R.warr[wi][k] = (uint32_t)a;
-            R.witem0[wi][k + 1] = R.witem0[wi][k] + (R.n[a] + kRansChunk - 1) / kRansChunk;
+            const uint32_t nch = (R.n[a] + kRansChunk - 1) / kRansChunk;
+            R.witem0[wi][k + 1] = R.witem0[wi][k] + (nch + kRansWaves - 1) / kRansWaves;
         }
         for (int wi = 0; wi < 3; wi++) witem[wi * (nf + 1) + f + 1] = witem[wi * (nf + 1) + f] + R.witem0[wi][R.nw[wi]];
         tmd_frame_in &I = in[f];
@@ -3800,9 +3923,9 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
         const uint32_t *dw = (const uint32_t *)(ws + H.witem);
         hipLaunchKernelGGL(k_fill32, dim3(1), dim3(256), 0, s, (uint32_t *)(ws + H.err), nf, 0u);
         hipLaunchKernelGGL(k_rans_prep, dim3(kRansPlanes * nf), dim3(256), 0, s, dd);
-        if (const uint32_t it = witem[0 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<1>, dim3(it), dim3(kRansLanes), 0, s, dd, dw, nf);
-        if (const uint32_t it = witem[1 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<2>, dim3(it), dim3(kRansLanes), 0, s, dd, dw, nf);
-        if (const uint32_t it = witem[2 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<4>, dim3(it), dim3(kRansLanes), 0, s, dd, dw, nf);
+        if (const uint32_t it = witem[0 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<1>, dim3(it), dim3(kRansLanes * kRansWaves), 0, s, dd, dw, nf);
+        if (const uint32_t it = witem[1 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<2>, dim3(it), dim3(kRansLanes * kRansWaves), 0, s, dd, dw, nf);
+        if (const uint32_t it = witem[2 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<4>, dim3(it), dim3(kRansLanes * kRansWaves), 0, s, dd, dw, nf);
         if (hipGetLastError() != hipSuccess) rc = TMD_E_HIP;
         if (ev.second) {
             if (rc == TMD_OK && hipEventRecord(ev.second, s) == hipSuccess) {
