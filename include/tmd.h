@@ -273,6 +273,21 @@ int tmd_pipe_create(const tmd_frame_shape *capacity, uint32_t depth, const tmd_p
 int tmd_pipe_run(tmd_pipe_t *pipe, uint32_t n_frames, const tmd_frame_shape *shapes, const tmd_frame_in *in,
                  tmd_frame_out *out, uint32_t *flags);
 
+/*
+ * As tmd_pipe_run, for entropy-coded frames in HOST memory (coded[i],
+ * coded_bytes[i]: the format of tmd_decode_rans): the coded bytes are what
+ * crosses the bus, and each slot decodes them with tmd_decode_rans.  The
+ * first call gives every slot a device buffer for coded frames up to the
+ * largest size the capacity's coder may produce (tmd_rans_encode_workspace)
+ * and the entropy decoding's workspace (hipMalloc, released by
+ * tmd_pipe_free).  A frame whose coded data is malformed gets TMD_F_CODED
+ * (TMD_E_STREAM).  Errors: as tmd_pipe_run, and TMD_E_CAPACITY if a coded
+ * frame is larger than that buffer.
+ */
+int tmd_pipe_run_rans(tmd_pipe_t *pipe, uint32_t n_frames, const tmd_frame_shape *shapes,
+                      const uint8_t *const *coded, const uint64_t *coded_bytes, tmd_frame_out *out,
+                      uint32_t *flags);
+
 /* Release a pipeline (waits for its streams). NULL is a no-op. */
 void tmd_pipe_free(tmd_pipe_t *pipe);
 

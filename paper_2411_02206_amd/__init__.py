@@ -383,6 +383,17 @@ def to_host(frame, pin=True):
     return out
 
 
+def pin_bytes(data):
+    """A copy of `data` (numpy uint8 or a CPU/device tensor) in page-locked
+    host memory, as a uint8 CPU tensor (for Pipeline.run_rans)."""
+    torch = _torch()
+    if hasattr(data, "is_cuda"):
+        data = data.cpu()
+    else:
+        data = torch.from_numpy(np.ascontiguousarray(data, np.uint8))
+    return data.pin_memory()
+
+
 def alloc_host_out(shape, pin=True, capacity=None):
     """Host output buffers (torch CPU tensors, page-locked if `pin`) for a
     frame of `shape`; same keys and types as alloc_out."""
@@ -444,6 +455,27 @@ class Pipeline:
         rc = _lib.lib().tmd_pipe_run(self._h, n, sh, fin, fout, flags)
         if rc not in (OK, E_INPUT, E_STREAM):
             _lib.check(rc, "tmd_pipe_run")
+        return [int(flags[i]) for i in range(n)]
+
+    def run_rans(self, coded, shapes, outs):
+        """Decode entropy-coded frames held in host memory (uint8 CPU tensors,
+        page-locked for overlap; see pin_bytes) of the given shapes into host
+        outputs (tmd_pipe_run_rans).  Returns the list of status flags."""
+        n = len(coded)
+        if len(outs) != n or len(shapes) != n:
+            raise ValueError("one shape and one output dict per coded frame")
+        sh = (_lib.FrameShape * max(n, 1))(*[_lib.FrameShape(*(int(v) for v in s)) for s in shapes])
+        ptrs = (C.c_void_p * max(n, 1))(*[c.data_ptr() for c in coded])
+        sizes = (C.c_uint64 * max(n, 1))(*[c.numel() for c in coded])
+        fout = (_lib.FrameOut * max(n, 1))()
+        for i in range(n):
+            for k in OUT_FIELDS:
+                setattr(fout[i], k, _ptr(outs[i][k]))
+            fout[i].capacity = int(outs[i]["capacity"])
+        flags = (C.c_uint32 * max(n, 1))()
+        rc = _lib.lib().tmd_pipe_run_rans(self._h, n, sh, ptrs, sizes, fout, flags)
+        if rc not in (OK, E_INPUT, E_STREAM):
+            _lib.check(rc, "tmd_pipe_run_rans")
         return [int(flags[i]) for i in range(n)]
 
 

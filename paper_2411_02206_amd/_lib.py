@@ -120,6 +120,9 @@ def lib():
         L.tmd_pipe_run.argtypes = [P, C.c_uint32, C.POINTER(FrameShape), C.POINTER(FrameIn), C.POINTER(FrameOut),
                                    C.POINTER(C.c_uint32)]
         L.tmd_pipe_run.restype = C.c_int
+        L.tmd_pipe_run_rans.argtypes = [P, C.c_uint32, C.POINTER(FrameShape), C.POINTER(P), C.POINTER(C.c_uint64),
+                                        C.POINTER(FrameOut), C.POINTER(C.c_uint32)]
+        L.tmd_pipe_run_rans.restype = C.c_int
         L.tmd_pipe_free.argtypes = [P]
         L.tmd_pipe_free.restype = None
         _LIB = L

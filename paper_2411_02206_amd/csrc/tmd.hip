@@ -4111,6 +4111,9 @@ struct PipeSlot {
     tmd_frame_in in{};
     tmd_frame_out out{};
     int64_t frame = -1;  // frame of the current run whose result is still in flight
+    void *dcoded = nullptr;  // coded frames (tmd_pipe_run_rans): device copy
+    uint64_t coded_cap = 0;
+    void *rws = nullptr;     // and the entropy decoding's workspace
 };
 
 }  // namespace
@@ -4139,6 +4142,8 @@ void tmd_pipe_free(tmd_pipe_t *Q)
         if (sl.ws) (void)hipFree(sl.ws);
         if (sl.din) (void)hipFree(sl.din);
         if (sl.dout) (void)hipFree(sl.dout);
+        if (sl.dcoded) (void)hipFree(sl.dcoded);
+        if (sl.rws) (void)hipFree(sl.rws);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     if (Q->up) (void)hipStreamDestroy(Q->up);
@@ -4205,32 +4210,31 @@ int tmd_pipe_create(const tmd_frame_shape *capacity, uint32_t depth, const tmd_p
     return TMD_OK;
 }
 
-int tmd_pipe_run(tmd_pipe_t *Q, uint32_t n_frames, const tmd_frame_shape *shapes, const tmd_frame_in *in,
-                 tmd_frame_out *out, uint32_t *flags)
+}  // extern "C"
+
+namespace {
+
+// Checks of the output buffers of frame i before anything is enqueued.
+int pipe_check_out(const tmd_pipe_t *Q, const tmd_frame_shape &S, const tmd_frame_out &O)
 {
-    if (!Q) return TMD_E_ARG;
-    if (n_frames == 0) return TMD_OK;
-    if (!shapes || !in || !out || !flags) return TMD_E_ARG;
-    // host-side checks of every frame before anything is enqueued
-    for (uint32_t i = 0; i < n_frames; i++) {
-        const tmd_frame_shape &S = shapes[i];
-        if (S.n_tracks > Q->cap.n_tracks || S.n_attached > Q->cap.n_attached ||
-            S.n_unattached > Q->cap.n_unattached)
-            return TMD_E_ARG;
-        const uint64_t nn = (uint64_t)S.n_attached + S.n_unattached;
-        if (out[i].capacity < nn) return TMD_E_CAPACITY;
-        for (const ArrSpec &a : kPipeIn) {
-            const void *h = in_ptr(in[i], a.off);
-            if (pipe_count(a.kind, S) && (!h || (uintptr_t)h % a.elem)) return TMD_E_ARG;
-        }
-        const tmd_frame_out &O = out[i];
-        if (!O.row_offset || !O.row_nattached || !aligned(O.row_offset) || !aligned(O.row_nattached))
-            return TMD_E_ARG;
-        if (nn && (!O.time || !O.pad || !O.qtot || !O.qmax || !aligned(O.time) || !aligned(O.pad) ||
-                   !aligned(O.qtot) || !aligned(O.qmax)))
-            return TMD_E_ARG;
-        flags[i] = 0;
-    }
+    if (S.n_tracks > Q->cap.n_tracks || S.n_attached > Q->cap.n_attached || S.n_unattached > Q->cap.n_unattached)
+        return TMD_E_ARG;
+    const uint64_t nn = (uint64_t)S.n_attached + S.n_unattached;
+    if (O.capacity < nn) return TMD_E_CAPACITY;
+    if (!O.row_offset || !O.row_nattached || !aligned(O.row_offset) || !aligned(O.row_nattached)) return TMD_E_ARG;
+    if (nn && (!O.time || !O.pad || !O.qtot || !O.qmax || !aligned(O.time) || !aligned(O.pad) || !aligned(O.qtot) ||
+               !aligned(O.qmax)))
+        return TMD_E_ARG;
+    return TMD_OK;
+}
+
+// The pipeline over n frames: for frame i, `enqueue(i, slot)` puts its
+// upload on Q->up and its decode on the slot's stream (ordered as described
+// at tmd_pipe_run); the download and the slot bookkeeping are shared.
+template <class Enqueue>
+int pipe_execute(tmd_pipe_t *Q, uint32_t n_frames, const tmd_frame_shape *shapes, tmd_frame_out *out,
+                 uint32_t *flags, Enqueue enqueue)
+{
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
     if (cur != Q->device) HIP_TRY(hipSetDevice(Q->device));
@@ -4253,25 +4257,11 @@ int tmd_pipe_run(tmd_pipe_t *Q, uint32_t n_frames, const tmd_frame_shape *shapes
         PipeSlot &sl = Q->slots[i % depth];
         if ((rc = finish(sl)) != TMD_OK) break;
         const tmd_frame_shape &S = shapes[i];
-        // upload (after the slot's previous decode has read its inputs)
+        // upload (after the slot's previous decode has read its inputs), then
+        // decode (after the upload, and after the slot's previous download has
+        // read its outputs)
         if (sl.used && hipStreamWaitEvent(Q->up, sl.dec, 0) != hipSuccess) { rc = TMD_E_HIP; break; }
-        for (const ArrSpec &a : kPipeIn) {
-            const size_t cnt = pipe_count(a.kind, S);
-            if (!cnt) continue;
-            if (hipMemcpyAsync((void *)in_ptr(sl.in, a.off), in_ptr(in[i], a.off), cnt * a.elem,
-                               hipMemcpyHostToDevice, Q->up) != hipSuccess) {
-                rc = TMD_E_HIP;
-                break;
-            }
-        }
-        if (rc != TMD_OK) break;
-        if (hipEventRecord(sl.up, Q->up) != hipSuccess) { rc = TMD_E_HIP; break; }
-        // decode (after the upload, and after the slot's previous download
-        // has read its outputs)
-        if (hipStreamWaitEvent(sl.stream, sl.up, 0) != hipSuccess) { rc = TMD_E_HIP; break; }
-        if (sl.used && hipStreamWaitEvent(sl.stream, sl.down, 0) != hipSuccess) { rc = TMD_E_HIP; break; }
-        tmd_frame_out dev = sl.out;
-        if ((rc = tmd_decode_shapes(sl.plan, &S, &sl.in, &dev, sl.ws, sl.stream)) != TMD_OK) break;
+        if ((rc = enqueue(i, sl)) != TMD_OK) break;
         if (hipEventRecord(sl.dec, sl.stream) != hipSuccess) { rc = TMD_E_HIP; break; }
         if (hipStreamWaitEvent(Q->down, sl.dec, 0) != hipSuccess) { rc = TMD_E_HIP; break; }
         const size_t nn = (size_t)S.n_attached + S.n_unattached;
@@ -4314,6 +4304,90 @@ int tmd_pipe_run(tmd_pipe_t *Q, uint32_t n_frames, const tmd_frame_shape *shapes
     if (any & TMD_F_COUNT) return TMD_E_INPUT;
     if (any) return TMD_E_STREAM;
     return TMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tmd_pipe_run(tmd_pipe_t *Q, uint32_t n_frames, const tmd_frame_shape *shapes, const tmd_frame_in *in,
+                 tmd_frame_out *out, uint32_t *flags)
+{
+    if (!Q) return TMD_E_ARG;
+    if (n_frames == 0) return TMD_OK;
+    if (!shapes || !in || !out || !flags) return TMD_E_ARG;
+    // host-side checks of every frame before anything is enqueued
+    for (uint32_t i = 0; i < n_frames; i++) {
+        const tmd_frame_shape &S = shapes[i];
+        if (const int rc = pipe_check_out(Q, S, out[i])) return rc;
+        for (const ArrSpec &a : kPipeIn) {
+            const void *h = in_ptr(in[i], a.off);
+            if (pipe_count(a.kind, S) && (!h || (uintptr_t)h % a.elem)) return TMD_E_ARG;
+        }
+        flags[i] = 0;
+    }
+    return pipe_execute(Q, n_frames, shapes, out, flags, [&](uint32_t i, PipeSlot &sl) -> int {
+        const tmd_frame_shape &S = shapes[i];
+        for (const ArrSpec &a : kPipeIn) {
+            const size_t cnt = pipe_count(a.kind, S);
+            if (!cnt) continue;
+            if (hipMemcpyAsync((void *)in_ptr(sl.in, a.off), in_ptr(in[i], a.off), cnt * a.elem,
+                               hipMemcpyHostToDevice, Q->up) != hipSuccess)
+                return TMD_E_HIP;
+        }
+        if (hipEventRecord(sl.up, Q->up) != hipSuccess) return TMD_E_HIP;
+        if (hipStreamWaitEvent(sl.stream, sl.up, 0) != hipSuccess) return TMD_E_HIP;
+        if (sl.used && hipStreamWaitEvent(sl.stream, sl.down, 0) != hipSuccess) return TMD_E_HIP;
+        tmd_frame_out dev = sl.out;
+        return tmd_decode_shapes(sl.plan, &S, &sl.in, &dev, sl.ws, sl.stream);
+    });
+}
+
+int tmd_pipe_run_rans(tmd_pipe_t *Q, uint32_t n_frames, const tmd_frame_shape *shapes,
+                      const uint8_t *const *coded, const uint64_t *coded_bytes, tmd_frame_out *out,
+                      uint32_t *flags)
+{
+    if (!Q) return TMD_E_ARG;
+    if (n_frames == 0) return TMD_OK;
+    if (!shapes || !coded || !coded_bytes || !out || !flags) return TMD_E_ARG;
+    size_t enc_ws = 0;
+    uint64_t bound = 0;
+    if (const int rc = tmd_rans_encode_workspace(&Q->cap, &enc_ws, &bound)) return rc;
+    for (uint32_t i = 0; i < n_frames; i++) {
+        if (const int rc = pipe_check_out(Q, shapes[i], out[i])) return rc;
+        if (!coded[i]) return TMD_E_ARG;
+        if (coded_bytes[i] > bound) return TMD_E_CAPACITY;
+        flags[i] = 0;
+    }
+    // the slots' buffers for coded frames, made on first use
+    {
+        int cur = 0;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != Q->device) HIP_TRY(hipSetDevice(Q->device));
+        size_t rws = 0;
+        int rc = tmd_rans_workspace(&Q->cap, 1, &rws);
+        for (PipeSlot &sl : Q->slots) {
+            if (rc != TMD_OK) break;
+            if (!sl.dcoded) {
+                if (hipMalloc(&sl.dcoded, std::max<uint64_t>(bound, 256)) != hipSuccess) { rc = TMD_E_HIP; break; }
+                sl.coded_cap = bound;
+            }
+            if (!sl.rws && hipMalloc(&sl.rws, std::max<size_t>(rws, 256)) != hipSuccess) rc = TMD_E_HIP;
+        }
+        if (cur != Q->device) (void)hipSetDevice(cur);
+        if (rc != TMD_OK) return rc;
+    }
+    return pipe_execute(Q, n_frames, shapes, out, flags, [&](uint32_t i, PipeSlot &sl) -> int {
+        if (coded_bytes[i] &&
+            hipMemcpyAsync(sl.dcoded, coded[i], coded_bytes[i], hipMemcpyHostToDevice, Q->up) != hipSuccess)
+            return TMD_E_HIP;
+        if (hipEventRecord(sl.up, Q->up) != hipSuccess) return TMD_E_HIP;
+        if (hipStreamWaitEvent(sl.stream, sl.up, 0) != hipSuccess) return TMD_E_HIP;
+        if (sl.used && hipStreamWaitEvent(sl.stream, sl.down, 0) != hipSuccess) return TMD_E_HIP;
+        tmd_frame_out dev = sl.out;
+        const uint8_t *dc = (const uint8_t *)sl.dcoded;
+        return tmd_decode_rans(sl.plan, &shapes[i], &dc, &coded_bytes[i], &dev, sl.ws, sl.rws, sl.stream);
+    });
 }
 
 }  // extern "C"

@@ -51,6 +51,7 @@ int main(void)
     EXPECT(tmd_pipe_create(&sh, 0, &p, &pipe) == TMD_E_ARG);
     EXPECT(tmd_pipe_create(&sh, TMD_PIPE_MAX_DEPTH + 1u, &p, &pipe) == TMD_E_ARG);
     EXPECT(tmd_pipe_run(NULL, 1, &sh, &in, &out, &fl) == TMD_E_ARG);
+    EXPECT(tmd_pipe_run_rans(NULL, 1, &sh, NULL, NULL, &out, &fl) == TMD_E_ARG);
     tmd_pipe_free(NULL);
     size_t eb = 0;
     EXPECT(tmd_encode_workspace(10, 100, 50, &eb) == TMD_OK && eb > 0);

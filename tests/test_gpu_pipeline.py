@@ -1,7 +1,8 @@
 """Host-resident frames through the native pipeline (tmd_pipe_*): frames in
 host memory are copied in, decoded and copied back on several streams, and
 every output must be bit-identical to the oracle's decode of the same frame,
-whatever the depth, and with page-locked or pageable host memory."""
+whatever the depth, and with page-locked or pageable host memory; likewise
+for entropy-coded frames (tmd_pipe_run_rans)."""
 import numpy as np
 import pytest
 
@@ -85,5 +86,48 @@ def test_pipeline_rejects_oversized_frames(tmd, frames):
     n = small[1] + small[2]
     with pytest.raises(tmd.TmdError) as e:
         pipe.run([f0], [tmd.alloc_host_out(small, capacity=max(n - 1, 0))])
+    assert e.value.code == tmd.E_CAPACITY
+    pipe.free()
+
+
+@pytest.mark.parametrize("depth", [1, 3])
+def test_pipeline_coded_frames_match_oracle(tmd, frames, expected, depth):
+    """Entropy-coded frames in page-locked host memory through the pipeline
+    (tmd_pipe_run_rans), interleaved with plain runs on the same slots."""
+    pipe = tmd.Pipeline(cap_of(tmd, frames), depth=depth)
+    coded = [tmd.pin_bytes(oracle.rans_encode(f)) for f in frames]
+    shapes = [tmd.frame_shape(f) for f in frames]
+    host = [tmd.to_host(f, pin=True) for f in frames]
+    outs = [tmd.alloc_host_out(s, pin=True) for s in shapes]
+    for run in ("coded", "plain", "coded"):
+        for o in outs:
+            for k in tmd.OUT_FIELDS:
+                o[k].fill_(-1)
+        flags = pipe.run_rans(coded, shapes, outs) if run == "coded" else pipe.run(host, outs)
+        check(tmd, frames, expected, outs, flags)
+    pipe.free()
+
+
+def test_pipeline_coded_malformed_frame_is_flagged(tmd, frames, expected):
+    pipe = tmd.Pipeline(cap_of(tmd, frames), depth=2)
+    shapes = [tmd.frame_shape(f) for f in frames]
+    blobs = [oracle.rans_encode(f) for f in frames]
+    bad = blobs[1].copy()
+    bad[0] = ord("X")  # not a coded frame
+    coded = [tmd.pin_bytes(b) for b in blobs[:1] + [bad] + blobs[2:]]
+    outs = [tmd.alloc_host_out(s, pin=True) for s in shapes]
+    flags = pipe.run_rans(coded, shapes, outs)
+    assert flags[1] & tmd.F_CODED
+    for i, (exp, est) in enumerate(expected):
+        if i == 1:
+            continue
+        got = tmd.to_numpy(outs[i])
+        for k in exp:
+            assert np.array_equal(exp[k], got[k]), (i, k)
+        assert flags[i] == est
+    # a coded frame larger than the slots' buffers
+    with pytest.raises(tmd.TmdError) as e:
+        big = np.zeros(tmd.rans_encode_sizes(cap_of(tmd, frames))[1] + 1, np.uint8)
+        pipe.run_rans([tmd.pin_bytes(big)], shapes[:1], outs[:1])
     assert e.value.code == tmd.E_CAPACITY
     pipe.free()
