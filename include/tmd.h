@@ -14,8 +14,13 @@
  *
  * Memory: every pointer in tmd_frame_in / tmd_frame_out and the workspace is
  * a DEVICE pointer owned by the caller.  The plan owns only its constant
- * tables, frame descriptors and status words.  No call blocks on the GPU
- * except tmd_status, tmd_stage_times and tmd_free.
+ * tables, frame descriptors and status words.  No call waits for the GPU's
+ * work except tmd_status, tmd_stage_times, tmd_free and the pipeline's
+ * tmd_pipe_run / tmd_pipe_run_rans; a decode call whose frame descriptors
+ * differ from the previous call's (and every tmd_decode_rans call) first
+ * waits until the previous upload of the plan's descriptors (a small copy
+ * from page-locked memory, enqueued by the previous call) has been made, as
+ * the staging buffer is reused.
  *
  * Errors: every entry point returns TMD_OK (0) or a negative TMD_E_* code;
  * tmd_strerror() gives a message.  Argument errors are detected on the host
