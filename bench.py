@@ -208,11 +208,18 @@ def roofline(kernel, nbytes, avg_ms, workload):
     from paper_2411_02206_amd import traffic as _traffic
     ach = nbytes / (avg_ms * 1e-3) / 1e9
     summ = _traffic.load_summary(workload)
-    kt = summ["kernels"].get(f"k_{kernel}") if summ else None
-    return {"bound": "hbm", "kernel": f"k_{kernel}", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+    traffic = None
+    if kernel == "rans":  # the entropy decoding's stage: its prep kernel and one decode kernel per element width
+        label = "k_rans_prep + k_rans<1,2,4>"
+        ks = [v for k, v in (summ["kernels"].items() if summ else []) if k.startswith("k_rans")]
+        traffic = sum(v["traffic_bytes"] for v in ks) if ks else None
+    else:
+        label = f"k_{kernel}"
+        kt = summ["kernels"].get(label) if summ else None
+        traffic = kt["traffic_bytes"] if kt else None
+    return {"bound": "hbm", "kernel": label, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-            "traffic": kt["traffic_bytes"] if kt else None, "bytes_per_launch": nbytes,
-            "avg_ms": round(avg_ms, 4)}
+            "traffic": traffic, "bytes_per_launch": nbytes, "avg_ms": round(avg_ms, 4)}
 
 
 def main():

@@ -53,7 +53,9 @@ def copy_program(mib):
 
 
 def kernel_name(raw):
-    return raw.replace("(anonymous namespace)::", "").split("(")[0].split("<")[0].strip()
+    """Short kernel name, template arguments kept (k_rans<2>)."""
+    name = raw.replace("(anonymous namespace)::", "").split("(")[0].strip()
+    return name[5:] if name.startswith("void ") else name
 
 
 def load_counters(d):
