@@ -21,8 +21,13 @@ HBM bytes per launch (attached kernel: 10 B in + 10 B out per attached
 cluster, 15 B per track header; unattached kernel: 10 B in + 10 B out per
 cluster) over its average duration from HIP events recorded around it on the
 decode stream during the timed steps (in graph mode: event-record nodes of
-the replayed graph).  `cpu_baseline` is the plain C oracle over the same
-frames: on one host core, and on all host cores with one frame per thread.
+the replayed graph), also as a fraction of a plain device copy's measured
+read + write bandwidth (`frac_of_copy`).  `cpu_baseline` is the plain C
+oracle over the same frames: on one host core, and on all host cores with one
+frame per thread; `cores_replaced_vs_plain_oracle` is the GPU's rate over the
+one-core oracle's (a ratio against a deliberately plain oracle, not against an
+optimised CPU decoder).  `plan_ms` is the plan's creation time on the host,
+outside the timed steps.
 """
 import argparse
 import json
@@ -202,12 +207,14 @@ def frames_for(workload, args):
     return frames, gen_s, False
 
 
-def roofline(kernel, nbytes, avg_ms, workload):
+def roofline(kernel, nbytes, avg_ms, workload, frames=64):
     if nbytes is None or not avg_ms or avg_ms <= 0:
         return None
     from paper_2411_02206_amd import traffic as _traffic
     ach = nbytes / (avg_ms * 1e-3) / 1e9
     summ = _traffic.load_summary(workload)
+    if summ and workload in ("batched", "coded", "served") and summ.get("frames", 64) != frames:
+        summ = None  # measured on another number of frames
     traffic = None
     if kernel == "rans":  # the entropy decoding's stage: its prep kernel and one decode kernel per element width
         label = "k_rans_prep + k_rans<1,2,4>"
@@ -220,6 +227,36 @@ def roofline(kernel, nbytes, avg_ms, workload):
     return {"bound": "hbm", "kernel": label, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
             "traffic": traffic, "bytes_per_launch": nbytes, "avg_ms": round(avg_ms, 4)}
+
+
+def copy_bandwidth(mib=2048, reps=5):
+    """Read + write GB/s of a plain device-to-device copy (torch copy_ of
+    `mib` MiB, best of `reps`, timed with HIP events): the bandwidth an HBM
+    stream reaches in practice, beside the 8 TB/s peak."""
+    import torch
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n / (best * 1e-3) / 1e9
+
+
+def add_copy_frac(roof, copy_gbs):
+    if roof is not None:
+        roof["copy_GBs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+    return roof
 
 
 def main():
@@ -272,7 +309,9 @@ def run_plain(args):
         single = oracle_single([frame], args.bz, args.cpu_seconds)
 
     dev = tmd.to_device(frame)
+    t_plan = time.perf_counter()
     plan = tmd.Plan([(nT, nA, nU)], bz=args.bz)
+    plan_ms = 1e3 * (time.perf_counter() - t_plan)
     out = tmd.alloc_out((nT, nA, nU))
     ws = plan.alloc_workspace()
     stream = torch.cuda.current_stream()
@@ -317,7 +356,7 @@ def run_plain(args):
     torch.cuda.synchronize()
     lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
     kb = kernel_bytes([(nT, nA, nU)])
-    roof = roofline(dominant, kb.get(dominant), dom_ms, args.workload)
+    roof = add_copy_frac(roofline(dominant, kb.get(dominant), dom_ms, args.workload), copy_bandwidth())
     _, _, all_b = algorithmic_bytes(nT, nA, nU)
     step_gbs = all_b / (ms_per_step * 1e-3) / 1e9
 
@@ -337,6 +376,8 @@ def run_plain(args):
                    "n_attached": nA, "n_unattached": nU, "bz_tesla": args.bz},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cores_replaced_vs_plain_oracle": (value / cpu["value"]) if cpu else None,
+        "plan_ms": round(plan_ms, 3),
         "bitexact_vs_oracle": bitexact,
         "status_flags": status,
         "step_algorithmic_GBs": round(step_gbs, 1),
@@ -405,7 +446,9 @@ def run_batched(args):
               file=sys.stderr, flush=True)
 
     # batched: one plan over all frames, its launch sequence one captured graph
+    t_plan = time.perf_counter()
     bplan = tmd.Plan(shapes, bz=args.bz, flags=tmd.PLAN_GRAPH)
+    plan_ms = 1e3 * (time.perf_counter() - t_plan)
     bws = bplan.alloc_workspace()
     outs_b = [tmd.alloc_out(s) for s in shapes]
 
@@ -519,8 +562,12 @@ def run_batched(args):
     if coded_run:
         # the entropy decoding reads the coded bytes and writes the arrays
         kb["rans"] = coded_info["coded_bytes"] + coded_info["array_bytes"]
-        coded_info["rans_roofline"] = roofline("rans", kb["rans"], coded_info["rans_ms"], args.workload)
-    roof = roofline(dominant, kb.get(dominant), dom_ms, args.workload)
+        coded_info["rans_roofline"] = roofline("rans", kb["rans"], coded_info["rans_ms"], args.workload,
+                                               len(frames))
+    copy_gbs = copy_bandwidth()
+    roof = add_copy_frac(roofline(dominant, kb.get(dominant), dom_ms, args.workload, len(frames)), copy_gbs)
+    if coded_run:
+        add_copy_frac(coded_info["rans_roofline"], copy_gbs)
     _, _, all_b = algorithmic_bytes(nT_all, nA_all, nU_all)
     all_b += (len(frames) - 1) * 5472 * BIN_BYTES
     step_gbs = all_b / t_batch / 1e9
@@ -535,6 +582,8 @@ def run_batched(args):
                    "n_tracks": nT_all, "n_attached": nA_all, "n_unattached": nU_all, "bz_tesla": args.bz},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cores_replaced_vs_plain_oracle": (n_clusters / t_batch / cpu["value"]) if cpu else None,
+        "plan_ms": round(plan_ms, 3),
         "bitexact_vs_oracle": oracle_ok,
         "bitexact_batched_vs_plain": same_plain,
         "status_flags": status,

@@ -130,7 +130,9 @@ def main():
         w = wr.get(k, {}).get("WRITE_SIZE", 0.0)
         kernels[k] = {"fetch_kib": round(f, 1), "write_kib": round(w, 1), "dispatches": nd[k],
                       "traffic_bytes": round(f * 1024.0 * f_fetch + w * 1024.0 * f_write)}
-    summary = {"workload": args.workload, "source_sha256": source_hash(), "copy_mib": COPY_MIB,
+    ba = args.bench_args.split()
+    frames = int(ba[ba.index("--frames") + 1]) if "--frames" in ba else 64
+    summary = {"workload": args.workload, "frames": frames, "source_sha256": source_hash(), "copy_mib": COPY_MIB,
                "factor_fetch": round(f_fetch, 4), "factor_write": round(f_write, 4), "kernels": kernels}
     lines = [f"# HBM traffic per launch, workload `{args.workload}`", "",
              "Made by `python -m paper_2411_02206_amd.traffic --workload "
