@@ -1,6 +1,7 @@
 """Full-size workloads against the oracle, every cluster of every frame:
   - the batched workload: 64 frames of log-uniform 10..200 collisions (about
-    1.1e9 clusters) through one graph plan, as bench.py times it;
+    1.1e9 clusters) through one graph plan, as bench.py times it, plain and
+    entropy-coded;
   - the stress workload (about 1e6 tracks and 1.25e8 clusters: loopers,
     sector crossings, rows skewed exponentially) through a plain plan, a
     graph plan and the serving loop (mixed with batched frames).
@@ -69,6 +70,45 @@ def test_batched_workload_full_size_graph(big):
         outs[i] = None
         exp[i] = None
     assert not any(flags), "the batched workload's streams are valid: no flag may be set"
+    plan.free()
+
+
+def test_coded_batched_workload_full_size(big):
+    """The batched frames entropy-coded on the GPU (tmd_encode_rans), as
+    bench.py's coded workload: the coder writes the oracle coder's bytes
+    (checked on the smallest and the largest frame), and one tmd_decode_rans
+    call on the graph plan decodes every frame as the oracle does."""
+    import torch
+    import paper_2411_02206_amd as tmd
+    frames = big["batched"]
+    shapes = [tmd.frame_shape(f) for f in frames]
+    ws_bytes = max(tmd.rans_encode_sizes(s)[0] for s in shapes)
+    enc_ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    coded = []
+    for f in frames:
+        dev = tmd.to_device(f)
+        coded.append(tmd.encode_rans(dev, workspace=enc_ws).clone())
+        del dev
+    del enc_ws
+    sizes = [s[1] + s[2] for s in shapes]
+    for i in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        assert np.array_equal(coded[i].cpu().numpy(), oracle.rans_encode(frames[i])), f"coded bytes of frame {i}"
+    outs = [tmd.alloc_out(s) for s in shapes]
+    plan = tmd.Plan(shapes, flags=tmd.PLAN_GRAPH)
+    ws = plan.alloc_workspace()
+    rws = torch.empty(plan.rans_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    for rep in range(2):
+        for o in outs:
+            o["time"].fill_(-1)
+        plan.decode_rans(coded, outs, ws, rws)
+        torch.cuda.synchronize()
+    flags = [plan.status(i) for i in range(len(frames))]
+    del coded, ws, rws
+    exp = oracle_many(frames)
+    for i, (e, est) in enumerate(exp):
+        check(tmd, e, est, outs[i], flags[i], f"coded frame {i}")
+        outs[i] = None
+        exp[i] = None
     plan.free()
 
 
