@@ -2325,6 +2325,9 @@ __device__ __forceinline__ void rans_chunk(const RansChunk<W> &C, const uint32_t
     constexpr uint32_t B = rans_blk(W), RING = rans_ring(W), AHEAD = 2 * kRansLanes * B;
     static_assert(B * W == 4 || B * W == 8, "4 or 8 bytes per lane and block");
     const uint32_t lane = C.lane, len = C.len, steps = C.steps;
+    // the plane of chain k (chain k is plane k when every plane is decoded:
+    // then the tables' places and the bytes' shifts are constants)
+    auto plane = [&](int k) -> uint32_t { return K == W ? (uint32_t)k : pl[k]; };
     // the chains' data: states, word streams
     uint32_t x[K ? K : 1], nwords[K ? K : 1], rd[K ? K : 1], wr[K ? K : 1];
     const GLB uint32_t *wsrc[K ? K : 1];
@@ -2332,7 +2335,7 @@ __device__ __forceinline__ void rans_chunk(const RansChunk<W> &C, const uint32_t
     const uint32_t *fc[K ? K : 1];
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        const uint64_t pos = readlane64(C.pinfo[2 * pl[k]]), data0 = readlane64(C.pinfo[2 * pl[k] + 1]);
+        const uint64_t pos = readlane64(C.pinfo[2 * plane(k)]), data0 = readlane64(C.pinfo[2 * plane(k) + 1]);
         const uint32_t o0 = readlane(rans_rd32(C.src, pos + 512 + 4ull * C.ch), 0);
         const uint32_t o1 = readlane(rans_rd32(C.src, pos + 512 + 4ull * C.ch + 4), 0);
         wsrc[k] = (const GLB uint32_t *)(C.src + data0 + o0);
@@ -2340,8 +2343,8 @@ __device__ __forceinline__ void rans_chunk(const RansChunk<W> &C, const uint32_t
         wsrc[k] += kRansLanes;
         nwords[k] = (o1 - o0 - 4 * kRansLanes) / 2;
         rd[k] = 0;
-        sym[k] = C.sym + 4096 * pl[k];
-        fc[k] = C.fc + 256 * pl[k];
+        sym[k] = C.sym + 4096 * plane(k);
+        fc[k] = C.fc + 256 * plane(k);
     }
     // the first AHEAD words of each stream (a chain's loads in flight together)
 #pragma unroll
@@ -2379,26 +2382,37 @@ __device__ __forceinline__ void rans_chunk(const RansChunk<W> &C, const uint32_t
         uint32_t v = C.cval;
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(msk[k] >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)msk[k], 0u));
-            const uint32_t w = ((const uint16_t *)(C.ring + k * (RING / 2)))[(rd[k] + r) & (RING - 1)];
-            xn[k] = (xn[k] << (need[k] << 4)) | (w & (0u - need[k]));
+            // rd + (lanes below this one that take a word), by mbcnt's addend
+            const uint32_t wi = __builtin_amdgcn_mbcnt_hi((uint32_t)(msk[k] >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)msk[k], rd[k]));
+            const uint32_t w = ((const uint16_t *)(C.ring + k * (RING / 2)))[wi & (RING - 1)];
+            // x = need ? x << 16 | w : x, as one select on the ballot's mask
+            // (written out, so that the ring read is not moved under a branch)
+            const uint32_t xs = (xn[k] << 16) | w;
+            uint32_t xr;
+            asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(xr) : "v"(xn[k]), "v"(xs), "s"(msk[k]));
+            xn[k] = xr;
             rd[k] += (uint32_t)__popcll(msk[k]);
             if (live) x[k] = xn[k];
-            v |= sy[k] << (8 * pl[k]);
+            v |= sy[k] << (8 * plane(k));
         }
         return v;
     };
     uint32_t over = 0;  // a stream read beyond its words
     for (uint32_t j0 = 0; j0 < steps; j0 += B) {
-        // read ahead what the next block may read: up to 3 units per chain
-        // (the units not needed are not loaded, their registers hold 0)
-        uint32_t pf[K ? K : 1][3], m[K ? K : 1];
+        // read ahead what the next block may read: up to P units per chain
+        // (the units not needed are not loaded, their registers hold 0).  P
+        // units always reach rd + AHEAD: the previous block's read-ahead
+        // reached its own rd + AHEAD, and a block reads fewer than kRansLanes B
+        // words, P units' worth.
+        constexpr int P = (int)(kRansLanes * B / kRansUnit);
+        static_assert(P >= 1 && P * kRansUnit == kRansLanes * B, "a block's reads are whole units");
+        uint32_t pf[K ? K : 1][P], m[K ? K : 1];
 #pragma unroll
         for (int k = 0; k < K; k++) {
             m[k] = 0;
 #pragma unroll
-            for (int u = 0; u < 3; u++) {
+            for (int u = 0; u < P; u++) {
                 const uint32_t u0 = wr[k] + kRansUnit * u;
                 const uint32_t wi = u0 + 2 * lane;
                 const bool take = u0 < rd[k] + AHEAD && u0 < nwords[k];
@@ -2423,7 +2437,7 @@ __device__ __forceinline__ void rans_chunk(const RansChunk<W> &C, const uint32_t
 #pragma unroll
         for (int k = 0; k < K; k++) {
 #pragma unroll
-            for (int u = 0; u < 3; u++) {
+            for (int u = 0; u < P; u++) {
                 uint32_t *d = (uint32_t)u < m[k] ? &C.ring[k * (RING / 2) + ((wr[k] + kRansUnit * u + 2 * lane) % RING) / 2]
                                                  : &C.trash[lane];
                 *d = pf[k][u];
