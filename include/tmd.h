@@ -393,12 +393,16 @@ int tmd_encode(tmd_plan_t *plan, const tmd_enc_in *in, tmd_enc_out *out, void *w
  * the plane's data), then the data.
  *
  * tmd_rans_workspace: bytes of the area where tmd_decode_rans puts the
- * decoded arrays of n_frames frames of these shapes.
+ * decoded arrays of n_frames frames of these shapes (all but the unattached
+ * ones) and its bookkeeping.
  * tmd_decode_rans: decode the coded frames (coded[i], coded_bytes[i]: DEVICE
- * buffers) into rans_workspace, then decode them as tmd_decode_shapes does
- * (shapes[i] no larger than the plan's; workspace as for tmd_decode), all on
- * `stream`.  A frame whose coded data is malformed gets TMD_F_CODED in its
- * status (tmd_status).
+ * buffers) as tmd_decode_shapes would decode the uncoded ones (shapes[i] no
+ * larger than the plan's; workspace as for tmd_decode), all on `stream`: the
+ * track and attached-cluster arrays are entropy-decoded into rans_workspace
+ * and then decoded; the unattached clusters' arrays are entropy-decoded
+ * straight into the output (their running sums and slots) once the output
+ * offsets are known.  A frame whose coded data is malformed gets TMD_F_CODED
+ * in its status (tmd_status); its malformed chunks count as zeros.
  * Errors: TMD_E_ARG (null or misaligned pointer, a shape above the plan's),
  * and those of tmd_decode_shapes.
  */
@@ -468,8 +472,10 @@ int tmd_set_schedule(tmd_plan_t *plan, uint32_t tracks_per_wave, uint32_t persis
  * TMD_PLAN_GRAPH mode the plan captures a second graph (once per stage mask)
  * with an event-record node before and after each selected stage, and every
  * replay points those nodes at fresh events, so each call is timed on its
- * own.  The last stage ("rans") is the entropy decoding of tmd_decode_rans,
- * all its frames between one pair of events.  tmd_stage_times waits for the
+ * own.  The last two stages are tmd_decode_rans's entropy decoding, all its
+ * frames between one pair of events each: "rans" before the track-model
+ * decode, "rans_un" (the unattached arrays, decoded into the output) after
+ * it.  tmd_stage_times waits for the
  * recorded calls, writes the summed milliseconds of each stage to
  * ms[0 .. n-1] (0 for unselected stages), the number of recorded calls to
  * *calls, and clears the record.  Returns the number of stages.

@@ -42,6 +42,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <type_traits>
@@ -175,7 +176,8 @@ constexpr int kHRow = NBIN + kNKey;  // per-tile histogram row: bins, then keys
     uint64_t cap; /* entries of the output cluster arrays; every store is checked */          \
     uint32_t nT, nA, nU, ntile, tile0;                                                        \
     uint32_t awaves; /* waves of the attached decode */                                       \
-    uint32_t pad_[2];
+    uint32_t un_fused; /* the unattached clusters are decoded with their entropy decoding */  \
+    uint32_t pad_;
 
 struct FrameDesc {
     TMD_FRAME_FIELDS(GLB)
@@ -812,6 +814,7 @@ __device__ __forceinline__ void store_wide(GLB T *p, const V &v)
 __global__ __launch_bounds__(kWave) void k_unattached(const FrameDesc *__restrict__ fd)
 {
     const FrameDesc F = fd[blockIdx.y];
+    if (F.un_fused) return;  // (done by the entropy decoding, k_rans<W, true>)
     const uint32_t k = blockIdx.x;
     const uint32_t cnt = F.ueff[k];
     if (cnt == 0) return;
@@ -2180,6 +2183,12 @@ __global__ __launch_bounds__(256) void k_enc_un_delta(const EncDesc E, const uns
 //     with one-dword-per-lane loads into an LDS ring per plane; the decoded
 //     elements of a block are staged in LDS and written out whole.  Global
 //     memory is touched only between blocks.
+//   k_rans<W, true>: the same decoding for the four arrays of unattached
+//     clusters, run after the output offsets are known (in place of
+//     k_unattached): each element goes straight to its output slot, time and
+//     pad differences as running sums within their bin.  A chunk's sums start
+//     at 0, so k_rans_unfix then adds to a chunk's leading elements the sum
+//     of their bin's elements in the chunks before (from a record per chunk).
 // ---------------------------------------------------------------------------
 constexpr int kRansPlanes = 39, kRansArrays = 19, kRansLanes = 64, kRansPerLane = 512;
 constexpr uint32_t kRansChunk = kRansLanes * kRansPerLane;
@@ -2206,7 +2215,11 @@ __device__ __constant__ const uint8_t kRansWidth[kRansArrays] = {1, 1, 1, 2, 4, 
 __device__ __constant__ const uint8_t kRansPlane0[kRansArrays] = {0,  1,  2,  3,  5,  9,  11, 13, 15, 16,
                                                                   17, 19, 21, 23, 25, 29, 33, 35, 37};
 
-struct RansDesc {  // (the same layout on the host and the device: 600 bytes)
+// The arrays of unattached clusters (time and pad differences, charges),
+// decoded straight into the output by k_rans<W, true>
+constexpr uint32_t kRansUn0 = 15;
+
+struct RansDesc {  // (the same layout on the host and the device: 920 bytes)
     const GLB uint8_t *src;       // the coded frame (16-byte aligned)
     uint64_t size;
     GLB uint8_t *dst[kRansArrays];
@@ -2214,13 +2227,17 @@ struct RansDesc {  // (the same layout on the host and the device: 600 bytes)
     GLB uint8_t *tabs;            // per plane kRansTab bytes: sym[4096], then f | c << 16 for each symbol
     GLB uint64_t *pinfo;          // per plane: its position, the start of its chunks' data (0: unusable)
     GLB uint32_t *err;            // TMD_F_CODED if the data is not a well-formed coded frame
+    GLB uint4 *urec;              // [2][chunks of nU]: time's, then pad's chunk records (k_rans_unfix)
     uint32_t nT, nA, nU;
-    uint32_t nw[3];               // arrays of width 1, 2 and 4, in order
-    uint32_t warr[3][12];
-    uint32_t witem0[3][13];       // first work item of each, then the total
+    // work lists: [0] the arrays decoded before the track-model decode,
+    // [1] the unattached ones; per width class (1, 2, 4 bytes) the arrays
+    uint32_t nw[2][3];
+    uint32_t warr[2][3][12];
+    uint32_t witem0[2][3][13];    // first work item of each, then the total
+    uint32_t pad_;
 };
 
-static_assert(sizeof(RansDesc) == 600, "descriptor layout");
+static_assert(sizeof(RansDesc) == 920, "descriptor layout");
 
 __global__ void k_fill32(uint32_t *p, uint32_t n, uint32_t v)
 {
@@ -2308,7 +2325,29 @@ struct RansChunk {
     uint32_t *trash;            // LDS: this wave's trash slots
     uint32_t lane;
     GLB uint32_t *err;
+    GLB uint32_t *err2;         // a second word to flag (the frame's status), or null
 };
+
+// The elements of a block (staged in LDS, step-major) written to the chunk's
+// place in its array: B consecutive elements per lane.
+template <int W>
+__device__ __forceinline__ void rans_store_block(const RansChunk<W> &C, uint32_t j0)
+{
+    using Elem = typename RansChunk<W>::Elem;
+    using Out = typename std::conditional<rans_blk(W) * W == 4, uint32_t, uint2>::type;  // a lane's elements of a block
+    constexpr uint32_t B = rans_blk(W);
+    static_assert(B * W == 4 || B * W == 8, "4 or 8 bytes per lane and block");
+    const uint32_t len = C.len, lane = C.lane;
+    const uint32_t nb = len - kRansLanes * j0 < kRansLanes * B ? len - kRansLanes * j0 : kRansLanes * B;
+    const Elem *sv = C.stage + B * lane;
+    GLB Elem *dv = C.dst + kRansLanes * j0 + B * lane;
+    if (B * lane + B <= nb) {
+        *(GLB Out *)dv = *(const Out *)sv;
+    } else {
+        for (uint32_t e = 0; e < B; e++)
+            if (B * lane + e < nb) dv[e] = sv[e];
+    }
+}
 
 // Decode one chunk whose planes pl[0 .. K-1] need decoding (K independent
 // state chains per lane).  One step takes one symbol of each chain per lane,
@@ -2316,14 +2355,14 @@ struct RansChunk {
 // then their ring reads).  A lane whose state fell below 2^16 takes the word
 // at rd + (the number of such lanes below it); every lane reads the ring and
 // masks the word out where it is not needed (no branch, so the chains' reads
-// can overlap).  Global memory is touched only between blocks.
-template <int W, int K>
-__device__ __forceinline__ void rans_chunk(const RansChunk<W> &C, const uint32_t *pl)
+// can overlap).  Global memory is touched only between blocks.  At the end of
+// each block, emit(j0) takes the block's elements from the stage (element
+// 64 (j0 + s) + l of the chunk at stage[64 s + l]).
+template <int W, int K, class Emit>
+__device__ __forceinline__ void rans_chunk(const RansChunk<W> &C, const uint32_t *pl, Emit &&emit)
 {
     using Elem = typename RansChunk<W>::Elem;
-    using Out = typename std::conditional<rans_blk(W) * W == 4, uint32_t, uint2>::type;  // a lane's elements of a block
     constexpr uint32_t B = rans_blk(W), RING = rans_ring(W), AHEAD = 2 * kRansLanes * B;
-    static_assert(B * W == 4 || B * W == 8, "4 or 8 bytes per lane and block");
     const uint32_t lane = C.lane, len = C.len, steps = C.steps;
     // the plane of chain k (chain k is plane k when every plane is decoded:
     // then the tables' places and the bytes' shifts are constants)
@@ -2449,15 +2488,7 @@ __device__ __forceinline__ void rans_chunk(const RansChunk<W> &C, const uint32_t
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const uint32_t nb = len - kRansLanes * j0 < kRansLanes * B ? len - kRansLanes * j0 : kRansLanes * B;
-        const Elem *sv = C.stage + B * lane;
-        GLB Elem *dv = C.dst + kRansLanes * j0 + B * lane;
-        if (B * lane + B <= nb) {
-            *(GLB Out *)dv = *(const Out *)sv;
-        } else {
-            for (uint32_t e = 0; e < B; e++)
-                if (B * lane + e < nb) dv[e] = sv[e];
-        }
+        emit(j0);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -2466,17 +2497,55 @@ __device__ __forceinline__ void rans_chunk(const RansChunk<W> &C, const uint32_t
     bool fine = !over;
 #pragma unroll
     for (int k = 0; k < K; k++) fine = fine && x[k] == kRansLow && nwords[k] - rd[k] < 8;
-    if (__ballot(!fine) && lane == 0) atomicOr(C.err, kRansBad);
+    if (__ballot(!fine) && lane == 0) {
+        atomicOr(C.err, kRansBad);
+        if (C.err2) atomicOr(C.err2, kRansBad);
+    }
 }
 
-// (witem: for each width class, the first work item of each frame, then the
-// total; a work item is kRansWaves consecutive chunks of one array of the
-// class)
-template <int W>
+// The fused placement of the unattached arrays (k_rans<W, true>): a wave's
+// chunk holds elements [c0, c0 + len) of one array; element g belongs to the
+// last bin b with uin[b] <= g and goes to output slot g + (roff[b] + rna[b] -
+// uin[b]) if g < uin[b] + room[b] (room: what k_unattached would store of the
+// bin).  Time and pad differences become running sums within the bin; the
+// sums of the chunk's leading elements (those of a bin that began in an
+// earlier chunk) miss that bin's earlier elements, which k_rans_unfix adds.
+// A window of 64 bins' start, shift and end (lane j: bin wb + j) is kept in
+// registers; the bin of the current element only moves forward.
+struct RansUnBins {
+    const GLB uint32_t *uin, *ueff, *roff, *rna;
+    uint64_t cap;
+    uint32_t wb;              // first bin of the window
+    uint32_t wst, wsh, wlim;  // (lane j) bin wb + j: start, slot shift, end of its stored elements
+
+    __device__ __forceinline__ void load(uint32_t b0, uint32_t lane)
+    {
+        wb = b0;
+        const uint32_t b = b0 + lane;
+        uint32_t st = 0xFFFFFFFFu, sh = 0, lim = 0;
+        if (b < (uint32_t)NBIN) {
+            const uint32_t u = uin[b], e = ueff[b], d = roff[b] + rna[b];
+            const uint32_t room = d < cap ? (uint32_t)min((uint64_t)e, cap - d) : 0u;
+            st = u;
+            sh = d - u;
+            lim = u + room;
+        }
+        wst = st;
+        wsh = sh;
+        wlim = lim;
+    }
+};
+
+// (witem: for each list and width class, the first work item of each frame,
+// then the total; a work item is kRansWaves consecutive chunks of one array
+// of the class.  UN: the list of unattached arrays, placed into the frame's
+// output, fd being the track-model decode's frame descriptors.)
+template <int W, bool UN>
 __global__ __launch_bounds__(kRansLanes * kRansWaves) void k_rans(const RansDesc *descs, const uint32_t *witem,
-                                                                  uint32_t nf)
+                                                                  uint32_t nf, const FrameDesc *fd)
 {
     constexpr int WI = W == 1 ? 0 : (W == 2 ? 1 : 2);
+    constexpr int PH = UN ? 1 : 0;
     constexpr uint32_t B = rans_blk(W), RING = rans_ring(W);
     using Elem = typename RansChunk<W>::Elem;
     __shared__ __align__(16) uint8_t sym[W][4096];  // the symbol of every slot
@@ -2486,7 +2555,7 @@ __global__ __launch_bounds__(kRansLanes * kRansWaves) void k_rans(const RansDesc
     __shared__ uint32_t trash[kRansWaves][kRansLanes];  // where read-ahead units not loaded are written
     const uint32_t wave = threadIdx.x / kRansLanes, lane = lane_id();
     // the frame of this work item: the last one whose first item is at or below it
-    const GLB uint32_t *fi = (const GLB uint32_t *)witem + WI * (nf + 1);
+    const GLB uint32_t *fi = (const GLB uint32_t *)witem + (3 * PH + WI) * (nf + 1);
     uint32_t flo = 0, fhi = nf - 1;
     while (flo < fhi) {
         const uint32_t mid = (flo + fhi + 1) >> 1;
@@ -2497,13 +2566,13 @@ __global__ __launch_bounds__(kRansLanes * kRansWaves) void k_rans(const RansDesc
     const uint32_t item = blockIdx.x - readlane(fi[flo], 0);
     // the array and chunks of this item (the descriptor's fields read once,
     // into wave-uniform registers)
-    uint32_t a = readlane(R->warr[WI][0], 0), i0 = 0;
-    const uint32_t nw = readlane(R->nw[WI], 0);
+    uint32_t a = readlane(R->warr[PH][WI][0], 0), i0 = 0;
+    const uint32_t nw = readlane(R->nw[PH][WI], 0);
 #pragma unroll
     for (int k = 1; k < 12; k++)
-        if ((uint32_t)k < nw && readlane(R->witem0[WI][k], 0) <= item) {
-            a = readlane(R->warr[WI][k], 0);
-            i0 = readlane(R->witem0[WI][k], 0);
+        if ((uint32_t)k < nw && readlane(R->witem0[PH][WI][k], 0) <= item) {
+            a = readlane(R->warr[PH][WI][k], 0);
+            i0 = readlane(R->witem0[PH][WI][k], 0);
         }
     const GLB uint8_t *const src = (const GLB uint8_t *)readlane64((uint64_t)R->src);
     const uint64_t size = readlane64(R->size);
@@ -2533,9 +2602,11 @@ __global__ __launch_bounds__(kRansLanes * kRansWaves) void k_rans(const RansDesc
     const uint32_t c0 = ch * kRansChunk;
     const uint32_t len = n - c0 < kRansChunk ? n - c0 : kRansChunk;
     const uint32_t steps = (len + kRansLanes - 1) / kRansLanes;
-    GLB Elem *dst = (GLB Elem *)readlane64((uint64_t)R->dst[a]) + c0;
+    GLB Elem *dst = UN ? nullptr : (GLB Elem *)readlane64((uint64_t)R->dst[a]) + c0;  // (UN: the output instead)
     uint32_t(*rg)[RING / 2] = ring[wave];
     Elem *stg = stage[wave];
+    GLB uint32_t *status = nullptr;
+    if constexpr (UN) status = (GLB uint32_t *)readlane64((uint64_t)((const GLB FrameDesc *)fd)[flo].status);
     // planes of one symbol: its byte, nothing to decode
     uint32_t cst = 0, csym[W];
 #pragma unroll
@@ -2564,34 +2635,157 @@ __global__ __launch_bounds__(kRansLanes * kRansWaves) void k_rans(const RansDesc
     // here, not inside the loop)
 #pragma unroll
     for (int q = 0; q < W; q++) bad |= __ballot(x[q] < kRansLow) != 0;
-    if (bad) {  // not a well-formed chunk: flagged, its elements 0
-        if (lane == 0) atomicOr(R->err, kRansBad);
+    if (bad && lane == 0) {  // not a well-formed chunk: flagged, its elements 0
+        atomicOr(R->err, kRansBad);
+        if (UN) atomicOr(status, kRansBad);
+    }
+    if (!UN && bad) {
         for (uint32_t e = lane; e < len; e += kRansLanes) dst[e] = 0;
         return;
     }
     // the planes that need decoding run as K chains; the others only add
-    // their byte to every element
+    // their byte to every element (a malformed chunk: no chains, elements 0)
     uint32_t cval = 0, K = 0, pl[W];
 #pragma unroll
     for (int q = 0; q < W; q++) {
         pl[q] = 0;
-        if ((cst >> q) & 1u) cval |= csym[q] << (8 * q);
+        if (((cst >> q) & 1u) && !bad) cval |= csym[q] << (8 * q);
     }
 #pragma unroll
     for (int q = 0; q < W; q++)
-        if (!((cst >> q) & 1u)) {
+        if (!((cst >> q) & 1u) && !bad) {
 #pragma unroll
             for (int k = 0; k < W; k++) pl[k] = (uint32_t)k == K ? (uint32_t)q : pl[k];
             K++;
         }
     RansChunk<W> C{src, R->pinfo + 2 * p0, ch, dst, len, steps, cval, &sym[0][0], &fc[0][0], &rg[0][0], stg,
-                   trash[wave], lane, R->err};
-    switch (K) {
-    case 0: rans_chunk<W, 0>(C, pl); break;
-    case 1: rans_chunk<W, 1>(C, pl); break;
-    case 2: if constexpr (W >= 2) rans_chunk<W, 2>(C, pl); break;
-    case 3: if constexpr (W >= 3) rans_chunk<W, 3>(C, pl); break;
-    default: if constexpr (W >= 4) rans_chunk<W, 4>(C, pl); break;
+                   trash[wave], lane, R->err, status};
+    auto run = [&](auto &&emit) {
+        switch (K) {
+        case 0: rans_chunk<W, 0>(C, pl, emit); break;
+        case 1: rans_chunk<W, 1>(C, pl, emit); break;
+        case 2: if constexpr (W >= 2) rans_chunk<W, 2>(C, pl, emit); break;
+        case 3: if constexpr (W >= 3) rans_chunk<W, 3>(C, pl, emit); break;
+        default: if constexpr (W >= 4) rans_chunk<W, 4>(C, pl, emit); break;
+        }
+    };
+    if constexpr (!UN) {
+        run([&](uint32_t j0) { rans_store_block<W>(C, j0); });
+    } else {
+        // the output array, and whether its elements are running sums
+        const GLB FrameDesc *F = (const GLB FrameDesc *)fd + flo;
+        const uint32_t q = a - kRansUn0;  // 0 time, 1 pad, 2 qtot, 3 qmax
+        const bool scan = q < 2;
+        GLB uint8_t *out;
+        if (W == 4) out = (GLB uint8_t *)readlane64((uint64_t)F->otime);
+        else out = (GLB uint8_t *)readlane64(q == 1 ? (uint64_t)F->opad : (q == 2 ? (uint64_t)F->oqtot : (uint64_t)F->oqmax));
+        RansUnBins U;
+        U.uin = (const GLB uint32_t *)readlane64((uint64_t)F->uin);
+        U.ueff = (const GLB uint32_t *)readlane64((uint64_t)F->ueff);
+        U.roff = (const GLB uint32_t *)readlane64((uint64_t)F->roff);
+        U.rna = (const GLB uint32_t *)readlane64((uint64_t)F->rna);
+        U.cap = readlane64(F->cap);
+        // the bin of element c0: the last bin whose start is at or below it
+        // (starts are non-decreasing, uin[0] = 0): 64 samples 86 bins apart,
+        // then the 85 bins after the last sample at or below c0
+        const uint32_t lo = 86u * ((uint32_t)__popcll(__ballot(U.uin[86u * lane] <= c0)) - 1u);
+        const uint32_t bA = lo + 1 + lane, bB = lo + 65 + lane;
+        const bool inA = bA < (uint32_t)NBIN && bA <= lo + 85 && U.uin[min(bA, (uint32_t)NBIN - 1)] <= c0;
+        const bool inB = bB < (uint32_t)NBIN && bB <= lo + 85 && U.uin[min(bB, (uint32_t)NBIN - 1)] <= c0;
+        uint32_t cb = lo + (uint32_t)__popcll(__ballot(inA)) + (uint32_t)__popcll(__ballot(inB));
+        U.load(cb, lane);
+        // the current bin cb (of the last element so far): its slot shift,
+        // the end of its stored elements, the chunk's sum before its start
+        uint32_t sh = readlane(U.wsh, 0), lim = readlane(U.wlim, 0), base = 0;
+        const uint32_t sh0 = sh, lim0 = lim;
+        uint32_t nstart = readlane(U.wst, 1);          // start of bin cb + 1
+        bool head = readlane(U.wst, 0) == c0;           // a bin begins in this chunk
+        uint32_t lead = head ? 0u : len;                 // elements before the first such bin
+        uint32_t carry = 0;                              // running sum of the chunk's elements
+        run([&](uint32_t j0) {
+#pragma unroll
+            for (uint32_t s = 0; s < B; s++) {
+                const uint32_t t0 = kRansLanes * (j0 + s);
+                if (t0 >= len) break;
+                const uint32_t t = t0 + lane;
+                const bool live = t < len;
+                const uint32_t v = live ? (uint32_t)stg[kRansLanes * s + lane] : 0u;
+                uint32_t S = v;
+                if (scan) {
+                    S = carry + wave_incl_add(v);
+                    carry = readlane(S, kRansLanes - 1);
+                }
+                const uint32_t gs = c0 + t0, g = gs + lane;
+                const uint32_t gl = c0 + (t0 + kRansLanes - 1 < len ? t0 + kRansLanes - 1 : len - 1);
+                // the lane's bin: the current one, or one that begins in this step
+                uint32_t lsh = sh, llim = lim, lbase = base;
+                while (nstart <= gl) {  // bin cb + 1 begins at lane nstart - gs of this step
+                    const uint32_t h = nstart - gs;
+                    base = readlane(S, (int)h) - readlane(v, (int)h);
+                    cb++;
+                    if (!head) {
+                        head = true;
+                        lead = nstart - c0;
+                    }
+                    if (cb + 1 - U.wb >= (uint32_t)kRansLanes) U.load(cb, lane);
+                    sh = readlane(U.wsh, (int)(cb - U.wb));
+                    lim = readlane(U.wlim, (int)(cb - U.wb));
+                    const bool sel = g >= nstart;
+                    lsh = sel ? sh : lsh;
+                    llim = sel ? lim : llim;
+                    lbase = sel ? base : lbase;
+                    nstart = readlane(U.wst, (int)(cb + 1 - U.wb));
+                }
+                const uint32_t val = scan ? S - lbase : v;
+                if (live && g < llim) {
+                    if (W == 4) ((GLB uint32_t *)out)[g + lsh] = val;
+                    else ((GLB uint16_t *)out)[g + lsh] = (uint16_t)val;
+                }
+            }
+        });
+        if (scan && lane == 0) {
+            // the chunk's record: the sum of its last bin's elements, whether
+            // a bin begins in it, how many leading elements were stored, and
+            // the slot of its first element
+            const uint32_t ls = lim0 > c0 ? min(lim0 - c0, lead) : 0u;
+            GLB uint4 *rec = (GLB uint4 *)readlane64((uint64_t)R->urec) + (uint64_t)q * nch + ch;
+            *rec = make_uint4(carry - base, head ? 1u : 0u, ls, c0 + sh0);
+        }
+    }
+}
+
+// The running sums of the chunks' leading elements: one wave per (chunk,
+// array: time or pad, frame).  The sum of their bin's elements in the chunks
+// before is the sum of those chunks' last-bin sums, back to the chunk in
+// which the bin began.
+__global__ __launch_bounds__(kRansLanes) void k_rans_unfix(const RansDesc *descs, const FrameDesc *fd)
+{
+    const uint32_t ch = blockIdx.x, q = blockIdx.y, lane = lane_id();
+    const GLB RansDesc *R = (const GLB RansDesc *)descs + blockIdx.z;
+    const uint32_t n = R->n[kRansUn0 + q];
+    const uint32_t nch = (n + kRansChunk - 1) / kRansChunk;
+    if (ch == 0 || ch >= nch) return;
+    const GLB uint4 *rec = R->urec + (uint64_t)q * nch;
+    const uint4 me = rec[ch];
+    const uint32_t ls = readlane(me.z, 0), d0 = readlane(me.w, 0);
+    if (ls == 0) return;
+    uint32_t carry = 0;
+    for (int32_t c = (int32_t)ch - 1; c >= 0; c -= kRansLanes) {
+        const int32_t ci = c - (int32_t)lane;
+        uint4 r = make_uint4(0u, 1u, 0u, 0u);
+        if (ci >= 0) r = rec[ci];
+        const uint64_t hm = __ballot(r.y != 0);
+        const uint32_t stop = hm ? (uint32_t)__builtin_ctzll(hm) : (uint32_t)kRansLanes;
+        carry += readlane(wave_incl_add(lane <= stop ? r.x : 0u), kRansLanes - 1);
+        if (hm) break;
+    }
+    const GLB FrameDesc *F = (const GLB FrameDesc *)fd + blockIdx.z;
+    if (q == 0) {
+        GLB uint32_t *o = (GLB uint32_t *)readlane64((uint64_t)F->otime) + d0;
+        for (uint32_t i = lane; i < ls; i += kRansLanes) o[i] += carry;
+    } else {
+        GLB uint16_t *o = (GLB uint16_t *)readlane64((uint64_t)F->opad) + d0;
+        for (uint32_t i = lane; i < ls; i += kRansLanes) o[i] = (uint16_t)(o[i] + carry);
     }
 }
 
@@ -2864,10 +3058,12 @@ static __device__ __align__(256) uint8_t scratch[TMD_STATIC_SCRATCH_BYTES];
 // host side
 // ---------------------------------------------------------------------------
 constexpr int kStages = 7;  // the decode's stages
-// (stage kStages, "rans": the entropy decoding of tmd_decode_rans)
-constexpr int kAllStages = kStages + 1;
-const char *kStageNames[kAllStages] = {"tilesum",  "count",      "colscan", "offsets",
-                                       "rank",     "attached",   "unattached", "rans"};
+// (stage kStages, "rans": the entropy decoding of tmd_decode_rans before the
+// track-model decode; kStages + 1, "rans_un": its fused decoding of the
+// unattached clusters after it)
+constexpr int kAllStages = kStages + 2;
+const char *kStageNames[kAllStages] = {"tilesum",  "count",    "colscan",    "offsets", "rank",
+                                       "attached", "unattached", "rans",     "rans_un"};
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -2903,11 +3099,12 @@ struct tmd_plan {
     bool called = false;  // `done` has been recorded at least once
     uint32_t profiling = 0;                            // stage mask
     bool prof_rans = false;                            // events around tmd_decode_rans's entropy decoding
+    bool prof_rans_un = false;                         // and around its fused unattached decode
     void *h_rans = nullptr;                            // pinned staging of its descriptors
     size_t h_rans_bytes = 0;
     hipEvent_t rans_copy = nullptr;                    // their last upload
     bool rans_staged = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> rans_events;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> rans_events, rans_un_events;
     std::vector<std::vector<hipEvent_t>> prof_events;  // per recorded call: 2 per stage (unrecorded: null)
     std::vector<hipEvent_t> event_pool;                // events ready for reuse
     hipGraphExec_t graph = nullptr;   // TMD_PLAN_GRAPH: the captured launch sequence
@@ -3214,10 +3411,11 @@ void tmd_free(tmd_plan_t *P)
     for (auto &v : P->prof_events)
         for (auto e : v)
             if (e) (void)hipEventDestroy(e);
-    for (auto &v : P->rans_events) {
-        (void)hipEventDestroy(v.first);
-        (void)hipEventDestroy(v.second);
-    }
+    for (auto *L : {&P->rans_events, &P->rans_un_events})
+        for (auto &v : *L) {
+            (void)hipEventDestroy(v.first);
+            (void)hipEventDestroy(v.second);
+        }
     for (auto e : P->event_pool) (void)hipEventDestroy(e);
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
     drop_prof_graph(P);
@@ -3343,8 +3541,9 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
 }  // extern "C"
 
 namespace {
+using PostLaunch = std::function<int(hipStream_t)>;
 int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
-                void *workspace, void *stream, const uint32_t *const *pre_status);
+                void *workspace, void *stream, const uint32_t *const *pre_status, const PostLaunch *post = nullptr);
 }  // namespace
 
 extern "C" {
@@ -3360,9 +3559,12 @@ int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_fr
 namespace {
 
 // tmd_decode_shapes, with an optional device word per frame that the frame's
-// status starts from (flags of a step before the decode)
+// status starts from (flags of a step before the decode).  With `post`, the
+// unattached clusters are not decoded here: post enqueues what decodes them
+// (after the launch sequence, before the status words are read back), and
+// the unattached input arrays may be null.
 int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
-                void *workspace, void *stream, const uint32_t *const *pre_status)
+                void *workspace, void *stream, const uint32_t *const *pre_status, const PostLaunch *post)
 {
     if (!P || !shapes || !in || !out || !workspace) return TMD_E_ARG;
     if ((uintptr_t)workspace % 256) return TMD_E_ARG;
@@ -3387,7 +3589,7 @@ int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in
                              !I.cls_qtot || !I.cls_qmax))
             return TMD_E_ARG;
         if (!I.un_count) return TMD_E_ARG;
-        if (S.n_unattached && (!I.un_time_diff || !I.un_pad_diff || !I.un_qtot || !I.un_qmax))
+        if (S.n_unattached && !post && (!I.un_time_diff || !I.un_pad_diff || !I.un_qtot || !I.un_qmax))
             return TMD_E_ARG;
         if (!O.row_offset || !O.row_nattached) return TMD_E_ARG;
         if ((S.n_attached || S.n_unattached) && (!O.time || !O.pad || !O.qtot || !O.qmax)) return TMD_E_ARG;
@@ -3426,6 +3628,7 @@ int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in
         D.ntile = (S.n_tracks + kTile - 1) / kTile;  // <= the planned L.ntile
         D.tile0 = L.tile0;
         D.awaves = attached_waves(S.n_tracks, P->n_frames == 1, P->simds, P->tracks_per_wave);
+        D.un_fused = post ? 1u : 0u;
     }
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
@@ -3490,6 +3693,7 @@ int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in
             }
             if (P->profiling) P->prof_events.push_back(ev);
         }
+        if (post && (rc = (*post)(s)) != TMD_OK) break;
         if (hipMemcpyAsync(P->h_status, P->d_status, sizeof(uint32_t) * P->n_frames, hipMemcpyDeviceToHost,
                            s) != hipSuccess) {
             rc = TMD_E_HIP;
@@ -3557,6 +3761,7 @@ int tmd_set_profiling(tmd_plan_t *P, uint32_t stage_mask)
     if (!P) return TMD_E_ARG;
     P->profiling = stage_mask & ((1u << kStages) - 1u);
     P->prof_rans = (stage_mask >> kStages) & 1u;
+    P->prof_rans_un = (stage_mask >> (kStages + 1)) & 1u;
     return TMD_OK;
 }
 
@@ -3573,24 +3778,29 @@ int tmd_stage_times(tmd_plan_t *P, double *ms, uint32_t n, uint32_t *calls)
             acc[i] += t;
         }
     }
-    double rans = 0.0;
-    for (auto &v : P->rans_events) {
-        HIP_TRY(hipEventSynchronize(v.second));
-        float t = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&t, v.first, v.second));
-        rans += t;
+    for (auto *L : {&P->rans_events, &P->rans_un_events}) {
+        double sum = 0.0;
+        for (auto &v : *L) {
+            HIP_TRY(hipEventSynchronize(v.second));
+            float t = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&t, v.first, v.second));
+            sum += t;
+        }
+        acc.push_back(sum);
     }
-    if (calls) *calls = (uint32_t)std::max(P->prof_events.size(), P->rans_events.size());
+    if (calls)
+        *calls = (uint32_t)std::max({P->prof_events.size(), P->rans_events.size(), P->rans_un_events.size()});
     for (auto &ev : P->prof_events)
         for (auto e : ev)
             if (e) P->event_pool.push_back(e);
     P->prof_events.clear();
-    for (auto &v : P->rans_events) {
-        P->event_pool.push_back(v.first);
-        P->event_pool.push_back(v.second);
+    for (auto *L : {&P->rans_events, &P->rans_un_events}) {
+        for (auto &v : *L) {
+            P->event_pool.push_back(v.first);
+            P->event_pool.push_back(v.second);
+        }
+        L->clear();
     }
-    P->rans_events.clear();
-    acc.push_back(rans);
     for (uint32_t i = 0; i < n && i < (uint32_t)kAllStages; i++) ms[i] = acc[i];
     return kAllStages;
 }
@@ -3790,8 +4000,9 @@ static_assert(rans_width_count(1) <= 12 && rans_width_count(2) <= 12 && rans_wid
 
 // The entropy decoding's workspace: the error words of all frames, their
 // descriptors and work-item offsets (copied in by each call), then for each
-// frame its planes' decode tables and positions and its decoded arrays (each
-// section 256-byte aligned).
+// frame its planes' decode tables and positions, its decoded arrays but the
+// unattached ones (those go straight to the output) and the chunk records of
+// the unattached time and pad differences (each section 256-byte aligned).
 constexpr size_t kRansTabOff = 0;
 constexpr size_t kRansInfoOff = kRansTabOff + 256 * ((kRansPlanes * (size_t)kRansTab + 255) / 256);
 constexpr size_t kRansArrOff = kRansInfoOff + 256 * ((16 * kRansPlanes + 255) / 256);
@@ -3806,17 +4017,19 @@ RansHead rans_head(uint32_t nf)
     H.err = 0;
     H.desc = align256(4ull * nf);
     H.witem = H.desc + align256(sizeof(RansDesc) * nf);
-    H.frames = H.witem + align256(4ull * 3 * (nf + 1));
+    H.frames = H.witem + align256(4ull * 6 * (nf + 1));
     return H;
 }
+
+uint32_t rans_chunks(uint32_t n) { return (uint32_t)(((uint64_t)n + kRansChunk - 1) / kRansChunk); }
 
 size_t rans_frame_bytes(const tmd_frame_shape &S)
 {
     uint32_t n[kRansArrays];
     rans_counts(S, n);
     size_t b = kRansArrOff;
-    for (int a = 0; a < kRansArrays; a++) b += align256((size_t)kRansWidthHost[a] * std::max<uint32_t>(n[a], 1));
-    return b;
+    for (int a = 0; a < (int)kRansUn0; a++) b += align256((size_t)kRansWidthHost[a] * std::max<uint32_t>(n[a], 1));
+    return b + align256(2 * sizeof(uint4) * std::max<uint32_t>(rans_chunks(S.n_unattached), 1));
 }
 
 }  // namespace
@@ -3859,6 +4072,7 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
     RansDesc *desc = (RansDesc *)hbuf.data();
     uint32_t *witem = (uint32_t *)(hbuf.data() + (H.witem - H.desc));
     char *fws = ws + H.frames;
+    uint32_t maxch = 0;  // most chunks of an unattached array
     for (uint32_t f = 0; f < nf; f++) {
         const tmd_frame_shape &S = shapes[f];
         RansDesc &R = desc[f];
@@ -3872,21 +4086,28 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
         R.tabs = (GLB uint8_t *)(fws + kRansTabOff);
         R.pinfo = (GLB uint64_t *)(fws + kRansInfoOff);
         size_t off = kRansArrOff;
-        void *arr[kRansArrays];
-        for (int a = 0; a < kRansArrays; a++) {
+        void *arr[kRansArrays] = {};
+        for (int a = 0; a < (int)kRansUn0; a++) {
             arr[a] = fws + off;
             R.dst[a] = (GLB uint8_t *)arr[a];
             off += align256((size_t)kRansWidthHost[a] * std::max<uint32_t>(R.n[a], 1));
         }
-        // work items of each width class: one per chunk of its arrays
+        R.urec = (GLB uint4 *)(fws + off);
+        // work items of each list and width class: one per kRansWaves chunks
+        // of its arrays (list 1: the unattached arrays)
         for (int a = 0; a < kRansArrays; a++) {
+            const int ph = a >= (int)kRansUn0 ? 1 : 0;
             const int wi = kRansWidthHost[a] == 1 ? 0 : (kRansWidthHost[a] == 2 ? 1 : 2);
-            const uint32_t k = R.nw[wi]++;
-            R.warr[wi][k] = (uint32_t)a;
-            const uint32_t nch = (R.n[a] + kRansChunk - 1) / kRansChunk;
-            R.witem0[wi][k + 1] = R.witem0[wi][k] + (nch + kRansWaves - 1) / kRansWaves;
+            const uint32_t k = R.nw[ph][wi]++;
+            R.warr[ph][wi][k] = (uint32_t)a;
+            R.witem0[ph][wi][k + 1] = R.witem0[ph][wi][k] + (rans_chunks(R.n[a]) + kRansWaves - 1) / kRansWaves;
         }
-        for (int wi = 0; wi < 3; wi++) witem[wi * (nf + 1) + f + 1] = witem[wi * (nf + 1) + f] + R.witem0[wi][R.nw[wi]];
+        for (int ph = 0; ph < 2; ph++)
+            for (int wi = 0; wi < 3; wi++) {
+                uint32_t *t = witem + (3 * ph + wi) * (nf + 1);
+                t[f + 1] = t[f] + R.witem0[ph][wi][R.nw[ph][wi]];
+            }
+        maxch = std::max(maxch, rans_chunks(S.n_unattached));
         tmd_frame_in &I = in[f];
         I.trk_ncls = (const uint8_t *)arr[0]; I.trk_sec0 = (const uint8_t *)arr[1]; I.trk_row0 = (const uint8_t *)arr[2];
         I.trk_pad0 = (const uint16_t *)arr[3]; I.trk_time0 = (const uint32_t *)arr[4];
@@ -3894,9 +4115,7 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
         I.cls_row_diff = (const int8_t *)arr[8]; I.cls_sec_diff = (const uint8_t *)arr[9];
         I.cls_pad_res = (const int16_t *)arr[10]; I.cls_time_res = (const int16_t *)arr[11];
         I.cls_qtot = (const uint16_t *)arr[12]; I.cls_qmax = (const uint16_t *)arr[13];
-        I.un_count = (const uint32_t *)arr[14]; I.un_time_diff = (const uint32_t *)arr[15];
-        I.un_pad_diff = (const uint16_t *)arr[16]; I.un_qtot = (const uint16_t *)arr[17];
-        I.un_qmax = (const uint16_t *)arr[18];
+        I.un_count = (const uint32_t *)arr[14];  // (the unattached arrays: decoded into the output by post)
         pre[f] = (const uint32_t *)(ws + H.err) + f;
         fws += rans_frame_bytes(S);
     }
@@ -3937,9 +4156,11 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
         const uint32_t *dw = (const uint32_t *)(ws + H.witem);
         hipLaunchKernelGGL(k_fill32, dim3(1), dim3(256), 0, s, (uint32_t *)(ws + H.err), nf, 0u);
         hipLaunchKernelGGL(k_rans_prep, dim3(kRansPlanes * nf), dim3(256), 0, s, dd);
-        if (const uint32_t it = witem[0 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<1>, dim3(it), dim3(kRansLanes * kRansWaves), 0, s, dd, dw, nf);
-        if (const uint32_t it = witem[1 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<2>, dim3(it), dim3(kRansLanes * kRansWaves), 0, s, dd, dw, nf);
-        if (const uint32_t it = witem[2 * (nf + 1) + nf]) hipLaunchKernelGGL(k_rans<4>, dim3(it), dim3(kRansLanes * kRansWaves), 0, s, dd, dw, nf);
+        const dim3 blk(kRansLanes * kRansWaves);
+        const FrameDesc *nofd = nullptr;
+        if (const uint32_t it = witem[0 * (nf + 1) + nf]) hipLaunchKernelGGL((k_rans<1, false>), dim3(it), blk, 0, s, dd, dw, nf, nofd);
+        if (const uint32_t it = witem[1 * (nf + 1) + nf]) hipLaunchKernelGGL((k_rans<2, false>), dim3(it), blk, 0, s, dd, dw, nf, nofd);
+        if (const uint32_t it = witem[2 * (nf + 1) + nf]) hipLaunchKernelGGL((k_rans<4, false>), dim3(it), blk, 0, s, dd, dw, nf, nofd);
         if (hipGetLastError() != hipSuccess) rc = TMD_E_HIP;
         if (ev.second) {
             if (rc == TMD_OK && hipEventRecord(ev.second, s) == hipSuccess) {
@@ -3952,7 +4173,39 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
     } while (0);
     if (cur != P->device) (void)hipSetDevice(cur);
     if (rc != TMD_OK) return rc;
-    return decode_impl(P, shapes, in.data(), out, workspace, stream, pre.data());
+    // after the offsets of the track-model decode: the unattached arrays,
+    // decoded into their output slots, then the leading sums of their chunks
+    const PostLaunch post = [&](hipStream_t q) -> int {
+        const RansDesc *dd = (const RansDesc *)(ws + H.desc);
+        const uint32_t *dw = (const uint32_t *)(ws + H.witem);
+        const FrameDesc *fd = P->d_desc;
+        std::pair<hipEvent_t, hipEvent_t> ev(nullptr, nullptr);
+        if (P->prof_rans_un) {
+            std::vector<hipEvent_t> two;
+            if (take_events(P, 1u, two) != TMD_OK) return TMD_E_HIP;
+            ev = {two[0], two[1]};
+            if (hipEventRecord(ev.first, q) != hipSuccess) {
+                P->event_pool.push_back(ev.first);
+                P->event_pool.push_back(ev.second);
+                return TMD_E_HIP;
+            }
+        }
+        const dim3 blk(kRansLanes * kRansWaves);
+        if (const uint32_t it = witem[5 * (nf + 1) + nf]) hipLaunchKernelGGL((k_rans<4, true>), dim3(it), blk, 0, q, dd, dw, nf, fd);
+        if (const uint32_t it = witem[4 * (nf + 1) + nf]) hipLaunchKernelGGL((k_rans<2, true>), dim3(it), blk, 0, q, dd, dw, nf, fd);
+        if (maxch > 1) hipLaunchKernelGGL(k_rans_unfix, dim3(maxch, 2, nf), dim3(kRansLanes), 0, q, dd, fd);
+        int r = hipGetLastError() == hipSuccess ? TMD_OK : TMD_E_HIP;
+        if (ev.second) {
+            if (r == TMD_OK && hipEventRecord(ev.second, q) == hipSuccess) {
+                P->rans_un_events.push_back(ev);
+            } else {
+                P->event_pool.push_back(ev.first);
+                P->event_pool.push_back(ev.second);
+            }
+        }
+        return r;
+    };
+    return decode_impl(P, shapes, in.data(), out, workspace, stream, pre.data(), &post);
 }
 
 }  // extern "C"

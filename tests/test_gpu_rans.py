@@ -111,3 +111,52 @@ def test_gpu_encoder_matches_oracle(tmd, case):
     got = tmd.encode_rans(tmd.to_device(fr)).cpu().numpy()
     assert got.size == want.size, (case, got.size, want.size)
     assert np.array_equal(got, want), (case, int(np.flatnonzero(got != want)[0]))
+
+
+def _long_bins(seed, mode):
+    """A frame whose unattached clusters sit in a few long bins (each over
+    several 32768-element chunks), many empty bins and short ones, with
+    differences that wrap; mode "exact": the counts add up to n_unattached,
+    "over": they exceed it (the cut falls inside a long bin), "under": they
+    fall short (the last elements belong to no bin)."""
+    rng = np.random.default_rng(seed)
+    cnt = np.where(rng.random(tmd_nbin()) < 0.3, rng.integers(0, 40, tmd_nbin()), 0).astype(np.int64)
+    cnt[:5] = 0
+    cnt[7] = 100_000
+    cnt[3000] = 70_001
+    cnt[-3:] = [33_000, 0, 65_536]
+    total = int(cnt.sum())
+    nu = {"exact": total, "over": total - 50_000, "under": total + 40_000}[mode]
+    fr = _garbage(seed, nt=300, na=20000, nu=nu)
+    fr["un_count"] = cnt.astype(np.uint32)
+    fr["un_time_diff"] = rng.integers(0, 2**32, nu, dtype=np.uint64).astype(np.uint32)
+    fr["un_pad_diff"] = rng.integers(0, 65536, nu).astype(np.uint16)
+    return fr
+
+
+def tmd_nbin():
+    return 36 * 152
+
+
+@pytest.mark.parametrize("mode", ["exact", "over", "under"])
+def test_coded_unattached_long_bins(tmd, mode):
+    """The unattached arrays are decoded straight into the output: running
+    sums whose bins span several chunks (the leading sums of a chunk come
+    from the chunks before), counts that overrun or fall short of
+    n_unattached, and a batched graph plan with a frame of short bins."""
+    import torch
+    frames = [_long_bins(31, mode), _garbage(32), _long_bins(33, "exact")]
+    shapes = [tmd.frame_shape(f) for f in frames]
+    coded = [torch.from_numpy(oracle.rans_encode(f)).cuda() for f in frames]
+    print(f"long bins {mode}: shapes {shapes}", flush=True)
+    for flags in (0, tmd.PLAN_GRAPH):
+        plan = tmd.Plan(shapes, flags=flags)
+        ws = plan.alloc_workspace()
+        rws = torch.empty(plan.rans_workspace_bytes(), dtype=torch.uint8, device="cuda")
+        outs = [tmd.alloc_out(s) for s in shapes]
+        for rep in range(2):
+            plan.decode_rans(coded, outs, ws, rws)
+            torch.cuda.synchronize()
+            for i, f in enumerate(frames):
+                check(tmd, *oracle.decode(f), outs[i], plan.status(i), (mode, flags, rep, i))
+        plan.free()

@@ -95,9 +95,25 @@ def test_kernel_symbols_agree_between_host_and_device():
     launch without a kernel)."""
     data = open(_lib.LIB_PATH, "rb").read()
     names = {}
-    for m in re.finditer(rb"_ZN12_GLOBAL__N_1(\d+)(k_[A-Za-z0-9_]+?)E[A-Za-z0-9_]*", data):
-        full = m.group(0).split(b".")[0]
-        names.setdefault(m.group(2), set()).add(full)
+    for m in re.finditer(rb"_ZN12_GLOBAL__N_1(\d+)", data):
+        # the kernel's name (its length comes first), then its template
+        # arguments if any (I ... E, literals L ... E inside)
+        st = m.end()
+        name = data[st:st + int(m.group(1))]
+        if not name.startswith(b"k_"):
+            continue
+        j = st + len(name)
+        if data[j:j + 1] == b"I":
+            depth, k = 0, j
+            while True:
+                c = data[k:k + 1]
+                depth += 1 if c in (b"I", b"L") else (-1 if c == b"E" else 0)
+                k += 1
+                if depth == 0:
+                    break
+            name += data[j:k]
+        full = re.match(rb"[A-Za-z0-9_]+", data[m.start():]).group(0)
+        names.setdefault(name, set()).add(full)
     assert len(names) >= 15
     bad = {k: v for k, v in names.items() if len(v) != 1}
     assert not bad, bad
