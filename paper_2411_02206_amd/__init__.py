@@ -238,7 +238,9 @@ class Plan:
         L = _lib.lib()
         if stages is not None:
             names = [L.tmd_stage_name(i).decode() for i in range(16)]
-            mask = sum(1 << names.index(st) for st in stages)
+            mask = 0
+            for st in set(stages):
+                mask |= 1 << names.index(st)
         else:
             mask = 0xFFFFFFFF if on else 0
         _lib.check(L.tmd_set_profiling(self._h, mask), "tmd_set_profiling")

@@ -814,7 +814,7 @@ __device__ __forceinline__ void store_wide(GLB T *p, const V &v)
 __global__ __launch_bounds__(kWave) void k_unattached(const FrameDesc *__restrict__ fd)
 {
     const FrameDesc F = fd[blockIdx.y];
-    if (F.un_fused) return;  // (done by the entropy decoding, k_rans<W, true>)
+    if (F.un_fused) return;  // (done by the entropy decoding, k_rans<W, kRansUnPhase>)
     const uint32_t k = blockIdx.x;
     const uint32_t cnt = F.ueff[k];
     if (cnt == 0) return;
@@ -2216,8 +2216,16 @@ __device__ __constant__ const uint8_t kRansPlane0[kRansArrays] = {0,  1,  2,  3,
                                                                   17, 19, 21, 23, 25, 29, 33, 35, 37};
 
 // The arrays of unattached clusters (time and pad differences, charges),
-// decoded straight into the output by k_rans<W, true>
+// decoded straight into the output by k_rans<W, kRansUnPhase>
 constexpr uint32_t kRansUn0 = 15;
+// Work lists (phases) of the entropy decoding: 0, the track and attached
+// arrays and the bin counts (before the track-model decode); 1, the
+// unattached arrays (into the output, once the decode's offsets are known).
+// (Decoding the arrays that only k_rank and k_attached read beside the
+// decode's first kernels instead saved nothing: those kernels and the
+// entropy decoding both need the vector ALUs.)
+constexpr int kRansPhases = 2, kRansUnPhase = 1;
+constexpr int rans_phase(int a) { return a >= (int)kRansUn0 ? 1 : 0; }
 
 struct RansDesc {  // (the same layout on the host and the device: 920 bytes)
     const GLB uint8_t *src;       // the coded frame (16-byte aligned)
@@ -2229,12 +2237,10 @@ struct RansDesc {  // (the same layout on the host and the device: 920 bytes)
     GLB uint32_t *err;            // TMD_F_CODED if the data is not a well-formed coded frame
     GLB uint4 *urec;              // [2][chunks of nU]: time's, then pad's chunk records (k_rans_unfix)
     uint32_t nT, nA, nU;
-    // work lists: [0] the arrays decoded before the track-model decode,
-    // [1] the unattached ones; per width class (1, 2, 4 bytes) the arrays
-    uint32_t nw[2][3];
-    uint32_t warr[2][3][12];
-    uint32_t witem0[2][3][13];    // first work item of each, then the total
-    uint32_t pad_;
+    // work lists: per phase and width class (1, 2, 4 bytes) the arrays
+    uint32_t nw[kRansPhases][3];
+    uint32_t warr[kRansPhases][3][12];
+    uint32_t witem0[kRansPhases][3][13];  // first work item of each, then the total
 };
 
 static_assert(sizeof(RansDesc) == 920, "descriptor layout");
@@ -2536,16 +2542,16 @@ struct RansUnBins {
     }
 };
 
-// (witem: for each list and width class, the first work item of each frame,
-// then the total; a work item is kRansWaves consecutive chunks of one array
-// of the class.  UN: the list of unattached arrays, placed into the frame's
-// output, fd being the track-model decode's frame descriptors.)
-template <int W, bool UN>
+// (witem: for each phase and width class, the first work item of each
+// frame, then the total; a work item is kRansWaves consecutive chunks of one
+// array of the class.  Phase kRansUnPhase: the unattached arrays, placed into
+// the frame's output, fd being the track-model decode's frame descriptors.)
+template <int W, int PH>
 __global__ __launch_bounds__(kRansLanes * kRansWaves) void k_rans(const RansDesc *descs, const uint32_t *witem,
                                                                   uint32_t nf, const FrameDesc *fd)
 {
     constexpr int WI = W == 1 ? 0 : (W == 2 ? 1 : 2);
-    constexpr int PH = UN ? 1 : 0;
+    constexpr bool UN = PH == kRansUnPhase;
     constexpr uint32_t B = rans_blk(W), RING = rans_ring(W);
     using Elem = typename RansChunk<W>::Elem;
     __shared__ __align__(16) uint8_t sym[W][4096];  // the symbol of every slot
@@ -2605,6 +2611,8 @@ __global__ __launch_bounds__(kRansLanes * kRansWaves) void k_rans(const RansDesc
     GLB Elem *dst = UN ? nullptr : (GLB Elem *)readlane64((uint64_t)R->dst[a]) + c0;  // (UN: the output instead)
     uint32_t(*rg)[RING / 2] = ring[wave];
     Elem *stg = stage[wave];
+    // the unattached arrays are decoded after k_tilesum took the frame's
+    // starting flags from R->err: their flags go to the frame's status too
     GLB uint32_t *status = nullptr;
     if constexpr (UN) status = (GLB uint32_t *)readlane64((uint64_t)((const GLB FrameDesc *)fd)[flo].status);
     // planes of one symbol: its byte, nothing to decode
@@ -3058,12 +3066,13 @@ static __device__ __align__(256) uint8_t scratch[TMD_STATIC_SCRATCH_BYTES];
 // host side
 // ---------------------------------------------------------------------------
 constexpr int kStages = 7;  // the decode's stages
-// (stage kStages, "rans": the entropy decoding of tmd_decode_rans before the
-// track-model decode; kStages + 1, "rans_un": its fused decoding of the
-// unattached clusters after it)
+// (tmd_decode_rans's entropy decoding: stage kStages, "rans", of the track
+// and attached arrays before the track-model decode; kStages + 1, "rans_un",
+// of the unattached clusters into the output, beside the rank and attached
+// kernels)
 constexpr int kAllStages = kStages + 2;
-const char *kStageNames[kAllStages] = {"tilesum",  "count",    "colscan",    "offsets", "rank",
-                                       "attached", "unattached", "rans",     "rans_un"};
+const char *kStageNames[kAllStages] = {"tilesum",  "count",      "colscan", "offsets", "rank",
+                                       "attached", "unattached", "rans",    "rans_un"};
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -3098,17 +3107,20 @@ struct tmd_plan {
     hipEvent_t done = nullptr;
     bool called = false;  // `done` has been recorded at least once
     uint32_t profiling = 0;                            // stage mask
-    bool prof_rans = false;                            // events around tmd_decode_rans's entropy decoding
-    bool prof_rans_un = false;                         // and around its fused unattached decode
+    uint32_t prof_rans = 0;                            // events around tmd_decode_rans's entropy decoding (2 bits)
     void *h_rans = nullptr;                            // pinned staging of its descriptors
     size_t h_rans_bytes = 0;
     hipEvent_t rans_copy = nullptr;                    // their last upload
     bool rans_staged = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> rans_events, rans_un_events;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> rans_events[2];  // its stages: before, unattached
     std::vector<std::vector<hipEvent_t>> prof_events;  // per recorded call: 2 per stage (unrecorded: null)
     std::vector<hipEvent_t> event_pool;                // events ready for reuse
     hipGraphExec_t graph = nullptr;   // TMD_PLAN_GRAPH: the captured launch sequence
     hipStream_t capture = nullptr;    // stream the graph is captured on
+    // tmd_decode_rans: the stream on which part of its entropy decoding runs
+    // beside the track-model decode, and the events that order the two
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     // TMD_PLAN_GRAPH with profiling: a second graph with an event-record node
     // before and after each selected stage; each replay points those nodes
     // at fresh events from the pool
@@ -3191,9 +3203,33 @@ int take_events(tmd_plan_t *P, uint32_t mask, std::vector<hipEvent_t> &ev)
     return TMD_OK;
 }
 
+// Work that tmd_decode_rans runs on the plan's second stream beside the
+// launch sequence, from the offsets on until its end: the unattached
+// clusters' decoding into the output, in place of k_unattached.  It enqueues
+// its kernels on the stream it is given.
+using SideWork = std::function<int(hipStream_t)>;
+
+// Enqueue side on the plan's second stream after what s holds so far, and
+// record the plan's join event after it.
+int fork_side(tmd_plan_t *P, hipStream_t s, const SideWork &side)
+{
+    if (!P->side) {
+        HIP_TRY(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&P->fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&P->join, hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventRecord(P->fork, s));
+    HIP_TRY(hipStreamWaitEvent(P->side, P->fork, 0));
+    const int rc = side(P->side);
+    HIP_TRY(hipEventRecord(P->join, P->side));  // (also after a failed launch: s must not wait forever)
+    return rc;
+}
+
 // Enqueue the pipeline on stream s, one kernel after the other.  Each stage
-// with events in `ev` (2 per stage, or empty) is bracketed by them.
-int launch_all(tmd_plan_t *P, hipStream_t s, const std::vector<hipEvent_t> &ev)
+// with events in `ev` (2 per stage, or empty) is bracketed by them.  With
+// `side`, once the offsets are known, side runs on the plan's second stream
+// (fork_side) and s waits for it at its end (k_unattached has nothing to do).
+int launch_all(tmd_plan_t *P, hipStream_t s, const std::vector<hipEvent_t> &ev, const SideWork *side = nullptr)
 {
     auto begin = [&](int st, hipStream_t q) -> int {
         return (ev.size() && ev[2 * st] && hipEventRecord(ev[2 * st], q) != hipSuccess) ? TMD_E_HIP : TMD_OK;
@@ -3213,6 +3249,8 @@ int launch_all(tmd_plan_t *P, hipStream_t s, const std::vector<hipEvent_t> &ev)
                        s, P->d_desc);
     if (end(2, s) || begin(3, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_offsets, dim3(P->n_frames), dim3(kOffThreads), 0, s, P->d_desc);
+    if (side)
+        if (const int rc = fork_side(P, s, *side)) return rc;
     if (end(3, s) || begin(4, s)) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_rank, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
     if (end(4, s)) return TMD_E_HIP;
@@ -3232,6 +3270,7 @@ int launch_all(tmd_plan_t *P, hipStream_t s, const std::vector<hipEvent_t> &ev)
     if (end(5, s) || begin(6, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_unattached, dim3(NBIN, P->n_frames), dim3(kWave), 0, s, P->d_desc);
     if (end(6, s)) return TMD_E_HIP;
+    if (side) HIP_TRY(hipStreamWaitEvent(s, P->join, 0));
     HIP_TRY(hipGetLastError());
     return TMD_OK;
 }
@@ -3411,8 +3450,8 @@ void tmd_free(tmd_plan_t *P)
     for (auto &v : P->prof_events)
         for (auto e : v)
             if (e) (void)hipEventDestroy(e);
-    for (auto *L : {&P->rans_events, &P->rans_un_events})
-        for (auto &v : *L) {
+    for (auto &L : P->rans_events)
+        for (auto &v : L) {
             (void)hipEventDestroy(v.first);
             (void)hipEventDestroy(v.second);
         }
@@ -3420,6 +3459,9 @@ void tmd_free(tmd_plan_t *P)
     if (P->graph) (void)hipGraphExecDestroy(P->graph);
     drop_prof_graph(P);
     if (P->capture) (void)hipStreamDestroy(P->capture);
+    if (P->side) (void)hipStreamDestroy(P->side);
+    if (P->fork) (void)hipEventDestroy(P->fork);
+    if (P->join) (void)hipEventDestroy(P->join);
     if (P->desc_done) (void)hipEventDestroy(P->desc_done);
     if (P->done) (void)hipEventDestroy(P->done);
     if (P->d_geo) (void)hipFree(P->d_geo);
@@ -3541,9 +3583,8 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
 }  // extern "C"
 
 namespace {
-using PostLaunch = std::function<int(hipStream_t)>;
 int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
-                void *workspace, void *stream, const uint32_t *const *pre_status, const PostLaunch *post = nullptr);
+                void *workspace, void *stream, const uint32_t *const *pre_status, const SideWork *side = nullptr);
 }  // namespace
 
 extern "C" {
@@ -3559,13 +3600,15 @@ int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_fr
 namespace {
 
 // tmd_decode_shapes, with an optional device word per frame that the frame's
-// status starts from (flags of a step before the decode).  With `post`, the
-// unattached clusters are not decoded here: post enqueues what decodes them
-// (after the launch sequence, before the status words are read back), and
-// the unattached input arrays may be null.
+// status starts from (flags of a step before the decode).  With `side`, the
+// unattached clusters are not decoded by the sequence: side decodes them on
+// the plan's second stream once the offsets are known (launch_all; the
+// kernels are then launched one by one, also for a graph plan), and the
+// unattached input arrays may be null.
 int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
-                void *workspace, void *stream, const uint32_t *const *pre_status, const PostLaunch *post)
+                void *workspace, void *stream, const uint32_t *const *pre_status, const SideWork *side)
 {
+    const bool post = side != nullptr;  // (the unattached clusters: by side)
     if (!P || !shapes || !in || !out || !workspace) return TMD_E_ARG;
     if ((uintptr_t)workspace % 256) return TMD_E_ARG;
     for (uint32_t f = 0; f < P->n_frames; f++) {
@@ -3651,7 +3694,7 @@ int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in
             P->last_desc = desc;
             P->desc_valid = true;
         }
-        if (P->params.flags & TMD_PLAN_GRAPH) {
+        if ((P->params.flags & TMD_PLAN_GRAPH) && !post) {
             // the kernels read only plan-owned buffers (descriptor table,
             // tables, tile map), so one captured graph serves every call
             if (P->profiling) {
@@ -3685,7 +3728,7 @@ int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in
         } else {
             std::vector<hipEvent_t> ev;
             if (P->profiling && (rc = take_events(P, P->profiling, ev)) != TMD_OK) break;
-            rc = launch_all(P, s, ev);
+            rc = launch_all(P, s, ev, side);
             if (rc != TMD_OK) {
                 for (hipEvent_t e : ev)
                     if (e) P->event_pool.push_back(e);
@@ -3693,7 +3736,6 @@ int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in
             }
             if (P->profiling) P->prof_events.push_back(ev);
         }
-        if (post && (rc = (*post)(s)) != TMD_OK) break;
         if (hipMemcpyAsync(P->h_status, P->d_status, sizeof(uint32_t) * P->n_frames, hipMemcpyDeviceToHost,
                            s) != hipSuccess) {
             rc = TMD_E_HIP;
@@ -3760,8 +3802,7 @@ int tmd_set_profiling(tmd_plan_t *P, uint32_t stage_mask)
 {
     if (!P) return TMD_E_ARG;
     P->profiling = stage_mask & ((1u << kStages) - 1u);
-    P->prof_rans = (stage_mask >> kStages) & 1u;
-    P->prof_rans_un = (stage_mask >> (kStages + 1)) & 1u;
+    P->prof_rans = (stage_mask >> kStages) & 3u;
     return TMD_OK;
 }
 
@@ -3778,9 +3819,9 @@ int tmd_stage_times(tmd_plan_t *P, double *ms, uint32_t n, uint32_t *calls)
             acc[i] += t;
         }
     }
-    for (auto *L : {&P->rans_events, &P->rans_un_events}) {
+    for (auto &L : P->rans_events) {
         double sum = 0.0;
-        for (auto &v : *L) {
+        for (auto &v : L) {
             HIP_TRY(hipEventSynchronize(v.second));
             float t = 0.0f;
             HIP_TRY(hipEventElapsedTime(&t, v.first, v.second));
@@ -3789,17 +3830,17 @@ int tmd_stage_times(tmd_plan_t *P, double *ms, uint32_t n, uint32_t *calls)
         acc.push_back(sum);
     }
     if (calls)
-        *calls = (uint32_t)std::max({P->prof_events.size(), P->rans_events.size(), P->rans_un_events.size()});
+        *calls = (uint32_t)std::max({P->prof_events.size(), P->rans_events[0].size(), P->rans_events[1].size()});
     for (auto &ev : P->prof_events)
         for (auto e : ev)
             if (e) P->event_pool.push_back(e);
     P->prof_events.clear();
-    for (auto *L : {&P->rans_events, &P->rans_un_events}) {
-        for (auto &v : *L) {
+    for (auto &L : P->rans_events) {
+        for (auto &v : L) {
             P->event_pool.push_back(v.first);
             P->event_pool.push_back(v.second);
         }
-        L->clear();
+        L.clear();
     }
     for (uint32_t i = 0; i < n && i < (uint32_t)kAllStages; i++) ms[i] = acc[i];
     return kAllStages;
@@ -3997,6 +4038,12 @@ constexpr int rans_width_count(int w, int a = 0)
 static_assert(rans_width_count(1) <= 12 && rans_width_count(2) <= 12 && rans_width_count(4) <= 12 &&
                   rans_width_count(1) + rans_width_count(2) + rans_width_count(4) == kRansArrays,
               "arrays of 1, 2 or 4 bytes, at most 12 of each");
+constexpr int rans_phase_count(int ph, int w, int a = 0)
+{
+    return a == kRansArrays ? 0 : (rans_phase(a) == ph && kRansWidthHost[a] == w) + rans_phase_count(ph, w, a + 1);
+}
+// (the kernels tmd_decode_rans launches for each phase)
+static_assert(rans_phase_count(1, 1) == 0, "phase 1: 2- and 4-byte arrays");
 
 // The entropy decoding's workspace: the error words of all frames, their
 // descriptors and work-item offsets (copied in by each call), then for each
@@ -4017,7 +4064,7 @@ RansHead rans_head(uint32_t nf)
     H.err = 0;
     H.desc = align256(4ull * nf);
     H.witem = H.desc + align256(sizeof(RansDesc) * nf);
-    H.frames = H.witem + align256(4ull * 6 * (nf + 1));
+    H.frames = H.witem + align256(4ull * 3 * kRansPhases * (nf + 1));
     return H;
 }
 
@@ -4093,16 +4140,16 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
             off += align256((size_t)kRansWidthHost[a] * std::max<uint32_t>(R.n[a], 1));
         }
         R.urec = (GLB uint4 *)(fws + off);
-        // work items of each list and width class: one per kRansWaves chunks
-        // of its arrays (list 1: the unattached arrays)
+        // work items of each phase and width class: one per kRansWaves
+        // chunks of its arrays
         for (int a = 0; a < kRansArrays; a++) {
-            const int ph = a >= (int)kRansUn0 ? 1 : 0;
+            const int ph = rans_phase(a);
             const int wi = kRansWidthHost[a] == 1 ? 0 : (kRansWidthHost[a] == 2 ? 1 : 2);
             const uint32_t k = R.nw[ph][wi]++;
             R.warr[ph][wi][k] = (uint32_t)a;
             R.witem0[ph][wi][k + 1] = R.witem0[ph][wi][k] + (rans_chunks(R.n[a]) + kRansWaves - 1) / kRansWaves;
         }
-        for (int ph = 0; ph < 2; ph++)
+        for (int ph = 0; ph < kRansPhases; ph++)
             for (int wi = 0; wi < 3; wi++) {
                 uint32_t *t = witem + (3 * ph + wi) * (nf + 1);
                 t[f + 1] = t[f] + R.witem0[ph][wi][R.nw[ph][wi]];
@@ -4115,10 +4162,51 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
         I.cls_row_diff = (const int8_t *)arr[8]; I.cls_sec_diff = (const uint8_t *)arr[9];
         I.cls_pad_res = (const int16_t *)arr[10]; I.cls_time_res = (const int16_t *)arr[11];
         I.cls_qtot = (const uint16_t *)arr[12]; I.cls_qmax = (const uint16_t *)arr[13];
-        I.un_count = (const uint32_t *)arr[14];  // (the unattached arrays: decoded into the output by post)
+        I.un_count = (const uint32_t *)arr[14];  // (the unattached arrays: decoded into the output)
         pre[f] = (const uint32_t *)(ws + H.err) + f;
         fws += rans_frame_bytes(S);
     }
+    // The kernels of one phase of the entropy decoding on stream q (phase 0
+    // with the tables' set-up), between a pair of events if its stage is
+    // profiled.
+    const RansDesc *dd = (const RansDesc *)(ws + H.desc);
+    const uint32_t *dw = (const uint32_t *)(ws + H.witem);
+    auto launch_phase = [&](int ph, hipStream_t q) -> int {
+        std::pair<hipEvent_t, hipEvent_t> ev(nullptr, nullptr);
+        if ((P->prof_rans >> ph) & 1u) {
+            std::vector<hipEvent_t> two;
+            if (take_events(P, 1u, two) != TMD_OK) return TMD_E_HIP;
+            ev = {two[0], two[1]};
+            if (hipEventRecord(ev.first, q) != hipSuccess) {
+                P->event_pool.push_back(ev.first);
+                P->event_pool.push_back(ev.second);
+                return TMD_E_HIP;
+            }
+        }
+        const dim3 blk(kRansLanes * kRansWaves);
+        const FrameDesc *fd = P->d_desc;
+        auto items = [&](int wi) { return witem[(3 * ph + wi) * (nf + 1) + nf]; };
+        if (ph == 0) {
+            hipLaunchKernelGGL(k_rans_prep, dim3(kRansPlanes * nf), dim3(256), 0, q, dd);
+            if (const uint32_t it = items(0)) hipLaunchKernelGGL((k_rans<1, 0>), dim3(it), blk, 0, q, dd, dw, nf, fd);
+            if (const uint32_t it = items(1)) hipLaunchKernelGGL((k_rans<2, 0>), dim3(it), blk, 0, q, dd, dw, nf, fd);
+            if (const uint32_t it = items(2)) hipLaunchKernelGGL((k_rans<4, 0>), dim3(it), blk, 0, q, dd, dw, nf, fd);
+        } else {
+            if (const uint32_t it = items(2)) hipLaunchKernelGGL((k_rans<4, kRansUnPhase>), dim3(it), blk, 0, q, dd, dw, nf, fd);
+            if (const uint32_t it = items(1)) hipLaunchKernelGGL((k_rans<2, kRansUnPhase>), dim3(it), blk, 0, q, dd, dw, nf, fd);
+            if (maxch > 1) hipLaunchKernelGGL(k_rans_unfix, dim3(maxch, 2, nf), dim3(kRansLanes), 0, q, dd, fd);
+        }
+        const int r = hipGetLastError() == hipSuccess ? TMD_OK : TMD_E_HIP;
+        if (ev.second) {
+            if (r == TMD_OK && hipEventRecord(ev.second, q) == hipSuccess) {
+                P->rans_events[ph].push_back(ev);
+            } else {
+                P->event_pool.push_back(ev.first);
+                P->event_pool.push_back(ev.second);
+            }
+        }
+        return r;
+    };
     int rc = TMD_OK;
     do {
         // (the previous call on this plan may still read the workspace, and
@@ -4143,69 +4231,16 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
             break;
         }
         P->rans_staged = true;
-        std::pair<hipEvent_t, hipEvent_t> ev(nullptr, nullptr);
-        if (P->prof_rans) {
-            std::vector<hipEvent_t> two;
-            if ((rc = take_events(P, 1u, two)) != TMD_OK) break;
-            ev = {two[0], two[1]};
-            if (hipEventRecord(ev.first, s) != hipSuccess) rc = TMD_E_HIP;
-        }
-        // the error words start at 0 (a fill kernel, not a memset node, so the
-        // sequence can be captured in a graph)
-        const RansDesc *dd = (const RansDesc *)(ws + H.desc);
-        const uint32_t *dw = (const uint32_t *)(ws + H.witem);
+        // the error words start at 0 (a fill kernel, not a memset node)
         hipLaunchKernelGGL(k_fill32, dim3(1), dim3(256), 0, s, (uint32_t *)(ws + H.err), nf, 0u);
-        hipLaunchKernelGGL(k_rans_prep, dim3(kRansPlanes * nf), dim3(256), 0, s, dd);
-        const dim3 blk(kRansLanes * kRansWaves);
-        const FrameDesc *nofd = nullptr;
-        if (const uint32_t it = witem[0 * (nf + 1) + nf]) hipLaunchKernelGGL((k_rans<1, false>), dim3(it), blk, 0, s, dd, dw, nf, nofd);
-        if (const uint32_t it = witem[1 * (nf + 1) + nf]) hipLaunchKernelGGL((k_rans<2, false>), dim3(it), blk, 0, s, dd, dw, nf, nofd);
-        if (const uint32_t it = witem[2 * (nf + 1) + nf]) hipLaunchKernelGGL((k_rans<4, false>), dim3(it), blk, 0, s, dd, dw, nf, nofd);
-        if (hipGetLastError() != hipSuccess) rc = TMD_E_HIP;
-        if (ev.second) {
-            if (rc == TMD_OK && hipEventRecord(ev.second, s) == hipSuccess) {
-                P->rans_events.push_back(ev);
-            } else {
-                P->event_pool.push_back(ev.first);
-                P->event_pool.push_back(ev.second);
-            }
-        }
+        rc = launch_phase(0, s);
     } while (0);
     if (cur != P->device) (void)hipSetDevice(cur);
     if (rc != TMD_OK) return rc;
-    // after the offsets of the track-model decode: the unattached arrays,
-    // decoded into their output slots, then the leading sums of their chunks
-    const PostLaunch post = [&](hipStream_t q) -> int {
-        const RansDesc *dd = (const RansDesc *)(ws + H.desc);
-        const uint32_t *dw = (const uint32_t *)(ws + H.witem);
-        const FrameDesc *fd = P->d_desc;
-        std::pair<hipEvent_t, hipEvent_t> ev(nullptr, nullptr);
-        if (P->prof_rans_un) {
-            std::vector<hipEvent_t> two;
-            if (take_events(P, 1u, two) != TMD_OK) return TMD_E_HIP;
-            ev = {two[0], two[1]};
-            if (hipEventRecord(ev.first, q) != hipSuccess) {
-                P->event_pool.push_back(ev.first);
-                P->event_pool.push_back(ev.second);
-                return TMD_E_HIP;
-            }
-        }
-        const dim3 blk(kRansLanes * kRansWaves);
-        if (const uint32_t it = witem[5 * (nf + 1) + nf]) hipLaunchKernelGGL((k_rans<4, true>), dim3(it), blk, 0, q, dd, dw, nf, fd);
-        if (const uint32_t it = witem[4 * (nf + 1) + nf]) hipLaunchKernelGGL((k_rans<2, true>), dim3(it), blk, 0, q, dd, dw, nf, fd);
-        if (maxch > 1) hipLaunchKernelGGL(k_rans_unfix, dim3(maxch, 2, nf), dim3(kRansLanes), 0, q, dd, fd);
-        int r = hipGetLastError() == hipSuccess ? TMD_OK : TMD_E_HIP;
-        if (ev.second) {
-            if (r == TMD_OK && hipEventRecord(ev.second, q) == hipSuccess) {
-                P->rans_un_events.push_back(ev);
-            } else {
-                P->event_pool.push_back(ev.first);
-                P->event_pool.push_back(ev.second);
-            }
-        }
-        return r;
-    };
-    return decode_impl(P, shapes, in.data(), out, workspace, stream, pre.data(), &post);
+    // once the offsets are known, on the plan's second stream beside the rank
+    // and attached kernels: the unattached arrays into their output slots
+    const SideWork side = [&](hipStream_t q) { return launch_phase(1, q); };
+    return decode_impl(P, shapes, in.data(), out, workspace, stream, pre.data(), &side);
 }
 
 }  // extern "C"
