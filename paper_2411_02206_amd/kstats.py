@@ -22,6 +22,8 @@ import subprocess
 import sys
 import time
 
+from paper_2411_02206_amd.traffic import kernel_name
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -76,7 +78,7 @@ def main():
              "| kernel | calls | total (us) | average (us) | min (us) | max (us) | share |",
              "|---|---|---|---|---|---|---|"]
     for row in rows:
-        name = col(row, "Name", "KernelName").replace("(anonymous namespace)::", "").split("(")[0]
+        name = kernel_name(col(row, "Name", "KernelName"))
         us = lambda *k: float(col(row, *k)) / 1e3  # noqa: E731  (ns -> us)
         lines.append(f"| {name} | {col(row, 'Calls')} | {us('TotalDurationNs'):.1f} | {us('AverageNs'):.2f} | "
                      f"{us('MinNs'):.2f} | {us('MaxNs'):.2f} | {float(col(row, 'Percentage')):.1f}% |")

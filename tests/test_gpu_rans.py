@@ -14,6 +14,8 @@ from test_gpu_parity import _garbage
 
 pytestmark = pytest.mark.gpu
 
+NBIN = 36 * 152  # (sector, row) bins
+
 
 @pytest.fixture(scope="module")
 def tmd():
@@ -120,7 +122,7 @@ def _long_bins(seed, mode):
     "over": they exceed it (the cut falls inside a long bin), "under": they
     fall short (the last elements belong to no bin)."""
     rng = np.random.default_rng(seed)
-    cnt = np.where(rng.random(tmd_nbin()) < 0.3, rng.integers(0, 40, tmd_nbin()), 0).astype(np.int64)
+    cnt = np.where(rng.random(NBIN) < 0.3, rng.integers(0, 40, NBIN), 0).astype(np.int64)
     cnt[:5] = 0
     cnt[7] = 100_000
     cnt[3000] = 70_001
@@ -132,10 +134,6 @@ def _long_bins(seed, mode):
     fr["un_time_diff"] = rng.integers(0, 2**32, nu, dtype=np.uint64).astype(np.uint32)
     fr["un_pad_diff"] = rng.integers(0, 65536, nu).astype(np.uint16)
     return fr
-
-
-def tmd_nbin():
-    return 36 * 152
 
 
 @pytest.mark.parametrize("mode", ["exact", "over", "under"])
