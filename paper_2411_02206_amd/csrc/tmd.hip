@@ -2711,6 +2711,41 @@ __global__ __launch_bounds__(kRansLanes * kRansWaves) void k_rans(const RansDesc
         uint32_t lead = head ? 0u : len;                 // elements before the first such bin
         uint32_t carry = 0;                              // running sum of the chunk's elements
         run([&](uint32_t j0) {
+            const uint32_t tb = kRansLanes * j0;  // the block's first element
+            const uint32_t nb = len - tb < kRansLanes * B ? len - tb : kRansLanes * B;
+            if (nstart > c0 + tb + nb - 1) {
+                // no bin begins in this block: every element is in bin cb.
+                // A lane takes B consecutive elements, their sums come from one
+                // wave scan of the lanes' totals, and they go out as one access
+                // (not aligned to its width; the hardware allows that).
+                static_assert(B * W == 8, "8 bytes per lane and block");
+                const uint32_t e0 = B * lane, g0 = c0 + tb + e0;
+                uint32_t v[B];
+#pragma unroll
+                for (uint32_t e = 0; e < B; e++) v[e] = e0 + e < nb ? (uint32_t)stg[e0 + e] : 0u;
+                if (scan) {
+#pragma unroll
+                    for (uint32_t e = 1; e < B; e++) v[e] += v[e - 1];
+                    const uint32_t I = wave_incl_add(v[B - 1]);
+                    const uint32_t add = carry + (I - v[B - 1]) - base;
+#pragma unroll
+                    for (uint32_t e = 0; e < B; e++) v[e] += add;
+                    carry += readlane(I, kRansLanes - 1);
+                }
+                if (e0 + B <= nb && g0 + B <= lim) {
+                    uint2 o;
+                    if constexpr (W == 4) o = make_uint2(v[0], v[1]);
+                    else o = make_uint2((v[0] & 0xFFFFu) | (v[1] << 16), (v[2] & 0xFFFFu) | (v[3] << 16));
+                    store_wide((GLB Elem *)out + g0 + sh, o);
+                } else {
+#pragma unroll
+                    for (uint32_t e = 0; e < B; e++)
+                        if (e0 + e < nb && g0 + e < lim) ((GLB Elem *)out)[g0 + e + sh] = (Elem)v[e];
+                }
+                return;
+            }
+            // a bin begins in this block: step by step, 64 consecutive
+            // elements at a time
 #pragma unroll
             for (uint32_t s = 0; s < B; s++) {
                 const uint32_t t0 = kRansLanes * (j0 + s);
