@@ -2173,9 +2173,11 @@ __global__ __launch_bounds__(256) void k_enc_un_delta(const EncDesc E, const uns
 //   k_rans_prep: one block per plane builds its decode tables (the symbol of
 //     every 12-bit slot; each symbol's frequency and start) and finds where
 //     its chunks' data begins.
-//   k_rans<W>: workgroups of kRansWaves waves, one wave per chunk of an
-//     array of W-byte elements; the waves of a workgroup take consecutive
-//     chunks of one array and share its planes' tables.  Lane l runs lane l
+//   k_rans<W, 0>: workgroups of kRansWaves waves, one wave per chunk of an
+//     array of W-byte elements (the track and attached-cluster arrays and
+//     the bin counts, before the track-model decode); the waves of a
+//     workgroup take consecutive chunks of one array and share its planes'
+//     tables.  Lane l runs lane l
 //     of the W planes side by side (W independent state chains), so every
 //     step yields whole elements; planes of a single symbol (f = 2^12) need
 //     no decoding.  A step's words are consecutive in the chunk's stream
@@ -2183,12 +2185,13 @@ __global__ __launch_bounds__(256) void k_enc_un_delta(const EncDesc E, const uns
 //     with one-dword-per-lane loads into an LDS ring per plane; the decoded
 //     elements of a block are staged in LDS and written out whole.  Global
 //     memory is touched only between blocks.
-//   k_rans<W, true>: the same decoding for the four arrays of unattached
-//     clusters, run after the output offsets are known (in place of
-//     k_unattached): each element goes straight to its output slot, time and
-//     pad differences as running sums within their bin.  A chunk's sums start
-//     at 0, so k_rans_unfix then adds to a chunk's leading elements the sum
-//     of their bin's elements in the chunks before (from a record per chunk).
+//   k_rans<W, 1>: the same decoding for the four arrays of unattached
+//     clusters, run once the output offsets are known (in place of
+//     k_unattached, on a second stream beside k_rank and k_attached): each
+//     element goes straight to its output slot, time and pad differences as
+//     running sums within their bin.  A chunk's sums start at 0, so
+//     k_rans_unfix then adds to a chunk's leading elements the sum of their
+//     bin's elements in the chunks before (from a record per chunk).
 // ---------------------------------------------------------------------------
 constexpr int kRansPlanes = 39, kRansArrays = 19, kRansLanes = 64, kRansPerLane = 512;
 constexpr uint32_t kRansChunk = kRansLanes * kRansPerLane;
@@ -2509,8 +2512,8 @@ __device__ __forceinline__ void rans_chunk(const RansChunk<W> &C, const uint32_t
     }
 }
 
-// The fused placement of the unattached arrays (k_rans<W, true>): a wave's
-// chunk holds elements [c0, c0 + len) of one array; element g belongs to the
+// The fused placement of the unattached arrays (k_rans<W, kRansUnPhase>): a
+// wave's chunk holds elements [c0, c0 + len) of one array; element g belongs to the
 // last bin b with uin[b] <= g and goes to output slot g + (roff[b] + rna[b] -
 // uin[b]) if g < uin[b] + room[b] (room: what k_unattached would store of the
 // bin).  Time and pad differences become running sums within the bin; the

@@ -53,7 +53,7 @@ def copy_program(mib):
 
 
 def kernel_name(raw):
-    """Short kernel name, template arguments kept (k_rans<2>)."""
+    """Short kernel name, template arguments kept (k_rans<2, 0>)."""
     name = raw.replace("(anonymous namespace)::", "").split("(")[0].strip()
     return name[5:] if name.startswith("void ") else name
 
