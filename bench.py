@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--frames-cache", default=None,
                     help="folder of generated frames: loaded if present, else written after generation")
     ap.add_argument("--seconds-per-load", type=float, default=2.0, help="served: arrival window per load")
+    ap.add_argument("--slots", type=int, default=8, help="served: batches in flight")
+    ap.add_argument("--max-batch", type=int, default=32, help="served: frames per batch at most")
     ap.add_argument("--gen-workers", type=int, default=16,
                     help="forked processes generating the synthetic frames (1 under a profiler that "
                          "initialises the GPU before the program starts)")
@@ -628,6 +630,7 @@ def run_batched(args):
         line["coded"] = coded_info
     if args.workload == "served":
         line["served"] = run_served(args, ins, shapes, len(frames) / t_batch, schedule)
+        line["served_config"] = {"slots": args.slots, "max_batch": args.max_batch, "hbm_budget_GB": 200}
         line["latency_ms"] = {"p50": line["served"]["100%"]["p50_ms"], "p99": line["served"]["100%"]["p99_ms"]}
     print(json.dumps(line), flush=True)
 
@@ -642,7 +645,7 @@ def run_served(args, ins, shapes, peak_fps, schedule=None):
     from paper_2411_02206_amd import serve
     loads = {}
     cap = tuple(max(s[i] for s in shapes) for i in range(3))
-    srv = serve.Server(bz=args.bz, hbm_budget=200e9, slots=4, max_batch=8, graph=True, capacity=cap,
+    srv = serve.Server(bz=args.bz, hbm_budget=200e9, slots=args.slots, max_batch=args.max_batch, graph=True, capacity=cap,
                        schedule=schedule)
     srv.warm()
     rng = np.random.default_rng(3)
