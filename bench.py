@@ -54,8 +54,9 @@ WORKLOADS = {
                "per-frame decodes",
     "coded": "the 64 batched frames entropy-coded (39 byte planes per frame, static 12-bit models, 64 "
              "interleaved rANS streams per 32768-symbol chunk; coded on the GPU before the timed steps); a "
-             "step is one tmd_decode_rans call: the entropy decoding of every frame, then the graph plan's "
-             "decode of all frames; compared with the same plan decoding the uncoded frames",
+             "step is one tmd_decode_rans call on the batched plan: the entropy decoding of every frame's track "
+             "and attached arrays, the decode of all frames, and beside it the unattached arrays decoded into "
+             "the output; compared with the same plan decoding the uncoded frames",
     "frame": "one Pb-Pb-like time frame: 100 collisions x 2000 tracks, 36 sectors, 152 rows, "
              "track lengths U{5..152}, 10% sector crossers, 40% unattached; plain single launch",
     "stress": "high-occupancy stress frame: 500 collisions x 2000 tracks, 15% low-pT loopers, "

@@ -158,3 +158,30 @@ def test_coded_unattached_long_bins(tmd, mode):
             for i, f in enumerate(frames):
                 check(tmd, *oracle.decode(f), outs[i], plan.status(i), (mode, flags, rep, i))
         plan.free()
+
+
+def test_coded_and_plain_calls_alternate_on_one_graph_plan(tmd):
+    """A graph plan decodes uncoded frames (its captured graph, k_unattached
+    doing the unattached clusters) and coded ones (the entropy decoding
+    placing them) in turn; every call equals the oracle."""
+    import torch
+    frames = [synth.make_frame(synth.spec_for("frame", collisions=2)), _long_bins(34, "over")]
+    shapes = [tmd.frame_shape(f) for f in frames]
+    devs = [tmd.to_device(f) for f in frames]
+    coded = [torch.from_numpy(oracle.rans_encode(f)).cuda() for f in frames]
+    expected = [oracle.decode(f) for f in frames]
+    plan = tmd.Plan(shapes, flags=tmd.PLAN_GRAPH)
+    ws = plan.alloc_workspace()
+    rws = torch.empty(plan.rans_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    outs = [tmd.alloc_out(s) for s in shapes]
+    for rep, kind in enumerate(("plain", "coded", "plain", "coded")):
+        for o in outs:
+            o["time"].fill_(-1)
+        if kind == "plain":
+            plan.decode(devs, outs, ws)
+        else:
+            plan.decode_rans(coded, outs, ws, rws)
+        torch.cuda.synchronize()
+        for i in range(len(frames)):
+            check(tmd, *expected[i], outs[i], plan.status(i), (rep, kind, i))
+    plan.free()
