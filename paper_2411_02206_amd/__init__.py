@@ -197,8 +197,9 @@ class Plan:
 
     def decode_rans(self, coded, outs, workspace, rans_workspace, stream=None, shapes=None):
         """Entropy-decode the coded frames (device uint8 tensors in the format
-        of include/tmd.h) into rans_workspace and decode them
-        (tmd_decode_rans)."""
+        of include/tmd.h) and decode them (tmd_decode_rans): the track and
+        attached arrays go through rans_workspace, the unattached ones
+        straight into the outputs."""
         torch = _torch()
         n = len(self.shapes)
         shapes = shapes or self.shapes
