@@ -3622,7 +3622,11 @@ int tmd_decode(tmd_plan_t *P, const tmd_frame_in *in, tmd_frame_out *out, void *
 
 namespace {
 int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
-                void *workspace, void *stream, const uint32_t *const *pre_status, const SideWork *side = nullptr);
+                void *workspace, void *stream);
+int decode_descs(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
+                 void *workspace, const uint32_t *const *pre_status, bool un_fused,
+                 std::vector<FrameDescHost> &desc);
+int decode_enqueue(tmd_plan_t *P, const std::vector<FrameDescHost> &desc, void *stream, const SideWork *side);
 }  // namespace
 
 extern "C" {
@@ -3630,23 +3634,23 @@ extern "C" {
 int tmd_decode_shapes(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
                       void *workspace, void *stream)
 {
-    return decode_impl(P, shapes, in, out, workspace, stream, nullptr);
+    return decode_impl(P, shapes, in, out, workspace, stream);
 }
 
 }  // extern "C"
 
 namespace {
 
-// tmd_decode_shapes, with an optional device word per frame that the frame's
-// status starts from (flags of a step before the decode).  With `side`, the
-// unattached clusters are not decoded by the sequence: side decodes them on
-// the plan's second stream once the offsets are known (launch_all; the
-// kernels are then launched one by one, also for a graph plan), and the
-// unattached input arrays may be null.
-int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
-                void *workspace, void *stream, const uint32_t *const *pre_status, const SideWork *side)
+// The argument checks of a decode call (nothing is enqueued) and its frame
+// descriptors.  pre_status: an optional device word per frame that the
+// frame's status starts from (flags of a step before the decode).  un_fused:
+// the unattached clusters are decoded elsewhere (their input arrays may be
+// null).
+int decode_descs(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
+                 void *workspace, const uint32_t *const *pre_status, bool un_fused,
+                 std::vector<FrameDescHost> &desc)
 {
-    const bool post = side != nullptr;  // (the unattached clusters: by side)
+    const bool post = un_fused;
     if (!P || !shapes || !in || !out || !workspace) return TMD_E_ARG;
     if ((uintptr_t)workspace % 256) return TMD_E_ARG;
     for (uint32_t f = 0; f < P->n_frames; f++) {
@@ -3654,8 +3658,7 @@ int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in
         if (S.n_tracks > C.n_tracks || S.n_attached > C.n_attached || S.n_unattached > C.n_unattached)
             return TMD_E_ARG;
     }
-    hipStream_t s = (hipStream_t)stream;
-    std::vector<FrameDescHost> desc(P->n_frames);
+    desc.assign(P->n_frames, FrameDescHost{});
     for (uint32_t f = 0; f < P->n_frames; f++) {
         const tmd_frame_shape &S = shapes[f];
         const tmd_frame_in &I = in[f];
@@ -3711,6 +3714,17 @@ int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in
         D.awaves = attached_waves(S.n_tracks, P->n_frames == 1, P->simds, P->tracks_per_wave);
         D.un_fused = post ? 1u : 0u;
     }
+    return TMD_OK;
+}
+
+// Enqueue a decode whose descriptors decode_descs built.  With `side`, the
+// unattached clusters are not decoded by the sequence: side decodes them on
+// the plan's second stream once the offsets are known (launch_all; the
+// kernels are then launched one by one, also for a graph plan).
+int decode_enqueue(tmd_plan_t *P, const std::vector<FrameDescHost> &desc, void *stream, const SideWork *side)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const bool post = side != nullptr;
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
     if (cur != P->device) HIP_TRY(hipSetDevice(P->device));
@@ -3784,6 +3798,15 @@ int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in
     } while (0);
     if (cur != P->device) (void)hipSetDevice(cur);
     return rc;
+}
+
+// tmd_decode_shapes: check, then enqueue
+int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
+                void *workspace, void *stream)
+{
+    std::vector<FrameDescHost> desc;
+    if (const int rc = decode_descs(P, shapes, in, out, workspace, nullptr, false, desc)) return rc;
+    return decode_enqueue(P, desc, stream, nullptr);
 }
 
 }  // namespace
@@ -4204,6 +4227,12 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
         pre[f] = (const uint32_t *)(ws + H.err) + f;
         fws += rans_frame_bytes(S);
     }
+    // the decode's arguments are checked before anything is enqueued
+    std::vector<FrameDescHost> fdesc;
+    if (const int rc = decode_descs(P, shapes, in.data(), out, workspace, pre.data(), true, fdesc)) {
+        if (cur != P->device) (void)hipSetDevice(cur);
+        return rc;
+    }
     // The kernels of one phase of the entropy decoding on stream q (phase 0
     // with the tables' set-up), between a pair of events if its stage is
     // profiled.
@@ -4278,7 +4307,7 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
     // once the offsets are known, on the plan's second stream beside the rank
     // and attached kernels: the unattached arrays into their output slots
     const SideWork side = [&](hipStream_t q) { return launch_phase(1, q); };
-    return decode_impl(P, shapes, in.data(), out, workspace, stream, pre.data(), &side);
+    return decode_enqueue(P, fdesc, stream, &side);
 }
 
 }  // extern "C"

@@ -185,3 +185,25 @@ def test_coded_and_plain_calls_alternate_on_one_graph_plan(tmd):
         for i in range(len(frames)):
             check(tmd, *expected[i], outs[i], plan.status(i), (rep, kind, i))
     plan.free()
+
+
+def test_rejected_call_enqueues_nothing(tmd):
+    """A tmd_decode_rans call whose output is too small is rejected before any
+    of its work is enqueued; the next valid call decodes as the oracle does."""
+    import torch
+    from paper_2411_02206_amd import _lib
+    fr = synth.make_frame(synth.spec_for("tiny"))
+    shape = tmd.frame_shape(fr)
+    coded = [torch.from_numpy(oracle.rans_encode(fr)).cuda()]
+    plan = tmd.Plan([shape])
+    ws = plan.alloc_workspace()
+    rws = torch.empty(plan.rans_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    small = tmd.alloc_out(shape, capacity=shape[1] + shape[2] - 1)
+    with pytest.raises(_lib.TmdError) as err:
+        plan.decode_rans(coded, [small], ws, rws)
+    assert err.value.code == _lib.E_CAPACITY
+    out = tmd.alloc_out(shape)
+    plan.decode_rans(coded, [out], ws, rws)
+    torch.cuda.synchronize()
+    check(tmd, *oracle.decode(fr), out, plan.status(0), "after a rejected call")
+    plan.free()
