@@ -381,16 +381,26 @@ int tmd_encode(tmd_plan_t *plan, const tmd_enc_in *in, tmd_enc_out *out, void *w
  * here is this project's:
  *   - the 19 arrays of tmd_frame_in, in that order, as 39 byte planes (plane
  *     p of an array of w-byte little-endian elements holds byte p of each);
- *   - per plane a static model: frequencies f[0..255] summing to 2^12;
- *   - the plane's symbols in chunks of 32768, symbol i of a chunk in
- *     interleaved stream i mod 64; each stream is rANS with a 32-bit state in
- *     [2^23, 2^31), byte-wise renormalisation, its final state first (4 bytes,
- *     little endian), then its renormalisation bytes in reading order.
- * Bytes (little endian): a 64-byte header ("TMDR", version 1, n_tracks,
- * n_attached, n_unattached, 0), the u64 offset of each of the 39 planes, then
- * the planes, each on an 8-byte boundary: f[256] as u16, for each chunk the
- * u32 offsets of its 64 streams and the end of the last (from the start of
- * the plane's data), then the data.
+ *   - per plane a static model: frequencies f[0..255] summing to 2^12 (c_s:
+ *     the sum of the frequencies below symbol s);
+ *   - the plane's symbols in chunks of 64 lanes x 512 steps: symbol i of a
+ *     chunk is step i / 64 of lane i % 64;
+ *   - each lane is an rANS coder with a 32-bit state x in [2^16, 2^32) that
+ *     is renormalised by 16-bit words, at most one per symbol, and the 64
+ *     lanes of a chunk read one shared word stream.  Decoding: every lane's x
+ *     starts at its stored state; step by step, and within a step lane by
+ *     lane in ascending order, a lane with a symbol there takes the s whose
+ *     [c_s, c_s + f_s) holds x % 2^12, sets x = f_s (x >> 12) + x % 2^12 - c_s,
+ *     and, if x < 2^16, x = (x << 16) | the next word.  A chunk is well formed
+ *     if at its end every x is 2^16 and every word has been read.
+ * Bytes (little endian): a 64-byte header ("TMDR", version 2, n_tracks,
+ * n_attached, n_unattached, 0, then zeros), the u64 offset of each of the 39
+ * planes from the start, then the planes, each on a 16-byte boundary: f[256]
+ * as u16, then ceil(n / 32768) + 1 u32 offsets of each chunk's data and of
+ * the end of the last chunk (multiples of 16, from the start of the plane's
+ * data, which is the next 16-byte boundary), then the chunks: the 64 lanes'
+ * states (u32) and the word stream (u16), zero-padded to a multiple of 16
+ * bytes.
  *
  * tmd_rans_workspace: bytes of the area where tmd_decode_rans puts the
  * decoded arrays of n_frames frames of these shapes (all but the unattached
@@ -427,8 +437,12 @@ int tmd_decode_rans(tmd_plan_t *plan, const tmd_frame_shape *shapes, const uint8
  * max(1, floor(count 2^12 / n)); while their sum is below 2^12 the symbol
  * with the smallest f n - count 2^12 gets one more, while it is above the
  * symbol with f > 1 and the largest f n - count 2^12 one less (ties: the
- * lowest symbol); a plane without symbols has f[0] = 2^12.  The bytes are
- * those of the format above, alignment gaps zero.
+ * lowest symbol); a plane without symbols has f[0] = 2^12.  A chunk is
+ * coded in the reverse order of its decoding (last step first, lanes
+ * descending, every x starting at 2^16): before coding s a lane emits
+ * x % 2^16 and shifts x right by 16 if x >= 2^20 f_s, then sets
+ * x = (x / f_s) 2^12 + x % f_s + c_s; the stream is the emitted words in
+ * reverse.  The bytes are those of the format above, alignment gaps zero.
  * Errors: TMD_E_ARG (null or misaligned pointer, an array of more than 2^30
  * elements), TMD_E_CAPACITY (capacity below the bound), TMD_E_HIP.
  */
