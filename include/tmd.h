@@ -208,8 +208,8 @@ int tmd_decode_shapes(tmd_plan_t *plan, const tmd_frame_shape *shapes, const tmd
  *
  * Flags of frame `frame` from the last tmd_decode on this plan; waits for that
  * decode to finish.  Returns TMD_OK if no flag is set, TMD_E_INPUT if
- * TMD_F_COUNT or TMD_F_CODED is set, TMD_E_STREAM if another flag is set, TMD_E_ARG for a bad
- * frame index; *flags receives the bits.
+ * TMD_F_COUNT or TMD_F_CODED is set, TMD_E_STREAM if another flag is set,
+ * TMD_E_ARG for a bad frame index; *flags receives the bits.
  */
 int tmd_status(tmd_plan_t *plan, uint32_t frame, uint32_t *flags);
 
