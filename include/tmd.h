@@ -411,8 +411,9 @@ int tmd_encode(tmd_plan_t *plan, const tmd_enc_in *in, tmd_enc_out *out, void *w
  * track and attached-cluster arrays are entropy-decoded into rans_workspace
  * and then decoded; the unattached clusters' arrays are entropy-decoded
  * straight into the output (their running sums and slots) once the output
- * offsets are known, on a second stream of the plan that runs beside the
- * attached decode and that `stream` waits for.  The decode's kernels are
+ * offsets are known.  Part of the work runs on a second stream of the plan
+ * (the 4-byte arrays beside the others, the unattached ones beside the
+ * attached decode), which `stream` waits for.  The decode's kernels are
  * launched one by one, also for a TMD_PLAN_GRAPH plan.  A frame whose coded
  * data is malformed gets TMD_F_CODED in its status (tmd_status); its
  * malformed chunks count as zeros.

@@ -755,6 +755,10 @@ __global__ __launch_bounds__(kOffThreads) void k_offsets(const FrameDesc *__rest
         us += cnt[i];
     }
     if (threadIdx.x == 0 && (all != F.nU || (F.nT == 0 && F.nA != 0))) atomicOr(F.status, TMD_F_COUNT);
+    // flags of a step before the decode that may have ended after k_tilesum
+    // took the frame's starting flags (entropy decoding beside the first
+    // kernels)
+    if (threadIdx.x == 0 && F.pre_status) atomicOr(F.status, *F.pre_status);
 
     uint32_t inc32 = wave_incl_add(ownout);
     if (lane == kWave - 1) part32[w] = inc32;
@@ -3158,7 +3162,7 @@ struct tmd_plan {
     // tmd_decode_rans: the stream on which part of its entropy decoding runs
     // beside the track-model decode, and the events that order the two
     hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t fork[2] = {}, join[2] = {};  // [0]: work before k_offsets, [1]: after
     // TMD_PLAN_GRAPH with profiling: a second graph with an event-record node
     // before and after each selected stage; each replay points those nodes
     // at fresh events from the pool
@@ -3248,18 +3252,20 @@ int take_events(tmd_plan_t *P, uint32_t mask, std::vector<hipEvent_t> &ev)
 using SideWork = std::function<int(hipStream_t)>;
 
 // Enqueue side on the plan's second stream after what s holds so far, and
-// record the plan's join event after it.
-int fork_side(tmd_plan_t *P, hipStream_t s, const SideWork &side)
+// record the plan's join event k after it.
+int fork_side(tmd_plan_t *P, hipStream_t s, const SideWork &side, int k)
 {
     if (!P->side) {
         HIP_TRY(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
-        HIP_TRY(hipEventCreateWithFlags(&P->fork, hipEventDisableTiming));
-        HIP_TRY(hipEventCreateWithFlags(&P->join, hipEventDisableTiming));
+        for (int e = 0; e < 2; e++) {
+            HIP_TRY(hipEventCreateWithFlags(&P->fork[e], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&P->join[e], hipEventDisableTiming));
+        }
     }
-    HIP_TRY(hipEventRecord(P->fork, s));
-    HIP_TRY(hipStreamWaitEvent(P->side, P->fork, 0));
+    HIP_TRY(hipEventRecord(P->fork[k], s));
+    HIP_TRY(hipStreamWaitEvent(P->side, P->fork[k], 0));
     const int rc = side(P->side);
-    HIP_TRY(hipEventRecord(P->join, P->side));  // (also after a failed launch: s must not wait forever)
+    HIP_TRY(hipEventRecord(P->join[k], P->side));  // (also after a failed launch: s must not wait forever)
     return rc;
 }
 
@@ -3267,7 +3273,10 @@ int fork_side(tmd_plan_t *P, hipStream_t s, const SideWork &side)
 // with events in `ev` (2 per stage, or empty) is bracketed by them.  With
 // `side`, once the offsets are known, side runs on the plan's second stream
 // (fork_side) and s waits for it at its end (k_unattached has nothing to do).
-int launch_all(tmd_plan_t *P, hipStream_t s, const std::vector<hipEvent_t> &ev, const SideWork *side = nullptr)
+// wait_early: work that the caller put on the second stream before (its join
+// event 0) must be done before k_offsets.
+int launch_all(tmd_plan_t *P, hipStream_t s, const std::vector<hipEvent_t> &ev, const SideWork *side = nullptr,
+               bool wait_early = false)
 {
     auto begin = [&](int st, hipStream_t q) -> int {
         return (ev.size() && ev[2 * st] && hipEventRecord(ev[2 * st], q) != hipSuccess) ? TMD_E_HIP : TMD_OK;
@@ -3285,10 +3294,12 @@ int launch_all(tmd_plan_t *P, hipStream_t s, const std::vector<hipEvent_t> &ev, 
     if (end(1, s) || begin(2, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_colscan, dim3((kHRow + kWave - 1) / kWave, P->n_frames), dim3(kWave * kScanWaves), 0,
                        s, P->d_desc);
-    if (end(2, s) || begin(3, s)) return TMD_E_HIP;
+    if (end(2, s)) return TMD_E_HIP;
+    if (wait_early) HIP_TRY(hipStreamWaitEvent(s, P->join[0], 0));
+    if (begin(3, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_offsets, dim3(P->n_frames), dim3(kOffThreads), 0, s, P->d_desc);
     if (side)
-        if (const int rc = fork_side(P, s, *side)) return rc;
+        if (const int rc = fork_side(P, s, *side, 1)) return rc;
     if (end(3, s) || begin(4, s)) return TMD_E_HIP;
     if (T) hipLaunchKernelGGL(k_rank, dim3(T), dim3(kTile), 0, s, P->d_desc, P->d_tile_frame);
     if (end(4, s)) return TMD_E_HIP;
@@ -3308,7 +3319,7 @@ int launch_all(tmd_plan_t *P, hipStream_t s, const std::vector<hipEvent_t> &ev, 
     if (end(5, s) || begin(6, s)) return TMD_E_HIP;
     hipLaunchKernelGGL(k_unattached, dim3(NBIN, P->n_frames), dim3(kWave), 0, s, P->d_desc);
     if (end(6, s)) return TMD_E_HIP;
-    if (side) HIP_TRY(hipStreamWaitEvent(s, P->join, 0));
+    if (side) HIP_TRY(hipStreamWaitEvent(s, P->join[1], 0));
     HIP_TRY(hipGetLastError());
     return TMD_OK;
 }
@@ -3498,8 +3509,10 @@ void tmd_free(tmd_plan_t *P)
     drop_prof_graph(P);
     if (P->capture) (void)hipStreamDestroy(P->capture);
     if (P->side) (void)hipStreamDestroy(P->side);
-    if (P->fork) (void)hipEventDestroy(P->fork);
-    if (P->join) (void)hipEventDestroy(P->join);
+    for (int k = 0; k < 2; k++) {
+        if (P->fork[k]) (void)hipEventDestroy(P->fork[k]);
+        if (P->join[k]) (void)hipEventDestroy(P->join[k]);
+    }
     if (P->desc_done) (void)hipEventDestroy(P->desc_done);
     if (P->done) (void)hipEventDestroy(P->done);
     if (P->d_geo) (void)hipFree(P->d_geo);
@@ -3626,7 +3639,8 @@ int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in
 int decode_descs(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in *in, tmd_frame_out *out,
                  void *workspace, const uint32_t *const *pre_status, bool un_fused,
                  std::vector<FrameDescHost> &desc);
-int decode_enqueue(tmd_plan_t *P, const std::vector<FrameDescHost> &desc, void *stream, const SideWork *side);
+int decode_enqueue(tmd_plan_t *P, const std::vector<FrameDescHost> &desc, void *stream, const SideWork *side,
+                   bool wait_early);
 }  // namespace
 
 extern "C" {
@@ -3720,8 +3734,10 @@ int decode_descs(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_i
 // Enqueue a decode whose descriptors decode_descs built.  With `side`, the
 // unattached clusters are not decoded by the sequence: side decodes them on
 // the plan's second stream once the offsets are known (launch_all; the
-// kernels are then launched one by one, also for a graph plan).
-int decode_enqueue(tmd_plan_t *P, const std::vector<FrameDescHost> &desc, void *stream, const SideWork *side)
+// kernels are then launched one by one, also for a graph plan).  wait_early:
+// see launch_all.
+int decode_enqueue(tmd_plan_t *P, const std::vector<FrameDescHost> &desc, void *stream, const SideWork *side,
+                   bool wait_early)
 {
     hipStream_t s = (hipStream_t)stream;
     const bool post = side != nullptr;
@@ -3746,7 +3762,7 @@ int decode_enqueue(tmd_plan_t *P, const std::vector<FrameDescHost> &desc, void *
             P->last_desc = desc;
             P->desc_valid = true;
         }
-        if ((P->params.flags & TMD_PLAN_GRAPH) && !post) {
+        if ((P->params.flags & TMD_PLAN_GRAPH) && !post && !wait_early) {
             // the kernels read only plan-owned buffers (descriptor table,
             // tables, tile map), so one captured graph serves every call
             if (P->profiling) {
@@ -3780,7 +3796,7 @@ int decode_enqueue(tmd_plan_t *P, const std::vector<FrameDescHost> &desc, void *
         } else {
             std::vector<hipEvent_t> ev;
             if (P->profiling && (rc = take_events(P, P->profiling, ev)) != TMD_OK) break;
-            rc = launch_all(P, s, ev, side);
+            rc = launch_all(P, s, ev, side, wait_early);
             if (rc != TMD_OK) {
                 for (hipEvent_t e : ev)
                     if (e) P->event_pool.push_back(e);
@@ -3806,7 +3822,7 @@ int decode_impl(tmd_plan_t *P, const tmd_frame_shape *shapes, const tmd_frame_in
 {
     std::vector<FrameDescHost> desc;
     if (const int rc = decode_descs(P, shapes, in, out, workspace, nullptr, false, desc)) return rc;
-    return decode_enqueue(P, desc, stream, nullptr);
+    return decode_enqueue(P, desc, stream, nullptr, false);
 }
 
 }  // namespace
@@ -4253,17 +4269,25 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
         const dim3 blk(kRansLanes * kRansWaves);
         const FrameDesc *fd = P->d_desc;
         auto items = [&](int wi) { return witem[(3 * ph + wi) * (nf + 1) + nf]; };
+        int r = TMD_OK;
         if (ph == 0) {
             hipLaunchKernelGGL(k_rans_prep, dim3(kRansPlanes * nf), dim3(256), 0, q, dd);
+            // the 4-byte arrays (track start times, bin counts: a few chunks
+            // per frame, each a long dependent chain) on the plan's second
+            // stream, beside the others; the decode waits for them before
+            // k_offsets
+            r = fork_side(P, q, [&](hipStream_t e) -> int {
+                if (const uint32_t it = items(2)) hipLaunchKernelGGL((k_rans<4, 0>), dim3(it), blk, 0, e, dd, dw, nf, fd);
+                return TMD_OK;
+            }, 0);
             if (const uint32_t it = items(0)) hipLaunchKernelGGL((k_rans<1, 0>), dim3(it), blk, 0, q, dd, dw, nf, fd);
             if (const uint32_t it = items(1)) hipLaunchKernelGGL((k_rans<2, 0>), dim3(it), blk, 0, q, dd, dw, nf, fd);
-            if (const uint32_t it = items(2)) hipLaunchKernelGGL((k_rans<4, 0>), dim3(it), blk, 0, q, dd, dw, nf, fd);
         } else {
             if (const uint32_t it = items(2)) hipLaunchKernelGGL((k_rans<4, kRansUnPhase>), dim3(it), blk, 0, q, dd, dw, nf, fd);
             if (const uint32_t it = items(1)) hipLaunchKernelGGL((k_rans<2, kRansUnPhase>), dim3(it), blk, 0, q, dd, dw, nf, fd);
             if (maxch > 1) hipLaunchKernelGGL(k_rans_unfix, dim3(maxch, 2, nf), dim3(kRansLanes), 0, q, dd, fd);
         }
-        const int r = hipGetLastError() == hipSuccess ? TMD_OK : TMD_E_HIP;
+        if (r == TMD_OK && hipGetLastError() != hipSuccess) r = TMD_E_HIP;
         if (ev.second) {
             if (r == TMD_OK && hipEventRecord(ev.second, q) == hipSuccess) {
                 P->rans_events[ph].push_back(ev);
@@ -4307,7 +4331,7 @@ int tmd_decode_rans(tmd_plan_t *P, const tmd_frame_shape *shapes, const uint8_t 
     // once the offsets are known, on the plan's second stream beside the rank
     // and attached kernels: the unattached arrays into their output slots
     const SideWork side = [&](hipStream_t q) { return launch_phase(1, q); };
-    return decode_enqueue(P, fdesc, stream, &side);
+    return decode_enqueue(P, fdesc, stream, &side, true);
 }
 
 }  // extern "C"
