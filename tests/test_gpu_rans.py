@@ -207,3 +207,25 @@ def test_rejected_call_enqueues_nothing(tmd):
     torch.cuda.synchronize()
     check(tmd, *oracle.decode(fr), out, plan.status(0), "after a rejected call")
     plan.free()
+
+
+@pytest.mark.parametrize("array", ["trk_time0", "un_count", "un_time_diff", "cls_pad_res"])
+def test_malformed_chunk_of_one_array_is_flagged(tmd, array):
+    """A chunk whose stored state is out of range, in one array only: the
+    frame is flagged whichever phase and stream decodes that array (the
+    4-byte arrays decoded beside the others, the unattached ones beside the
+    attached decode)."""
+    from test_oracle_rans import WIDTH, planes
+    fr = synth.make_frame(synth.spec_for("tiny"))
+    shape = oracle.frame_sizes(fr)
+    blob = oracle.rans_encode(fr)
+    a = [k for k, _ in oracle.RANS_ARRAYS].index(array)
+    p = sum(WIDTH[:a])  # the array's first plane
+    n, f, table, data0 = planes(blob, shape)[p]
+    assert n > 0
+    bad = blob.copy()
+    bad[data0 + int(table[0]):data0 + int(table[0]) + 4] = 0  # lane 0's state: 0 < 2^16
+    out, flags = tmd.decode_rans(bad, shape)
+    assert flags & tmd.F_CODED, (array, flags)
+    out, flags = tmd.decode_rans(blob, shape)
+    assert not flags & tmd.F_CODED
