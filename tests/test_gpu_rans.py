@@ -229,3 +229,36 @@ def test_malformed_chunk_of_one_array_is_flagged(tmd, array):
     assert flags & tmd.F_CODED, (array, flags)
     out, flags = tmd.decode_rans(blob, shape)
     assert not flags & tmd.F_CODED
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_coded_random_frames(tmd, seed):
+    """Random streams of random sizes (unattached clusters from none to
+    several chunks, bin counts spread evenly, skewed or in a few bins, and
+    adding up to n_unattached or not), entropy-coded and decoded in one
+    batched call, each frame against the oracle."""
+    import torch
+    rng = np.random.default_rng(100 + seed)
+    frames = []
+    for i in range(3):
+        nt = int(rng.integers(0, 600))
+        na = int(rng.integers(0, 40000))
+        w = rng.random(NBIN) ** float(rng.choice([1.0, 4.0, 16.0]))
+        total = int(rng.choice([0, 5, 20000, 90000]))
+        cnt = np.floor(w / w.sum() * total).astype(np.int64) if total else np.zeros(NBIN, np.int64)
+        nu = int(cnt.sum()) + int(rng.choice([0, 0, 7, -3])) if total else 0
+        fr = _garbage(200 + 10 * seed + i, nt=nt, na=na, nu=max(nu, 0))
+        fr["un_count"] = cnt.astype(np.uint32)
+        frames.append(fr)
+    shapes = [tmd.frame_shape(f) for f in frames]
+    coded = [torch.from_numpy(oracle.rans_encode(f)).cuda() for f in frames]
+    print(f"random coded frames, seed {seed}: {shapes}", flush=True)
+    plan = tmd.Plan(shapes, flags=tmd.PLAN_GRAPH if seed % 2 else 0, bz=5.0 if seed % 3 == 0 else 0.5)
+    ws = plan.alloc_workspace()
+    rws = torch.empty(plan.rans_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    outs = [tmd.alloc_out(s) for s in shapes]
+    plan.decode_rans(coded, outs, ws, rws)
+    torch.cuda.synchronize()
+    for i, f in enumerate(frames):
+        check(tmd, *oracle.decode(f, bz=5.0 if seed % 3 == 0 else 0.5), outs[i], plan.status(i), (seed, i))
+    plan.free()
