@@ -13,8 +13,9 @@ tmd_encode_rans; a step decodes the coded bytes and then the frames, one
 tmd_decode_rans call), `frame` (one frame of 100 collisions, plain single launch),
 `stress` (500 collisions with loopers, plain launch), `stress-batched` (the
 stress frame through a graph plan), `tiny`, `served` (Poisson arrivals,
-continuous batching, p50/p99 at several offered loads) and `pipeline` (frames
-in host memory, PCIe-inclusive).
+continuous batching, p50/p99 at several offered loads), `pipeline` (frames
+in host memory, PCIe-inclusive) and `encode` (the track-model encoder on one
+frame's physical clusters; its roofline entry covers the whole call).
 
 Prints one JSON line.  `roofline` reports the dominant kernel's algorithmic
 HBM bytes per launch (attached kernel: 10 B in + 10 B out per attached
@@ -66,6 +67,10 @@ WORKLOADS = {
     "tiny": "tiny plain decode: 1 sector, 1000 tracks of 20..152 clusters, 20000 unattached",
     "served": "Poisson arrivals of frames from the batched mix at 25/50/75/100% of the batched peak; "
               "continuous batching under a 200 GB HBM budget; p50/p99 latency",
+    "encode": "track-model encoding of one frame's physical clusters (the frame workload's shape: 100 "
+              "collisions x 2000 tracks, 40% unattached; exact circles with Gaussian noise, pads and times as "
+              "doubles) resident in HBM: quantisation, float32 model, residuals, header compaction, and the "
+              "unattached clusters sorted per bin and delta-coded; one tmd_encode call per step",
     "pipeline": "the frame workload held in page-locked host memory, decoded through the native pipeline "
                 "(one upload stream, a decode stream per slot, one download stream, ordered by events), "
                 "3 slots against 1 (no overlap), and the same frame entropy-coded (coded bytes uploaded, "
@@ -77,6 +82,18 @@ def algorithmic_bytes(nT, nA, nU):
     att = nA * (CLUSTER_IN_BYTES + CLUSTER_OUT_BYTES) + nT * HDR_BYTES
     una = nU * (UNATT_IN_BYTES + CLUSTER_OUT_BYTES)
     return att, una, att + una + 5472 * BIN_BYTES
+
+
+ENC_TRACK_IN = 4 + 8 + 8        # trk_first, q/pT, tan lambda
+ENC_CLUSTER_IN = 1 + 1 + 8 + 8 + 8 + 2 + 2   # sector, row, pad, time, sin phi, charges
+ENC_UNATT_IN = 1 + 1 + 8 + 8 + 2 + 2         # sector, row, pad, time, charges
+
+
+def encode_bytes(nT, nA, nU, nH):
+    """Bytes an encode must move at least: its input (per track, attached and
+    unattached cluster) and the compressed frame it writes (nH headers)."""
+    return (ENC_TRACK_IN * nT + ENC_CLUSTER_IN * nA + ENC_UNATT_IN * nU
+            + HDR_BYTES * nH + CLUSTER_IN_BYTES * nA + UNATT_IN_BYTES * nU + 4 * 5472)
 
 
 def kernel_bytes(shapes):
@@ -223,6 +240,12 @@ def roofline(kernel, nbytes, avg_ms, workload, frames=64):
         ks = [v for k, v in (summ["kernels"].items() if summ else [])
               if k in ("k_rans_prep", "k_rans<1, 0>", "k_rans<2, 0>", "k_rans<4, 0>")]
         traffic = sum(v["traffic_bytes"] for v in ks) if ks else None
+    elif kernel == "encode":  # every kernel of one tmd_encode call, the sort's twelve passes included
+        label = "tmd_encode (all kernels)"
+        ks = summ["kernels"] if summ else {}
+        per_call = ks.get("k_enc_tracks", {}).get("dispatches")
+        traffic = sum(v["traffic_bytes"] * v["dispatches"] / per_call for k, v in ks.items()
+                      if k.startswith(("k_enc", "k_rad"))) if per_call else None
     else:
         label = f"k_{kernel}"
         kt = summ["kernels"].get(label) if summ else None
@@ -291,6 +314,8 @@ def main():
         sys.exit(2)
     if args.workload == "pipeline":
         return run_pipeline(args)
+    if args.workload == "encode":
+        return run_encode(args)
     if args.workload in ("batched", "served", "stress-batched", "coded"):
         return run_batched(args)
     return run_plain(args)
@@ -681,6 +706,82 @@ def run_served(args, ins, shapes, peak_fps, schedule=None):
               file=sys.stderr, flush=True)
     srv.close()
     return loads
+
+
+def run_encode(args):
+    """tmd_encode of one frame's physical clusters, resident in HBM; a step is
+    one call.  The oracle's encoder on the same clusters is the CPU baseline
+    and the bit-exact check."""
+    import synth
+    t = time.perf_counter()
+    phys = synth.make_phys(synth.spec_for("frame"), workers=args.gen_workers)   # before any GPU use
+    nT, nA, nU = synth.phys_sizes(phys)
+    print(f"[bench] encode: {nT} tracks, {nA} attached, {nU} unattached (generated in "
+          f"{time.perf_counter() - t:.1f} s)", file=sys.stderr, flush=True)
+    exp = cpu = None
+    if not args.no_cpu:
+        import oracle
+        t_start, dt, runs = time.perf_counter(), 0.0, 0
+        while runs == 0 or time.perf_counter() - t_start < args.cpu_seconds:
+            t0 = time.perf_counter()
+            exp = oracle.encode(phys, bz=args.bz)
+            dt += time.perf_counter() - t0
+            runs += 1
+        rate = (nA + nU) * runs / dt
+        cpu = {"value": rate, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+               "sample": f"the frame's {nA + nU} clusters encoded {runs} times by the single-threaded C "
+                         f"oracle encoder ({dt:.1f} s)", "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+        print(f"[bench] oracle encoder, one core: {rate:.3e} clusters/s", file=sys.stderr, flush=True)
+    import numpy as np
+    import torch
+
+    import paper_2411_02206_amd as tmd
+
+    dev = tmd.enc_to_device(phys)
+    del phys
+    out = tmd.alloc_enc_out(nT, nA, nU)
+    ws = torch.empty(max(tmd.enc_workspace_bytes(nT, nA, nU), 256), dtype=torch.uint8, device="cuda")
+    plan = tmd.Plan([(1, 1, 1)], bz=args.bz)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        tmd.encode_device(plan, dev, out, ws, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(stream)
+        tmd.encode_device(plan, dev, out, ws, stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    call_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = (nA + nU) * args.steps / elapsed
+    got, split = tmd.enc_result(out, nA, nU)
+    nH = int(got["trk_ncls"].shape[0])
+    print(f"[bench] encode: {ms_per_step:.3f} ms/step, {value:.3e} clusters/s, {nH} headers ({split} opened "
+          f"inside a track)", file=sys.stderr, flush=True)
+    bitexact = None
+    if exp is not None:
+        ef, esplit = exp
+        bitexact = bool(all(np.array_equal(ef[k], got[k]) for k in ef) and esplit == split)
+    nbytes = encode_bytes(nT, nA, nU, nH)
+    roof = add_copy_frac(roofline("encode", nbytes, float(call_ms.mean()), "encode"), copy_bandwidth())
+    line = {
+        "metric": "encoded TPC clusters/s on 1 MI355X (bit-exact)", "value": value, "unit": "clusters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"encode: {WORKLOADS['encode']}", "n_tracks": nT, "n_attached": nA,
+                   "n_unattached": nU, "bz_tesla": args.bz},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "bitexact_vs_oracle": bitexact,
+        "headers": nH, "headers_opened_inside_a_track": split,
+        "latency_ms": {"p50": round(float(np.percentile(call_ms, 50)), 4),
+                       "p99": round(float(np.percentile(call_ms, 99)), 4)},
+    }
+    plan.free()
+    print(json.dumps(line), flush=True)
 
 
 def run_pipeline(args):

@@ -264,14 +264,10 @@ ENC_DTYPES = {"trk_first": np.uint32, "trk_qpt": np.float64, "trk_tgl": np.float
               "un_pad": np.float64, "un_time": np.float64, "un_qtot": np.uint16, "un_qmax": np.uint16}
 
 
-def encode(phys, bz=0.5, device="cuda", stream=None, plan=None):
-    """Encode physical clusters (dict of arrays, keys as ENC_DTYPES: tracks
-    by trk_first ranges, pads and times as doubles) on the GPU into a
-    compressed frame (tmd_encode).  Returns (frame dict of numpy arrays, number
-    of headers opened inside a track).  Raises TmdError on an input outside
-    the codable range."""
+def enc_to_device(phys, device="cuda"):
+    """Physical clusters (dict keyed as ENC_DTYPES) -> device tensors (the
+    input of encode_device)."""
     torch = _torch()
-    L = _lib.lib()
     dev = {}
     for k, dt in ENC_DTYPES.items():
         a = np.ascontiguousarray(phys[k], dtype=dt)
@@ -279,35 +275,58 @@ def encode(phys, bz=0.5, device="cuda", stream=None, plan=None):
             dev[k] = torch.from_numpy(a).to(device)
         else:
             dev[k] = torch.from_numpy(a.view(_SIGNED[a.dtype])).to(device)
-    nt = int(dev["trk_qpt"].numel())
-    n = int(dev["cl_pad"].numel())
-    nu = int(dev["un_pad"].numel())
-    ein = _lib.EncIn(nt, n, nu)
-    for k in _lib.ENC_IN_TRACK + _lib.ENC_IN_CLUSTER + _lib.ENC_IN_UNATT:
-        setattr(ein, k, _ptr(dev[k]))
+    return dev
+
+
+def enc_shape(dev):
+    """(tracks, attached clusters, unattached clusters) of device or host
+    physical clusters."""
+    return (int(dev["trk_qpt"].shape[0]), int(dev["cl_pad"].shape[0]), int(dev["un_pad"].shape[0]))
+
+
+def alloc_enc_out(nt, n, nu, device="cuda"):
+    """Device arrays of the compressed frame tmd_encode writes (header arrays
+    sized for one header per cluster at most) and its 3 count words
+    ("counts")."""
+    torch = _torch()
     sizes = {"trk": max(n, 1), "cls": max(n, 1), "un": max(nu, 1)}
     out = {}
     for k in IN_FIELDS:
         dt = _SIGNED[np.dtype(IN_DTYPES[k])]
         cnt = NBIN if k == "un_count" else sizes[k.split("_")[0]]
         out[k] = torch.empty(cnt, dtype=getattr(torch, np.dtype(dt).name), device=device)
-    counts = torch.zeros(4, dtype=torch.int32, device=device)
+    out["counts"] = torch.zeros(4, dtype=torch.int32, device=device)
+    return out
+
+
+def enc_workspace_bytes(nt, n, nu):
+    wsb = C.c_size_t()
+    _lib.check(_lib.lib().tmd_encode_workspace(nt, n, nu, C.byref(wsb)), "tmd_encode_workspace")
+    return int(wsb.value)
+
+
+def encode_device(plan, dev, out, ws, stream):
+    """Enqueue tmd_encode of device physical clusters `dev` (enc_to_device)
+    into `out` (alloc_enc_out) with the caller's workspace tensor `ws` on
+    `stream`; no synchronisation."""
+    L = _lib.lib()
+    nt, n, nu = enc_shape(dev)
+    ein = _lib.EncIn(nt, n, nu)
+    for k in _lib.ENC_IN_TRACK + _lib.ENC_IN_CLUSTER + _lib.ENC_IN_UNATT:
+        setattr(ein, k, _ptr(dev[k]))
     eout = _lib.EncOut()
     for k in IN_FIELDS:
         setattr(eout, k, _ptr(out[k]))
-    eout.counts = _ptr(counts)
-    wsb = C.c_size_t()
-    _lib.check(L.tmd_encode_workspace(nt, n, nu, C.byref(wsb)), "tmd_encode_workspace")
-    ws = torch.empty(max(int(wsb.value), 256), dtype=torch.uint8, device=device)
-    own = plan is None
-    if own:
-        plan = Plan([(1, 1, 1)], bz=bz)
-    if stream is None:
-        stream = torch.cuda.current_stream()
-    _lib.check(L.tmd_encode(plan._h, C.byref(ein), C.byref(eout), _ptr(ws), int(wsb.value),
+    eout.counts = _ptr(out["counts"])
+    _lib.check(L.tmd_encode(plan._h, C.byref(ein), C.byref(eout), _ptr(ws), int(ws.numel()),
                             C.c_void_p(stream.cuda_stream)), "tmd_encode")
-    stream.synchronize()
-    c = counts.cpu().numpy().view(np.uint32)
+
+
+def enc_result(out, n, nu):
+    """The compressed frame written by encode_device as numpy arrays, cut to
+    the header count, and the number of headers opened inside a track.
+    Raises TmdError if the input was outside the codable range."""
+    c = out["counts"].cpu().numpy().view(np.uint32)
     if c[2]:
         raise TmdError(E_INPUT, "tmd_encode: input outside the codable range")
     res = {}
@@ -320,9 +339,32 @@ def encode(phys, bz=0.5, device="cuda", stream=None, plan=None):
         elif k != "un_count":
             a = a[:nu]
         res[k] = a.copy()
-    if own:
-        plan.free()
     return res, int(c[1])
+
+
+def encode(phys, bz=0.5, device="cuda", stream=None, plan=None):
+    """Encode physical clusters (dict of arrays, keys as ENC_DTYPES: tracks
+    by trk_first ranges, pads and times as doubles) on the GPU into a
+    compressed frame (tmd_encode).  Returns (frame dict of numpy arrays, number
+    of headers opened inside a track).  Raises TmdError on an input outside
+    the codable range."""
+    torch = _torch()
+    dev = enc_to_device(phys, device)
+    nt, n, nu = enc_shape(dev)
+    out = alloc_enc_out(nt, n, nu, device)
+    ws = torch.empty(max(enc_workspace_bytes(nt, n, nu), 256), dtype=torch.uint8, device=device)
+    own = plan is None
+    if own:
+        plan = Plan([(1, 1, 1)], bz=bz)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    try:
+        encode_device(plan, dev, out, ws, stream)
+        stream.synchronize()
+        return enc_result(out, n, nu)
+    finally:
+        if own:
+            plan.free()
 
 
 def decode_rans(coded, shape, bz=0.5, device="cuda"):

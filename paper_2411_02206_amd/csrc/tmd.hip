@@ -1789,7 +1789,8 @@ struct EncDesc {
     GLB uint32_t *bsum;  // [ceil(n / 1024) + 1] headers per block of clusters, then their prefix
     GLB unsigned long long *k0, *k1;  // [nU] sort keys (ping-pong)
     GLB uint32_t *v0, *v1;            // [nU] sort payloads (qTot << 16 | qMax)
-    GLB uint32_t *rhist;              // [256 * rblocks] radix histograms, then offsets
+    GLB uint32_t *rhist;              // [256 * rblocks + 256] radix histograms, digit-major (digit d of
+                                      // tile b at d * rblocks + b), then offsets; the digit totals last
     uint32_t rblocks;
 };
 
@@ -1891,7 +1892,9 @@ __global__ __launch_bounds__(256) void k_enc_tracks(const EncDesc E, const Geo *
     const int16_t qptq = enc_q16(E.qpt[it], 1024.0), tglq = enc_q16(E.tgl[it], 4096.0);
     uint32_t hdr = a, hcount = 0, splits = 0, err = 0;
     EncState st = {};
+    uint32_t prow = 0, psec = 0;  // the previous cluster's row and sector
     for (uint32_t c = a; c < e; c++) {
+        const uint32_t crow = E.row[c], csec = E.sec[c];
         const double pq = __builtin_rint(E.pad[c] * 32.0), tq = __builtin_rint(E.time[c] * 32.0);
         if (!(pq >= 0.0 && pq <= 65535.0 && tq >= 0.0 && tq < (double)kTimeLim)) {
             err = 1;
@@ -1901,21 +1904,21 @@ __global__ __launch_bounds__(256) void k_enc_tracks(const EncDesc E, const Geo *
         bool open_new = c == a;
         int32_t rd = 0, sd = 0, pr = 0, tr = 0;
         if (!open_new) {
-            const int drow = (int)E.row[c] - (int)E.row[c - 1];
-            const bool same_side = (E.sec[c] / 18) == (E.sec[c - 1] / 18);
+            const int drow = (int)crow - (int)prow;
+            const bool same_side = (csec / 18) == (psec / 18);
             if (drow < -128 || drow > 127 || !same_side || hcount == 255) {
                 open_new = true;
             } else {
                 rd = drow;
-                sd = ((int)(E.sec[c] % 18) - (int)(E.sec[c - 1] % 18) + 18) % 18;
+                sd = ((int)(csec % 18) - (int)(psec % 18) + 18) % 18;
                 EncState trial = st;
                 uint32_t fl = 0;
                 int32_t P, T;
                 enc_predict(g, trial, (uint32_t)sd, rd, P, T, fl);
                 const int64_t p64 = (int64_t)padq - P;
                 const int64_t t64 = (int64_t)timeq - trial.t0 - T;
-                if (fl || p64 < -32768 || p64 > 32767 || t64 < -32768 || t64 > 32767 || trial.sec != (int)E.sec[c] ||
-                    trial.row != (int)E.row[c]) {
+                if (fl || p64 < -32768 || p64 > 32767 || t64 < -32768 || t64 > 32767 || trial.sec != (int)csec ||
+                    trial.row != (int)crow) {
                     open_new = true;
                 } else {
                     pr = (int32_t)p64;
@@ -1935,7 +1938,7 @@ __global__ __launch_bounds__(256) void k_enc_tracks(const EncDesc E, const Geo *
             hcount = 1;
             E.htrk[c] = it;
             uint32_t fl = 0;
-            enc_init(g, st, E.sec[c], E.row[c], (uint32_t)padq, (uint32_t)timeq, qptq, enc_q16(E.snp[c], 32768.0),
+            enc_init(g, st, (int)csec, (int)crow, (uint32_t)padq, (uint32_t)timeq, qptq, enc_q16(E.snp[c], 32768.0),
                      tglq, fl);
             rd = sd = pr = tr = 0;
         } else {
@@ -1946,8 +1949,8 @@ __global__ __launch_bounds__(256) void k_enc_tracks(const EncDesc E, const Geo *
         E.sdiff[c] = (uint8_t)sd;
         E.pres[c] = (int16_t)pr;
         E.tres[c] = (int16_t)tr;
-        E.cqtot[c] = E.qtot[c];
-        E.cqmax[c] = E.qmax[c];
+        prow = crow;
+        psec = csec;
     }
     if (err) {
         atomicOr(&E.counts[2], kEncErrInput);
@@ -1957,13 +1960,20 @@ __global__ __launch_bounds__(256) void k_enc_tracks(const EncDesc E, const Geo *
     if (splits) atomicAdd(&E.counts[1], splits);
 }
 
-// E2: headers per block of 1024 clusters
+// E2: headers per block of 1024 clusters; the clusters' charges are copied
+// here, in cluster order
 __global__ __launch_bounds__(256) void k_enc_scan_blocks(const EncDesc E)
 {
     const uint32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
     uint32_t h = 0;
 #pragma unroll
-    for (int q = 0; q < 4; q++) h += (c0 + q < E.n && E.hn[c0 + q] != 0) ? 1u : 0u;
+    for (int q = 0; q < 4; q++) {
+        if (c0 + q < E.n) {
+            h += E.hn[c0 + q] != 0 ? 1u : 0u;
+            E.cqtot[c0 + q] = E.qtot[c0 + q];
+            E.cqmax[c0 + q] = E.qmax[c0 + q];
+        }
+    }
     uint32_t tot;
     block_excl_add(h, &tot);
     if (threadIdx.x == 0) E.bsum[blockIdx.x] = tot;
@@ -2069,24 +2079,32 @@ __global__ __launch_bounds__(256) void k_rad_hist(const EncDesc E, const unsigne
         if (i < E.nU) atomicAdd(&cnt[rad_digit(key_pass, kin[i], vin[i], shift)], 1u);
     }
     __syncthreads();
-    E.rhist[(size_t)blockIdx.x * 256 + threadIdx.x] = cnt[threadIdx.x];
+    E.rhist[(size_t)threadIdx.x * E.rblocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// histograms -> offsets: rhist[b][d] = sum of all digits < d + digit d in blocks < b
+// one block per digit d: its counts over the tiles -> their exclusive prefix
+// (in place, 256 tiles per round); the digit's total after all histograms.
+// The scatter adds the totals of the digits below its own.
 __global__ __launch_bounds__(256) void k_rad_offsets(const EncDesc E)
 {
-    const uint32_t d = threadIdx.x;
-    uint32_t run = 0;
-    for (uint32_t b = 0; b < E.rblocks; b++) {
-        const uint32_t v = E.rhist[(size_t)b * 256 + d];
-        E.rhist[(size_t)b * 256 + d] = run;
-        run += v;
+    const uint32_t d = blockIdx.x, nb = E.rblocks;
+    GLB uint32_t *col = E.rhist + (size_t)d * nb;
+    uint32_t base = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += 256) {
+        const uint32_t b = b0 + threadIdx.x;
+        const uint32_t v = b < nb ? col[b] : 0u;
+        uint32_t all;
+        const uint32_t ex = block_excl_add(v, &all);
+        if (b < nb) col[b] = base + ex;
+        base += all;
     }
-    uint32_t all;
-    const uint32_t before = block_excl_add(run, &all);
-    for (uint32_t b = 0; b < E.rblocks; b++) E.rhist[(size_t)b * 256 + d] += before;
+    if (threadIdx.x == 0) E.rhist[(size_t)256 * nb + d] = base;
 }
 
+// The tile is ranked in LDS first: each element's place in the tile sorted
+// by digit (stable), then the sorted tile is written out, so that every
+// digit's elements go to consecutive addresses.  The tile's elements are read
+// once, into registers.
 __global__ __launch_bounds__(256) void k_rad_scatter(const EncDesc E, const unsigned long long *kin_,
                                                      const uint32_t *vin_, unsigned long long *kout_,
                                                      uint32_t *vout_, uint32_t key_pass, uint32_t shift)
@@ -2095,37 +2113,58 @@ __global__ __launch_bounds__(256) void k_rad_scatter(const EncDesc E, const unsi
     const GLB uint32_t *vin = (const GLB uint32_t *)vin_;
     GLB unsigned long long *kout = (GLB unsigned long long *)kout_;
     GLB uint32_t *vout = (GLB uint32_t *)vout_;
-    __shared__ uint32_t wcnt[4][256];  // per wave: digit counts, then running positions
+    __shared__ uint32_t wcnt[4][256];  // per wave: digit counts, then running places in the sorted tile
+    __shared__ uint32_t gdst[256];     // per digit: output index of the sorted tile's place 0
+    __shared__ unsigned long long sk[kRadTile];
+    __shared__ uint32_t sv[kRadTile];
     const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     for (uint32_t q = threadIdx.x; q < 4 * 256; q += 256) (&wcnt[0][0])[q] = 0;
     __syncthreads();
-    const uint32_t base = blockIdx.x * kRadTile + w * 1024;
-    for (uint32_t ch = 0; ch < 16; ch++) {
+    const uint32_t t0 = blockIdx.x * kRadTile, base = t0 + w * 1024;
+    unsigned long long kr[16];
+    uint32_t vr[16];
+#pragma unroll
+    for (int ch = 0; ch < 16; ch++) {
         const uint32_t i = base + ch * kWave + lane;
-        if (i < E.nU) atomicAdd(&wcnt[w][rad_digit(key_pass, kin[i], vin[i], shift)], 1u);
+        kr[ch] = 0;
+        vr[ch] = 0;
+        if (i < E.nU) {
+            kr[ch] = kin[i];
+            vr[ch] = vin[i];
+        }
+    }
+#pragma unroll
+    for (int ch = 0; ch < 16; ch++) {
+        const uint32_t i = base + ch * kWave + lane;
+        if (i < E.nU) atomicAdd(&wcnt[w][rad_digit(key_pass, kr[ch], vr[ch], shift)], 1u);
     }
     __syncthreads();
     {
         const uint32_t d = threadIdx.x;
-        uint32_t run = E.rhist[(size_t)blockIdx.x * 256 + d];
+        uint32_t c[4], tile = 0;
+#pragma unroll
         for (int ww = 0; ww < 4; ww++) {
-            const uint32_t c = wcnt[ww][d];
-            wcnt[ww][d] = run;
-            run += c;
+            c[ww] = wcnt[ww][d];
+            tile += c[ww];
         }
+        uint32_t all;
+        const uint32_t loc = block_excl_add(tile, &all);  // digit d's first place in the sorted tile
+        uint32_t run = loc;
+#pragma unroll
+        for (int ww = 0; ww < 4; ww++) {
+            wcnt[ww][d] = run;
+            run += c[ww];
+        }
+        const uint32_t gstart = block_excl_add(E.rhist[(size_t)256 * E.rblocks + d], &all) +
+                                E.rhist[(size_t)d * E.rblocks + blockIdx.x];
+        gdst[d] = gstart - loc;
     }
     __syncthreads();
     const uint64_t below = (1ull << lane) - 1ull;
-    for (uint32_t ch = 0; ch < 16; ch++) {
-        const uint32_t i = base + ch * kWave + lane;
-        const bool act = i < E.nU;
-        unsigned long long k = 0;
-        uint32_t v = 0, dg = 0;
-        if (act) {
-            k = kin[i];
-            v = vin[i];
-            dg = rad_digit(key_pass, k, v, shift);
-        }
+#pragma unroll
+    for (int ch = 0; ch < 16; ch++) {
+        const bool act = base + ch * kWave + lane < E.nU;
+        const uint32_t dg = act ? rad_digit(key_pass, kr[ch], vr[ch], shift) : 0u;
         uint64_t same = __ballot(act);
 #pragma unroll
         for (int bit = 0; bit < 8; bit++) {
@@ -2134,13 +2173,22 @@ __global__ __launch_bounds__(256) void k_rad_scatter(const EncDesc E, const unsi
         }
         if (act) {
             const uint32_t pos = wcnt[w][dg] + (uint32_t)__popcll(same & below);
-            kout[pos] = k;
-            vout[pos] = v;
+            sk[pos] = kr[ch];
+            sv[pos] = vr[ch];
         }
         __builtin_amdgcn_wave_barrier();
-        // the last lane of each digit group moves that digit's position on
+        // the last lane of each digit group moves that digit's place on
         if (act && (same & ~below & ~(1ull << lane)) == 0) wcnt[w][dg] += (uint32_t)__popcll(same);
         __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    const uint32_t nt = E.nU - t0 < (uint32_t)kRadTile ? E.nU - t0 : (uint32_t)kRadTile;
+    for (uint32_t q = threadIdx.x; q < nt; q += 256) {
+        const unsigned long long k = sk[q];
+        const uint32_t v = sv[q];
+        const uint32_t o = gdst[rad_digit(key_pass, k, v, shift)] + q;
+        kout[o] = k;
+        vout[o] = v;
     }
 }
 
@@ -3980,7 +4028,7 @@ EncLayout enc_layout(uint32_t n, uint32_t nU)
     L.k1 = off;    off += align256(8 * std::max<size_t>(nU, 1));
     L.v0 = off;    off += align256(4 * std::max<size_t>(nU, 1));
     L.v1 = off;    off += align256(4 * std::max<size_t>(nU, 1));
-    L.rhist = off; off += align256(4 * 256 * std::max<size_t>(L.rblocks, 1));
+    L.rhist = off; off += align256(4 * 256 * (std::max<size_t>(L.rblocks, 1) + 1));
     L.total = off;
     return L;
 }
@@ -4077,7 +4125,7 @@ int tmd_encode(tmd_plan_t *P, const tmd_enc_in *in, tmd_enc_out *out, void *work
             const uint32_t key_pass = pass >= 4 ? 1u : 0u;
             const uint32_t shift = key_pass ? 8u * (uint32_t)(pass - 4) : 8u * (uint32_t)pass;
             hipLaunchKernelGGL(k_rad_hist, dim3(L.rblocks), dim3(256), 0, s, E, ka, va, key_pass, shift);
-            hipLaunchKernelGGL(k_rad_offsets, dim3(1), dim3(256), 0, s, E);
+            hipLaunchKernelGGL(k_rad_offsets, dim3(256), dim3(256), 0, s, E);
             hipLaunchKernelGGL(k_rad_scatter, dim3(L.rblocks), dim3(256), 0, s, E, ka, va, kb, vb, key_pass, shift);
             std::swap(ka, kb);
             std::swap(va, vb);

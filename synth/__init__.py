@@ -7,3 +7,4 @@ valid decoder input.  Both the GPU library's tests and benchmarks and the CPU
 oracle consume its frames.  See synth.frames.
 """
 from .frames import WORKLOADS, FrameSpec, batch_specs, make_frame, make_frames, spec_for  # noqa: F401
+from .phys import make_phys, phys_sizes  # noqa: F401,E402

@@ -75,3 +75,11 @@ def test_encode_empty_and_bad_input(tmd):
     bad["un_pad"][3] = 5000.0   # 160000 in 1/32 pad: beyond 16 bits
     with pytest.raises(tmd.TmdError):
         tmd.encode(bad, bz=0.5)
+
+
+def test_encode_synth_frame(tmd):
+    """The encoder benchmark's input generator at a tenth of its size: every
+    array bit for bit, and the round trip."""
+    import synth
+    phys = synth.make_phys(synth.spec_for("frame", collisions=10))
+    check_encode(tmd, phys, 0.5, "synth frame")

@@ -83,3 +83,16 @@ def test_committed_summaries_parse(workload):
     s = json.loads(lines[0][len("traffic-json: "):])
     assert s["workload"] == workload and len(s["source_sha256"]) == 64
     assert s["kernels"]["k_attached"]["traffic_bytes"] > 0
+
+
+def test_encode_bytes_and_roofline(monkeypatch):
+    # 20 B in per track, 30 B in and 10 B out per attached cluster, 22 B in and 10 B out per unattached one,
+    # 15 B per header written and the bin counts
+    assert bench.encode_bytes(2, 10, 5, 3) == 20 * 2 + 40 * 10 + 32 * 5 + 15 * 3 + 4 * 5472
+    summ = {"frames": 64, "kernels": {"k_enc_tracks": {"traffic_bytes": 1e6, "dispatches": 4},
+                                      "k_rad_scatter": {"traffic_bytes": 2e6, "dispatches": 48},
+                                      "k_attached": {"traffic_bytes": 9e9, "dispatches": 4}}}
+    monkeypatch.setattr(traffic, "load_summary", lambda w: summ)
+    r = bench.roofline("encode", 4e8, 0.2, "encode")
+    assert r["kernel"] == "tmd_encode (all kernels)" and r["achieved"] == 2000.0
+    assert r["traffic"] == 1e6 + 12 * 2e6   # per call: twelve scatter passes
