@@ -1749,16 +1749,22 @@ __global__ void k_selftest_fp(const float *a, const float *b, float *out, uint32
 // one).  Input: clusters in physical units (pad and time as doubles, grouped
 // by track) and track parameters; output: a compressed frame for tmd_decode.
 //
-//   E1 k_enc_tracks   one lane per track: quantise, run the same float32 model
-//                     as the decode, store residuals; open a new header where
-//                     the model cannot follow (row step beyond int8, side
-//                     change, 255 clusters, a clamp, a residual beyond int16)
-//   E2 k_enc_scan_*   header clusters -> header indices (block sums, prefix)
+//   E0 k_enc_pack     one lane per cluster: quantise, check the range, pack
+//                     the cluster into an 8-byte record
+//   E1 k_enc_tracks   one lane per track, over the records: run the same
+//                     float32 model as the decode, store packed residuals;
+//                     open a new header where the model cannot follow (row
+//                     step beyond int8, side change, 255 clusters, a clamp, a
+//                     residual beyond int16)
+//   E2 k_enc_scan_*   unpack the residuals and copy the charges (one lane per
+//                     cluster); header clusters -> header indices (block
+//                     sums, prefix)
 //   E3 k_enc_headers  header arrays and cluster counts
-//   U1 k_enc_un_keys  unattached: quantise, bin counts, sort keys
+//   U1 k_enc_un_keys  unattached: quantise, sort keys
 //   U2 k_rad_*        stable LSD radix sort of (bin, time, pad) then (qTot,
 //                     qMax) as the lower digits: 12 passes of 8 bits
-//   U3 k_enc_un_delta differences to the predecessor within the bin
+//   U3 k_enc_un_delta differences to the predecessor within the bin; bin
+//                     counts from where the sorted bins begin and end
 // ---------------------------------------------------------------------------
 struct EncDesc {
     // input
@@ -1785,6 +1791,8 @@ struct EncDesc {
     GLB uint32_t *counts;  // [0] headers, [1] splits, [2] input errors
     // workspace
     GLB uint8_t *hn;     // [n] clusters of the header opened at cluster c, else 0
+    GLB unsigned long long *rec;  // [n] per cluster: the packed input (k_enc_pack), then the packed
+                                  // output of the track walk (k_enc_tracks), in place
     GLB uint32_t *htrk;  // [n] track of the header opened at cluster c
     GLB uint32_t *bsum;  // [ceil(n / 1024) + 1] headers per block of clusters, then their prefix
     GLB unsigned long long *k0, *k1;  // [nU] sort keys (ping-pong)
@@ -1878,7 +1886,30 @@ __device__ void enc_update(const Geo *__restrict__ g, EncState &st, int32_t pres
     st.tgl = st.tgl + (nuz * R.kt);
 }
 
-// E1: one lane per track
+// Packed records of the track walk.  In: pad code (16 bits), time code (24),
+// row (8), sector (8).  Out: row step (8), sector step (8), pad residual
+// (16), time residual (16), and bit 48 set where a header opens.
+constexpr int kRecTime = 16, kRecRow = 40, kRecSec = 48, kRecOpen = 48;
+
+// E0: one lane per cluster: quantise (rint of 32 x pad and time, in double),
+// check the codable range, pack
+__global__ __launch_bounds__(256) void k_enc_pack(const EncDesc E)
+{
+    const uint32_t c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= E.n) return;
+    const double pq = __builtin_rint(E.pad[c] * 32.0), tq = __builtin_rint(E.time[c] * 32.0);
+    unsigned long long r = 0;
+    if (pq >= 0.0 && pq <= 65535.0 && tq >= 0.0 && tq < (double)kTimeLim) {
+        r = (unsigned long long)(uint32_t)pq | ((unsigned long long)(uint32_t)tq << kRecTime) |
+            ((unsigned long long)E.row[c] << kRecRow) | ((unsigned long long)E.sec[c] << kRecSec);
+    } else {
+        atomicOr(&E.counts[2], kEncErrInput);
+    }
+    E.rec[c] = r;
+}
+
+// E1: one lane per track, over the packed records (one 8-byte load and one
+// 8-byte store per cluster)
 __global__ __launch_bounds__(256) void k_enc_tracks(const EncDesc E, const Geo *__restrict__ g)
 {
     const uint32_t it = blockIdx.x * 256 + threadIdx.x;
@@ -1890,17 +1921,21 @@ __global__ __launch_bounds__(256) void k_enc_tracks(const EncDesc E, const Geo *
         return;
     }
     const int16_t qptq = enc_q16(E.qpt[it], 1024.0), tglq = enc_q16(E.tgl[it], 4096.0);
-    uint32_t hdr = a, hcount = 0, splits = 0, err = 0;
+    uint32_t hdr = a, hcount = 0, splits = 0;
     EncState st = {};
     uint32_t prow = 0, psec = 0;  // the previous cluster's row and sector
+    // the next four records are loaded ahead (a record is overwritten only
+    // after the one four places on has been loaded)
+    unsigned long long q0 = a < e ? E.rec[a] : 0ull, q1 = a + 1 < e ? E.rec[a + 1] : 0ull;
+    unsigned long long q2 = a + 2 < e ? E.rec[a + 2] : 0ull, q3 = a + 3 < e ? E.rec[a + 3] : 0ull;
     for (uint32_t c = a; c < e; c++) {
-        const uint32_t crow = E.row[c], csec = E.sec[c];
-        const double pq = __builtin_rint(E.pad[c] * 32.0), tq = __builtin_rint(E.time[c] * 32.0);
-        if (!(pq >= 0.0 && pq <= 65535.0 && tq >= 0.0 && tq < (double)kTimeLim)) {
-            err = 1;
-            break;
-        }
-        const int32_t padq = (int32_t)pq, timeq = (int32_t)tq;
+        const unsigned long long in = q0;
+        q0 = q1;
+        q1 = q2;
+        q2 = q3;
+        q3 = c + 4 < e ? E.rec[c + 4] : 0ull;
+        const uint32_t crow = (uint32_t)(in >> kRecRow) & 0xFFu, csec = (uint32_t)(in >> kRecSec) & 0xFFu;
+        const int32_t padq = (int32_t)(in & 0xFFFFu), timeq = (int32_t)((in >> kRecTime) & 0xFFFFFFu);
         bool open_new = c == a;
         int32_t rd = 0, sd = 0, pr = 0, tr = 0;
         if (!open_new) {
@@ -1943,35 +1978,37 @@ __global__ __launch_bounds__(256) void k_enc_tracks(const EncDesc E, const Geo *
             rd = sd = pr = tr = 0;
         } else {
             hcount++;
-            E.hn[c] = 0;
         }
-        E.rdiff[c] = (int8_t)rd;
-        E.sdiff[c] = (uint8_t)sd;
-        E.pres[c] = (int16_t)pr;
-        E.tres[c] = (int16_t)tr;
+        E.rec[c] = (unsigned long long)(uint8_t)rd | ((unsigned long long)(uint8_t)sd << 8) |
+                   ((unsigned long long)(uint16_t)pr << 16) | ((unsigned long long)(uint16_t)tr << 32) |
+                   ((unsigned long long)(open_new ? 1u : 0u) << kRecOpen);
         prow = crow;
         psec = csec;
-    }
-    if (err) {
-        atomicOr(&E.counts[2], kEncErrInput);
-        return;
     }
     if (e > a) E.hn[hdr] = (uint8_t)hcount;
     if (splits) atomicAdd(&E.counts[1], splits);
 }
 
-// E2: headers per block of 1024 clusters; the clusters' charges are copied
-// here, in cluster order
+// E2: headers per block of 1024 clusters; the track walk's records are
+// unpacked into the cluster arrays (hn of a cluster that opens no header set
+// to 0) and the charges copied, in cluster order
 __global__ __launch_bounds__(256) void k_enc_scan_blocks(const EncDesc E)
 {
-    const uint32_t c0 = blockIdx.x * 1024 + threadIdx.x * 4;
     uint32_t h = 0;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        if (c0 + q < E.n) {
-            h += E.hn[c0 + q] != 0 ? 1u : 0u;
-            E.cqtot[c0 + q] = E.qtot[c0 + q];
-            E.cqmax[c0 + q] = E.qmax[c0 + q];
+        const uint32_t c = blockIdx.x * 1024 + q * 256 + threadIdx.x;
+        if (c < E.n) {
+            const unsigned long long r = E.rec[c];
+            const uint32_t open = (uint32_t)(r >> kRecOpen) & 1u;
+            h += open;
+            if (!open) E.hn[c] = 0;
+            E.rdiff[c] = (int8_t)(r & 0xFFu);
+            E.sdiff[c] = (uint8_t)((r >> 8) & 0xFFu);
+            E.pres[c] = (int16_t)(uint16_t)((r >> 16) & 0xFFFFu);
+            E.tres[c] = (int16_t)(uint16_t)((r >> 32) & 0xFFFFu);
+            E.cqtot[c] = E.qtot[c];
+            E.cqmax[c] = E.qmax[c];
         }
     }
     uint32_t tot;
@@ -2027,7 +2064,7 @@ __global__ __launch_bounds__(256) void k_enc_headers(const EncDesc E)
     }
 }
 
-// U1: quantise unattached clusters, count them per bin, build sort keys
+// U1: quantise unattached clusters, build sort keys
 // (bin << 48 | time << 16 | pad) and payloads (qTot << 16 | qMax)
 __global__ __launch_bounds__(256) void k_enc_un_keys(const EncDesc E)
 {
@@ -2044,7 +2081,6 @@ __global__ __launch_bounds__(256) void k_enc_un_keys(const EncDesc E)
     const uint64_t bin = sec * NROW + row;
     E.k0[i] = (bin << 48) | ((uint64_t)(uint32_t)tq << 16) | (uint64_t)(uint32_t)pq;
     E.v0[i] = ((uint32_t)E.uqtot[i] << 16) | E.uqmax[i];
-    atomicAdd(&E.ucount[bin], 1u);
 }
 
 __global__ __launch_bounds__(256) void k_enc_clear(const EncDesc E)
@@ -2076,7 +2112,7 @@ __global__ __launch_bounds__(256) void k_rad_hist(const EncDesc E, const unsigne
     const uint32_t base = blockIdx.x * kRadTile;
     for (uint32_t q = threadIdx.x; q < (uint32_t)kRadTile; q += 256) {
         const uint32_t i = base + q;
-        if (i < E.nU) atomicAdd(&cnt[rad_digit(key_pass, kin[i], vin[i], shift)], 1u);
+        if (i < E.nU) atomicAdd(&cnt[key_pass ? (uint32_t)(kin[i] >> shift) & 0xFFu : (vin[i] >> shift) & 0xFFu], 1u);
     }
     __syncthreads();
     E.rhist[(size_t)threadIdx.x * E.rblocks + blockIdx.x] = cnt[threadIdx.x];
@@ -2192,7 +2228,8 @@ __global__ __launch_bounds__(256) void k_rad_scatter(const EncDesc E, const unsi
     }
 }
 
-// U3: differences to the predecessor in the same bin (the first against zero)
+// U3: differences to the predecessor in the same bin (the first against zero);
+// a bin's count is the distance from its first element to past its last
 __global__ __launch_bounds__(256) void k_enc_un_delta(const EncDesc E, const unsigned long long *ks_,
                                                       const uint32_t *vs_)
 {
@@ -2201,14 +2238,19 @@ __global__ __launch_bounds__(256) void k_enc_un_delta(const EncDesc E, const uns
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
     if (i >= E.nU) return;
     const unsigned long long k = ks[i];
+    const uint32_t bin = (uint32_t)(k >> 48);
     uint32_t pt = 0, pp = 0;
+    bool first = true;
     if (i > 0) {
         const unsigned long long kp = ks[i - 1];
-        if ((kp >> 48) == (k >> 48)) {
+        if ((kp >> 48) == bin) {
             pt = (uint32_t)(kp >> 16);
             pp = (uint32_t)kp & 0xFFFFu;
+            first = false;
         }
     }
+    if (first) atomicSub(&E.ucount[bin], i);
+    if (i + 1 == E.nU || (uint32_t)(ks[i + 1] >> 48) != bin) atomicAdd(&E.ucount[bin], i + 1);
     const uint32_t v = vs[i];
     E.utdiff[i] = (uint32_t)(k >> 16) - pt;
     E.updiff[i] = (uint16_t)(((uint32_t)k & 0xFFFFu) - pp);
@@ -4011,7 +4053,7 @@ int tmd_selftest_fp(const float *a, const float *b, float *out, uint32_t n, void
 namespace {
 
 struct EncLayout {
-    size_t hn, htrk, bsum, k0, k1, v0, v1, rhist, total;
+    size_t hn, htrk, rec, bsum, k0, k1, v0, v1, rhist, total;
     uint32_t nb, rblocks;
 };
 
@@ -4023,6 +4065,7 @@ EncLayout enc_layout(uint32_t n, uint32_t nU)
     size_t off = 0;
     L.hn = off;    off += align256(std::max<size_t>(n, 1));
     L.htrk = off;  off += align256(4 * std::max<size_t>(n, 1));
+    L.rec = off;   off += align256(8 * std::max<size_t>(n, 1));
     L.bsum = off;  off += align256(4 * ((size_t)L.nb + 1));
     L.k0 = off;    off += align256(8 * std::max<size_t>(nU, 1));
     L.k1 = off;    off += align256(8 * std::max<size_t>(nU, 1));
@@ -4096,6 +4139,7 @@ int tmd_encode(tmd_plan_t *P, const tmd_enc_in *in, tmd_enc_out *out, void *work
     E.uoqmax = (GLB uint16_t *)out->un_qmax; E.counts = (GLB uint32_t *)out->counts;
     char *ws = (char *)workspace;
     E.hn = (GLB uint8_t *)(ws + L.hn); E.htrk = (GLB uint32_t *)(ws + L.htrk);
+    E.rec = (GLB unsigned long long *)(ws + L.rec);
     E.bsum = (GLB uint32_t *)(ws + L.bsum);
     E.k0 = (GLB unsigned long long *)(ws + L.k0); E.k1 = (GLB unsigned long long *)(ws + L.k1);
     E.v0 = (GLB uint32_t *)(ws + L.v0); E.v1 = (GLB uint32_t *)(ws + L.v1);
@@ -4109,6 +4153,7 @@ int tmd_encode(tmd_plan_t *P, const tmd_enc_in *in, tmd_enc_out *out, void *work
     // but keep the plan's ordering rule)
     if (P->called) (void)hipStreamWaitEvent(s, P->done, 0);
     hipLaunchKernelGGL(k_enc_clear, dim3((NBIN + 255) / 256), dim3(256), 0, s, E);
+    if (n) hipLaunchKernelGGL(k_enc_pack, dim3((n + 255) / 256), dim3(256), 0, s, E);
     if (nT) hipLaunchKernelGGL(k_enc_tracks, dim3((nT + 255) / 256), dim3(256), 0, s, E, P->d_geo);
     if (n) {
         hipLaunchKernelGGL(k_enc_scan_blocks, dim3(L.nb), dim3(256), 0, s, E);
