@@ -1819,7 +1819,7 @@ struct EncState {
     int32_t t0;
 };
 
-__device__ void enc_init(const Geo *__restrict__ g, EncState &st, int sec0, int row0, uint32_t pad0, uint32_t time0,
+__device__ __forceinline__ void enc_init(const Geo *__restrict__ g, EncState &st, int sec0, int row0, uint32_t pad0, uint32_t time0,
                          int16_t qptq, int16_t snpq, int16_t tglq, uint32_t &fl)
 {
     if (sec0 >= NSEC) { fl |= TMD_F_HDR; sec0 = sec0 % NSEC; }
@@ -1839,7 +1839,7 @@ __device__ void enc_init(const Geo *__restrict__ g, EncState &st, int sec0, int 
 }
 
 // the decode's step (rotation, row step, helix propagation, predicted codes)
-__device__ void enc_predict(const Geo *__restrict__ g, EncState &st, uint32_t sd, int rd, int32_t &P, int32_t &T,
+__device__ __forceinline__ void enc_predict(const Geo *__restrict__ g, EncState &st, uint32_t sd, int rd, int32_t &P, int32_t &T,
                             uint32_t &fl)
 {
     uint32_t d = sd;
@@ -1875,7 +1875,7 @@ __device__ void enc_predict(const Geo *__restrict__ g, EncState &st, uint32_t sd
     T = sat_rint(st.z * g->inv_vd32);
 }
 
-__device__ void enc_update(const Geo *__restrict__ g, EncState &st, int32_t pres, int32_t tres, uint32_t &fl)
+__device__ __forceinline__ void enc_update(const Geo *__restrict__ g, EncState &st, int32_t pres, int32_t tres, uint32_t &fl)
 {
     const RowGeo &R = g->row[st.row];
     const float nuy = (float)pres * R.pwq;
@@ -1908,82 +1908,116 @@ __global__ __launch_bounds__(256) void k_enc_pack(const EncDesc E)
     E.rec[c] = r;
 }
 
-// E1: one lane per track, over the packed records (one 8-byte load and one
-// 8-byte store per cluster)
+// E1: one lane per track, over the packed records.  A wave's 64 tracks are
+// walked kEncSeg steps at a time: the next kEncSeg records of every lane's
+// track are staged in LDS by loads that take 16 consecutive records per 16
+// lanes, the lanes step through them there and leave their output records in
+// the same slots, and the slots are written back the same way.
+constexpr uint32_t kEncSeg = 16;
+
 __global__ __launch_bounds__(256) void k_enc_tracks(const EncDesc E, const Geo *__restrict__ g)
 {
+    // [wave][lane][slot]; 17 slots per lane keep 16 lanes' reads of one slot
+    // on distinct banks
+    __shared__ unsigned long long ring[4][kWave][kEncSeg + 1];
+    __shared__ uint32_t ta[4][kWave], te[4][kWave];
+    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
     const uint32_t it = blockIdx.x * 256 + threadIdx.x;
     if (it == 0 && (E.first[0] != 0 || E.first[E.nT] != E.n)) atomicOr(&E.counts[2], kEncErrInput);
-    if (it >= E.nT) return;
-    const uint32_t a = E.first[it], e = E.first[it + 1];
-    if (a > e || e > E.n) {
-        atomicOr(&E.counts[2], kEncErrInput);
-        return;
+    uint32_t a = 0, e = 0;
+    int16_t qptq = 0, tglq = 0;
+    if (it < E.nT) {
+        a = E.first[it];
+        e = E.first[it + 1];
+        if (a > e || e > E.n) {
+            atomicOr(&E.counts[2], kEncErrInput);
+            a = e = 0;
+        }
+        qptq = enc_q16(E.qpt[it], 1024.0);
+        tglq = enc_q16(E.tgl[it], 4096.0);
     }
-    const int16_t qptq = enc_q16(E.qpt[it], 1024.0), tglq = enc_q16(E.tgl[it], 4096.0);
+    ta[w][lane] = a;
+    te[w][lane] = e;
+    const uint32_t maxlen = wave_max_u32(e - a);
     uint32_t hdr = a, hcount = 0, splits = 0;
     EncState st = {};
     uint32_t prow = 0, psec = 0;  // the previous cluster's row and sector
-    // the next four records are loaded ahead (a record is overwritten only
-    // after the one four places on has been loaded)
-    unsigned long long q0 = a < e ? E.rec[a] : 0ull, q1 = a + 1 < e ? E.rec[a + 1] : 0ull;
-    unsigned long long q2 = a + 2 < e ? E.rec[a + 2] : 0ull, q3 = a + 3 < e ? E.rec[a + 3] : 0ull;
-    for (uint32_t c = a; c < e; c++) {
-        const unsigned long long in = q0;
-        q0 = q1;
-        q1 = q2;
-        q2 = q3;
-        q3 = c + 4 < e ? E.rec[c + 4] : 0ull;
-        const uint32_t crow = (uint32_t)(in >> kRecRow) & 0xFFu, csec = (uint32_t)(in >> kRecSec) & 0xFFu;
-        const int32_t padq = (int32_t)(in & 0xFFFFu), timeq = (int32_t)((in >> kRecTime) & 0xFFFFFFu);
-        bool open_new = c == a;
-        int32_t rd = 0, sd = 0, pr = 0, tr = 0;
-        if (!open_new) {
-            const int drow = (int)crow - (int)prow;
-            const bool same_side = (csec / 18) == (psec / 18);
-            if (drow < -128 || drow > 127 || !same_side || hcount == 255) {
-                open_new = true;
-            } else {
-                rd = drow;
-                sd = ((int)(csec % 18) - (int)(psec % 18) + 18) % 18;
-                EncState trial = st;
-                uint32_t fl = 0;
-                int32_t P, T;
-                enc_predict(g, trial, (uint32_t)sd, rd, P, T, fl);
-                const int64_t p64 = (int64_t)padq - P;
-                const int64_t t64 = (int64_t)timeq - trial.t0 - T;
-                if (fl || p64 < -32768 || p64 > 32767 || t64 < -32768 || t64 > 32767 || trial.sec != (int)csec ||
-                    trial.row != (int)crow) {
+    const uint32_t sk = lane % kEncSeg, sq = lane / kEncSeg;
+    for (uint32_t j0 = 0; j0 < maxlen; j0 += kEncSeg) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 4
+        for (uint32_t r = 0; r < kWave / 4; r++) {
+            const uint32_t sl = 4 * r + sq, cc = ta[w][sl] + j0 + sk;
+            if (cc < te[w][sl]) ring[w][sl][sk] = E.rec[cc];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t jj = 0; jj < kEncSeg; jj++) {
+            const uint32_t c = a + j0 + jj;
+            if (c >= e) break;
+            const unsigned long long in = ring[w][lane][jj];
+            const uint32_t crow = (uint32_t)(in >> kRecRow) & 0xFFu, csec = (uint32_t)(in >> kRecSec) & 0xFFu;
+            const int32_t padq = (int32_t)(in & 0xFFFFu), timeq = (int32_t)((in >> kRecTime) & 0xFFFFFFu);
+            bool open_new = c == a;
+            int32_t rd = 0, sd = 0, pr = 0, tr = 0;
+            if (!open_new) {
+                const int drow = (int)crow - (int)prow;
+                const bool same_side = (csec / 18) == (psec / 18);
+                if (drow < -128 || drow > 127 || !same_side || hcount == 255) {
                     open_new = true;
                 } else {
-                    pr = (int32_t)p64;
-                    tr = (int32_t)t64;
-                    enc_update(g, trial, pr, tr, fl);
-                    if (fl) open_new = true;
-                    else st = trial;
+                    rd = drow;
+                    sd = ((int)(csec % 18) - (int)(psec % 18) + 18) % 18;
+                    EncState trial = st;
+                    uint32_t fl = 0;
+                    int32_t P, T;
+                    enc_predict(g, trial, (uint32_t)sd, rd, P, T, fl);
+                    const int64_t p64 = (int64_t)padq - P;
+                    const int64_t t64 = (int64_t)timeq - trial.t0 - T;
+                    if (fl || p64 < -32768 || p64 > 32767 || t64 < -32768 || t64 > 32767 || trial.sec != (int)csec ||
+                        trial.row != (int)crow) {
+                        open_new = true;
+                    } else {
+                        pr = (int32_t)p64;
+                        tr = (int32_t)t64;
+                        enc_update(g, trial, pr, tr, fl);
+                        if (fl) open_new = true;
+                        else st = trial;
+                    }
                 }
             }
-        }
-        if (open_new) {
-            if (c != a) {
-                splits++;
-                E.hn[hdr] = (uint8_t)hcount;
+            if (open_new) {
+                if (c != a) {
+                    splits++;
+                    E.hn[hdr] = (uint8_t)hcount;
+                }
+                hdr = c;
+                hcount = 1;
+                E.htrk[c] = it;
+                uint32_t fl = 0;
+                enc_init(g, st, (int)csec, (int)crow, (uint32_t)padq, (uint32_t)timeq, qptq,
+                         enc_q16(E.snp[c], 32768.0), tglq, fl);
+                rd = sd = pr = tr = 0;
+            } else {
+                hcount++;
             }
-            hdr = c;
-            hcount = 1;
-            E.htrk[c] = it;
-            uint32_t fl = 0;
-            enc_init(g, st, (int)csec, (int)crow, (uint32_t)padq, (uint32_t)timeq, qptq, enc_q16(E.snp[c], 32768.0),
-                     tglq, fl);
-            rd = sd = pr = tr = 0;
-        } else {
-            hcount++;
+            ring[w][lane][jj] = (unsigned long long)(uint8_t)rd | ((unsigned long long)(uint8_t)sd << 8) |
+                                ((unsigned long long)(uint16_t)pr << 16) | ((unsigned long long)(uint16_t)tr << 32) |
+                                ((unsigned long long)(open_new ? 1u : 0u) << kRecOpen);
+            prow = crow;
+            psec = csec;
         }
-        E.rec[c] = (unsigned long long)(uint8_t)rd | ((unsigned long long)(uint8_t)sd << 8) |
-                   ((unsigned long long)(uint16_t)pr << 16) | ((unsigned long long)(uint16_t)tr << 32) |
-                   ((unsigned long long)(open_new ? 1u : 0u) << kRecOpen);
-        prow = crow;
-        psec = csec;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 4
+        for (uint32_t r = 0; r < kWave / 4; r++) {
+            const uint32_t sl = 4 * r + sq, cc = ta[w][sl] + j0 + sk;
+            if (cc < te[w][sl]) E.rec[cc] = ring[w][sl][sk];
+        }
     }
     if (e > a) E.hn[hdr] = (uint8_t)hcount;
     if (splits) atomicAdd(&E.counts[1], splits);
