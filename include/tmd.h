@@ -367,7 +367,11 @@ int tmd_encode_workspace(uint32_t n_tracks, uint32_t n_clusters, uint32_t n_unat
  * first cluster, and wherever the row step leaves int8, the side changes, a
  * header already has 255 clusters, the prediction clamps or flags anything,
  * the cluster is not where the model puts it, or a residual leaves int16.
- * tmd_decode of the result restores the quantised clusters exactly.
+ * tmd_decode of the result restores the quantised clusters exactly.  The
+ * unattached clusters are encoded on the plan's second stream, which forks
+ * from `stream` after the call's first kernel and joins it again before the
+ * call's work on `stream` ends, so the call is ordered on `stream` like a
+ * single kernel.  Calls on one plan must not overlap on the host.
  * Errors: TMD_E_ARG (null or misaligned pointer), TMD_E_CAPACITY (workspace
  * too small), TMD_E_HIP; data problems are reported in out->counts[2].
  */

@@ -4187,6 +4187,33 @@ int tmd_encode(tmd_plan_t *P, const tmd_enc_in *in, tmd_enc_out *out, void *work
     // but keep the plan's ordering rule)
     if (P->called) (void)hipStreamWaitEvent(s, P->done, 0);
     hipLaunchKernelGGL(k_enc_clear, dim3((NBIN + 255) / 256), dim3(256), 0, s, E);
+    // the unattached clusters (keys, sort, differences) on the plan's second
+    // stream, beside the track walk, which leaves most of the GPU idle
+    if (nU) {
+        const int rc = fork_side(P, s, [&](hipStream_t q) -> int {
+            hipLaunchKernelGGL(k_enc_un_keys, dim3((nU + 255) / 256), dim3(256), 0, q, E);
+            // the payload's digits first (the lower-order part of the order),
+            // then the key's; 12 passes, so the result ends in (k0, v0)
+            unsigned long long *ka = (unsigned long long *)E.k0, *kb = (unsigned long long *)E.k1;
+            uint32_t *va = (uint32_t *)E.v0, *vb = (uint32_t *)E.v1;
+            for (int pass = 0; pass < 12; pass++) {
+                const uint32_t key_pass = pass >= 4 ? 1u : 0u;
+                const uint32_t shift = key_pass ? 8u * (uint32_t)(pass - 4) : 8u * (uint32_t)pass;
+                hipLaunchKernelGGL(k_rad_hist, dim3(L.rblocks), dim3(256), 0, q, E, ka, va, key_pass, shift);
+                hipLaunchKernelGGL(k_rad_offsets, dim3(256), dim3(256), 0, q, E);
+                hipLaunchKernelGGL(k_rad_scatter, dim3(L.rblocks), dim3(256), 0, q, E, ka, va, kb, vb, key_pass,
+                                   shift);
+                std::swap(ka, kb);
+                std::swap(va, vb);
+            }
+            hipLaunchKernelGGL(k_enc_un_delta, dim3((nU + 255) / 256), dim3(256), 0, q, E, ka, va);
+            return hipGetLastError() == hipSuccess ? TMD_OK : TMD_E_HIP;
+        }, 0);
+        if (rc != TMD_OK) {
+            if (cur != P->device) (void)hipSetDevice(cur);
+            return rc;
+        }
+    }
     if (n) hipLaunchKernelGGL(k_enc_pack, dim3((n + 255) / 256), dim3(256), 0, s, E);
     if (nT) hipLaunchKernelGGL(k_enc_tracks, dim3((nT + 255) / 256), dim3(256), 0, s, E, P->d_geo);
     if (n) {
@@ -4194,24 +4221,8 @@ int tmd_encode(tmd_plan_t *P, const tmd_enc_in *in, tmd_enc_out *out, void *work
         hipLaunchKernelGGL(k_enc_scan_prefix, dim3(1), dim3(1024), 0, s, E, L.nb);
         hipLaunchKernelGGL(k_enc_headers, dim3(L.nb), dim3(256), 0, s, E);
     }
-    if (nU) {
-        hipLaunchKernelGGL(k_enc_un_keys, dim3((nU + 255) / 256), dim3(256), 0, s, E);
-        // the payload's digits first (the lower-order part of the order),
-        // then the key's; 12 passes, so the result ends in (k0, v0)
-        unsigned long long *ka = (unsigned long long *)E.k0, *kb = (unsigned long long *)E.k1;
-        uint32_t *va = (uint32_t *)E.v0, *vb = (uint32_t *)E.v1;
-        for (int pass = 0; pass < 12; pass++) {
-            const uint32_t key_pass = pass >= 4 ? 1u : 0u;
-            const uint32_t shift = key_pass ? 8u * (uint32_t)(pass - 4) : 8u * (uint32_t)pass;
-            hipLaunchKernelGGL(k_rad_hist, dim3(L.rblocks), dim3(256), 0, s, E, ka, va, key_pass, shift);
-            hipLaunchKernelGGL(k_rad_offsets, dim3(256), dim3(256), 0, s, E);
-            hipLaunchKernelGGL(k_rad_scatter, dim3(L.rblocks), dim3(256), 0, s, E, ka, va, kb, vb, key_pass, shift);
-            std::swap(ka, kb);
-            std::swap(va, vb);
-        }
-        hipLaunchKernelGGL(k_enc_un_delta, dim3((nU + 255) / 256), dim3(256), 0, s, E, ka, va);
-    }
     hipError_t e = hipGetLastError();
+    if (nU && hipStreamWaitEvent(s, P->join[0], 0) != hipSuccess) e = hipErrorUnknown;
     if (cur != P->device) (void)hipSetDevice(cur);
     return e == hipSuccess ? TMD_OK : TMD_E_HIP;
 }
