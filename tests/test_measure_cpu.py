@@ -73,8 +73,10 @@ def test_bench_refuses_several_gpus():
     assert r.stdout == ""
 
 
-@pytest.mark.parametrize("workload", ["batched", "coded", "frame", "stress"])
-def test_committed_summaries_parse(workload):
+@pytest.mark.parametrize("workload,kernel", [("batched", "k_attached"), ("coded", "k_attached"),
+                                             ("frame", "k_attached"), ("stress", "k_attached"),
+                                             ("encode", "k_enc_tracks")])
+def test_committed_summaries_parse(workload, kernel):
     """Every committed traffic summary carries its JSON line and the kernels'
     calibrated bytes (whether it is current is checked by load_summary)."""
     fn = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
@@ -82,7 +84,7 @@ def test_committed_summaries_parse(workload):
     assert len(lines) == 1
     s = json.loads(lines[0][len("traffic-json: "):])
     assert s["workload"] == workload and len(s["source_sha256"]) == 64
-    assert s["kernels"]["k_attached"]["traffic_bytes"] > 0
+    assert s["kernels"][kernel]["traffic_bytes"] > 0
 
 
 def test_encode_bytes_and_roofline(monkeypatch):
