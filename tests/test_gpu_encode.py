@@ -83,3 +83,56 @@ def test_encode_synth_frame(tmd):
     import synth
     phys = synth.make_phys(synth.spec_for("frame", collisions=10))
     check_encode(tmd, phys, 0.5, "synth frame")
+
+
+@pytest.mark.parametrize("field,index,value", [("cl_time", 7, 2.0 ** 19), ("cl_pad", 3, -1.0),
+                                               ("cl_pad", 40, 2048.0)])
+def test_encode_attached_out_of_range(tmd, field, index, value):
+    """An attached cluster outside the codable range (time code of 2^24 or
+    more, pad code below 0 or beyond 16 bits) is refused, by the oracle's
+    encoder and by the GPU's."""
+    bad = pg.generate(seed=2, n_tracks=5, n_un=10, bz=0.5)
+    bad[field] = bad[field].copy()
+    bad[field][index] = value
+    with pytest.raises(RuntimeError):
+        oracle.encode(bad, bz=0.5)
+    with pytest.raises(tmd.TmdError):
+        tmd.encode(bad, bz=0.5)
+
+
+def test_encode_unattached_only(tmd):
+    """No tracks and no attached clusters: only the sort and the bin counts
+    (a bin's first and last element in one place, bins 0 and 5471)."""
+    un = [(1, 2, 3.25, 4.0, 5, 6), (1, 2, 3.0, 4.0, 5, 6), (35, 151, 10.0, 1e6, 1, 1), (0, 0, 0.0, 0.0, 0, 0),
+          (1, 2, 3.25, 4.0, 5, 5)]
+    phys = _manual_phys([], un=un)
+    check_encode(tmd, phys, 0.5, "unattached only")
+
+
+def test_encode_calls_in_a_row_share_a_workspace(tmd):
+    """Two encodes after one another on one stream and one plan, reusing one
+    workspace, twice over, the second smaller: the second stream of each call
+    joins its own call, so nothing of one call's unattached sort mixes with
+    the next call's."""
+    import torch
+    big = pg.generate(seed=5, n_tracks=400, n_un=60000, bz=0.5)
+    small = pg.generate(seed=6, n_tracks=50, n_un=7000, bz=0.5)
+    plan = tmd.Plan([(1, 1, 1)], bz=0.5)
+    devb, devs = tmd.enc_to_device(big), tmd.enc_to_device(small)
+    shb, shs = tmd.enc_shape(devb), tmd.enc_shape(devs)
+    outb, outs = tmd.alloc_enc_out(*shb), tmd.alloc_enc_out(*shs)
+    ws = torch.empty(tmd.enc_workspace_bytes(*shb), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    try:
+        for _ in range(2):
+            tmd.encode_device(plan, devb, outb, ws, stream)
+            tmd.encode_device(plan, devs, outs, ws, stream)
+        stream.synchronize()
+        for phys, out, sh, label in ((big, outb, shb, "big"), (small, outs, shs, "small")):
+            got, split = tmd.enc_result(out, sh[1], sh[2])
+            exp, esplit = oracle.encode(phys, bz=0.5)
+            for k in exp:
+                assert np.array_equal(exp[k], got[k]), (label, k)
+            assert split == esplit, label
+    finally:
+        plan.free()
