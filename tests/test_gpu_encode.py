@@ -136,3 +136,18 @@ def test_encode_calls_in_a_row_share_a_workspace(tmd):
             assert split == esplit, label
     finally:
         plan.free()
+
+
+def test_encode_full_frame(tmd):
+    """The encoder benchmark's workload at its full size (200 000 tracks,
+    2.46e7 clusters), in the launch configuration the benchmark times: every
+    array bit for bit against the oracle's encoder."""
+    import synth
+    print("generating the physical clusters of the frame workload", flush=True)
+    phys = synth.make_phys(synth.spec_for("frame"))
+    print("oracle encoder", flush=True)
+    exp, esplit = oracle.encode(phys, bz=0.5)
+    got, split = tmd.encode(phys, bz=0.5)
+    for k in exp:
+        assert np.array_equal(exp[k], got[k]), k
+    assert split == esplit
