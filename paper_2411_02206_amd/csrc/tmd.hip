@@ -1761,8 +1761,9 @@ __global__ void k_selftest_fp(const float *a, const float *b, float *out, uint32
 //                     sums, prefix)
 //   E3 k_enc_headers  header arrays and cluster counts
 //   U1 k_enc_un_keys  unattached: quantise, sort keys
-//   U2 k_rad_*        stable LSD radix sort of (bin, time, pad) then (qTot,
-//                     qMax) as the lower digits: 12 passes of 8 bits
+//   U2 k_rad_*        stable LSD radix sort by (bin, time, pad), 8 passes of
+//                     8 bits; runs of equal keys then sorted by (qTot, qMax),
+//                     or, for a run of more than 64, the full 12-pass sort
 //   U3 k_enc_un_delta differences to the predecessor within the bin; bin
 //                     counts from where the sorted bins begin and end
 // ---------------------------------------------------------------------------
@@ -1799,6 +1800,7 @@ struct EncDesc {
     GLB uint32_t *v0, *v1;            // [nU] sort payloads (qTot << 16 | qMax)
     GLB uint32_t *rhist;              // [256 * rblocks + 256] radix histograms, digit-major (digit d of
                                       // tile b at d * rblocks + b), then offsets; the digit totals last
+    GLB uint32_t *rflag;  // [1] set when a run of equal keys is too long to sort in place
     uint32_t rblocks;
 };
 
@@ -2122,11 +2124,18 @@ __global__ __launch_bounds__(256) void k_enc_clear(const EncDesc E)
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
     if (i < NBIN) E.ucount[i] = 0;
     if (i < 3) E.counts[i] = 0;
+    if (i == 0) E.rflag[0] = 0;
 }
 
 // U2: one pass of a stable LSD radix sort on 8-bit digit `shift` of the key
 // (key_pass) or of the payload.  Blocks own tiles of kRadTile elements in
 // order; within a tile, wave w owns elements [1024 w, 1024 w + 1024).
+// The order wanted is (key, payload).  The key's 8 passes run first; then
+// k_rad_fix sorts each run of equal keys by payload (equal keys are rare:
+// clusters at one position of one bin).  A run longer than kFixRun sets a flag
+// instead, and the full sort follows on the result (4 payload passes, then the
+// key's 8): its kernels are always enqueued, as `gated` passes that return at
+// once unless the flag is set.
 __device__ __forceinline__ uint32_t rad_digit(bool key_pass, unsigned long long k, uint32_t v, uint32_t shift)
 {
     return key_pass ? (uint32_t)(k >> shift) & 0xFFu : (v >> shift) & 0xFFu;
@@ -2136,8 +2145,10 @@ __device__ __forceinline__ uint32_t rad_digit(bool key_pass, unsigned long long 
 // inside: a qualified parameter type would give the kernel a different symbol
 // in the device and host compilations)
 __global__ __launch_bounds__(256) void k_rad_hist(const EncDesc E, const unsigned long long *kin_,
-                                                  const uint32_t *vin_, uint32_t key_pass, uint32_t shift)
+                                                  const uint32_t *vin_, uint32_t key_pass, uint32_t shift,
+                                                  uint32_t gated)
 {
+    if (gated && E.rflag[0] == 0) return;
     const GLB unsigned long long *kin = (const GLB unsigned long long *)kin_;
     const GLB uint32_t *vin = (const GLB uint32_t *)vin_;
     __shared__ uint32_t cnt[256];
@@ -2155,8 +2166,9 @@ __global__ __launch_bounds__(256) void k_rad_hist(const EncDesc E, const unsigne
 // one block per digit d: its counts over the tiles -> their exclusive prefix
 // (in place, 256 tiles per round); the digit's total after all histograms.
 // The scatter adds the totals of the digits below its own.
-__global__ __launch_bounds__(256) void k_rad_offsets(const EncDesc E)
+__global__ __launch_bounds__(256) void k_rad_offsets(const EncDesc E, uint32_t gated)
 {
+    if (gated && E.rflag[0] == 0) return;
     const uint32_t d = blockIdx.x, nb = E.rblocks;
     GLB uint32_t *col = E.rhist + (size_t)d * nb;
     uint32_t base = 0;
@@ -2177,8 +2189,10 @@ __global__ __launch_bounds__(256) void k_rad_offsets(const EncDesc E)
 // once, into registers.
 __global__ __launch_bounds__(256) void k_rad_scatter(const EncDesc E, const unsigned long long *kin_,
                                                      const uint32_t *vin_, unsigned long long *kout_,
-                                                     uint32_t *vout_, uint32_t key_pass, uint32_t shift)
+                                                     uint32_t *vout_, uint32_t key_pass, uint32_t shift,
+                                                     uint32_t gated)
 {
+    if (gated && E.rflag[0] == 0) return;
     const GLB unsigned long long *kin = (const GLB unsigned long long *)kin_;
     const GLB uint32_t *vin = (const GLB uint32_t *)vin_;
     GLB unsigned long long *kout = (GLB unsigned long long *)kout_;
@@ -2259,6 +2273,36 @@ __global__ __launch_bounds__(256) void k_rad_scatter(const EncDesc E, const unsi
         const uint32_t o = gdst[rad_digit(key_pass, k, v, shift)] + q;
         kout[o] = k;
         vout[o] = v;
+    }
+}
+
+// after the key passes: the lane of the first element of a run of equal keys
+// sorts the run's payloads (insertion sort; the keys are all the same), or
+// sets the flag if the run is longer than kFixRun
+constexpr uint32_t kFixRun = 64;
+
+__global__ __launch_bounds__(256) void k_rad_fix(const EncDesc E, const unsigned long long *ks_, uint32_t *vs_)
+{
+    const GLB unsigned long long *ks = (const GLB unsigned long long *)ks_;
+    GLB uint32_t *vs = (GLB uint32_t *)vs_;
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i + 1 >= E.nU) return;
+    const unsigned long long k = ks[i];
+    if (ks[i + 1] != k || (i > 0 && ks[i - 1] == k)) return;
+    uint32_t j = i + 2;
+    while (j < E.nU && j - i <= kFixRun && ks[j] == k) j++;
+    if (j - i > kFixRun) {
+        E.rflag[0] = 1u;
+        return;
+    }
+    for (uint32_t a = i + 1; a < j; a++) {
+        const uint32_t v = vs[a];
+        uint32_t b = a;
+        while (b > i && vs[b - 1] > v) {
+            vs[b] = vs[b - 1];
+            b--;
+        }
+        vs[b] = v;
     }
 }
 
@@ -4087,7 +4131,7 @@ int tmd_selftest_fp(const float *a, const float *b, float *out, uint32_t n, void
 namespace {
 
 struct EncLayout {
-    size_t hn, htrk, rec, bsum, k0, k1, v0, v1, rhist, total;
+    size_t hn, htrk, rec, bsum, k0, k1, v0, v1, rhist, rflag, total;
     uint32_t nb, rblocks;
 };
 
@@ -4106,6 +4150,7 @@ EncLayout enc_layout(uint32_t n, uint32_t nU)
     L.v0 = off;    off += align256(4 * std::max<size_t>(nU, 1));
     L.v1 = off;    off += align256(4 * std::max<size_t>(nU, 1));
     L.rhist = off; off += align256(4 * 256 * (std::max<size_t>(L.rblocks, 1) + 1));
+    L.rflag = off; off += 256;
     L.total = off;
     return L;
 }
@@ -4178,6 +4223,7 @@ int tmd_encode(tmd_plan_t *P, const tmd_enc_in *in, tmd_enc_out *out, void *work
     E.k0 = (GLB unsigned long long *)(ws + L.k0); E.k1 = (GLB unsigned long long *)(ws + L.k1);
     E.v0 = (GLB uint32_t *)(ws + L.v0); E.v1 = (GLB uint32_t *)(ws + L.v1);
     E.rhist = (GLB uint32_t *)(ws + L.rhist);
+    E.rflag = (GLB uint32_t *)(ws + L.rflag);
     E.rblocks = L.rblocks;
     hipStream_t s = (hipStream_t)stream;
     int cur = 0;
@@ -4192,20 +4238,24 @@ int tmd_encode(tmd_plan_t *P, const tmd_enc_in *in, tmd_enc_out *out, void *work
     if (nU) {
         const int rc = fork_side(P, s, [&](hipStream_t q) -> int {
             hipLaunchKernelGGL(k_enc_un_keys, dim3((nU + 255) / 256), dim3(256), 0, q, E);
-            // the payload's digits first (the lower-order part of the order),
-            // then the key's; 12 passes, so the result ends in (k0, v0)
+            // the key's 8 passes, the runs of equal keys sorted by payload;
+            // then, gated on a run too long for that, the full sort of the
+            // result: the payload's 4 passes, then the key's 8.  Both counts
+            // are even, so the result ends in (k0, v0) either way.
             unsigned long long *ka = (unsigned long long *)E.k0, *kb = (unsigned long long *)E.k1;
             uint32_t *va = (uint32_t *)E.v0, *vb = (uint32_t *)E.v1;
-            for (int pass = 0; pass < 12; pass++) {
-                const uint32_t key_pass = pass >= 4 ? 1u : 0u;
-                const uint32_t shift = key_pass ? 8u * (uint32_t)(pass - 4) : 8u * (uint32_t)pass;
-                hipLaunchKernelGGL(k_rad_hist, dim3(L.rblocks), dim3(256), 0, q, E, ka, va, key_pass, shift);
-                hipLaunchKernelGGL(k_rad_offsets, dim3(256), dim3(256), 0, q, E);
+            auto pass = [&](uint32_t key_pass, uint32_t shift, uint32_t gated) {
+                hipLaunchKernelGGL(k_rad_hist, dim3(L.rblocks), dim3(256), 0, q, E, ka, va, key_pass, shift, gated);
+                hipLaunchKernelGGL(k_rad_offsets, dim3(256), dim3(256), 0, q, E, gated);
                 hipLaunchKernelGGL(k_rad_scatter, dim3(L.rblocks), dim3(256), 0, q, E, ka, va, kb, vb, key_pass,
-                                   shift);
+                                   shift, gated);
                 std::swap(ka, kb);
                 std::swap(va, vb);
-            }
+            };
+            for (uint32_t d = 0; d < 8; d++) pass(1u, 8u * d, 0u);
+            hipLaunchKernelGGL(k_rad_fix, dim3((nU + 255) / 256), dim3(256), 0, q, E, ka, va);
+            for (uint32_t d = 0; d < 4; d++) pass(0u, 8u * d, 1u);
+            for (uint32_t d = 0; d < 8; d++) pass(1u, 8u * d, 1u);
             hipLaunchKernelGGL(k_enc_un_delta, dim3((nU + 255) / 256), dim3(256), 0, q, E, ka, va);
             return hipGetLastError() == hipSuccess ? TMD_OK : TMD_E_HIP;
         }, 0);

@@ -151,3 +151,26 @@ def test_encode_full_frame(tmd):
     for k in exp:
         assert np.array_equal(exp[k], got[k]), k
     assert split == esplit
+
+
+@pytest.mark.parametrize("presorted", [False, True])
+def test_encode_equal_positions_over_many_tiles(tmd, presorted):
+    """20 000 unattached clusters at one position in one bin, plus others
+    spread out: their order is decided by the charges alone, given in random
+    or in charge order.  A run of equal keys this long is ordered by the full
+    sort (key and charges); short runs, as in the other tests here, are sorted
+    by charge in place after the key's passes."""
+    rng = np.random.default_rng(12)
+    n_same, n_other = 20000, 30000
+    qtot = rng.integers(0, 65536, n_same)
+    qmax = rng.integers(0, 65536, n_same)
+    if presorted:
+        o = np.lexsort((qmax, qtot))
+        qtot, qmax = qtot[o], qmax[o]
+    un = [(7, 30, 12.5, 700.25, int(a), int(b)) for a, b in zip(qtot, qmax)]
+    sec = rng.integers(0, 36, n_other)
+    row = rng.integers(0, 152, n_other)
+    un += [(int(s), int(r), float(rng.uniform(0, 60)), float(rng.uniform(0, 5000)), int(rng.integers(0, 9)),
+            int(rng.integers(0, 9))) for s, r in zip(sec, row)]
+    phys = _manual_phys([(0.5, 0.1, [(3, 10 + i, 30.0 + 0.1 * i, 900.0 + i, 0.0) for i in range(20)])], un=un)
+    check_encode(tmd, phys, 0.5, f"equal positions, presorted {presorted}")
