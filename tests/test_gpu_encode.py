@@ -174,3 +174,13 @@ def test_encode_equal_positions_over_many_tiles(tmd, presorted):
             int(rng.integers(0, 9))) for s, r in zip(sec, row)]
     phys = _manual_phys([(0.5, 0.1, [(3, 10 + i, 30.0 + 0.1 * i, 900.0 + i, 0.0) for i in range(20)])], un=un)
     check_encode(tmd, phys, 0.5, f"equal positions, presorted {presorted}")
+
+
+def test_encode_skewed_rows(tmd):
+    """Physical clusters with the stress workload's row skew (start rows and
+    unattached rows ~ exp(-row/40), so that the inner rows' bins hold many
+    more clusters than the outer ones), at 5 collisions: bit for bit and the
+    round trip."""
+    import synth
+    phys = synth.make_phys(synth.spec_for("stress", collisions=5))
+    check_encode(tmd, phys, 0.5, "skewed rows")
